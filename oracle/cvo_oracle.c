@@ -1,0 +1,319 @@
+/*
+ * FP64 CPU oracle for continuous sensor registration (Ghaffari et al.,
+ * "Continuous Direct Sparse Visual Odometry from RGB-D Images").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow definition that the
+ * GPU library is checked against.  Only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it; the library never does.
+ * It shares no code, header or constant with the GPU path.
+ *
+ * Everything is FP64.  Point coordinates and labels arrive as FP32 and are
+ * promoted exactly.  Every pair (i, j) is enumerated (brute force); with a
+ * cutoff kappa > 0 a pair contributes only if |x_i - z~_j|^2 <= (kappa*ell)^2.
+ *
+ * Notation (paper, Sections III-IV and VI):
+ *   X = {x_i}, labels l_i;  Z = {z_j}, labels m_j.
+ *   h = (R_h, t_h) in SE(3) is the paper's pose; the paper evaluates the
+ *   objective at z~_j = h^-1 z_j = R_h^T z_j - R_h^T t_h (gradient at h).
+ *   The library's pose T acts on target points, so T = h^-1.
+ *   c_ij = s_f <l_i, m_j>           (label inner product, Sec. VII-B remark)
+ *   k_ij = sigma^2 exp(-|x_i - z~_j|^2 / (2 ell^2))   (Sec. IV kernel)
+ *   F    = sum_ij c_ij k_ij         (eq. scalar, Problem 1)
+ *   omega = 1/(a^2 ell^2) sum_ij c_ij k_ij (x_i x z~_j)      (eq. 3_gradient)
+ *   v     = 1/(b^2 ell^2) sum_ij c_ij k_ij (z~_j - x_i)      (eq. 3_gradient,
+ *           sign as obtained by differentiating the kernel; the printed
+ *           x_i - z~_j has the opposite sign, see the reading list)
+ *   step:  h <- h exp(t (omega^, v)), i.e. R <- R dR, t <- R dT + t
+ *          (eq. newstep), dR, dT from the closed-form SE(3) exponential
+ *          (eq. step), with the step length t = eta ell^2 / F (project rule;
+ *          the paper's quartic line search is a separate later stage).
+ *
+ * parity pins: see the oracle tests (finite differences along the six
+ * generators, rigid-motion invariance, zero gradient at identical clouds,
+ * two-point closed forms, matrix-exponential library routine, recovery).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOOVERLAP (-4)
+
+typedef struct {
+    int n, m, fd;
+    const float *x, *lx, *z, *lz;
+    double sigma, sf, ell, kappa, a2, b2;
+    double Rt[9], tt[3]; /* z~ = Rt z + tt  (Rt = R_h^T, tt = -R_h^T t_h) */
+    int j0, j1;
+    /* per-target outputs (optional) */
+    const int *sel;
+    double *per_target; /* [nsel][7] */
+    /* results */
+    double sum[7], abs_sum[7];
+    long long within, examined;
+} job_t;
+
+static void pose_to_inverse_action(const double h[16], double Rt[9], double tt[3]) {
+    /* h = [R t; 0 1]; h^-1 z = R^T z - R^T t */
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) Rt[3 * r + c] = h[4 * c + r];
+    for (int r = 0; r < 3; r++) {
+        double s = 0.0;
+        for (int c = 0; c < 3; c++) s += Rt[3 * r + c] * h[4 * c + 3];
+        tt[r] = -s;
+    }
+}
+
+/* Terms of the double sum for one target point j, over all sources i. */
+static void target_terms(const job_t* J, int j, double s7[7], double a7[7], long long* within) {
+    const double zx = J->z[3 * j], zy = J->z[3 * j + 1], zz = J->z[3 * j + 2];
+    double zt[3];
+    for (int r = 0; r < 3; r++)
+        zt[r] = J->Rt[3 * r] * zx + J->Rt[3 * r + 1] * zy + J->Rt[3 * r + 2] * zz + J->tt[r];
+    const double inv2l2 = 1.0 / (2.0 * J->ell * J->ell);
+    const double rc2 = (J->kappa > 0.0) ? (J->kappa * J->ell) * (J->kappa * J->ell) : INFINITY;
+    const double s2 = J->sigma * J->sigma;
+    const double cw = 1.0 / (J->a2 * J->ell * J->ell);
+    const double cv = 1.0 / (J->b2 * J->ell * J->ell);
+    for (int q = 0; q < 7; q++) { s7[q] = 0.0; a7[q] = 0.0; }
+    long long cnt = 0;
+    for (int i = 0; i < J->n; i++) {
+        const double x0 = J->x[3 * i], x1 = J->x[3 * i + 1], x2 = J->x[3 * i + 2];
+        const double d0 = zt[0] - x0, d1 = zt[1] - x1, d2 = zt[2] - x2;
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        if (!(r2 <= rc2)) continue;
+        cnt++;
+        double lm = 0.0;
+        for (int f = 0; f < J->fd; f++) lm += (double)J->lx[J->fd * i + f] * (double)J->lz[J->fd * j + f];
+        const double cij = J->sf * lm;
+        const double kij = s2 * exp(-r2 * inv2l2);
+        const double w = cij * kij;
+        /* x_i cross z~_j */
+        const double c0 = x1 * zt[2] - x2 * zt[1];
+        const double c1 = x2 * zt[0] - x0 * zt[2];
+        const double c2 = x0 * zt[1] - x1 * zt[0];
+        const double t[7] = {w, cw * w * c0, cw * w * c1, cw * w * c2, cv * w * d0, cv * w * d1, cv * w * d2};
+        for (int q = 0; q < 7; q++) { s7[q] += t[q]; a7[q] += fabs(t[q]); }
+    }
+    *within = cnt;
+}
+
+static void* run_job(void* arg) {
+    job_t* J = (job_t*)arg;
+    for (int q = 0; q < 7; q++) { J->sum[q] = 0.0; J->abs_sum[q] = 0.0; }
+    J->within = 0; J->examined = 0;
+    for (int jj = J->j0; jj < J->j1; jj++) {
+        const int j = J->sel ? J->sel[jj] : jj;
+        double s7[7], a7[7];
+        long long w;
+        target_terms(J, j, s7, a7, &w);
+        for (int q = 0; q < 7; q++) { J->sum[q] += s7[q]; J->abs_sum[q] += a7[q]; }
+        J->within += w;
+        J->examined += J->n;
+        if (J->per_target)
+            for (int q = 0; q < 7; q++) J->per_target[7 * jj + q] = s7[q];
+    }
+    return NULL;
+}
+
+static int check_cloud(int n, int fd, const float* x, const float* l) {
+    if (n <= 0 || fd < 1 || fd > 8 || !x || !l) return 0;
+    for (long k = 0; k < 3L * n; k++) if (!isfinite(x[k])) return 0;
+    for (long k = 0; k < (long)fd * n; k++) if (!isfinite(l[k])) return 0;
+    return 1;
+}
+
+/* Mean squared norm of the source points (the default a^2), FP64. */
+double cvo_oracle_mean_sqnorm(int n, const float* x) {
+    double s = 0.0;
+    for (int i = 0; i < n; i++) {
+        const double a = x[3 * i], b = x[3 * i + 1], c = x[3 * i + 2];
+        s += a * a + b * b + c * c;
+    }
+    return s / (double)n;
+}
+
+/*
+ * Objective and gradient at the paper's pose h (row-major 4x4).
+ *   out[7]    = F, omega[3], v[3]
+ *   absout[7] = the same sums with every term replaced by its absolute value
+ *   counts[2] = pairs inside the cutoff, pairs examined
+ * If sel != NULL only targets sel[0..nsel) are summed and per_target[nsel][7]
+ * (optional) receives each target's own terms.  nthreads >= 1 splits the
+ * targets into contiguous blocks whose partials are added in block order.
+ */
+int cvo_oracle_eval_h(int n, const float* x, const float* lx, int m, const float* z, const float* lz,
+                      int fd, double sigma, double feat_scale, double ell, double kappa, double a2,
+                      double b2, const double h[16], int nsel, const int* sel, int nthreads,
+                      double out[7], double absout[7], long long counts[2], double* per_target) {
+    if (!check_cloud(n, fd, x, lx) || !check_cloud(m, fd, z, lz)) return OR_EINVAL;
+    if (!(ell > 0.0) || !(a2 > 0.0) || !(b2 > 0.0) || kappa < 0.0) return OR_EINVAL;
+    const int nt_total = sel ? nsel : m;
+    if (sel)
+        for (int k = 0; k < nsel; k++) if (sel[k] < 0 || sel[k] >= m) return OR_EINVAL;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > nt_total) nthreads = nt_total > 0 ? nt_total : 1;
+    job_t* jobs = (job_t*)calloc((size_t)nthreads, sizeof(job_t));
+    pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!jobs || !th) { free(jobs); free(th); return OR_EINVAL; }
+    for (int k = 0; k < nthreads; k++) {
+        job_t* J = &jobs[k];
+        J->n = n; J->m = m; J->fd = fd; J->x = x; J->lx = lx; J->z = z; J->lz = lz;
+        J->sigma = sigma; J->sf = feat_scale; J->ell = ell; J->kappa = kappa; J->a2 = a2; J->b2 = b2;
+        pose_to_inverse_action(h, J->Rt, J->tt);
+        J->j0 = (int)((long long)nt_total * k / nthreads);
+        J->j1 = (int)((long long)nt_total * (k + 1) / nthreads);
+        J->sel = sel; J->per_target = per_target;
+    }
+    for (int k = 1; k < nthreads; k++) pthread_create(&th[k], NULL, run_job, &jobs[k]);
+    run_job(&jobs[0]);
+    for (int k = 1; k < nthreads; k++) pthread_join(th[k], NULL);
+    for (int q = 0; q < 7; q++) { out[q] = 0.0; absout[q] = 0.0; }
+    counts[0] = counts[1] = 0;
+    for (int k = 0; k < nthreads; k++) {
+        for (int q = 0; q < 7; q++) { out[q] += jobs[k].sum[q]; absout[q] += jobs[k].abs_sum[q]; }
+        counts[0] += jobs[k].within; counts[1] += jobs[k].examined;
+    }
+    free(jobs); free(th);
+    return OR_OK;
+}
+
+/* Closed-form SE(3) exponential (eq. step) of the twist t*(w^, u), t = 1:
+ *   dR = I + (sin th/th) w^ + ((1-cos th)/th^2) w^2
+ *   dT = [I + ((1-cos th)/th^2) w^ + ((th - sin th)/th^3) w^2] u,  th = |w|.
+ * (1 - cos th) is evaluated as 2 sin^2(th/2), the same quantity without the
+ * cancellation of 1 - cos th near 0 (which would leave an absolute error of
+ * about eps*|u|/th in dT).  For th < 1e-3 the three coefficients use their
+ * Taylor series through th^6 (truncation below 1e-29). */
+void cvo_oracle_expmap(const double w[3], const double u[3], double dR[9], double dT[3]) {
+    const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    const double th = sqrt(th2);
+    double A, B, C;
+    if (th < 1e-3) {
+        A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0 - th2 * th2 * th2 / 5040.0;
+        B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0 - th2 * th2 * th2 / 40320.0;
+        C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0 - th2 * th2 * th2 / 362880.0;
+    } else {
+        const double sh = sin(0.5 * th);
+        A = sin(th) / th;
+        B = 2.0 * sh * sh / th2;
+        C = (th - sin(th)) / (th2 * th);
+    }
+    const double W[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+    double W2[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            double s = 0.0;
+            for (int k = 0; k < 3; k++) s += W[3 * r + k] * W[3 * k + c];
+            W2[3 * r + c] = s;
+        }
+    double V[9];
+    for (int k = 0; k < 9; k++) {
+        const double I = (k % 4 == 0) ? 1.0 : 0.0;
+        dR[k] = I + A * W[k] + B * W2[k];
+        V[k] = I + B * W[k] + C * W2[k];
+    }
+    for (int r = 0; r < 3; r++) dT[r] = V[3 * r] * u[0] + V[3 * r + 1] * u[1] + V[3 * r + 2] * u[2];
+}
+
+/* h <- h exp(t xi): R <- R dR, t_h <- R dT + t_h (eq. newstep). */
+static void newstep(double h[16], const double w[3], const double u[3], double t) {
+    double tw[3] = {t * w[0], t * w[1], t * w[2]}, tu[3] = {t * u[0], t * u[1], t * u[2]};
+    double dR[9], dT[3];
+    cvo_oracle_expmap(tw, tu, dR, dT);
+    double R[9], tr[3];
+    for (int r = 0; r < 3; r++) {
+        for (int c = 0; c < 3; c++) R[3 * r + c] = h[4 * r + c];
+        tr[r] = h[4 * r + 3];
+    }
+    for (int r = 0; r < 3; r++) {
+        for (int c = 0; c < 3; c++) {
+            double s = 0.0;
+            for (int k = 0; k < 3; k++) s += R[3 * r + k] * dR[3 * k + c];
+            h[4 * r + c] = s;
+        }
+        h[4 * r + 3] = R[3 * r] * dT[0] + R[3 * r + 1] * dT[1] + R[3 * r + 2] * dT[2] + tr[r];
+    }
+    h[12] = h[13] = h[14] = 0.0;
+    h[15] = 1.0;
+}
+
+static void rigid_inverse(const double A[16], double B[16]) {
+    for (int r = 0; r < 3; r++) {
+        for (int c = 0; c < 3; c++) B[4 * r + c] = A[4 * c + r];
+        B[4 * r + 3] = -(A[r] * A[3] + A[4 + r] * A[7] + A[8 + r] * A[11]);
+    }
+    B[12] = B[13] = B[14] = 0.0;
+    B[15] = 1.0;
+}
+
+/* Same objective, evaluated at the library's convention T = h^-1. */
+int cvo_oracle_eval(int n, const float* x, const float* lx, int m, const float* z, const float* lz,
+                    int fd, double sigma, double feat_scale, double ell, double kappa, double a2,
+                    double b2, const double T[16], int nsel, const int* sel, int nthreads,
+                    double out[7], double absout[7], long long counts[2], double* per_target) {
+    double h[16];
+    rigid_inverse(T, h);
+    return cvo_oracle_eval_h(n, x, lx, m, z, lz, fd, sigma, feat_scale, ell, kappa, a2, b2, h, nsel,
+                             sel, nthreads, out, absout, counts, per_target);
+}
+
+/*
+ * The registration iteration (Section VI): at every iteration k,
+ *   ell   = schedule length-scale of the stage containing k
+ *   (F, omega, v) at the current h
+ *   F <= 1e-300 -> no overlap (error)
+ *   tau = eta ell^2 / F,  h <- h exp(tau (omega^, v))
+ *   stop when the last stage is reached and |tau (omega, v)|_2 < tol.
+ * Stage s spans stage_iters[s] iterations; the last stage runs to max_iters.
+ * T0 and T_out use the library convention T = h^-1.
+ * trace (optional) receives per iteration 26 doubles:
+ *   F, omega[3], v[3], tau, ell, within-pairs, then T (16, row-major) after the step.
+ */
+int cvo_oracle_register(int n, const float* x, const float* lx, int m, const float* z, const float* lz,
+                        int fd, double sigma, double feat_scale, double a2, double b2, double eta,
+                        double kappa, int n_stages, const int* stage_iters, const double* stage_ell,
+                        int max_iters, double tol, const double T0[16], int nthreads, double T_out[16],
+                        double* trace, int* iters_out, int* converged_out) {
+    if (n_stages < 1 || !stage_ell || max_iters < 1 || !(eta > 0.0)) return OR_EINVAL;
+    for (int s = 0; s < n_stages; s++) {
+        if (!(stage_ell[s] > 0.0)) return OR_EINVAL;
+        if (s < n_stages - 1 && (!stage_iters || stage_iters[s] < 1)) return OR_EINVAL;
+    }
+    if (!check_cloud(n, fd, x, lx) || !check_cloud(m, fd, z, lz)) return OR_EINVAL;
+    if (!(a2 > 0.0)) a2 = cvo_oracle_mean_sqnorm(n, x);
+    double h[16];
+    rigid_inverse(T0, h);
+    int stage = 0, stage_start = 0, k = 0, conv = 0, rc = OR_OK;
+    for (k = 0; k < max_iters; k++) {
+        while (stage < n_stages - 1 && k - stage_start >= stage_iters[stage]) {
+            stage_start += stage_iters[stage];
+            stage++;
+        }
+        const double ell = stage_ell[stage];
+        double g[7], ga[7];
+        long long cnt[2];
+        rc = cvo_oracle_eval_h(n, x, lx, m, z, lz, fd, sigma, feat_scale, ell, kappa, a2, b2, h, 0,
+                               NULL, nthreads, g, ga, cnt, NULL);
+        if (rc != OR_OK) break;
+        if (!(g[0] > 1e-300)) { rc = OR_ENOOVERLAP; break; }
+        const double tau = eta * ell * ell / g[0];
+        newstep(h, g + 1, g + 4, tau);
+        double sq = 0.0;
+        for (int q = 1; q < 7; q++) sq += (tau * g[q]) * (tau * g[q]);
+        if (trace) {
+            double* tr = trace + 26 * (size_t)k;
+            for (int q = 0; q < 7; q++) tr[q] = g[q];
+            tr[7] = tau; tr[8] = ell; tr[9] = (double)cnt[0];
+            rigid_inverse(h, tr + 10);
+        }
+        if (stage == n_stages - 1 && sqrt(sq) < tol) { conv = 1; k++; break; }
+    }
+    rigid_inverse(h, T_out);
+    if (iters_out) *iters_out = k;
+    if (converged_out) *converged_out = conv;
+    return rc;
+}

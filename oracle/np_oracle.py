@@ -1,0 +1,91 @@
+"""NumPy FP64 oracle for tiny inputs (TEST INFRASTRUCTURE ONLY).
+
+A second, independent transcription of the paper's definitions, kept apart
+from cvo_oracle.c so that the two can check each other:
+  * the objective F(h) = sum_ij c_ij k(x_i, h^-1 z_j)  (eq. scalar, Sec. III);
+  * the gradient in the general-n coordinates of eq. flow (Sec. IV-C),
+    omega^{pq} = 1/(a^2 l^2) sum c k (x^p z~^q - x^q z~^p),
+    v^m        = 1/(b^2 l^2) sum c k (z~^m - x^m)   (sign from the kernel's
+    derivative; the printed x - z~ is the opposite sign),
+    read back as the 3-vector omega = (w^{23}, w^{31}, w^{12}) with
+    w^ = [[0, -w3, w2], [w3, 0, -w1], [-w2, w1, 0]];
+  * the group exponential as the matrix exponential of the 4x4 twist
+    (Sec. VI-A: exp is "merely the matrix exponential"), via a scaled and
+    squared Taylor series rather than the closed form.
+Everything is O(N M) dense NumPy: keep N*M below ~1e7.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def hat(w):
+    return np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
+
+
+def twist_matrix(w, u):
+    X = np.zeros((4, 4))
+    X[:3, :3] = hat(w)
+    X[:3, 3] = u
+    return X
+
+
+def expm_series(A, terms=30):
+    """exp(A) by scaling and squaring of a truncated Taylor series (FP64)."""
+    nrm = np.abs(A).sum(axis=1).max()
+    s = 0
+    while nrm > 0.5:
+        nrm /= 2.0
+        s += 1
+    B = A / (2.0 ** s)
+    E = np.eye(A.shape[0])
+    term = np.eye(A.shape[0])
+    for k in range(1, terms):
+        term = term @ B / k
+        E = E + term
+    for _ in range(s):
+        E = E @ E
+    return E
+
+
+def terms(x, lx, z, lz, T, *, sigma=0.1, feat_scale=0.2, ell=0.1, kappa=0.0, a2=None, b2=1.0):
+    """Per-pair weights w_ij = c_ij k_ij, displacement z~_j - x_i and z~.
+
+    T acts on target points (T = h^-1).
+    """
+    x = np.asarray(x, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    lx = np.asarray(lx, dtype=np.float64)
+    lz = np.asarray(lz, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    zt = z @ T[:3, :3].T + T[:3, 3]
+    d = zt[None, :, :] - x[:, None, :]            # [N, M, 3]
+    r2 = (d * d).sum(axis=2)
+    c = feat_scale * (lx @ lz.T)
+    k = sigma ** 2 * np.exp(-r2 / (2.0 * ell * ell))
+    if kappa > 0:
+        k = np.where(r2 <= (kappa * ell) ** 2, k, 0.0)
+    return c * k, d, zt, r2
+
+
+def evaluate(x, lx, z, lz, T, *, sigma=0.1, feat_scale=0.2, ell=0.1, kappa=0.0, a2=None, b2=1.0):
+    """Returns (F, omega[3], v[3])."""
+    x = np.asarray(x, dtype=np.float64)
+    if a2 is None:
+        a2 = float((x * x).sum(axis=1).mean())
+    w, d, zt, _ = terms(x, lx, z, lz, T, sigma=sigma, feat_scale=feat_scale, ell=ell,
+                        kappa=kappa)
+    F = w.sum()
+    W = np.zeros((3, 3))
+    for p in range(3):
+        for q in range(3):
+            W[p, q] = (w * (x[:, None, p] * zt[None, :, q] - x[:, None, q] * zt[None, :, p])).sum()
+    W /= a2 * ell * ell
+    omega = np.array([W[1, 2], W[2, 0], W[0, 1]])
+    v = (w[:, :, None] * d).sum(axis=(0, 1)) / (b2 * ell * ell)
+    return F, omega, v
+
+
+def objective(x, lx, z, lz, T, **kw):
+    w, _, _, _ = terms(x, lx, z, lz, T, **kw)
+    return w.sum()
