@@ -1,0 +1,176 @@
+/*
+ * cvo.h - C ABI of the MI355X continuous sensor registration library.
+ *
+ * Method: Ghaffari, Clark, Bloch, Eustice, Grizzle, "Continuous Direct Sparse
+ * Visual Odometry from RGB-D Images".  Two labelled point clouds X (source)
+ * and Z (target) become functions in a reproducing kernel Hilbert space; the
+ * registration maximises their inner product (Section III, Problem 1)
+ *
+ *     F = sum_ij c_ij k_ij,   c_ij = s_f <l_i, m_j>,
+ *     k_ij = sigma^2 exp(-|x_i - z~_j|^2 / (2 ell^2)),   z~_j = T z_j,
+ *
+ * (eq. scalar; squared-exponential kernel of Section IV; label inner product
+ * of the Section VII-B remark, scaled by s_f) by the gradient flow on SE(3):
+ *
+ *     omega = 1/(a^2 ell^2) sum_ij c_ij k_ij (x_i x z~_j)
+ *     v     = 1/(b^2 ell^2) sum_ij c_ij k_ij (z~_j - x_i)          (eq. 3_gradient)
+ *
+ * integrated with the closed-form exponential map (eq. step, eq. newstep).
+ *
+ * Conventions
+ *   - T is a row-major 4x4 FP64 rigid transform that acts on TARGET points
+ *     (z~ = R z + t).  The paper's pose h is T^-1; the update h <- h exp(tau xi)
+ *     is applied here as T <- Exp(-tau (omega, v)) T.
+ *   - v carries the sign obtained by differentiating the kernel (z~ - x); the
+ *     paper prints the opposite sign in eq. 3_gradient while its own
+ *     differential and Taylor coefficients imply this one.
+ *   - Step length (project rule, not the paper's quartic line search):
+ *     tau = eta * ell^2 / F.
+ *   - With cutoff_mult = kappa > 0 a pair contributes only if
+ *     |x_i - z~_j| <= kappa * ell (the paper sparsifies small kernel values,
+ *     Section VII-B; here in distance form); kappa = 0 sums all pairs.
+ *
+ * Ownership and threading
+ *   - Host inputs (on_device = 0) are copied before the call returns (or
+ *     before cvo_submit returns).
+ *   - Device inputs (on_device = 1) must be device pointers on the context's
+ *     device.  They are read on the context's stream and borrowed until the
+ *     call returns (cvo_eval, cvo_register) or until cvo_poll reports a
+ *     terminal status for the ticket (cvo_submit).
+ *   - All outputs go to caller buffers; the context owns all device state.
+ *   - cvo_eval / cvo_register serialise on the context.  cvo_submit and
+ *     cvo_poll are thread-safe.
+ *   - No C++ exception crosses this boundary.
+ *
+ * Return codes: 0 success, CVO_PENDING (>0) from cvo_poll, negative on error.
+ */
+#ifndef CVO_H_
+#define CVO_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cvo_ctx cvo_ctx;
+
+enum {
+  CVO_OK = 0,
+  CVO_PENDING = 1,       /* cvo_poll: the request has not finished */
+  CVO_EINVAL = -1,       /* bad argument: n <= 0, feat_dim outside [1,8], non-finite input, bad schedule */
+  CVO_ENOMEM = -2,       /* one request needs more device memory than the context budget */
+  CVO_EBUSY = -3,        /* the submission queue is full */
+  CVO_ENOOVERLAP = -4,   /* F <= 1e-300 at some iteration: no pair within reach */
+  CVO_EDEVICE = -5,      /* HIP runtime error (see cvo_strerror / cvo_last_error) */
+  CVO_ENOTFOUND = -6     /* unknown ticket */
+};
+
+enum { CVO_FP32_KAHAN = 0, CVO_FP64 = 1 };
+
+/* One labelled point cloud (Section III-A: points x_i with labels l(x_i) in R^feat_dim). */
+typedef struct {
+  int32_t n;           /* number of points, >= 1 */
+  int32_t feat_dim;    /* label channels, 1..8 (both clouds must match) */
+  const float* xyz;    /* [n][3] row-major, finite */
+  const float* feat;   /* [n][feat_dim] row-major, finite */
+  int32_t on_device;   /* 0: host pointers; 1: device pointers on the context's device */
+} cvo_cloud;
+
+/* Registration parameters (Section IV kernel; Table 1 lists the paper's values). */
+typedef struct {
+  double sigma;             /* kernel signal parameter; the prefactor is sigma^2 (> 0) */
+  double feat_scale;        /* s_f in c_ij = s_f <l_i, m_j> (> 0) */
+  double a2;                /* rotational metric weight a^2; <= 0 selects mean |x_i|^2 of the source */
+  double b2;                /* translational metric weight b^2 (> 0) */
+  double eta;               /* step rule tau = eta ell^2 / F (> 0) */
+  double cutoff_mult;       /* kappa >= 0; 0 = every pair (brute force) */
+  int32_t n_stages;         /* length-scale stages, 1..8 */
+  const int32_t* stage_iters; /* [n_stages-1] iterations spent in each stage but the last (>= 1) */
+  const double* stage_ell;  /* [n_stages] length-scale of each stage (> 0) */
+  int32_t max_iters;        /* iteration cap, >= 1 */
+  double tol;               /* stop once the last stage is reached and |tau (omega, v)|_2 < tol */
+  int32_t precision;        /* CVO_FP32_KAHAN (FP32 pair terms, Kahan FP32 partials, FP64
+                               reduction and step) or CVO_FP64 (every pair term in FP64) */
+  int32_t trace;            /* 1: keep the per-iteration trace (cvo_trace) */
+} cvo_params;
+
+typedef struct {
+  int32_t status;           /* 0 or a negative code */
+  int32_t iters;            /* iterations performed */
+  int32_t converged;        /* 1 if the tolerance test stopped the flow */
+  int32_t reserved;
+  double F, omega[3], v[3]; /* at the last evaluated pose */
+  double gpu_ms;            /* device time of the request (event-timed, register path) */
+  double wall_ms;           /* host time from call (or submission) to completion */
+  uint64_t pairs_within;    /* pairs inside the cutoff, summed over iterations */
+  uint64_t pairs_examined;  /* candidate pairs tested, summed over iterations */
+} cvo_result;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device
+ * memory of concurrently admitted requests (0: 80% of free memory); max_slots
+ * bounds concurrently active requests of the batched path (1..4096). */
+int cvo_create(int device, uint64_t hbm_budget_bytes, int max_slots, cvo_ctx** out);
+
+/* Wait for outstanding requests, free every device buffer, destroy the context. */
+int cvo_destroy(cvo_ctx* ctx);
+
+/* Run subsequent eval/register work on this hipStream_t (e.g. torch's current
+ * stream).  NULL selects the context's own stream. */
+int cvo_set_stream(cvo_ctx* ctx, void* hip_stream);
+
+/* One evaluation of F, omega, v at pose T (Section VI-C, eq. 3_gradient) with
+ * ell = params->stage_ell[0]; no step is taken. */
+int cvo_eval(cvo_ctx* ctx, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* params,
+             const double T[16], double* F, double omega[3], double v[3]);
+
+/* Per-target terms of the same double sum: for each selected original target
+ * index sel[k] (0 <= sel[k] < tgt->n), out[7k..7k+6] = (F_j, omega_j, v_j),
+ * the sums over sources i of the terms of eq. scalar and eq. 3_gradient.
+ * nsel = 0 with sel = NULL returns all targets in original order. */
+int cvo_eval_targets(cvo_ctx* ctx, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* params,
+                     const double T[16], int32_t nsel, const int32_t* sel, double* out);
+
+/* Full registration: from T0, iterate the gradient flow (Section VI) through
+ * the length-scale stages until max_iters or the tolerance; T_out receives the
+ * final pose, res the summary.  Synchronous. */
+int cvo_register(cvo_ctx* ctx, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* params,
+                 const double T0[16], double T_out[16], cvo_result* res);
+
+/* Asynchronous registration through the continuous-batching scheduler:
+ * requests are admitted while device memory and slots allow and run together,
+ * one launch per iteration for all active requests.  Returns a ticket. */
+int cvo_submit(cvo_ctx* ctx, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* params,
+               const double T0[16], uint64_t* ticket);
+
+/* Wait up to wait_us microseconds (0: do not wait, <0: wait forever) for the
+ * ticket.  Returns CVO_PENDING if unfinished; otherwise the request's status,
+ * with T_out and res filled, and the ticket is released. */
+int cvo_poll(cvo_ctx* ctx, uint64_t ticket, int32_t wait_us, double T_out[16], cvo_result* res);
+
+/* Copy the per-iteration trace of the last cvo_register call (ticket 0) into
+ * buf[iters][26]: F, omega[3], v[3], tau, ell, pairs within the cutoff, then
+ * the pose T (row-major 4x4) after that iteration's step.  Returns the number
+ * of rows written (<= cap) or a negative code. */
+int cvo_trace(cvo_ctx* ctx, uint64_t ticket, double* buf, int32_t cap);
+
+/* Event timing of the iteration kernel: when enabled, every iteration launch
+ * of cvo_register is bracketed by HIP events on the launch stream. */
+int cvo_set_profiling(cvo_ctx* ctx, int32_t enable);
+/* Totals since the last reset: iteration launches timed, their summed device
+ * milliseconds, and the pairs within the cutoff they evaluated. */
+int cvo_kernel_stats(cvo_ctx* ctx, int32_t reset, int64_t* launches, double* total_ms, uint64_t* pairs);
+
+/* Work split of the iteration kernel: slices of candidate sources per target
+ * cluster (0: automatic).  Results are deterministic for a fixed split. */
+int cvo_set_split(cvo_ctx* ctx, int32_t brute_split, int32_t cutoff_split);
+
+/* Static text for a return code; cvo_last_error gives the last HIP message. */
+const char* cvo_strerror(int code);
+const char* cvo_last_error(cvo_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CVO_H_ */

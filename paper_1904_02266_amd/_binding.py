@@ -1,0 +1,322 @@
+"""ctypes binding of the C ABI in include/cvo.h (argument marshalling only).
+
+Every step of the registration runs in the HIP library; this module only
+turns NumPy arrays / torch tensors into cvo_cloud structs and back.  If the
+built library is missing, loading fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libcvo.so")
+
+CVO_OK = 0
+CVO_PENDING = 1
+CVO_EINVAL = -1
+CVO_ENOMEM = -2
+CVO_EBUSY = -3
+CVO_ENOOVERLAP = -4
+CVO_EDEVICE = -5
+CVO_ENOTFOUND = -6
+CVO_FP32_KAHAN = 0
+CVO_FP64 = 1
+TRACE_COLS = 26
+
+
+class cvo_cloud(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("feat_dim", ctypes.c_int32),
+                ("xyz", ctypes.c_void_p), ("feat", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+class cvo_params(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("feat_scale", ctypes.c_double),
+                ("a2", ctypes.c_double), ("b2", ctypes.c_double), ("eta", ctypes.c_double),
+                ("cutoff_mult", ctypes.c_double), ("n_stages", ctypes.c_int32),
+                ("stage_iters", ctypes.POINTER(ctypes.c_int32)),
+                ("stage_ell", ctypes.POINTER(ctypes.c_double)),
+                ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("trace", ctypes.c_int32)]
+
+
+class cvo_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("F", ctypes.c_double), ("omega", ctypes.c_double * 3), ("v", ctypes.c_double * 3),
+                ("gpu_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
+                ("pairs_within", ctypes.c_uint64), ("pairs_examined", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return dict(status=self.status, iters=self.iters, converged=bool(self.converged), F=self.F,
+                    omega=np.array(self.omega[:]), v=np.array(self.v[:]), gpu_ms=self.gpu_ms,
+                    wall_ms=self.wall_ms, pairs_within=int(self.pairs_within),
+                    pairs_examined=int(self.pairs_examined))
+
+
+_lib = None
+
+
+def load():
+    """Load the built HIP library; raise if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run __graft_entry__.build() or python -m paper_1904_02266_amd.build)")
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7.  Loading
+    # torch first makes the library bind to that already-loaded runtime (same
+    # soname), so device pointers and streams are shared with torch.
+    try:
+        import torch  # noqa: F401
+    except ImportError:  # pragma: no cover - the library also works without torch
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, i32, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+    L.cvo_create.argtypes = [ctypes.c_int, u64, ctypes.c_int, P(vp)]
+    L.cvo_destroy.argtypes = [vp]
+    L.cvo_set_stream.argtypes = [vp, vp]
+    L.cvo_eval.argtypes = [vp, P(cvo_cloud), P(cvo_cloud), P(cvo_params), P(dbl), P(dbl), P(dbl), P(dbl)]
+    L.cvo_eval_targets.argtypes = [vp, P(cvo_cloud), P(cvo_cloud), P(cvo_params), P(dbl), i32,
+                                   P(i32), P(dbl)]
+    L.cvo_register.argtypes = [vp, P(cvo_cloud), P(cvo_cloud), P(cvo_params), P(dbl), P(dbl),
+                               P(cvo_result)]
+    L.cvo_submit.argtypes = [vp, P(cvo_cloud), P(cvo_cloud), P(cvo_params), P(dbl), P(u64)]
+    L.cvo_poll.argtypes = [vp, u64, i32, P(dbl), P(cvo_result)]
+    L.cvo_trace.argtypes = [vp, u64, P(dbl), i32]
+    L.cvo_set_profiling.argtypes = [vp, i32]
+    L.cvo_kernel_stats.argtypes = [vp, i32, P(ctypes.c_int64), P(dbl), P(u64)]
+    L.cvo_set_split.argtypes = [vp, i32, i32]
+    L.cvo_strerror.argtypes = [ctypes.c_int]
+    L.cvo_strerror.restype = ctypes.c_char_p
+    L.cvo_last_error.argtypes = [vp]
+    L.cvo_last_error.restype = ctypes.c_char_p
+    for name in ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
+                 "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
+                 "cvo_kernel_stats", "cvo_set_split"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+EXPORTED = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
+            "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
+            "cvo_kernel_stats", "cvo_set_split", "cvo_strerror", "cvo_last_error")
+
+
+class CvoError(RuntimeError):
+    def __init__(self, code, msg=""):
+        L = load()
+        text = L.cvo_strerror(code).decode()
+        super().__init__(f"cvo error {code} ({text}) {msg}".strip())
+        self.code = code
+
+
+@dataclass
+class Params:
+    sigma: float = 0.1
+    feat_scale: float = 0.2
+    a2: float = -1.0
+    b2: float = 1.0
+    eta: float = 1.0
+    cutoff_mult: float = 0.0
+    stage_iters: Sequence[int] = field(default_factory=tuple)
+    stage_ell: Sequence[float] = field(default_factory=lambda: (0.1,))
+    max_iters: int = 50
+    tol: float = 0.0
+    precision: str = "fp32"
+    trace: bool = False
+
+    def to_c(self):
+        ns = len(self.stage_ell)
+        si = (ctypes.c_int32 * max(1, ns))(*([int(v) for v in self.stage_iters] + [0] * (ns - len(self.stage_iters))))
+        se = (ctypes.c_double * max(1, ns))(*[float(v) for v in self.stage_ell])
+        p = cvo_params(self.sigma, self.feat_scale, self.a2, self.b2, self.eta, self.cutoff_mult, ns,
+                       ctypes.cast(si, ctypes.POINTER(ctypes.c_int32)),
+                       ctypes.cast(se, ctypes.POINTER(ctypes.c_double)), self.max_iters, self.tol,
+                       CVO_FP64 if self.precision == "fp64" else CVO_FP32_KAHAN, 1 if self.trace else 0)
+        return p, (si, se)
+
+
+def params_planes(**kw):
+    """Three-plane brute-force workload: ell = 0.1 fixed, all pairs, 50 steps."""
+    base = dict(stage_ell=(0.1,), max_iters=50, cutoff_mult=0.0)
+    base.update(kw)
+    return Params(**base)
+
+
+def params_rgbd(**kw):
+    """RGB-D frame workload: cutoff 3 ell, ell annealed 0.2 -> 0.05 m geometrically
+    over 4 stages of 25 iterations (100 iterations)."""
+    ells = tuple(0.2 * (0.25 ** (s / 3.0)) for s in range(4))
+    base = dict(stage_ell=ells, stage_iters=(25, 25, 25), max_iters=100, cutoff_mult=3.0)
+    base.update(kw)
+    return Params(**base)
+
+
+class _Cloud:
+    """Keeps the buffers of one cloud alive while the call runs."""
+
+    def __init__(self, xyz, feat):
+        self.keep = []
+        try:
+            import torch
+            is_t = isinstance(xyz, torch.Tensor)
+        except ImportError:  # pragma: no cover
+            is_t = False
+        if is_t:
+            import torch
+            if xyz.is_cuda != feat.is_cuda:
+                raise ValueError("xyz and feat must live on the same device")
+            xyz = xyz.to(torch.float32).contiguous()
+            feat = feat.to(torch.float32).contiguous()
+            if xyz.dim() != 2 or xyz.shape[1] != 3 or feat.dim() != 2 or feat.shape[0] != xyz.shape[0]:
+                raise ValueError("xyz must be [n,3] and feat [n,F]")
+            self.keep = [xyz, feat]
+            self.on_device = 1 if xyz.is_cuda else 0
+            self.c = cvo_cloud(xyz.shape[0], feat.shape[1], xyz.data_ptr(), feat.data_ptr(), self.on_device)
+        else:
+            xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+            feat = np.ascontiguousarray(feat, dtype=np.float32)
+            if xyz.ndim != 2 or xyz.shape[1] != 3 or feat.ndim != 2 or feat.shape[0] != xyz.shape[0]:
+                raise ValueError("xyz must be [n,3] and feat [n,F]")
+            self.keep = [xyz, feat]
+            self.on_device = 0
+            self.c = cvo_cloud(xyz.shape[0], feat.shape[1], xyz.ctypes.data, feat.ctypes.data, 0)
+
+
+def _pose(T):
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.float64).reshape(16))
+    return T, T.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Context:
+    """One library context on one HIP device."""
+
+    def __init__(self, device=0, hbm_budget=0, max_slots=256):
+        self.L = load()
+        h = ctypes.c_void_p()
+        rc = self.L.cvo_create(device, hbm_budget, max_slots, ctypes.byref(h))
+        if rc != 0:
+            raise CvoError(rc, "cvo_create")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.cvo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise CvoError(rc, f"{what}: {self.L.cvo_last_error(self.h).decode()}")
+        return rc
+
+    def _sync_stream(self, clouds):
+        if any(c.on_device for c in clouds):
+            import torch
+            self.L.cvo_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+        else:
+            self.L.cvo_set_stream(self.h, None)
+
+    def set_profiling(self, on=True):
+        self._check(self.L.cvo_set_profiling(self.h, 1 if on else 0), "set_profiling")
+
+    def kernel_stats(self, reset=False):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        pairs = ctypes.c_uint64()
+        self._check(self.L.cvo_kernel_stats(self.h, 1 if reset else 0, ctypes.byref(n), ctypes.byref(ms),
+                                            ctypes.byref(pairs)), "kernel_stats")
+        return dict(launches=n.value, ms=ms.value, pairs=pairs.value)
+
+    def set_split(self, brute=0, cutoff=0):
+        self._check(self.L.cvo_set_split(self.h, brute, cutoff), "set_split")
+
+    def eval(self, src_xyz, src_feat, tgt_xyz, tgt_feat, T, params: Params):
+        s, t = _Cloud(src_xyz, src_feat), _Cloud(tgt_xyz, tgt_feat)
+        self._sync_stream([s, t])
+        p, keep = params.to_c()
+        Ta, Tp = _pose(T)
+        F = ctypes.c_double()
+        w = (ctypes.c_double * 3)()
+        v = (ctypes.c_double * 3)()
+        self._check(self.L.cvo_eval(self.h, ctypes.byref(s.c), ctypes.byref(t.c), ctypes.byref(p), Tp,
+                                    ctypes.byref(F), w, v), "cvo_eval")
+        return np.array([F.value, *w[:], *v[:]])
+
+    def eval_targets(self, src_xyz, src_feat, tgt_xyz, tgt_feat, T, params: Params, sel=None):
+        s, t = _Cloud(src_xyz, src_feat), _Cloud(tgt_xyz, tgt_feat)
+        self._sync_stream([s, t])
+        p, keep = params.to_c()
+        Ta, Tp = _pose(T)
+        if sel is None:
+            out = np.zeros((t.c.n, 7))
+            rc = self.L.cvo_eval_targets(self.h, ctypes.byref(s.c), ctypes.byref(t.c), ctypes.byref(p), Tp, 0,
+                                         None, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        else:
+            sel = np.ascontiguousarray(sel, dtype=np.int32)
+            out = np.zeros((sel.size, 7))
+            rc = self.L.cvo_eval_targets(self.h, ctypes.byref(s.c), ctypes.byref(t.c), ctypes.byref(p), Tp,
+                                         sel.size, sel.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        self._check(rc, "cvo_eval_targets")
+        return out
+
+    def register(self, src_xyz, src_feat, tgt_xyz, tgt_feat, params: Params, T0=None, check=True):
+        s, t = _Cloud(src_xyz, src_feat), _Cloud(tgt_xyz, tgt_feat)
+        self._sync_stream([s, t])
+        p, keep = params.to_c()
+        Ta, Tp = _pose(np.eye(4) if T0 is None else T0)
+        Tout = np.zeros(16)
+        res = cvo_result()
+        rc = self.L.cvo_register(self.h, ctypes.byref(s.c), ctypes.byref(t.c), ctypes.byref(p), Tp,
+                                 Tout.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(res))
+        if check:
+            self._check(rc, "cvo_register")
+        out = res.as_dict()
+        out["rc"] = rc
+        out["T"] = Tout.reshape(4, 4)
+        return out
+
+    def trace(self, cap=100000):
+        buf = np.zeros((cap, TRACE_COLS))
+        rows = self._check(self.L.cvo_trace(self.h, 0, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cap),
+                           "cvo_trace")
+        return buf[:rows]
+
+    def submit(self, src_xyz, src_feat, tgt_xyz, tgt_feat, params: Params, T0=None):
+        """Returns (ticket, keepalive); keep `keepalive` until the ticket is polled
+        when passing device tensors (they are borrowed)."""
+        s, t = _Cloud(src_xyz, src_feat), _Cloud(tgt_xyz, tgt_feat)
+        p, keep = params.to_c()
+        Ta, Tp = _pose(np.eye(4) if T0 is None else T0)
+        tk = ctypes.c_uint64()
+        self._check(self.L.cvo_submit(self.h, ctypes.byref(s.c), ctypes.byref(t.c), ctypes.byref(p), Tp,
+                                      ctypes.byref(tk)), "cvo_submit")
+        return tk.value, (s, t)
+
+    def poll(self, ticket, wait_us=-1):
+        Tout = np.zeros(16)
+        res = cvo_result()
+        rc = self.L.cvo_poll(self.h, ticket, wait_us, Tout.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             ctypes.byref(res))
+        if rc == CVO_PENDING:
+            return None
+        out = res.as_dict()
+        out["rc"] = rc
+        out["T"] = Tout.reshape(4, 4)
+        return out

@@ -1,0 +1,923 @@
+// Host side of the C ABI: contexts, per-request device arenas, the ingest
+// sequence, the iteration driver (one fused kernel launch per gradient-flow
+// iteration for every active request) and the continuous-batching scheduler
+// behind cvo_submit / cvo_poll.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/cvo.h"
+#include "cvo_internal.h"
+
+using namespace cvo;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int round_up4(int v) { return (v + 3) / 4 * 4; }
+
+// ---------------------------------------------------------------------------
+// request description (host copy of everything the device needs)
+// ---------------------------------------------------------------------------
+struct Request {
+  uint64_t ticket = 0;
+  int mode = kModeRegister;
+  int n = 0, m = 0, fd = 0, n_stages = 1, max_iters = 1, precision = 0, trace_on = 0;
+  double sigma = 0.1, sf = 0.2, a2 = -1.0, b2 = 1.0, eta = 1.0, kappa = 0.0, tol = 0.0;
+  int stage_iters[kMaxStages] = {0};
+  double stage_ell[kMaxStages] = {0.0};
+  double T0[16];
+  // inputs: device pointers (borrowed or pointing into host_copy after upload)
+  bool on_device = false;
+  const float *sx = nullptr, *sfeat = nullptr, *tx = nullptr, *tfeat = nullptr;
+  std::vector<float> hsx, hsf, htx, htf;  // host copies (submit with host inputs)
+  int split = 1;
+  // device arena
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  ReqStatic st{};
+  ReqState* state = nullptr;
+  double* trace_dev = nullptr;
+  double* per_target_dev = nullptr;
+  // completion
+  int status = CVO_PENDING;
+  cvo_result res{};
+  double T_out[16];
+  std::vector<double> trace;
+  Clock::time_point t_submit;
+};
+
+struct Layout {
+  size_t off_sx, off_sf, off_tx, off_tf;
+  size_t off_xpart, off_zpart, off_xbox, off_zbox, off_T0, off_ell;
+  size_t off_grid, off_ncell, off_skeys, off_tkeys, off_sperm, off_tperm;
+  size_t off_count[kMaxStages + 1], off_cursor[kMaxStages + 1], off_tmp[kMaxStages + 1];
+  size_t off_segs, off_zrec, off_zorig, off_xrec[kMaxStages], off_xrecptr;
+  size_t off_slots, off_state, off_trace, off_pt;
+  size_t total;
+  int kcap, zs, xs, nclus, n_items, nblk_bbox;
+};
+
+constexpr int kBboxBlocks = 256;
+
+int pick_split(const Request& q, int brute_split, int cutoff_split) {
+  const int nclus = (q.m + kWave - 1) / kWave;
+  if (q.mode == kModeEvalTargets) return 1;
+  if (q.kappa > 0.0) {
+    if (cutoff_split > 0) return cutoff_split;
+    int s = (2048 + nclus - 1) / nclus;
+    return std::max(1, std::min(s, 16));
+  }
+  if (brute_split > 0) return brute_split;
+  int s = (4096 + nclus - 1) / nclus;
+  int cap = std::max(1, q.n / 256);
+  return std::max(1, std::min(s, std::min(cap, 256)));
+}
+
+Layout plan(const Request& q) {
+  Layout L{};
+  const int S = q.n_stages;
+  L.kcap = std::min(std::max(1 << 16, 8 * q.n), 1 << 24);
+  L.zs = round_up4(3 + q.fd);
+  L.xs = round_up4(3 + q.fd);
+  L.nclus = (q.m + kWave - 1) / kWave;
+  L.n_items = L.nclus * q.split;
+  L.nblk_bbox = kBboxBlocks;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + std::max<size_t>(bytes, 1), 256);
+    return r;
+  };
+  const size_t n = (size_t)q.n, m = (size_t)q.m, fd = (size_t)q.fd;
+  if (!q.on_device) {
+    L.off_sx = take(n * 3 * 4);
+    L.off_sf = take(n * fd * 4);
+    L.off_tx = take(m * 3 * 4);
+    L.off_tf = take(m * fd * 4);
+  }
+  L.off_xpart = take(kBboxBlocks * 7 * 8);
+  L.off_zpart = take(kBboxBlocks * 7 * 8);
+  L.off_xbox = take(8 * 8);
+  L.off_zbox = take(8 * 8);
+  L.off_T0 = take(16 * 8);
+  L.off_ell = take(kMaxStages * 8);
+  L.off_grid = take(sizeof(GridInfo) * kMaxStages);
+  L.off_ncell = take(4 * (kMaxStages + 1));
+  L.off_skeys = take(4 * n * S);
+  L.off_tkeys = take(4 * m);
+  L.off_sperm = take(4 * n * S);
+  L.off_tperm = take(4 * m);
+  for (int s = 0; s <= S; s++) {
+    const size_t kc = (s < S) ? (size_t)L.kcap : (size_t)kZBuckets;
+    const size_t nn = (s < S) ? n : m;
+    L.off_count[s] = take(4 * (kc + 1));
+    L.off_cursor[s] = take(4 * kc);
+    L.off_tmp[s] = take(4 * nn);
+  }
+  L.off_segs = take(sizeof(SortSeg) * (S + 1));
+  L.off_zrec = take(m * L.zs * 4);
+  L.off_zorig = take(m * 4);
+  const size_t xb = (q.precision == CVO_FP64) ? 8 : 4;
+  for (int s = 0; s < S; s++) L.off_xrec[s] = take(n * L.xs * xb);
+  L.off_xrecptr = take(sizeof(void*) * kMaxStages);
+  L.off_slots = take((size_t)L.n_items * kSlot * 8);
+  L.off_state = take(sizeof(ReqState));
+  L.off_trace = q.trace_on ? take((size_t)q.max_iters * kTraceCols * 8) : 0;
+  L.off_pt = (q.mode == kModeEvalTargets) ? take(m * 7 * 8) : 0;
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct cvo_ctx {
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;  // eval/register stream (user-selectable)
+  std::mutex call_mu;            // serialises eval/register
+  std::string last_error;
+  uint64_t budget = 0;
+  int max_slots = 256;
+  int brute_split = 0, cutoff_split = 0;
+
+  // pinned host staging
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+
+  // cached arena for the synchronous path
+  char* sync_arena = nullptr;
+  size_t sync_arena_bytes = 0;
+  ReqStatic* d_reqs_sync = nullptr;
+  int* d_item_end_sync = nullptr;
+  Request last_register;
+  bool have_last = false;
+
+  // profiling
+  bool profile = false;
+  std::vector<hipEvent_t> ev_pool;
+  int64_t prof_launches = 0;
+  double prof_ms = 0.0;
+  uint64_t prof_pairs = 0;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+
+  // serving
+  std::mutex q_mu;
+  std::condition_variable q_cv;     // scheduler wake-up
+  std::condition_variable done_cv;  // pollers
+  std::deque<Request*> pending;
+  std::unordered_map<uint64_t, Request*> tickets;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread sched;
+  bool sched_started = false;
+  hipStream_t serve_stream = nullptr;
+  size_t max_pending = 65536;
+};
+
+static int fail(cvo_ctx* c, hipError_t e, const char* what) {
+  if (c) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    c->last_error = buf;
+  }
+  return CVO_EDEVICE;
+}
+
+#define HIPCHK(ctx, expr)                              \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return fail(ctx, e_, #expr); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// validation and request construction
+// ---------------------------------------------------------------------------
+static bool finite_host(const float* p, size_t cnt) {
+  for (size_t i = 0; i < cnt; i++)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* p, const double* T0,
+                         int mode, Request& q) {
+  if (!src || !tgt || !p || !T0) return CVO_EINVAL;
+  if (src->n <= 0 || tgt->n <= 0) return CVO_EINVAL;
+  if (src->feat_dim < 1 || src->feat_dim > kMaxFeat || src->feat_dim != tgt->feat_dim) return CVO_EINVAL;
+  if (!src->xyz || !src->feat || !tgt->xyz || !tgt->feat) return CVO_EINVAL;
+  if (src->on_device != tgt->on_device) return CVO_EINVAL;
+  if (!(p->sigma > 0.0) || !(p->feat_scale > 0.0) || !(p->b2 > 0.0) || !(p->eta > 0.0)) return CVO_EINVAL;
+  if (!(p->cutoff_mult >= 0.0) || !std::isfinite(p->cutoff_mult) || !std::isfinite(p->a2)) return CVO_EINVAL;
+  if (p->n_stages < 1 || p->n_stages > kMaxStages || !p->stage_ell) return CVO_EINVAL;
+  if (p->n_stages > 1 && !p->stage_iters) return CVO_EINVAL;
+  if (p->max_iters < 1 || !(p->tol >= 0.0)) return CVO_EINVAL;
+  if (p->precision != CVO_FP32_KAHAN && p->precision != CVO_FP64) return CVO_EINVAL;
+  for (int s = 0; s < p->n_stages; s++) {
+    if (!(p->stage_ell[s] > 0.0) || !std::isfinite(p->stage_ell[s])) return CVO_EINVAL;
+    if (s < p->n_stages - 1 && p->stage_iters[s] < 1) return CVO_EINVAL;
+  }
+  for (int k = 0; k < 16; k++)
+    if (!std::isfinite(T0[k])) return CVO_EINVAL;
+  q.mode = mode;
+  q.n = src->n;
+  q.m = tgt->n;
+  q.fd = src->feat_dim;
+  q.n_stages = (mode == kModeRegister) ? p->n_stages : 1;
+  q.max_iters = (mode == kModeRegister) ? p->max_iters : 1;
+  q.precision = p->precision;
+  q.trace_on = (mode == kModeRegister) ? (p->trace ? 1 : 0) : 0;
+  q.sigma = p->sigma;
+  q.sf = p->feat_scale;
+  q.a2 = p->a2;
+  q.b2 = p->b2;
+  q.eta = p->eta;
+  q.kappa = p->cutoff_mult;
+  q.tol = p->tol;
+  for (int s = 0; s < q.n_stages; s++) {
+    q.stage_ell[s] = p->stage_ell[s];
+    q.stage_iters[s] = (s < q.n_stages - 1) ? p->stage_iters[s] : INT_MAX;
+  }
+  memcpy(q.T0, T0, sizeof(q.T0));
+  q.on_device = src->on_device != 0;
+  if (!q.on_device) {
+    if (!finite_host(src->xyz, 3ull * q.n) || !finite_host(src->feat, (size_t)q.fd * q.n) ||
+        !finite_host(tgt->xyz, 3ull * q.m) || !finite_host(tgt->feat, (size_t)q.fd * q.m))
+      return CVO_EINVAL;
+  }
+  q.sx = src->xyz;
+  q.sfeat = src->feat;
+  q.tx = tgt->xyz;
+  q.tfeat = tgt->feat;
+  return CVO_OK;
+}
+
+// Fill q.st (device pointers into the arena) and enqueue the ingest sequence.
+static int enqueue_ingest(cvo_ctx* c, Request& q, const Layout& L, hipStream_t s, void* pinned_scratch) {
+  char* A = q.arena;
+  // host-side structures staged through pinned memory
+  struct Staging {
+    double T0[16];
+    double ell[kMaxStages];
+    SortSeg segs[kMaxStages + 1];
+    void* xrecptr[kMaxStages];
+  };
+  Staging* h = (Staging*)pinned_scratch;
+  memcpy(h->T0, q.T0, sizeof(h->T0));
+  for (int k = 0; k < kMaxStages; k++) h->ell[k] = (k < q.n_stages) ? q.stage_ell[k] : 1.0;
+  const int S = q.n_stages;
+  int* ncell = (int*)(A + L.off_ncell);
+  for (int sidx = 0; sidx <= S; sidx++) {
+    SortSeg& g = h->segs[sidx];
+    const bool tgt = sidx == S;
+    g.keys = tgt ? (const int*)(A + L.off_tkeys) : (const int*)(A + L.off_skeys) + (size_t)sidx * q.n;
+    g.nkeys = ncell + sidx;
+    g.count = (int*)(A + L.off_count[sidx]);
+    g.cursor = (int*)(A + L.off_cursor[sidx]);
+    g.tmp = (int*)(A + L.off_tmp[sidx]);
+    g.perm = tgt ? (int*)(A + L.off_tperm) : (int*)(A + L.off_sperm) + (size_t)sidx * q.n;
+    g.n = tgt ? q.m : q.n;
+    g.kcap = tgt ? kZBuckets : L.kcap;
+  }
+  for (int k = 0; k < kMaxStages; k++) h->xrecptr[k] = (k < S) ? (void*)(A + L.off_xrec[k]) : nullptr;
+
+  HIPCHK(c, hipMemcpyAsync(A + L.off_T0, h->T0, sizeof(h->T0), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(A + L.off_ell, h->ell, sizeof(h->ell), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(A + L.off_segs, h->segs, sizeof(SortSeg) * (S + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(A + L.off_xrecptr, h->xrecptr, sizeof(h->xrecptr), hipMemcpyHostToDevice, s));
+
+  const float *sx = q.sx, *sf = q.sfeat, *tx = q.tx, *tf = q.tfeat;
+  if (!q.on_device) {
+    HIPCHK(c, hipMemcpyAsync(A + L.off_sx, q.sx, 12ull * q.n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(A + L.off_sf, q.sfeat, 4ull * q.fd * q.n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(A + L.off_tx, q.tx, 12ull * q.m, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(A + L.off_tf, q.tfeat, 4ull * q.fd * q.m, hipMemcpyHostToDevice, s));
+    sx = (const float*)(A + L.off_sx);
+    sf = (const float*)(A + L.off_sf);
+    tx = (const float*)(A + L.off_tx);
+    tf = (const float*)(A + L.off_tf);
+  }
+  IngestArgs a{};
+  a.sx = sx;
+  a.sfeat = sf;
+  a.tx = tx;
+  a.tfeat = tf;
+  a.n = q.n;
+  a.m = q.m;
+  a.fd = q.fd;
+  a.zs = L.zs;
+  a.xs = L.xs;
+  a.n_stages = S;
+  a.precision = q.precision;
+  a.kappa = q.kappa;
+  a.cells_per_reach = 1;
+  a.brute_div = 4;
+  a.kcap = L.kcap;
+  a.a2_param = q.a2;
+  a.T0 = (const double*)(A + L.off_T0);
+  a.stage_ell = (const double*)(A + L.off_ell);
+  a.xpart = (double*)(A + L.off_xpart);
+  a.zpart = (double*)(A + L.off_zpart);
+  a.xbox = (double*)(A + L.off_xbox);
+  a.zbox = (double*)(A + L.off_zbox);
+  a.grid = (GridInfo*)(A + L.off_grid);
+  a.ncell = ncell;
+  a.src_keys = (int*)(A + L.off_skeys);
+  a.tgt_keys = (int*)(A + L.off_tkeys);
+  a.src_perm = (int*)(A + L.off_sperm);
+  a.tgt_perm = (int*)(A + L.off_tperm);
+  a.segs = (SortSeg*)(A + L.off_segs);
+  a.max_seg_n = std::max(q.n, q.m);
+  a.max_kcap = std::max(L.kcap, kZBuckets);
+  a.zrec = (float*)(A + L.off_zrec);
+  a.zorig = (int*)(A + L.off_zorig);
+  a.xrec_dev = (void* const*)(A + L.off_xrecptr);
+  a.state = (ReqState*)(A + L.off_state);
+  a.nblk_bbox = L.nblk_bbox;
+  HIPCHK(c, launch_ingest(a, s));
+
+  ReqStatic& st = q.st;
+  memset(&st, 0, sizeof(st));
+  st.state = a.state;
+  st.zrec = a.zrec;
+  st.zorig = a.zorig;
+  for (int k = 0; k < S; k++) {
+    st.xrec[k] = A + L.off_xrec[k];
+    st.cstart[k] = (const int*)(A + L.off_count[k]);
+  }
+  st.grid = a.grid;
+  st.slots = (double*)(A + L.off_slots);
+  st.trace = q.trace_on ? (double*)(A + L.off_trace) : nullptr;
+  st.per_target = (q.mode == kModeEvalTargets) ? (double*)(A + L.off_pt) : nullptr;
+  st.m = q.m;
+  st.n = q.n;
+  st.fd = q.fd;
+  st.zs = L.zs;
+  st.xs = L.xs;
+  st.nclus = L.nclus;
+  st.split = q.split;
+  st.n_items = L.n_items;
+  st.n_stages = S;
+  st.max_iters = q.max_iters;
+  st.mode = q.mode;
+  st.precision = q.precision;
+  int end = 0;
+  for (int k = 0; k < kMaxStages; k++) {
+    if (k < S - 1) {
+      end += q.stage_iters[k];
+      st.stage_end[k] = end;
+    } else {
+      st.stage_end[k] = INT_MAX;
+    }
+    st.stage_ell[k] = (k < S) ? q.stage_ell[k] : 1.0;
+  }
+  st.s2f = q.sigma * q.sigma * q.sf;
+  st.b2 = q.b2;
+  st.eta = q.eta;
+  st.tol = q.tol;
+  q.state = a.state;
+  q.trace_dev = st.trace;
+  q.per_target_dev = st.per_target;
+  return CVO_OK;
+}
+
+static int ensure_pinned(cvo_ctx* c, size_t bytes) {
+  if (c->pinned_bytes >= bytes) return CVO_OK;
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  c->pinned = nullptr;
+  c->pinned_bytes = 0;
+  size_t b = std::max(bytes, (size_t)1 << 20);
+  HIPCHK(c, hipHostMalloc(&c->pinned, b, hipHostMallocDefault));
+  c->pinned_bytes = b;
+  return CVO_OK;
+}
+
+static void fill_result(Request& q, const ReqState& hs) {
+  q.res.status = hs.status;
+  q.res.iters = hs.iter;
+  q.res.converged = hs.converged;
+  q.res.F = hs.g[0];
+  for (int a = 0; a < 3; a++) {
+    q.res.omega[a] = hs.g[1 + a];
+    q.res.v[a] = hs.g[4 + a];
+  }
+  q.res.pairs_within = hs.pairs_within;
+  q.res.pairs_examined = hs.pairs_examined;
+  for (int k = 0; k < 12; k++) q.T_out[k] = hs.T[k];
+  q.T_out[12] = q.T_out[13] = q.T_out[14] = 0.0;
+  q.T_out[15] = 1.0;
+  q.status = hs.status;
+}
+
+// Synchronous single-request run (eval, eval-targets, register).
+static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out) {
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  const auto t0 = Clock::now();
+  q.split = pick_split(q, c->brute_split, c->cutoff_split);
+  const Layout L = plan(q);
+  if (c->budget && L.total > c->budget) return CVO_ENOMEM;
+  if (c->sync_arena_bytes < L.total) {
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (c->sync_arena) HIPCHK(c, hipFree(c->sync_arena));
+    c->sync_arena = nullptr;
+    c->sync_arena_bytes = 0;
+    size_t want = align_up(L.total + (L.total >> 3), 1 << 20);
+    HIPCHK(c, hipMalloc(&c->sync_arena, want));
+    c->sync_arena_bytes = want;
+  }
+  if (!c->d_reqs_sync) HIPCHK(c, hipMalloc(&c->d_reqs_sync, sizeof(ReqStatic)));
+  if (!c->d_item_end_sync) HIPCHK(c, hipMalloc(&c->d_item_end_sync, sizeof(int)));
+  q.arena = c->sync_arena;
+  q.arena_bytes = L.total;
+  int rc = ensure_pinned(c, 64 * 1024);
+  if (rc) return rc;
+  char* pin = (char*)c->pinned;
+  rc = enqueue_ingest(c, q, L, s, pin);
+  if (rc) return rc;
+  ReqStatic* hst = (ReqStatic*)(pin + 16384);
+  int* hend = (int*)(pin + 16384 + sizeof(ReqStatic) + 64);
+  *hst = q.st;
+  *hend = L.n_items;
+  HIPCHK(c, hipMemcpyAsync(c->d_reqs_sync, hst, sizeof(ReqStatic), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_item_end_sync, hend, sizeof(int), hipMemcpyHostToDevice, s));
+
+  if (!c->ev_a) {
+    HIPCHK(c, hipEventCreate(&c->ev_a));
+    HIPCHK(c, hipEventCreate(&c->ev_b));
+  }
+  const int blocks = (L.n_items + kItemsPerBlock - 1) / kItemsPerBlock;
+  const bool cut = q.kappa > 0.0;
+  const bool prof = c->profile && q.mode == kModeRegister;
+  if (prof && (int)c->ev_pool.size() < 2 * q.max_iters) {
+    while ((int)c->ev_pool.size() < 2 * q.max_iters) {
+      hipEvent_t e;
+      HIPCHK(c, hipEventCreate(&e));
+      c->ev_pool.push_back(e);
+    }
+  }
+  ReqState* hs = (ReqState*)(pin + 32768);
+  HIPCHK(c, hipEventRecord(c->ev_a, s));
+  int launched = 0;
+  const int chunk = (q.tol > 0.0) ? 16 : q.max_iters;
+  for (int k = 0; k < q.max_iters;) {
+    const int kend = std::min(q.max_iters, k + chunk);
+    for (; k < kend; k++) {
+      if (prof) HIPCHK(c, hipEventRecord(c->ev_pool[2 * k], s));
+      HIPCHK(c, launch_iterate(q.precision, q.fd, cut, blocks, c->d_reqs_sync, c->d_item_end_sync, 1, L.n_items, s));
+      if (prof) HIPCHK(c, hipEventRecord(c->ev_pool[2 * k + 1], s));
+      launched++;
+    }
+    if (k < q.max_iters) {
+      HIPCHK(c, hipMemcpyAsync(hs, q.state, sizeof(ReqState), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      if (hs->done) break;
+    }
+  }
+  HIPCHK(c, hipEventRecord(c->ev_b, s));
+  HIPCHK(c, hipMemcpyAsync(hs, q.state, sizeof(ReqState), hipMemcpyDeviceToHost, s));
+  if (per_target_out) {
+    per_target_out->resize((size_t)q.m * 7);
+    HIPCHK(c, hipMemcpyAsync(per_target_out->data(), q.per_target_dev, (size_t)q.m * 7 * 8, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  fill_result(q, *hs);
+  if (q.trace_on) {
+    const int rows = std::min(hs->iter, q.max_iters);
+    q.trace.resize((size_t)rows * kTraceCols);
+    if (rows > 0)
+      HIPCHK(c, hipMemcpy(q.trace.data(), q.trace_dev, q.trace.size() * 8, hipMemcpyDeviceToHost));
+  }
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
+  q.res.gpu_ms = ms;
+  if (prof) {
+    double tot = 0.0;
+    for (int k = 0; k < launched; k++) {
+      float e = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&e, c->ev_pool[2 * k], c->ev_pool[2 * k + 1]));
+      tot += e;
+    }
+    c->prof_launches += launched;
+    c->prof_ms += tot;
+    c->prof_pairs += hs->pairs_within;
+  }
+  q.res.wall_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+  return CVO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// continuous-batching scheduler (cvo_submit / cvo_poll)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Batch {
+  std::vector<Request*> active;
+};
+
+void complete(cvo_ctx* c, Request* q, int status) {
+  std::lock_guard<std::mutex> g(c->q_mu);
+  q->status = status;
+  q->res.status = status;
+  q->res.wall_ms = std::chrono::duration<double, std::milli>(Clock::now() - q->t_submit).count();
+  c->done_cv.notify_all();
+}
+
+void scheduler(cvo_ctx* c) {
+  (void)hipSetDevice(c->device);
+  hipStream_t s = c->serve_stream;
+  std::vector<Request*> active;
+  uint64_t in_use = 0;
+  ReqStatic* d_reqs = nullptr;
+  int* d_end = nullptr;
+  int cap_reqs = 0;
+  ReqStatic* h_reqs = nullptr;
+  int* h_end = nullptr;
+  ReqState* h_states = nullptr;
+  void* h_stage = nullptr;
+  (void)hipHostMalloc(&h_stage, 64 * 1024, hipHostMallocDefault);
+  const int chunk = 8;
+  for (;;) {
+    // admission
+    std::vector<Request*> admit;
+    {
+      std::unique_lock<std::mutex> lk(c->q_mu);
+      if (active.empty())
+        c->q_cv.wait(lk, [&] { return c->stop || !c->pending.empty(); });
+      if (c->stop && c->pending.empty() && active.empty()) break;
+      while (!c->pending.empty() && (int)(active.size() + admit.size()) < c->max_slots) {
+        Request* q = c->pending.front();
+        q->split = pick_split(*q, c->brute_split, c->cutoff_split);
+        const Layout L = plan(*q);
+        if (c->budget && L.total > c->budget) {
+          c->pending.pop_front();
+          q->status = CVO_ENOMEM;
+          q->res.status = CVO_ENOMEM;
+          c->done_cv.notify_all();
+          continue;
+        }
+        if (c->budget && in_use + L.total > c->budget && !(active.empty() && admit.empty())) break;
+        c->pending.pop_front();
+        q->arena_bytes = L.total;
+        in_use += L.total;
+        admit.push_back(q);
+      }
+    }
+    for (Request* q : admit) {
+      const Layout L = plan(*q);
+      int rc = CVO_OK;
+      if (hipMalloc(&q->arena, L.total) != hipSuccess) rc = CVO_ENOMEM;
+      if (rc == CVO_OK) rc = enqueue_ingest(c, *q, L, s, h_stage);
+      if (rc == CVO_OK && hipStreamSynchronize(s) != hipSuccess) rc = CVO_EDEVICE;  // staging reuse
+      if (rc != CVO_OK) {
+        if (q->arena) (void)hipFree(q->arena);
+        q->arena = nullptr;
+        in_use -= q->arena_bytes;
+        complete(c, q, rc);
+        continue;
+      }
+      active.push_back(q);
+    }
+    if (active.empty()) continue;
+
+    // one launch per iteration per kernel variant, for all active requests
+    std::map<std::tuple<int, int, int>, std::vector<Request*>> groups;
+    for (Request* q : active) groups[std::make_tuple(q->precision, q->fd, q->kappa > 0.0 ? 1 : 0)].push_back(q);
+    const int nreq = (int)active.size();
+    if (nreq > cap_reqs) {
+      if (d_reqs) (void)hipFree(d_reqs);
+      if (d_end) (void)hipFree(d_end);
+      if (h_reqs) (void)hipHostFree(h_reqs);
+      if (h_end) (void)hipHostFree(h_end);
+      if (h_states) (void)hipHostFree(h_states);
+      cap_reqs = std::max(nreq, 2 * cap_reqs);
+      (void)hipMalloc(&d_reqs, sizeof(ReqStatic) * cap_reqs);
+      (void)hipMalloc(&d_end, sizeof(int) * cap_reqs);
+      (void)hipHostMalloc(&h_reqs, sizeof(ReqStatic) * cap_reqs, hipHostMallocDefault);
+      (void)hipHostMalloc(&h_end, sizeof(int) * cap_reqs, hipHostMallocDefault);
+      (void)hipHostMalloc(&h_states, sizeof(ReqState) * cap_reqs, hipHostMallocDefault);
+    }
+    struct G {
+      int precision, fd, cut, first, count, items;
+    };
+    std::vector<G> gl;
+    int pos = 0;
+    std::vector<Request*> order;
+    for (auto& kv : groups) {
+      G g{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), pos, (int)kv.second.size(), 0};
+      int items = 0;
+      for (Request* q : kv.second) {
+        h_reqs[pos] = q->st;
+        items += q->st.n_items;
+        h_end[pos] = items;
+        order.push_back(q);
+        pos++;
+      }
+      g.items = items;
+      gl.push_back(g);
+    }
+    bool dev_ok = hipMemcpyAsync(d_reqs, h_reqs, sizeof(ReqStatic) * nreq, hipMemcpyHostToDevice, s) == hipSuccess &&
+                  hipMemcpyAsync(d_end, h_end, sizeof(int) * nreq, hipMemcpyHostToDevice, s) == hipSuccess;
+    for (int it = 0; it < chunk && dev_ok; it++) {
+      for (const G& g : gl) {
+        const int blocks = (g.items + kItemsPerBlock - 1) / kItemsPerBlock;
+        if (launch_iterate(g.precision, g.fd, g.cut != 0, blocks, d_reqs + g.first, d_end + g.first, g.count, g.items,
+                           s) != hipSuccess)
+          dev_ok = false;
+      }
+    }
+    for (int k = 0; k < nreq && dev_ok; k++)
+      if (hipMemcpyAsync(h_states + k, order[k]->state, sizeof(ReqState), hipMemcpyDeviceToHost, s) != hipSuccess)
+        dev_ok = false;
+    if (dev_ok && hipStreamSynchronize(s) != hipSuccess) dev_ok = false;
+    // retire
+    std::vector<Request*> still;
+    for (int k = 0; k < nreq; k++) {
+      Request* q = order[k];
+      if (!dev_ok || h_states[k].done) {
+        if (dev_ok) {
+          fill_result(*q, h_states[k]);
+          if (q->trace_on) {
+            const int rows = std::min(h_states[k].iter, q->max_iters);
+            q->trace.resize((size_t)rows * kTraceCols);
+            if (rows > 0) (void)hipMemcpy(q->trace.data(), q->trace_dev, q->trace.size() * 8, hipMemcpyDeviceToHost);
+          }
+        }
+        (void)hipFree(q->arena);
+        q->arena = nullptr;
+        in_use -= q->arena_bytes;
+        complete(c, q, dev_ok ? h_states[k].status : CVO_EDEVICE);
+      } else {
+        still.push_back(q);
+      }
+    }
+    active.swap(still);
+  }
+  if (d_reqs) (void)hipFree(d_reqs);
+  if (d_end) (void)hipFree(d_end);
+  if (h_reqs) (void)hipHostFree(h_reqs);
+  if (h_end) (void)hipHostFree(h_end);
+  if (h_states) (void)hipHostFree(h_states);
+  if (h_stage) (void)hipHostFree(h_stage);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int cvo_create(int device, uint64_t hbm_budget_bytes, int max_slots, cvo_ctx** out) {
+  if (!out) return CVO_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CVO_EDEVICE;
+  if (max_slots < 0 || max_slots > 4096) return CVO_EINVAL;
+  cvo_ctx* c = new (std::nothrow) cvo_ctx();
+  if (!c) return CVO_ENOMEM;
+  c->device = device;
+  c->max_slots = max_slots > 0 ? max_slots : 256;
+  if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->serve_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return CVO_EDEVICE;
+  }
+  c->stream = c->own_stream;
+  if (hbm_budget_bytes == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) hbm_budget_bytes = (uint64_t)(0.8 * (double)fr);
+  }
+  c->budget = hbm_budget_bytes;
+  *out = c;
+  return CVO_OK;
+}
+
+int cvo_destroy(cvo_ctx* c) {
+  if (!c) return CVO_EINVAL;
+  {
+    std::lock_guard<std::mutex> g(c->q_mu);
+    c->stop = true;
+  }
+  c->q_cv.notify_all();
+  if (c->sched.joinable()) c->sched.join();
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->sync_arena) (void)hipFree(c->sync_arena);
+  if (c->d_reqs_sync) (void)hipFree(c->d_reqs_sync);
+  if (c->d_item_end_sync) (void)hipFree(c->d_item_end_sync);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->ev_a) (void)hipEventDestroy(c->ev_a);
+  if (c->ev_b) (void)hipEventDestroy(c->ev_b);
+  for (auto& kv : c->tickets) delete kv.second;
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+  if (c->serve_stream) (void)hipStreamDestroy(c->serve_stream);
+  delete c;
+  return CVO_OK;
+}
+
+int cvo_set_stream(cvo_ctx* c, void* stream) {
+  if (!c) return CVO_EINVAL;
+  std::lock_guard<std::mutex> g(c->call_mu);
+  c->stream = stream ? (hipStream_t)stream : c->own_stream;
+  return CVO_OK;
+}
+
+int cvo_set_profiling(cvo_ctx* c, int32_t enable) {
+  if (!c) return CVO_EINVAL;
+  std::lock_guard<std::mutex> g(c->call_mu);
+  c->profile = enable != 0;
+  return CVO_OK;
+}
+
+int cvo_kernel_stats(cvo_ctx* c, int32_t reset, int64_t* launches, double* total_ms, uint64_t* pairs) {
+  if (!c) return CVO_EINVAL;
+  std::lock_guard<std::mutex> g(c->call_mu);
+  if (launches) *launches = c->prof_launches;
+  if (total_ms) *total_ms = c->prof_ms;
+  if (pairs) *pairs = c->prof_pairs;
+  if (reset) {
+    c->prof_launches = 0;
+    c->prof_ms = 0.0;
+    c->prof_pairs = 0;
+  }
+  return CVO_OK;
+}
+
+int cvo_set_split(cvo_ctx* c, int32_t brute_split, int32_t cutoff_split) {
+  if (!c || brute_split < 0 || cutoff_split < 0 || brute_split > 4096 || cutoff_split > 4096) return CVO_EINVAL;
+  std::lock_guard<std::mutex> g(c->call_mu);
+  std::lock_guard<std::mutex> g2(c->q_mu);
+  c->brute_split = brute_split;
+  c->cutoff_split = cutoff_split;
+  return CVO_OK;
+}
+
+int cvo_eval(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* p, const double T[16],
+             double* F, double omega[3], double v[3]) {
+  if (!c) return CVO_EINVAL;
+  Request q;
+  int rc = build_request(src, tgt, p, T, kModeEval, q);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(c->call_mu);
+  rc = run_sync(c, q, nullptr);
+  if (rc) return rc;
+  if (q.status) return q.status;
+  if (F) *F = q.res.F;
+  for (int a = 0; a < 3; a++) {
+    if (omega) omega[a] = q.res.omega[a];
+    if (v) v[a] = q.res.v[a];
+  }
+  return CVO_OK;
+}
+
+int cvo_eval_targets(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* p,
+                     const double T[16], int32_t nsel, const int32_t* sel, double* out) {
+  if (!c || !out || nsel < 0 || (nsel > 0 && !sel)) return CVO_EINVAL;
+  Request q;
+  int rc = build_request(src, tgt, p, T, kModeEvalTargets, q);
+  if (rc) return rc;
+  for (int k = 0; k < nsel; k++)
+    if (sel[k] < 0 || sel[k] >= q.m) return CVO_EINVAL;
+  std::lock_guard<std::mutex> g(c->call_mu);
+  std::vector<double> all;
+  rc = run_sync(c, q, &all);
+  if (rc) return rc;
+  if (q.status) return q.status;
+  if (nsel == 0) {
+    memcpy(out, all.data(), all.size() * 8);
+  } else {
+    for (int k = 0; k < nsel; k++) memcpy(out + 7 * (size_t)k, all.data() + 7 * (size_t)sel[k], 7 * 8);
+  }
+  return CVO_OK;
+}
+
+int cvo_register(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* p, const double T0[16],
+                 double T_out[16], cvo_result* res) {
+  if (!c) return CVO_EINVAL;
+  Request q;
+  int rc = build_request(src, tgt, p, T0, kModeRegister, q);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(c->call_mu);
+  rc = run_sync(c, q, nullptr);
+  if (rc) return rc;
+  if (T_out) memcpy(T_out, q.T_out, sizeof(q.T_out));
+  if (res) *res = q.res;
+  c->last_register = std::move(q);
+  c->have_last = true;
+  return c->last_register.status;
+}
+
+int cvo_submit(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* p, const double T0[16],
+               uint64_t* ticket) {
+  if (!c || !ticket) return CVO_EINVAL;
+  Request* q = new (std::nothrow) Request();
+  if (!q) return CVO_ENOMEM;
+  int rc = build_request(src, tgt, p, T0, kModeRegister, *q);
+  if (rc) {
+    delete q;
+    return rc;
+  }
+  if (!q->on_device) {
+    q->hsx.assign(q->sx, q->sx + 3ull * q->n);
+    q->hsf.assign(q->sfeat, q->sfeat + (size_t)q->fd * q->n);
+    q->htx.assign(q->tx, q->tx + 3ull * q->m);
+    q->htf.assign(q->tfeat, q->tfeat + (size_t)q->fd * q->m);
+    q->sx = q->hsx.data();
+    q->sfeat = q->hsf.data();
+    q->tx = q->htx.data();
+    q->tfeat = q->htf.data();
+  }
+  q->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> g(c->q_mu);
+    if (c->pending.size() >= c->max_pending) {
+      delete q;
+      return CVO_EBUSY;
+    }
+    q->ticket = c->next_ticket++;
+    c->tickets[q->ticket] = q;
+    c->pending.push_back(q);
+    if (!c->sched_started) {
+      c->sched_started = true;
+      c->sched = std::thread(scheduler, c);
+    }
+  }
+  c->q_cv.notify_all();
+  *ticket = q->ticket;
+  return CVO_OK;
+}
+
+int cvo_poll(cvo_ctx* c, uint64_t ticket, int32_t wait_us, double T_out[16], cvo_result* res) {
+  if (!c) return CVO_EINVAL;
+  std::unique_lock<std::mutex> lk(c->q_mu);
+  auto it = c->tickets.find(ticket);
+  if (it == c->tickets.end()) return CVO_ENOTFOUND;
+  Request* q = it->second;
+  auto ready = [&] { return q->status != CVO_PENDING; };
+  if (!ready()) {
+    if (wait_us < 0)
+      c->done_cv.wait(lk, ready);
+    else if (wait_us > 0)
+      c->done_cv.wait_for(lk, std::chrono::microseconds(wait_us), ready);
+  }
+  if (!ready()) return CVO_PENDING;
+  if (T_out) memcpy(T_out, q->T_out, sizeof(q->T_out));
+  if (res) *res = q->res;
+  const int st = q->status;
+  c->tickets.erase(it);
+  delete q;
+  return st;
+}
+
+int cvo_trace(cvo_ctx* c, uint64_t ticket, double* buf, int32_t cap) {
+  if (!c || cap < 0 || (cap > 0 && !buf)) return CVO_EINVAL;
+  if (ticket != 0) return CVO_ENOTFOUND;
+  std::lock_guard<std::mutex> g(c->call_mu);
+  if (!c->have_last) return CVO_ENOTFOUND;
+  const int rows = (int)(c->last_register.trace.size() / kTraceCols);
+  const int w = std::min(rows, cap);
+  if (w > 0) memcpy(buf, c->last_register.trace.data(), (size_t)w * kTraceCols * 8);
+  return w;
+}
+
+const char* cvo_strerror(int code) {
+  switch (code) {
+    case CVO_OK: return "ok";
+    case CVO_PENDING: return "pending";
+    case CVO_EINVAL: return "invalid argument";
+    case CVO_ENOMEM: return "request exceeds the device memory budget";
+    case CVO_EBUSY: return "submission queue full";
+    case CVO_ENOOVERLAP: return "no pair within reach (F <= 1e-300)";
+    case CVO_EDEVICE: return "HIP device error";
+    case CVO_ENOTFOUND: return "unknown ticket";
+    default: return "unknown error";
+  }
+}
+
+const char* cvo_last_error(cvo_ctx* c) { return c ? c->last_error.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+"""Parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerance (FP32 pair terms, compensated FP32 partials, FP64 reduction):
+  F:          |F - F_ref| <= 1e-5 F_ref               (F is a sum of positive terms)
+  omega, v:   |g_k - g_ref,k| <= 1e-5 A_k, A_k = sum_ij |term_k,ij| from the oracle
+  (the gradient cancels towards zero near convergence, so its error is measured
+  against the magnitude of the summed terms, not against its own value)
+  FP64 path:  the same with 1e-10.
+Pairs on the cutoff boundary may flip between FP32 and FP64 decisions; pair
+counts are compared with a small allowance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1904_02266_amd import Context, Params, params_planes, params_rgbd, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def check(g, ref, rtol=1e-5, what=""):
+    r = ref["g"]
+    A = ref["abs"]
+    assert abs(g[0] - r[0]) <= rtol * r[0], (what, "F", g[0], r[0], (g[0] - r[0]) / r[0])
+    for k in range(1, 7):
+        assert abs(g[k] - r[k]) <= rtol * A[k], (what, k, g[k], r[k], (g[k] - r[k]) / A[k])
+
+
+def rel_err(g, ref):
+    r, A = ref["g"], ref["abs"]
+    return max([abs(g[0] - r[0]) / r[0]] + [abs(g[k] - r[k]) / A[k] for k in range(1, 7)])
+
+
+@pytest.fixture(scope="module")
+def planes():
+    return synth.planes_pair(2000, seed=1)
+
+
+@pytest.fixture(scope="module")
+def rgbd_small():
+    return synth.rgbd_pair(6000, 5000, seed=31)
+
+
+def test_eval_planes_brute_force(ctx, planes):
+    p = planes
+    rng = np.random.default_rng(0)
+    for trial in range(4):
+        T = np.eye(4) if trial == 0 else synth.random_motion(rng, 10.0, 0.1)
+        g = ctx.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, params_planes())
+        ref = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=0.1)
+        check(g, ref, what=f"trial {trial}")
+
+
+@pytest.mark.parametrize("ell", [0.2, 0.08, 0.05])
+def test_eval_rgbd_cutoff(ctx, rgbd_small, ell):
+    p = rgbd_small
+    T = synth.random_motion(np.random.default_rng(3), 3.0, 0.03) @ p.T_true
+    prm = Params(stage_ell=(ell,), cutoff_mult=3.0)
+    g = ctx.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, prm)
+    ref = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=ell, kappa=3.0)
+    check(g, ref, what=f"ell {ell}")
+
+
+def test_eval_fp64_path(ctx, rgbd_small):
+    p = rgbd_small
+    T = p.T_true
+    for kappa, ell in ((3.0, 0.1), (0.0, 0.15)):
+        prm = Params(stage_ell=(ell,), cutoff_mult=kappa, precision="fp64")
+        g = ctx.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, prm)
+        ref = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=ell, kappa=kappa)
+        check(g, ref, rtol=1e-10, what=f"fp64 kappa {kappa}")
+
+
+def test_eval_targets_match_oracle(ctx, rgbd_small):
+    p = rgbd_small
+    T = p.T_true
+    prm = Params(stage_ell=(0.1,), cutoff_mult=3.0)
+    sel = np.random.default_rng(5).choice(p.tgt_xyz.shape[0], 64, replace=False).astype(np.int32)
+    out = ctx.eval_targets(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, prm, sel=sel)
+    ref = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=0.1, kappa=3.0, sel=sel,
+                      per_target=True)
+    pt = ref["per_target"]
+    for k in range(64):
+        if pt[k, 0] == 0.0:
+            assert out[k, 0] == 0.0
+            continue
+        assert abs(out[k, 0] - pt[k, 0]) <= 2e-5 * pt[k, 0], (k, out[k], pt[k])
+    # the sum over all targets is the objective
+    allt = ctx.eval_targets(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, prm)
+    g = ctx.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, prm)
+    # different work splits round differently in FP32; both are within the parity bound
+    np.testing.assert_allclose(allt.sum(axis=0)[0], g[0], rtol=1e-6)
+
+
+def test_pair_counts(ctx, rgbd_small):
+    p = rgbd_small
+    T = p.T_true
+    prm = params_rgbd(max_iters=1, stage_ell=(0.1,), stage_iters=())
+    out = ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, prm, T0=T)
+    ref = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=0.1, kappa=3.0)
+    assert abs(out["pairs_within"] - ref["within"]) <= 20, (out["pairs_within"], ref["within"])
+    assert out["pairs_examined"] >= out["pairs_within"]
+
+
+def test_register_planes_trajectory(ctx, planes):
+    """Config-1 registration (2,000 points, brute force, 50 steps): teacher-forced
+    per-iteration parity and final-pose parity against the oracle trajectory."""
+    p = planes
+    prm = params_planes(trace=True)
+    out = ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, prm)
+    tr = ctx.trace()
+    assert out["iters"] == 50 and tr.shape == (50, 26)
+    ref = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, stage_ell=(0.1,), max_iters=50)
+    E = out["T"][:3, :3] @ ref["T"][:3, :3].T
+    ang = np.arccos(np.clip((np.trace(E) - 1) / 2, -1, 1))
+    assert ang < 1e-4 and np.linalg.norm(out["T"][:3, 3] - E @ ref["T"][:3, 3]) < 1e-4
+    # teacher forcing: the oracle at the GPU's pose before each step
+    a2 = oracle.mean_sqnorm(p.src_xyz)
+    Tk = np.eye(4)
+    for k in (0, 1, 10, 49):
+        if k > 0:
+            Tk = tr[k - 1, 10:26].reshape(4, 4)
+        r = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, Tk, ell=0.1, a2=a2)
+        check(tr[k, :7], r, what=f"iter {k}")
+
+
+def test_register_rgbd_schedule_small(ctx):
+    p = synth.rgbd_pair(4000, 4000, seed=41)
+    prm = params_rgbd(max_iters=40, stage_iters=(10, 10, 10), trace=True)
+    out = ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, prm)
+    tr = ctx.trace()
+    ref = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, kappa=3.0,
+                          stage_iters=(10, 10, 10), stage_ell=prm.stage_ell, max_iters=40)
+    np.testing.assert_allclose(tr[:, 8], ref["trace"][:, 8])  # same stage schedule
+    E = out["T"][:3, :3] @ ref["T"][:3, :3].T
+    ang = np.arccos(np.clip((np.trace(E) - 1) / 2, -1, 1))
+    assert ang < 1e-4, ang
+    assert np.linalg.norm(out["T"][:3, 3] - E @ ref["T"][:3, 3]) < 1e-4
+
+
+def test_deterministic_reruns(ctx, rgbd_small):
+    p = rgbd_small
+    prm = params_rgbd(max_iters=12, stage_iters=(3, 3, 3))
+    a = ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, prm)
+    b = ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, prm)
+    assert np.array_equal(a["T"], b["T"]) and a["F"] == b["F"]
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (7, 63), (65, 64), (300, 130), (129, 1)])
+def test_ragged_sizes(ctx, n, m):
+    rng = np.random.default_rng(n * 1000 + m)
+    x = rng.uniform(-0.3, 0.3, size=(n, 3)).astype(np.float32)
+    z = rng.uniform(-0.3, 0.3, size=(m, 3)).astype(np.float32)
+    lx = rng.uniform(0, 1, size=(n, 5)).astype(np.float32)
+    lz = rng.uniform(0, 1, size=(m, 5)).astype(np.float32)
+    T = synth.random_motion(rng, 5.0, 0.02)
+    for kappa in (0.0, 3.0):
+        prm = Params(stage_ell=(0.2,), cutoff_mult=kappa, a2=1.0)
+        g = ctx.eval(x, lx, z, lz, T, prm)
+        ref = oracle.eval(x, lx, z, lz, T, ell=0.2, kappa=kappa, a2=1.0)
+        if ref["g"][0] == 0.0:
+            assert g[0] == 0.0
+        else:
+            check(g, ref, what=f"{n}x{m} kappa {kappa}")
+
+
+@pytest.mark.parametrize("fd", [1, 3, 8])
+def test_feature_dims(ctx, fd):
+    rng = np.random.default_rng(fd)
+    x = rng.uniform(-1, 1, size=(700, 3)).astype(np.float32)
+    z = (x + rng.normal(0, 0.02, size=x.shape)).astype(np.float32)
+    lx = rng.uniform(0, 1, size=(700, fd)).astype(np.float32)
+    lz = rng.uniform(0, 1, size=(700, fd)).astype(np.float32)
+    for kappa in (0.0, 3.0):
+        prm = Params(stage_ell=(0.1,), cutoff_mult=kappa)
+        g = ctx.eval(x, lx, z, lz, np.eye(4), prm)
+        ref = oracle.eval(x, lx, z, lz, np.eye(4), ell=0.1, kappa=kappa)
+        check(g, ref, what=f"fd {fd}")
+
+
+def test_errors(ctx, rgbd_small):
+    from paper_1904_02266_amd import CVO_EINVAL, CVO_ENOOVERLAP, CvoError
+    p = rgbd_small
+    bad = p.src_xyz.copy()
+    bad[5, 2] = np.inf
+    with pytest.raises(CvoError) as e:
+        ctx.eval(bad, p.src_feat, p.tgt_xyz, p.tgt_feat, np.eye(4), Params())
+    assert e.value.code == CVO_EINVAL
+    with pytest.raises(CvoError) as e:
+        ctx.eval(p.src_xyz, p.src_feat[:, :3], p.tgt_xyz, p.tgt_feat, np.eye(4), Params())
+    assert e.value.code == CVO_EINVAL
+    with pytest.raises(CvoError) as e:
+        ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, Params(stage_ell=(-1.0,)))
+    assert e.value.code == CVO_EINVAL
+    far = p.tgt_xyz + np.float32(50.0)
+    out = ctx.register(p.src_xyz, p.src_feat, far, p.tgt_feat, params_rgbd(max_iters=3, stage_iters=(1, 1, 1)),
+                       check=False)
+    assert out["rc"] == CVO_ENOOVERLAP and out["iters"] == 0
+
+
+def test_device_inputs_same_as_host(ctx, rgbd_small):
+    import torch
+    p = rgbd_small
+    dev = torch.device("cuda:0")
+    prm = params_rgbd(max_iters=8, stage_iters=(2, 2, 2))
+    a = ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, prm)
+    b = ctx.register(torch.from_numpy(p.src_xyz).to(dev), torch.from_numpy(p.src_feat).to(dev),
+                     torch.from_numpy(p.tgt_xyz).to(dev), torch.from_numpy(p.tgt_feat).to(dev), prm)
+    assert np.array_equal(a["T"], b["T"])
