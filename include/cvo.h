@@ -70,7 +70,7 @@ enum { CVO_FP32_KAHAN = 0, CVO_FP64 = 1 };
 
 /* One labelled point cloud (Section III-A: points x_i with labels l(x_i) in R^feat_dim). */
 typedef struct {
-  int32_t n;           /* number of points, >= 1 */
+  int32_t n;           /* number of points, 1 .. 16,000,000 */
   int32_t feat_dim;    /* label channels, 1..8 (both clouds must match) */
   const float* xyz;    /* [n][3] row-major, finite */
   const float* feat;   /* [n][feat_dim] row-major, finite */
@@ -154,16 +154,15 @@ int cvo_poll(cvo_ctx* ctx, uint64_t ticket, int32_t wait_us, double T_out[16], c
  * of rows written (<= cap) or a negative code. */
 int cvo_trace(cvo_ctx* ctx, uint64_t ticket, double* buf, int32_t cap);
 
-/* Event timing of the iteration kernel: when enabled, every iteration launch
- * of cvo_register is bracketed by HIP events on the launch stream. */
+/* Event timing of the two kernels of each iteration (the per-cluster
+ * candidate-list kernel and the pair kernel): when enabled, every iteration of
+ * cvo_register brackets them with HIP events on the launch stream. */
 int cvo_set_profiling(cvo_ctx* ctx, int32_t enable);
-/* Totals since the last reset: iteration launches timed, their summed device
- * milliseconds, and the pairs within the cutoff they evaluated. */
-int cvo_kernel_stats(cvo_ctx* ctx, int32_t reset, int64_t* launches, double* total_ms, uint64_t* pairs);
-
-/* Work split of the iteration kernel: slices of candidate sources per target
- * cluster (0: automatic).  Results are deterministic for a fixed split. */
-int cvo_set_split(cvo_ctx* ctx, int32_t brute_split, int32_t cutoff_split);
+/* Totals since the last reset: iterations timed, summed device milliseconds of
+ * the pair kernel and of the candidate-list kernel, and the pairs within the
+ * cutoff evaluated. */
+int cvo_kernel_stats(cvo_ctx* ctx, int32_t reset, int64_t* iterations, double* pair_ms, double* prepare_ms,
+                     uint64_t* pairs);
 
 /* Static text for a return code; cvo_last_error gives the last HIP message. */
 const char* cvo_strerror(int code);

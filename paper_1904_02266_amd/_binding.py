@@ -92,15 +92,14 @@ def load():
     L.cvo_poll.argtypes = [vp, u64, i32, P(dbl), P(cvo_result)]
     L.cvo_trace.argtypes = [vp, u64, P(dbl), i32]
     L.cvo_set_profiling.argtypes = [vp, i32]
-    L.cvo_kernel_stats.argtypes = [vp, i32, P(ctypes.c_int64), P(dbl), P(u64)]
-    L.cvo_set_split.argtypes = [vp, i32, i32]
+    L.cvo_kernel_stats.argtypes = [vp, i32, P(ctypes.c_int64), P(dbl), P(dbl), P(u64)]
     L.cvo_strerror.argtypes = [ctypes.c_int]
     L.cvo_strerror.restype = ctypes.c_char_p
     L.cvo_last_error.argtypes = [vp]
     L.cvo_last_error.restype = ctypes.c_char_p
     for name in ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
                  "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
-                 "cvo_kernel_stats", "cvo_set_split"):
+                 "cvo_kernel_stats"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -108,7 +107,7 @@ def load():
 
 EXPORTED = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
             "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
-            "cvo_kernel_stats", "cvo_set_split", "cvo_strerror", "cvo_last_error")
+            "cvo_kernel_stats", "cvo_strerror", "cvo_last_error")
 
 
 class CvoError(RuntimeError):
@@ -238,13 +237,11 @@ class Context:
     def kernel_stats(self, reset=False):
         n = ctypes.c_int64()
         ms = ctypes.c_double()
+        prep = ctypes.c_double()
         pairs = ctypes.c_uint64()
         self._check(self.L.cvo_kernel_stats(self.h, 1 if reset else 0, ctypes.byref(n), ctypes.byref(ms),
-                                            ctypes.byref(pairs)), "kernel_stats")
-        return dict(launches=n.value, ms=ms.value, pairs=pairs.value)
-
-    def set_split(self, brute=0, cutoff=0):
-        self._check(self.L.cvo_set_split(self.h, brute, cutoff), "set_split")
+                                            ctypes.byref(prep), ctypes.byref(pairs)), "kernel_stats")
+        return dict(launches=n.value, ms=ms.value, prepare_ms=prep.value, pairs=pairs.value)
 
     def eval(self, src_xyz, src_feat, tgt_xyz, tgt_feat, T, params: Params):
         s, t = _Cloud(src_xyz, src_feat), _Cloud(tgt_xyz, tgt_feat)

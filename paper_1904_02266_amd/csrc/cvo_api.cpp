@@ -51,10 +51,12 @@ struct Request {
   bool on_device = false;
   const float *sx = nullptr, *sfeat = nullptr, *tx = nullptr, *tfeat = nullptr;
   std::vector<float> hsx, hsf, htx, htf;  // host copies (submit with host inputs)
-  int split = 1;
-  // device arena
+  int nclus = 0;   // target clusters (read back after ingest)
+  // device arenas: set-up data (A) and per-cluster iteration buffers (B)
   char* arena = nullptr;
   size_t arena_bytes = 0;
+  char* arena_b = nullptr;
+  size_t arena_b_bytes = 0;
   ReqStatic st{};
   ReqState* state = nullptr;
   double* trace_dev = nullptr;
@@ -71,37 +73,31 @@ struct Layout {
   size_t off_sx, off_sf, off_tx, off_tf;
   size_t off_xpart, off_zpart, off_xbox, off_zbox, off_T0, off_ell;
   size_t off_grid, off_ncell, off_skeys, off_tkeys, off_sperm, off_tperm;
-  size_t off_count[kMaxStages + 1], off_cursor[kMaxStages + 1], off_tmp[kMaxStages + 1];
-  size_t off_segs, off_zrec, off_zorig, off_xrec[kMaxStages], off_xrecptr;
-  size_t off_slots, off_state, off_trace, off_pt;
+  size_t off_count[kMaxStages + 1], off_cursor[kMaxStages + 1], off_tmp[kMaxStages + 1], off_sums[kMaxStages + 1];
+  size_t off_segs, off_scans, off_clscan_args, off_zrec, off_zorig, off_xrec[kMaxStages], off_xrecptr;
+  size_t off_clflag, off_clscan, off_clfirst, off_clsums, off_clstart, off_clcount;
+  size_t off_state;
   size_t total;
-  int kcap, zs, xs, nclus, n_items, nblk_bbox;
+  int kcap, zs, xs, nblk_bbox;
+};
+
+// per-cluster iteration buffers, sized once the cluster count is known
+struct LayoutB {
+  size_t off_cinfo, off_cells, off_rslots, off_trace, off_pt;
+  size_t total;
 };
 
 constexpr int kBboxBlocks = 256;
+constexpr int kMaxPoints = 16000000;  // bounded by the single-level tile scan
 
-int pick_split(const Request& q, int brute_split, int cutoff_split) {
-  const int nclus = (q.m + kWave - 1) / kWave;
-  if (q.mode == kModeEvalTargets) return 1;
-  if (q.kappa > 0.0) {
-    if (cutoff_split > 0) return cutoff_split;
-    int s = (2048 + nclus - 1) / nclus;
-    return std::max(1, std::min(s, 16));
-  }
-  if (brute_split > 0) return brute_split;
-  int s = (4096 + nclus - 1) / nclus;
-  int cap = std::max(1, q.n / 256);
-  return std::max(1, std::min(s, std::min(cap, 256)));
-}
+int scan_tiles(long long len) { return (int)((len + kScanTile - 1) / kScanTile); }
 
 Layout plan(const Request& q) {
   Layout L{};
   const int S = q.n_stages;
-  L.kcap = std::min(std::max(1 << 16, 8 * q.n), 1 << 24);
+  L.kcap = std::min(std::max(1 << 16, 8 * q.n), (1 << 24) - 16);
   L.zs = round_up4(3 + q.fd);
   L.xs = round_up4(3 + q.fd);
-  L.nclus = (q.m + kWave - 1) / kWave;
-  L.n_items = L.nclus * q.split;
   L.nblk_bbox = kBboxBlocks;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -134,19 +130,50 @@ Layout plan(const Request& q) {
     L.off_count[s] = take(4 * (kc + 1));
     L.off_cursor[s] = take(4 * kc);
     L.off_tmp[s] = take(4 * nn);
+    L.off_sums[s] = take(4 * (size_t)(scan_tiles((long long)kc + 1) + 1));
   }
   L.off_segs = take(sizeof(SortSeg) * (S + 1));
+  L.off_scans = take(sizeof(ScanArgs) * (S + 1));
+  L.off_clscan_args = take(sizeof(ScanArgs));
   L.off_zrec = take(m * L.zs * 4);
   L.off_zorig = take(m * 4);
   const size_t xb = (q.precision == CVO_FP64) ? 8 : 4;
   for (int s = 0; s < S; s++) L.off_xrec[s] = take(n * L.xs * xb);
   L.off_xrecptr = take(sizeof(void*) * kMaxStages);
-  L.off_slots = take((size_t)L.n_items * kSlot * 8);
+  L.off_clflag = take(4 * m);
+  L.off_clscan = take(4 * m);
+  L.off_clfirst = take(4 * m);
+  L.off_clsums = take(4 * (size_t)(scan_tiles((long long)m) + 1));
+  L.off_clstart = take(4 * m);
+  L.off_clcount = take(4 * m);
   L.off_state = take(sizeof(ReqState));
-  L.off_trace = q.trace_on ? take((size_t)q.max_iters * kTraceCols * 8) : 0;
-  L.off_pt = (q.mode == kModeEvalTargets) ? take(m * 7 * 8) : 0;
   L.total = o;
   return L;
+}
+
+LayoutB plan_b(const Request& q, int nclus) {
+  LayoutB L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + std::max<size_t>(bytes, 1), 256);
+    return r;
+  };
+  const size_t nc = (size_t)nclus;
+  L.off_cinfo = take(sizeof(ClusInfo) * nc);
+  L.off_cells = take(sizeof(CellEntry) * nc * kCellCap);
+  L.off_rslots = take(8 * nc * kSlot);
+  L.off_trace = q.trace_on ? take((size_t)q.max_iters * kTraceCols * 8) : 0;
+  L.off_pt = (q.mode == kModeEvalTargets) ? take((size_t)q.m * 7 * 8) : 0;
+  L.total = o;
+  return L;
+}
+
+// conservative device-memory estimate of a request before its cluster count is known
+size_t footprint(const Request& q) {
+  const Layout L = plan(q);
+  const int nclus_max = (q.m + kWave - 1) / kWave * 2 + 64;
+  return L.total + plan_b(q, std::min(nclus_max, q.m)).total;
 }
 
 }  // namespace
@@ -162,7 +189,6 @@ struct cvo_ctx {
   std::string last_error;
   uint64_t budget = 0;
   int max_slots = 256;
-  int brute_split = 0, cutoff_split = 0;
 
   // pinned host staging
   void* pinned = nullptr;
@@ -171,8 +197,10 @@ struct cvo_ctx {
   // cached arena for the synchronous path
   char* sync_arena = nullptr;
   size_t sync_arena_bytes = 0;
+  char* sync_arena_b = nullptr;
+  size_t sync_arena_b_bytes = 0;
   ReqStatic* d_reqs_sync = nullptr;
-  int* d_item_end_sync = nullptr;
+  int* d_clus_end_sync = nullptr;
   Request last_register;
   bool have_last = false;
 
@@ -180,7 +208,8 @@ struct cvo_ctx {
   bool profile = false;
   std::vector<hipEvent_t> ev_pool;
   int64_t prof_launches = 0;
-  double prof_ms = 0.0;
+  double prof_ms = 0.0;          // pair kernel
+  double prof_prep_ms = 0.0;     // prepare kernel
   uint64_t prof_pairs = 0;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
 
@@ -226,6 +255,7 @@ static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
                          int mode, Request& q) {
   if (!src || !tgt || !p || !T0) return CVO_EINVAL;
   if (src->n <= 0 || tgt->n <= 0) return CVO_EINVAL;
+  if (src->n > kMaxPoints || tgt->n > kMaxPoints) return CVO_EINVAL;
   if (src->feat_dim < 1 || src->feat_dim > kMaxFeat || src->feat_dim != tgt->feat_dim) return CVO_EINVAL;
   if (!src->xyz || !src->feat || !tgt->xyz || !tgt->feat) return CVO_EINVAL;
   if (src->on_device != tgt->on_device) return CVO_EINVAL;
@@ -274,16 +304,19 @@ static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
   return CVO_OK;
 }
 
-// Fill q.st (device pointers into the arena) and enqueue the ingest sequence.
+// Enqueue the set-up sequence of one request into its arena A.  The host
+// structures are staged through pinned memory (valid until the stream syncs).
 static int enqueue_ingest(cvo_ctx* c, Request& q, const Layout& L, hipStream_t s, void* pinned_scratch) {
   char* A = q.arena;
-  // host-side structures staged through pinned memory
   struct Staging {
     double T0[16];
     double ell[kMaxStages];
     SortSeg segs[kMaxStages + 1];
+    ScanArgs scans[kMaxStages + 1];
+    ScanArgs clscan;
     void* xrecptr[kMaxStages];
   };
+  static_assert(sizeof(Staging) < 16384, "staging area");
   Staging* h = (Staging*)pinned_scratch;
   memcpy(h->T0, q.T0, sizeof(h->T0));
   for (int k = 0; k < kMaxStages; k++) h->ell[k] = (k < q.n_stages) ? q.stage_ell[k] : 1.0;
@@ -298,14 +331,26 @@ static int enqueue_ingest(cvo_ctx* c, Request& q, const Layout& L, hipStream_t s
     g.cursor = (int*)(A + L.off_cursor[sidx]);
     g.tmp = (int*)(A + L.off_tmp[sidx]);
     g.perm = tgt ? (int*)(A + L.off_tperm) : (int*)(A + L.off_sperm) + (size_t)sidx * q.n;
+    g.sums = (int*)(A + L.off_sums[sidx]);
     g.n = tgt ? q.m : q.n;
     g.kcap = tgt ? kZBuckets : L.kcap;
+    ScanArgs& sa = h->scans[sidx];
+    sa.data = g.count;
+    sa.lenp = g.nkeys;  // K + 1 entries
+    sa.len0 = 1;
+    sa.sums = g.sums;
   }
+  h->clscan.data = (int*)(A + L.off_clscan);
+  h->clscan.lenp = nullptr;
+  h->clscan.len0 = q.m;
+  h->clscan.sums = (int*)(A + L.off_clsums);
   for (int k = 0; k < kMaxStages; k++) h->xrecptr[k] = (k < S) ? (void*)(A + L.off_xrec[k]) : nullptr;
 
   HIPCHK(c, hipMemcpyAsync(A + L.off_T0, h->T0, sizeof(h->T0), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(A + L.off_ell, h->ell, sizeof(h->ell), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(A + L.off_segs, h->segs, sizeof(SortSeg) * (S + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(A + L.off_scans, h->scans, sizeof(ScanArgs) * (S + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(A + L.off_clscan_args, &h->clscan, sizeof(ScanArgs), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(A + L.off_xrecptr, h->xrecptr, sizeof(h->xrecptr), hipMemcpyHostToDevice, s));
 
   const float *sx = q.sx, *sf = q.sfeat, *tx = q.tx, *tf = q.tfeat;
@@ -332,7 +377,7 @@ static int enqueue_ingest(cvo_ctx* c, Request& q, const Layout& L, hipStream_t s
   a.n_stages = S;
   a.precision = q.precision;
   a.kappa = q.kappa;
-  a.cells_per_reach = 1;
+  a.cells_per_reach = 2;
   a.brute_div = 4;
   a.kcap = L.kcap;
   a.a2_param = q.a2;
@@ -349,36 +394,56 @@ static int enqueue_ingest(cvo_ctx* c, Request& q, const Layout& L, hipStream_t s
   a.src_perm = (int*)(A + L.off_sperm);
   a.tgt_perm = (int*)(A + L.off_tperm);
   a.segs = (SortSeg*)(A + L.off_segs);
+  a.sort_scans = (ScanArgs*)(A + L.off_scans);
+  a.cl_scan_args = (ScanArgs*)(A + L.off_clscan_args);
   a.max_seg_n = std::max(q.n, q.m);
   a.max_kcap = std::max(L.kcap, kZBuckets);
   a.zrec = (float*)(A + L.off_zrec);
   a.zorig = (int*)(A + L.off_zorig);
   a.xrec_dev = (void* const*)(A + L.off_xrecptr);
+  a.cl_flag = (int*)(A + L.off_clflag);
+  a.cl_scan = (int*)(A + L.off_clscan);
+  a.cl_first = (int*)(A + L.off_clfirst);
+  a.cl_sums = (int*)(A + L.off_clsums);
+  a.clus_start = (int*)(A + L.off_clstart);
+  a.clus_count = (int*)(A + L.off_clcount);
   a.state = (ReqState*)(A + L.off_state);
   a.nblk_bbox = L.nblk_bbox;
   HIPCHK(c, launch_ingest(a, s));
+  q.state = a.state;
+  return CVO_OK;
+}
 
+// Fill q.st once the cluster count is known and arena B is allocated.
+static int finish_setup(cvo_ctx* c, Request& q, const Layout& L, const LayoutB& LB, hipStream_t s) {
+  (void)c;
+  (void)s;
+  char* A = q.arena;
+  char* Bp = q.arena_b;
   ReqStatic& st = q.st;
   memset(&st, 0, sizeof(st));
-  st.state = a.state;
-  st.zrec = a.zrec;
-  st.zorig = a.zorig;
+  const int S = q.n_stages;
+  st.state = (ReqState*)(A + L.off_state);
+  st.zrec = (const float*)(A + L.off_zrec);
+  st.zorig = (const int*)(A + L.off_zorig);
+  st.clus_start = (const int*)(A + L.off_clstart);
+  st.clus_count = (const int*)(A + L.off_clcount);
   for (int k = 0; k < S; k++) {
     st.xrec[k] = A + L.off_xrec[k];
     st.cstart[k] = (const int*)(A + L.off_count[k]);
   }
-  st.grid = a.grid;
-  st.slots = (double*)(A + L.off_slots);
-  st.trace = q.trace_on ? (double*)(A + L.off_trace) : nullptr;
-  st.per_target = (q.mode == kModeEvalTargets) ? (double*)(A + L.off_pt) : nullptr;
+  st.grid = (const GridInfo*)(A + L.off_grid);
+  st.cinfo = (ClusInfo*)(Bp + LB.off_cinfo);
+  st.cells = (CellEntry*)(Bp + LB.off_cells);
+  st.rslots = (double*)(Bp + LB.off_rslots);
+  st.trace = q.trace_on ? (double*)(Bp + LB.off_trace) : nullptr;
+  st.per_target = (q.mode == kModeEvalTargets) ? (double*)(Bp + LB.off_pt) : nullptr;
   st.m = q.m;
   st.n = q.n;
   st.fd = q.fd;
   st.zs = L.zs;
   st.xs = L.xs;
-  st.nclus = L.nclus;
-  st.split = q.split;
-  st.n_items = L.n_items;
+  st.nclus = q.nclus;
   st.n_stages = S;
   st.max_iters = q.max_iters;
   st.mode = q.mode;
@@ -397,7 +462,6 @@ static int enqueue_ingest(cvo_ctx* c, Request& q, const Layout& L, hipStream_t s
   st.b2 = q.b2;
   st.eta = q.eta;
   st.tol = q.tol;
-  q.state = a.state;
   q.trace_dev = st.trace;
   q.per_target_dev = st.per_target;
   return CVO_OK;
@@ -431,63 +495,92 @@ static void fill_result(Request& q, const ReqState& hs) {
   q.status = hs.status;
 }
 
+static int grow(cvo_ctx* c, char** buf, size_t* have, size_t need, hipStream_t s) {
+  if (*have >= need) return CVO_OK;
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (*buf) HIPCHK(c, hipFree(*buf));
+  *buf = nullptr;
+  *have = 0;
+  const size_t want = align_up(need + (need >> 3), 1 << 20);
+  if (hipMalloc(buf, want) != hipSuccess) {
+    *buf = nullptr;
+    return CVO_ENOMEM;
+  }
+  *have = want;
+  return CVO_OK;
+}
+
 // Synchronous single-request run (eval, eval-targets, register).
 static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out) {
   HIPCHK(c, hipSetDevice(c->device));
   hipStream_t s = c->stream;
   const auto t0 = Clock::now();
-  q.split = pick_split(q, c->brute_split, c->cutoff_split);
   const Layout L = plan(q);
-  if (c->budget && L.total > c->budget) return CVO_ENOMEM;
-  if (c->sync_arena_bytes < L.total) {
-    HIPCHK(c, hipStreamSynchronize(s));
-    if (c->sync_arena) HIPCHK(c, hipFree(c->sync_arena));
-    c->sync_arena = nullptr;
-    c->sync_arena_bytes = 0;
-    size_t want = align_up(L.total + (L.total >> 3), 1 << 20);
-    HIPCHK(c, hipMalloc(&c->sync_arena, want));
-    c->sync_arena_bytes = want;
-  }
+  if (c->budget && footprint(q) > c->budget) return CVO_ENOMEM;
+  int rc = grow(c, &c->sync_arena, &c->sync_arena_bytes, L.total, s);
+  if (rc) return rc;
   if (!c->d_reqs_sync) HIPCHK(c, hipMalloc(&c->d_reqs_sync, sizeof(ReqStatic)));
-  if (!c->d_item_end_sync) HIPCHK(c, hipMalloc(&c->d_item_end_sync, sizeof(int)));
+  if (!c->d_clus_end_sync) HIPCHK(c, hipMalloc(&c->d_clus_end_sync, sizeof(int)));
   q.arena = c->sync_arena;
   q.arena_bytes = L.total;
-  int rc = ensure_pinned(c, 64 * 1024);
+  rc = ensure_pinned(c, 64 * 1024);
   if (rc) return rc;
   char* pin = (char*)c->pinned;
-  rc = enqueue_ingest(c, q, L, s, pin);
-  if (rc) return rc;
-  ReqStatic* hst = (ReqStatic*)(pin + 16384);
-  int* hend = (int*)(pin + 16384 + sizeof(ReqStatic) + 64);
-  *hst = q.st;
-  *hend = L.n_items;
-  HIPCHK(c, hipMemcpyAsync(c->d_reqs_sync, hst, sizeof(ReqStatic), hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_item_end_sync, hend, sizeof(int), hipMemcpyHostToDevice, s));
-
   if (!c->ev_a) {
     HIPCHK(c, hipEventCreate(&c->ev_a));
     HIPCHK(c, hipEventCreate(&c->ev_b));
   }
-  const int blocks = (L.n_items + kItemsPerBlock - 1) / kItemsPerBlock;
+  HIPCHK(c, hipEventRecord(c->ev_a, s));
+  rc = enqueue_ingest(c, q, L, s, pin);
+  if (rc) return rc;
+  // the cluster count sizes the iteration buffers
+  ReqState* hs = (ReqState*)(pin + 32768);
+  HIPCHK(c, hipMemcpyAsync(hs, q.state, sizeof(ReqState), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  q.nclus = hs->nclus;
+  if (hs->done) {  // invalid input detected on the device
+    fill_result(q, *hs);
+    q.res.wall_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+    return CVO_OK;
+  }
+  const LayoutB LB = plan_b(q, q.nclus);
+  rc = grow(c, &c->sync_arena_b, &c->sync_arena_b_bytes, LB.total, s);
+  if (rc) return rc;
+  q.arena_b = c->sync_arena_b;
+  q.arena_b_bytes = LB.total;
+  rc = finish_setup(c, q, L, LB, s);
+  if (rc) return rc;
+  ReqStatic* hst = (ReqStatic*)(pin + 16384);
+  int* hend = (int*)(pin + 16384 + sizeof(ReqStatic) + 64);
+  *hst = q.st;
+  *hend = q.nclus;
+  HIPCHK(c, hipMemcpyAsync(c->d_reqs_sync, hst, sizeof(ReqStatic), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_clus_end_sync, hend, sizeof(int), hipMemcpyHostToDevice, s));
+
   const bool cut = q.kappa > 0.0;
   const bool prof = c->profile && q.mode == kModeRegister;
-  if (prof && (int)c->ev_pool.size() < 2 * q.max_iters) {
-    while ((int)c->ev_pool.size() < 2 * q.max_iters) {
+  if (prof && (int)c->ev_pool.size() < 3 * q.max_iters) {
+    while ((int)c->ev_pool.size() < 3 * q.max_iters) {
       hipEvent_t e;
       HIPCHK(c, hipEventCreate(&e));
       c->ev_pool.push_back(e);
     }
   }
-  ReqState* hs = (ReqState*)(pin + 32768);
-  HIPCHK(c, hipEventRecord(c->ev_a, s));
   int launched = 0;
   const int chunk = (q.tol > 0.0) ? 16 : q.max_iters;
   for (int k = 0; k < q.max_iters;) {
     const int kend = std::min(q.max_iters, k + chunk);
     for (; k < kend; k++) {
-      if (prof) HIPCHK(c, hipEventRecord(c->ev_pool[2 * k], s));
-      HIPCHK(c, launch_iterate(q.precision, q.fd, cut, blocks, c->d_reqs_sync, c->d_item_end_sync, 1, L.n_items, s));
-      if (prof) HIPCHK(c, hipEventRecord(c->ev_pool[2 * k + 1], s));
+      if (prof) {
+        HIPCHK(c, hipEventRecord(c->ev_pool[3 * k], s));
+        HIPCHK(c, launch_prepare(c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, s));
+        HIPCHK(c, hipEventRecord(c->ev_pool[3 * k + 1], s));
+        HIPCHK(c, launch_pair_kernel(q.precision, q.fd, cut, c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, s));
+        HIPCHK(c, hipEventRecord(c->ev_pool[3 * k + 2], s));
+        HIPCHK(c, launch_step(c->d_reqs_sync, 1, s));
+      } else {
+        HIPCHK(c, launch_iteration(q.precision, q.fd, cut, c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, s));
+      }
       launched++;
     }
     if (k < q.max_iters) {
@@ -514,14 +607,17 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
   q.res.gpu_ms = ms;
   if (prof) {
-    double tot = 0.0;
+    double tot = 0.0, prep = 0.0;
     for (int k = 0; k < launched; k++) {
-      float e = 0.f;
-      HIPCHK(c, hipEventElapsedTime(&e, c->ev_pool[2 * k], c->ev_pool[2 * k + 1]));
-      tot += e;
+      float e1 = 0.f, e2 = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&e1, c->ev_pool[3 * k], c->ev_pool[3 * k + 1]));
+      HIPCHK(c, hipEventElapsedTime(&e2, c->ev_pool[3 * k + 1], c->ev_pool[3 * k + 2]));
+      prep += e1;
+      tot += e2;
     }
     c->prof_launches += launched;
     c->prof_ms += tot;
+    c->prof_prep_ms += prep;
     c->prof_pairs += hs->pairs_within;
   }
   q.res.wall_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
@@ -533,16 +629,45 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
 // ---------------------------------------------------------------------------
 namespace {
 
-struct Batch {
-  std::vector<Request*> active;
-};
-
 void complete(cvo_ctx* c, Request* q, int status) {
   std::lock_guard<std::mutex> g(c->q_mu);
   q->status = status;
   q->res.status = status;
   q->res.wall_ms = std::chrono::duration<double, std::milli>(Clock::now() - q->t_submit).count();
   c->done_cv.notify_all();
+}
+
+void release(Request* q, uint64_t& in_use) {
+  if (q->arena) (void)hipFree(q->arena);
+  if (q->arena_b) (void)hipFree(q->arena_b);
+  q->arena = nullptr;
+  q->arena_b = nullptr;
+  in_use -= q->arena_bytes;
+  q->arena_bytes = 0;
+}
+
+// Admit one request: allocate, ingest, read back its cluster count, allocate
+// the iteration buffers.  Returns CVO_OK or an error code for the request.
+int admit_one(cvo_ctx* c, Request* q, hipStream_t s, void* h_stage) {
+  const Layout L = plan(*q);
+  if (hipMalloc(&q->arena, L.total) != hipSuccess) {
+    q->arena = nullptr;
+    return CVO_ENOMEM;
+  }
+  int rc = enqueue_ingest(c, *q, L, s, h_stage);
+  if (rc) return rc;
+  ReqState* hs = (ReqState*)((char*)h_stage + 32768);
+  if (hipMemcpyAsync(hs, q->state, sizeof(ReqState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return CVO_EDEVICE;
+  if (hs->done) return hs->status ? hs->status : CVO_EINVAL;
+  q->nclus = hs->nclus;
+  const LayoutB LB = plan_b(*q, q->nclus);
+  if (hipMalloc(&q->arena_b, LB.total) != hipSuccess) {
+    q->arena_b = nullptr;
+    return CVO_ENOMEM;
+  }
+  return finish_setup(c, *q, L, LB, s);
 }
 
 void scheduler(cvo_ctx* c) {
@@ -560,41 +685,32 @@ void scheduler(cvo_ctx* c) {
   (void)hipHostMalloc(&h_stage, 64 * 1024, hipHostMallocDefault);
   const int chunk = 8;
   for (;;) {
-    // admission
     std::vector<Request*> admit;
     {
       std::unique_lock<std::mutex> lk(c->q_mu);
-      if (active.empty())
-        c->q_cv.wait(lk, [&] { return c->stop || !c->pending.empty(); });
+      if (active.empty()) c->q_cv.wait(lk, [&] { return c->stop || !c->pending.empty(); });
       if (c->stop && c->pending.empty() && active.empty()) break;
       while (!c->pending.empty() && (int)(active.size() + admit.size()) < c->max_slots) {
         Request* q = c->pending.front();
-        q->split = pick_split(*q, c->brute_split, c->cutoff_split);
-        const Layout L = plan(*q);
-        if (c->budget && L.total > c->budget) {
+        const size_t fp = footprint(*q);
+        if (c->budget && fp > c->budget) {
           c->pending.pop_front();
           q->status = CVO_ENOMEM;
           q->res.status = CVO_ENOMEM;
           c->done_cv.notify_all();
           continue;
         }
-        if (c->budget && in_use + L.total > c->budget && !(active.empty() && admit.empty())) break;
+        if (c->budget && in_use + fp > c->budget && !(active.empty() && admit.empty())) break;
         c->pending.pop_front();
-        q->arena_bytes = L.total;
-        in_use += L.total;
+        q->arena_bytes = fp;
+        in_use += fp;
         admit.push_back(q);
       }
     }
     for (Request* q : admit) {
-      const Layout L = plan(*q);
-      int rc = CVO_OK;
-      if (hipMalloc(&q->arena, L.total) != hipSuccess) rc = CVO_ENOMEM;
-      if (rc == CVO_OK) rc = enqueue_ingest(c, *q, L, s, h_stage);
-      if (rc == CVO_OK && hipStreamSynchronize(s) != hipSuccess) rc = CVO_EDEVICE;  // staging reuse
+      const int rc = admit_one(c, q, s, h_stage);
       if (rc != CVO_OK) {
-        if (q->arena) (void)hipFree(q->arena);
-        q->arena = nullptr;
-        in_use -= q->arena_bytes;
+        release(q, in_use);
         complete(c, q, rc);
         continue;
       }
@@ -602,7 +718,7 @@ void scheduler(cvo_ctx* c) {
     }
     if (active.empty()) continue;
 
-    // one launch per iteration per kernel variant, for all active requests
+    // one launch pair per iteration per kernel variant, for all active requests
     std::map<std::tuple<int, int, int>, std::vector<Request*>> groups;
     for (Request* q : active) groups[std::make_tuple(q->precision, q->fd, q->kappa > 0.0 ? 1 : 0)].push_back(q);
     const int nreq = (int)active.size();
@@ -620,31 +736,31 @@ void scheduler(cvo_ctx* c) {
       (void)hipHostMalloc(&h_states, sizeof(ReqState) * cap_reqs, hipHostMallocDefault);
     }
     struct G {
-      int precision, fd, cut, first, count, items;
+      int precision, fd, cut, first, count, clusters;
     };
     std::vector<G> gl;
     int pos = 0;
     std::vector<Request*> order;
     for (auto& kv : groups) {
       G g{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), pos, (int)kv.second.size(), 0};
-      int items = 0;
+      int cl = 0;
       for (Request* q : kv.second) {
         h_reqs[pos] = q->st;
-        items += q->st.n_items;
-        h_end[pos] = items;
+        cl += q->nclus;
+        h_end[pos] = cl;
         order.push_back(q);
         pos++;
       }
-      g.items = items;
+      g.clusters = cl;
       gl.push_back(g);
     }
-    bool dev_ok = hipMemcpyAsync(d_reqs, h_reqs, sizeof(ReqStatic) * nreq, hipMemcpyHostToDevice, s) == hipSuccess &&
+    bool dev_ok = d_reqs && d_end && h_reqs && h_end && h_states &&
+                  hipMemcpyAsync(d_reqs, h_reqs, sizeof(ReqStatic) * nreq, hipMemcpyHostToDevice, s) == hipSuccess &&
                   hipMemcpyAsync(d_end, h_end, sizeof(int) * nreq, hipMemcpyHostToDevice, s) == hipSuccess;
     for (int it = 0; it < chunk && dev_ok; it++) {
       for (const G& g : gl) {
-        const int blocks = (g.items + kItemsPerBlock - 1) / kItemsPerBlock;
-        if (launch_iterate(g.precision, g.fd, g.cut != 0, blocks, d_reqs + g.first, d_end + g.first, g.count, g.items,
-                           s) != hipSuccess)
+        if (launch_iteration(g.precision, g.fd, g.cut != 0, d_reqs + g.first, d_end + g.first, g.count, g.clusters,
+                             s) != hipSuccess)
           dev_ok = false;
       }
     }
@@ -652,7 +768,6 @@ void scheduler(cvo_ctx* c) {
       if (hipMemcpyAsync(h_states + k, order[k]->state, sizeof(ReqState), hipMemcpyDeviceToHost, s) != hipSuccess)
         dev_ok = false;
     if (dev_ok && hipStreamSynchronize(s) != hipSuccess) dev_ok = false;
-    // retire
     std::vector<Request*> still;
     for (int k = 0; k < nreq; k++) {
       Request* q = order[k];
@@ -665,9 +780,7 @@ void scheduler(cvo_ctx* c) {
             if (rows > 0) (void)hipMemcpy(q->trace.data(), q->trace_dev, q->trace.size() * 8, hipMemcpyDeviceToHost);
           }
         }
-        (void)hipFree(q->arena);
-        q->arena = nullptr;
-        in_use -= q->arena_bytes;
+        release(q, in_use);
         complete(c, q, dev_ok ? h_states[k].status : CVO_EDEVICE);
       } else {
         still.push_back(q);
@@ -727,7 +840,8 @@ int cvo_destroy(cvo_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   if (c->sync_arena) (void)hipFree(c->sync_arena);
   if (c->d_reqs_sync) (void)hipFree(c->d_reqs_sync);
-  if (c->d_item_end_sync) (void)hipFree(c->d_item_end_sync);
+  if (c->d_clus_end_sync) (void)hipFree(c->d_clus_end_sync);
+  if (c->sync_arena_b) (void)hipFree(c->sync_arena_b);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->ev_a) (void)hipEventDestroy(c->ev_a);
@@ -753,26 +867,20 @@ int cvo_set_profiling(cvo_ctx* c, int32_t enable) {
   return CVO_OK;
 }
 
-int cvo_kernel_stats(cvo_ctx* c, int32_t reset, int64_t* launches, double* total_ms, uint64_t* pairs) {
+int cvo_kernel_stats(cvo_ctx* c, int32_t reset, int64_t* launches, double* pair_ms, double* prepare_ms,
+                     uint64_t* pairs) {
   if (!c) return CVO_EINVAL;
   std::lock_guard<std::mutex> g(c->call_mu);
   if (launches) *launches = c->prof_launches;
-  if (total_ms) *total_ms = c->prof_ms;
+  if (pair_ms) *pair_ms = c->prof_ms;
+  if (prepare_ms) *prepare_ms = c->prof_prep_ms;
   if (pairs) *pairs = c->prof_pairs;
   if (reset) {
     c->prof_launches = 0;
     c->prof_ms = 0.0;
+    c->prof_prep_ms = 0.0;
     c->prof_pairs = 0;
   }
-  return CVO_OK;
-}
-
-int cvo_set_split(cvo_ctx* c, int32_t brute_split, int32_t cutoff_split) {
-  if (!c || brute_split < 0 || cutoff_split < 0 || brute_split > 4096 || cutoff_split > 4096) return CVO_EINVAL;
-  std::lock_guard<std::mutex> g(c->call_mu);
-  std::lock_guard<std::mutex> g2(c->q_mu);
-  c->brute_split = brute_split;
-  c->cutoff_split = cutoff_split;
   return CVO_OK;
 }
 

@@ -9,11 +9,19 @@ namespace cvo {
 constexpr int kMaxStages = 8;
 constexpr int kMaxFeat = 8;
 constexpr int kWave = 64;           // CDNA wavefront width
-constexpr int kItemsPerBlock = 4;   // one work item per wavefront, 256-thread blocks
-constexpr int kSlot = 8;            // doubles per work-item partial: W, omega[3], D[3], pairs
+constexpr int kWavesPerBlock = 4;   // one work item per wavefront, 256-thread blocks
+constexpr int kSlot = 9;            // doubles per partial: W, omega[3], D[3], pairs within, pairs examined
 constexpr int kTraceCols = 26;      // F, omega[3], v[3], tau, ell, pairs, T[16] after the step
 constexpr int kZBits = 6;           // Morton bits per axis for the target spatial order
 constexpr int kZBuckets = 1 << (3 * kZBits);
+constexpr int kPairWaves = 8;       // wavefronts (candidate slices) per target cluster in the pair kernel
+constexpr int kCellCap = 512;       // cell-list entries per cluster; beyond: box enumeration
+constexpr int kMaxDim = 2047;       // cells per grid axis (packed coordinates use 11 bits)
+constexpr int kStage32 = 128;       // sources staged in LDS per round and wave (FP32 path)
+constexpr int kStage64 = 64;        // sources staged in LDS per round and wave (FP64 path)
+constexpr int kScanPerThread = 16;  // multi-block scan: elements per thread
+constexpr int kScanBlock = 1024;    // multi-block scan: threads per block
+constexpr int kScanTile = kScanPerThread * kScanBlock;
 
 enum Mode : int { kModeRegister = 0, kModeEval = 1, kModeEvalTargets = 2 };
 
@@ -30,6 +38,22 @@ struct GridInfo {
   int pad;
 };
 
+// One reachable, non-empty source cell of a target cluster's candidate list.
+struct CellEntry {
+  int cell;   // cell coordinates packed as cx | cy << 11 | cz << 22
+  int first;  // first sorted source of the cell
+  int count;  // sources in the cell
+  int end;    // inclusive prefix of counts along the list
+};
+
+// Per target cluster, rebuilt every iteration by the prepare kernel.
+struct ClusInfo {
+  int total;     // candidate sources of the cluster
+  int ncells;    // list entries (may exceed kCellCap: then overflow)
+  int overflow;  // 1: the pair kernel enumerates the candidate box itself
+  int pad;
+};
+
 struct ReqState;
 
 // Per-request constants, written by the host before the first launch.
@@ -37,14 +61,17 @@ struct ReqStatic {
   ReqState* state;                   // this request's mutable state
   const float* zrec;                 // [m][zs] target xyz (raw FP32) + labels, spatially sorted
   const int* zorig;                  // [m] original index of each sorted target
+  const int* clus_start;             // [nclus] first sorted target of each cluster
+  const int* clus_count;             // [nclus] targets in each cluster (1..64)
   const void* xrec[kMaxStages];      // per stage: [n][xs] scaled cell-local offsets + labels
   const int* cstart[kMaxStages];     // per stage: [ncell+1] first sorted source of each cell
   const GridInfo* grid;              // [n_stages]
-  double* slots;                     // [n_items][kSlot]
+  ClusInfo* cinfo;                   // [nclus]
+  CellEntry* cells;                  // [nclus][kCellCap]
+  double* rslots;                    // [nclus][kSlot] cluster partials
   double* trace;                     // [max_iters][kTraceCols] or null
   double* per_target;                // [m][7] or null (per-target terms, eval-targets mode)
-  int m, n, fd, zs, xs;
-  int nclus, split, n_items;         // work items = nclus * split
+  int m, n, fd, zs, xs, nclus;
   int n_stages, max_iters, mode, precision;
   int stage_end[kMaxStages];         // iteration index where stage s ends; last = INT_MAX
   double stage_ell[kMaxStages];
@@ -60,9 +87,9 @@ struct ReqState {
   double tau;
   unsigned long long pairs_within, pairs_examined;
   int iter, stage, done, status, converged;
-  unsigned int arrive;               // arrivals of work items in the current launch
+  unsigned int reserved;
   int bad_input;                     // set by the finiteness check
-  int pad;
+  int nclus;                         // target clusters (device-computed at ingest)
 };
 
 // Descriptor of a counting sort over one key segment (one per stage for the
@@ -74,8 +101,17 @@ struct SortSeg {
   int* cursor;       // [Kcap] scatter cursors
   int* tmp;          // [n] scatter output (arbitrary order within a key)
   int* perm;         // [n] stable order: sorted position -> original index
+  int* sums;         // [Kcap/kScanTile + 1] scan block totals
   int n;
   int kcap;
+};
+
+// Exclusive in-place scan of data[0..len) with len = (lenp ? *lenp : 0) + len0.
+struct ScanArgs {
+  int* data;
+  const int* lenp;
+  int len0;
+  int* sums;  // [ceil(len / kScanTile)] tile totals
 };
 
 // ---------------------------------------------------------------------------
@@ -97,15 +133,29 @@ struct IngestArgs {
   int* src_perm;             // [n_stages][n]
   int* tgt_perm;             // [m]
   SortSeg* segs;             // device [n_stages + 1] (target segment last)
+  ScanArgs* sort_scans;      // device [n_stages + 1], over the count arrays (K + 1 entries)
+  ScanArgs* cl_scan_args;    // device [1], over cl_scan (m entries)
   int max_seg_n, max_kcap;
   float* zrec;
   int* zorig;
   void* const* xrec_dev;     // device array [n_stages] of record pointers
+  // target clustering: scratch [m] each (cl_sums: [m/kScanTile + 1]), outputs [m]
+  int *cl_flag, *cl_scan, *cl_first, *cl_sums;
+  int *clus_start, *clus_count;
   ReqState* state;
   int nblk_bbox;
 };
 hipError_t launch_ingest(const IngestArgs& a, hipStream_t s);
-hipError_t launch_iterate(int precision, int fd, bool cutoff, int blocks, const ReqStatic* reqs,
-                          const int* item_end, int nreq, int total_items, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// One gradient-flow iteration (or one evaluation) for a batch of requests that
+// share precision, label dimension and cutoff mode.  clus_end[r] is the
+// cumulative cluster count of requests 0..r.
+hipError_t launch_iteration(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end,
+                            int nreq, int total_clusters, hipStream_t s);
+// the three kernels of an iteration, separately (for event timing)
+hipError_t launch_step(const ReqStatic* reqs, int nreq, hipStream_t s);
+hipError_t launch_prepare(const ReqStatic* reqs, const int* clus_end, int nreq, int total_clusters, hipStream_t s);
+hipError_t launch_pair_kernel(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end, int nreq,
+                              int total_clusters, hipStream_t s);
 
 }  // namespace cvo

@@ -1,22 +1,26 @@
 // HIP kernels (gfx950) for continuous sensor registration.
 //
-// Hot path, per gradient-flow iteration (one launch, k_iterate):
-//   every wavefront owns one work item = (request, cluster of 64 spatially
-//   sorted target points, slice of the candidate source points);
-//   z~_j = T z_j in FP64 per lane, cluster bounding box, candidate source
-//   cells within the cutoff reach, per-pair FP32 terms
-//       d = z~_j - x_i,  r^2,  e = exp(-r^2/(2 l^2)),  c = <l_i, m_j>,
-//       W_j += c e,  D_j += c e d
-//   with the source point wave-uniform (scalar loads) and the target per lane;
-//   compensated (Kahan) FP32 partials per lane, FP64 wave reduction to a
-//   fixed slot per work item; the last wavefront of a request to arrive sums
-//   its slots in fixed order (FP64), forms F, omega, v (eq. scalar and
-//   eq. 3_gradient), and applies the FP64 exponential-map step (eq. step,
-//   eq. newstep) to the device-resident pose.
+// Hot path, per gradient-flow iteration (three launches for all active requests):
+//   k_prepare  one wavefront per cluster of <= 64 spatially sorted targets:
+//              z~_j = T z_j in FP64, cluster bounding box and sphere, the
+//              compacted list of reachable non-empty source cells of the
+//              current length-scale grid, candidate count, work chunks.
+//   k_pairs    one workgroup per cluster; each wavefront stages its slice of
+//              the cluster's candidate sources in LDS (cluster-relative FP32
+//              coordinates) and pairs them, at a wave-uniform LDS address,
+//              with the cluster's targets (one per lane), FP32 pair terms
+//                  d = z~_j - x_i, r^2, e = exp(-r^2/(2 l^2)), c = <l_i, m_j>,
+//                  W_j += c e, D_j += c e d          (eq. scalar, eq. 3_gradient)
+//              with compensated (Kahan) FP32 partials per lane, FP64 wave
+//              reductions and a fixed-order combination of the wave partials
+//              in LDS into one slot per cluster.
+//   k_step     one wavefront per request: fixed-order FP64 sum of the cluster
+//              partials, F, omega, v and the FP64 exponential-map step
+//              (eq. step, eq. newstep) applied to the pose.
 //
-// Set-up kernels: bounding boxes and the default a^2 (FP64), source grids per
-// length-scale stage (deterministic counting sort by cell), and a Morton
-// order of the target points.
+// Set-up kernels (once per registration): bounding boxes and the default
+// a^2 (FP64), one source grid per length-scale stage (deterministic counting
+// sort by cell), a Morton order of the targets and its clusters.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -31,6 +35,13 @@ namespace cvo {
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename P>
+__device__ __forceinline__ P* uniform_ptr(P* p) {
+  const unsigned long long u = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return (P*)(((unsigned long long)hi << 32) | lo);
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -154,8 +165,13 @@ __global__ void k_grid_setup(const double* __restrict__ xbox, int n_stages, cons
   bool fits = false;
   for (int it = 0; it < 256 && !fits; it++) {
     double cells = 1.0;
-    for (int a = 0; a < 3; a++) cells *= floor(ext[a] / h) + 1.0;
-    if (cells <= (double)kcap) fits = true;
+    bool axis_ok = true;
+    for (int a = 0; a < 3; a++) {
+      const double d = floor(ext[a] / h) + 1.0;
+      cells *= d;
+      axis_ok = axis_ok && d <= (double)kMaxDim;
+    }
+    if (cells <= (double)kcap && axis_ok) fits = true;
     else h *= 1.25;
   }
   if (!fits) h = 2.0 * emax + 1.0;  // at most 8 cells
@@ -259,34 +275,6 @@ __global__ __launch_bounds__(256) void k_sort_hist(const SortSeg* __restrict__ s
     atomicAdd(&S.count[S.keys[i]], 1);
 }
 
-// single workgroup per segment, 1024 threads, over K+1 entries
-__global__ __launch_bounds__(1024) void k_sort_scan(const SortSeg* __restrict__ segs) {
-  const SortSeg S = segs[blockIdx.y];
-  const int K = *S.nkeys;
-  const int total = K + 1;
-  const int T = blockDim.x;
-  const int per = (total + T - 1) / T;
-  const int t = threadIdx.x;
-  const int b0 = min(t * per, total), b1 = min(b0 + per, total);
-  int local = 0;
-  for (int k = b0; k < b1; k++) local += (k < K) ? S.count[k] : 0;
-  __shared__ int sh[1024];
-  sh[t] = local;
-  __syncthreads();
-  for (int o = 1; o < T; o <<= 1) {
-    int v = (t >= o) ? sh[t - o] : 0;
-    __syncthreads();
-    sh[t] += v;
-    __syncthreads();
-  }
-  int run = sh[t] - local;  // exclusive
-  for (int k = b0; k < b1; k++) {
-    const int c = (k < K) ? S.count[k] : 0;
-    S.count[k] = run;
-    run += c;
-  }
-}
-
 __global__ __launch_bounds__(256) void k_sort_scatter(const SortSeg* __restrict__ segs) {
   const SortSeg S = segs[blockIdx.y];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < S.n; i += gridDim.x * blockDim.x) {
@@ -350,7 +338,146 @@ __global__ __launch_bounds__(256) void k_src_records(const float* __restrict__ x
 
 
 // ---------------------------------------------------------------------------
-// 6) the iteration kernel
+// multi-block exclusive scan (in place), batched over segments (blockIdx.y)
+//   up:   per-tile totals      mid: scan of the tile totals      down: apply
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int scan_len(const ScanArgs& A) { return (A.lenp ? *A.lenp : 0) + A.len0; }
+
+// exclusive scan of one value per thread over a 1024-thread block
+__device__ __forceinline__ int block_excl_scan(int v, int* sh, int& total) {
+  const int l = lane_id(), w = threadIdx.x >> 6;
+  const int incl = wave_incl_scan(v);
+  if (l == kWave - 1) sh[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    const int nw = blockDim.x / kWave;
+    const int t = (l < nw) ? sh[l] : 0;
+    const int ti = wave_incl_scan(t);
+    if (l < nw) sh[l] = ti - t;
+    if (l == nw - 1) sh[32] = ti;
+  }
+  __syncthreads();
+  total = sh[32];
+  const int r = sh[w] + incl - v;
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_up(const ScanArgs* __restrict__ args) {
+  const ScanArgs A = args[blockIdx.y];
+  const int len = scan_len(A);
+  const long long base = (long long)blockIdx.x * kScanTile;
+  if (base >= len) return;
+  const long long t0 = base + (long long)threadIdx.x * kScanPerThread;
+  int s = 0;
+  for (int k = 0; k < kScanPerThread; k++)
+    if (t0 + k < len) s += A.data[t0 + k];
+  __shared__ int sh[33];
+  int total;
+  (void)block_excl_scan(s, sh, total);
+  if (threadIdx.x == 0) A.sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_mid(const ScanArgs* __restrict__ args) {
+  const ScanArgs A = args[blockIdx.y];
+  const int len = scan_len(A);
+  const int nt = (len + kScanTile - 1) / kScanTile;  // <= kScanBlock (checked on the host)
+  const int t = threadIdx.x;
+  const int v = (t < nt) ? A.sums[t] : 0;
+  __shared__ int sh[33];
+  int total;
+  const int e = block_excl_scan(v, sh, total);
+  if (t < nt) A.sums[t] = e;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_down(const ScanArgs* __restrict__ args) {
+  const ScanArgs A = args[blockIdx.y];
+  const int len = scan_len(A);
+  const long long base = (long long)blockIdx.x * kScanTile;
+  if (base >= len) return;
+  const long long t0 = base + (long long)threadIdx.x * kScanPerThread;
+  int v[kScanPerThread];
+  int s = 0;
+  for (int k = 0; k < kScanPerThread; k++) {
+    v[k] = (t0 + k < len) ? A.data[t0 + k] : 0;
+    s += v[k];
+  }
+  __shared__ int sh[33];
+  int total;
+  int run = block_excl_scan(s, sh, total) + A.sums[blockIdx.x];
+  for (int k = 0; k < kScanPerThread; k++) {
+    if (t0 + k < len) A.data[t0 + k] = run;
+    run += v[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// target clusters: runs of at most 64 consecutive Morton-ordered targets, cut
+// wherever two consecutive targets are farther apart than D (2.5 Morton
+// bucket edges), so that no cluster straddles a jump of the Morton curve.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cl_flags(const float* __restrict__ zrec, int zs, int m,
+                                                  const double* __restrict__ zbox, int* __restrict__ flag,
+                                                  int* __restrict__ scan) {
+  double e = 0.0;
+  for (int a = 0; a < 3; a++) e = fmax(e, zbox[3 + a] - zbox[a]);
+  const double D = 2.5 * e / (double)(1 << kZBits);
+  const double D2 = isfinite(D) ? D * D : 0.0;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
+    int f = 1;
+    if (p > 0) {
+      const float* a = zrec + (size_t)p * zs;
+      const float* b = zrec + (size_t)(p - 1) * zs;
+      const double dx = (double)a[0] - b[0], dy = (double)a[1] - b[1], dz = (double)a[2] - b[2];
+      f = (dx * dx + dy * dy + dz * dz > D2) ? 1 : 0;
+    }
+    flag[p] = f;
+    scan[p] = f;
+  }
+}
+
+// segment of p = (exclusive flag scan at p) + flag[p] - 1; record segment starts
+__global__ __launch_bounds__(256) void k_cl_segfirst(const int* __restrict__ flag, const int* __restrict__ scan, int m,
+                                                     int* __restrict__ first) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x)
+    if (flag[p]) first[scan[p]] = p;
+}
+
+// cluster-start flags: a segment start, or every 64th target inside a segment
+__global__ __launch_bounds__(256) void k_cl_cflags(int* __restrict__ flag, int* __restrict__ scan,
+                                                   const int* __restrict__ first, int m) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
+    const int seg = scan[p] + flag[p] - 1;
+    const int pos = p - first[seg];
+    const int c = (pos % kWave == 0) ? 1 : 0;
+    flag[p] = c;
+    scan[p] = c;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cl_table(const int* __restrict__ cflag, const int* __restrict__ cscan, int m,
+                                                  int* __restrict__ clus_start, ReqState* __restrict__ S) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
+    if (cflag[p]) clus_start[cscan[p]] = p;
+    if (p == m - 1) S->nclus = cscan[p] + cflag[p];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cl_count(const int* __restrict__ clus_start, const ReqState* __restrict__ S,
+                                                  int m, int* __restrict__ clus_count) {
+  const int nc = S->nclus;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x)
+    clus_count[c] = ((c + 1 < nc) ? clus_start[c + 1] : m) - clus_start[c];
+}
+
+__global__ __launch_bounds__(256) void k_zero(unsigned* __restrict__ p, size_t words) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// pair terms
 // ---------------------------------------------------------------------------
 template <typename CT>
 struct Acc;  // per-lane accumulators of W and D
@@ -402,50 +529,76 @@ __device__ __forceinline__ double kexp2(double a) { return exp2(a); }
 
 constexpr int kBlock = 64;  // pairs per lane between Kahan folds
 
-// All sources of one cell segment [a, b) against the lane's target.
-// Returns nothing; counts are kept in scalar registers by the caller.
+// Source records are read through the constant address space with a
+// wave-uniform index, so they arrive in scalar registers (s_load) and every
+// lane pairs the same source with its own target.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
 template <typename CT, int FD, bool CUT>
-__device__ __forceinline__ void cell_segment(const CT* __restrict__ xr, int xs, int a, int b, CT zx, CT zy,
-                                             CT zz, const CT (&mj)[FD], CT rc2, Acc<CT>& acc,
-                                             unsigned long long& within) {
+__device__ __forceinline__ void one_pair(const CT* __restrict__ r, CT zx, CT zy, CT zz, const CT (&mj)[FD], CT rc2,
+                                         Acc<CT>& acc, unsigned long long& within) {
+  const CT dx = zx - r[0];
+  const CT dy = zy - r[1];
+  const CT dz = zz - r[2];
+  const CT r2 = dx * dx + dy * dy + dz * dz;
+  const CT e = kexp2(-r2);
+  CT c = r[3] * mj[0];
+#pragma unroll
+  for (int f = 1; f < FD; f++) c += r[3 + f] * mj[f];
+  CT w = c * e;
+  if (CUT) {
+    // branch-free cutoff: the pair count comes from the scalar unit
+    const bool in = r2 <= rc2;
+    within += (unsigned long long)__popcll(__ballot(in));
+    w = in ? w : (CT)0;
+  }
+  acc.w += w;
+  acc.dx += w * dx;
+  acc.dy += w * dy;
+  acc.dz += w * dz;
+}
+
+// All sources of one cell segment [a, b) against the lane's target.
+template <typename CT, int FD, bool CUT>
+__device__ __forceinline__ void cell_segment(cptr<CT> xr, int xs, int a, int b, CT zx, CT zy, CT zz,
+                                             const CT (&mj)[FD], CT rc2, Acc<CT>& acc, unsigned long long& within) {
+  constexpr int NR = 3 + FD;
+  constexpr int U = 4;
   for (int b0 = a; b0 < b; b0 += kBlock) {
     const int b1 = min(b0 + kBlock, b);
-    for (int i = b0; i < b1; i++) {
-      const CT* r = xr + (size_t)i * xs;
-      const CT dx = zx - r[0];
-      const CT dy = zy - r[1];
-      const CT dz = zz - r[2];
-      const CT r2 = dx * dx + dy * dy + dz * dz;
-      bool in = true;
-      if (CUT) {
-        in = r2 <= rc2;
-        const unsigned long long bal = __ballot(in);
-        if (bal == 0ull) continue;
-        within += (unsigned long long)__popcll(bal);
-      }
-      const CT e = kexp2(-r2);
-      CT c = r[3] * mj[0];
+    int i = b0;
+    for (; i + U <= b1; i += U) {
+      CT rec[U][NR];
 #pragma unroll
-      for (int f = 1; f < FD; f++) c += r[3 + f] * mj[f];
-      CT w = c * e;
-      if (CUT) w = in ? w : (CT)0;
-      acc.w += w;
-      acc.dx += w * dx;
-      acc.dy += w * dy;
-      acc.dz += w * dz;
+      for (int u = 0; u < U; u++)
+#pragma unroll
+        for (int q = 0; q < NR; q++) rec[u][q] = xr[(size_t)(i + u) * xs + q];
+#pragma unroll
+      for (int u = 0; u < U; u++) one_pair<CT, FD, CUT>(rec[u], zx, zy, zz, mj, rc2, acc, within);
+    }
+    for (; i < b1; i++) {
+      CT rec[NR];
+#pragma unroll
+      for (int q = 0; q < NR; q++) rec[q] = xr[(size_t)i * xs + q];
+      one_pair<CT, FD, CUT>(rec, zx, zy, zz, mj, rc2, acc, within);
     }
     acc.fold();
   }
 }
 
-__device__ __forceinline__ int find_request(const int* __restrict__ item_end, int nreq, int item) {
-  int lo = 0, hi = nreq - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (item < item_end[mid]) hi = mid;
-    else lo = mid + 1;
+// Can a target within the cluster sphere (centre cc, squared reach
+// reach2 = (radius + cutoff reach)^2) have a source in cell (ix, iy, iz)?
+__device__ __forceinline__ bool cell_reachable(const GridInfo& g, int ix, int iy, int iz, const double (&cc)[3],
+                                               double reach2) {
+  if (!g.cutoff) return true;
+  const double lo[3] = {g.ox + ix * g.h, g.oy + iy * g.h, g.oz + iz * g.h};
+  double d2 = 0.0;
+  for (int a = 0; a < 3; a++) {
+    const double d = fmax(fmax(lo[a] - cc[a], cc[a] - (lo[a] + g.h)), 0.0);
+    d2 += d * d;
   }
-  return lo;
+  return d2 <= reach2;
 }
 
 // SE(3) exponential of the twist (w^, u) (eq. step with t = 1), composed on
@@ -490,18 +643,200 @@ __device__ void left_compose_exp(double T[12], const double w[3], const double u
   for (int q = 0; q < 12; q++) T[q] = out[q];
 }
 
-// The final reduction and step of one request, run by its last-arriving wave.
-__device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S) {
-  const int l = lane_id();
-  double acc[kSlot];
-  for (int q = 0; q < kSlot; q++) acc[q] = 0.0;
-  for (int it = l; it < R.n_items; it += kWave) {
-    const double* sl = R.slots + (size_t)it * kSlot;
-    for (int q = 0; q < kSlot; q++) acc[q] += sl[q];
+// ---------------------------------------------------------------------------
+// iteration kernels
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_request(const int* __restrict__ clus_end, int nreq, int item) {
+  int lo = 0, hi = nreq - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (item < clus_end[mid]) hi = mid;
+    else lo = mid + 1;
   }
-  for (int q = 0; q < kSlot; q++) acc[q] = wave_sum(acc[q]);
-  if (l != 0) return;
+  return lo;
+}
 
+// XCD-aware block order: consecutive logical blocks share an XCD (L2); the
+// hardware places block b on XCD b mod 8.
+__device__ __forceinline__ int logical_block() {
+  const int nb = gridDim.x;
+  const int full = (nb / 8) * 8;
+  const int b = blockIdx.x;
+  return (b < full) ? (b % 8) * (full / 8) + b / 8 : b;
+}
+
+// The cluster's targets: FP64 transformed position and labels.
+template <typename CT, int FD>
+__device__ __forceinline__ void load_targets(const ReqStatic& R, const double* __restrict__ T, int s0, bool valid,
+                                             double (&zt)[3], CT (&mj)[FD]) {
+  const int j = s0 + (valid ? lane_id() : 0);
+  const float* zr = R.zrec + (size_t)j * R.zs;
+  const double z0 = zr[0], z1 = zr[1], z2 = zr[2];
+#pragma unroll
+  for (int f = 0; f < FD; f++) mj[f] = (CT)zr[3 + f];
+  for (int a = 0; a < 3; a++) zt[a] = T[4 * a] * z0 + T[4 * a + 1] * z1 + T[4 * a + 2] * z2 + T[4 * a + 3];
+}
+
+// Candidate cell box of the cluster and its bounding sphere.
+struct CandBox {
+  int lo0, lo1, lo2, rx, ry, rz, ncand;
+  double cc[3];
+  double reach2;
+};
+
+__device__ __forceinline__ CandBox cand_box(const GridInfo& g, const double (&zt)[3], bool valid) {
+  CandBox B;
+  int lo[3], hi[3];
+  B.cc[0] = B.cc[1] = B.cc[2] = 0.0;
+  B.reach2 = INFINITY;
+  if (g.cutoff) {
+    const double o[3] = {g.ox, g.oy, g.oz};
+    const int dim[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; a++) {
+      const double bmin = wave_min(valid ? zt[a] : INFINITY);
+      const double bmax = wave_max(valid ? zt[a] : -INFINITY);
+      B.cc[a] = 0.5 * (bmin + bmax);
+      const double fl = floor((bmin - g.reach - o[a]) / g.h);
+      const double fh = floor((bmax + g.reach - o[a]) / g.h);
+      lo[a] = (int)fmin(fmax(fl, 0.0), (double)dim[a]);
+      hi[a] = (int)fmax(fmin(fh, (double)(dim[a] - 1)), -1.0);
+    }
+    const double d0 = zt[0] - B.cc[0], d1 = zt[1] - B.cc[1], d2 = zt[2] - B.cc[2];
+    const double rho = sqrt(wave_max(valid ? d0 * d0 + d1 * d1 + d2 * d2 : 0.0));
+    B.reach2 = (rho + g.reach) * (rho + g.reach);
+  } else {
+    lo[0] = lo[1] = lo[2] = 0;
+    hi[0] = g.nx - 1;
+    hi[1] = g.ny - 1;
+    hi[2] = g.nz - 1;
+  }
+  B.rx = uniform(max(hi[0] - lo[0] + 1, 0));
+  B.ry = uniform(max(hi[1] - lo[1] + 1, 0));
+  B.rz = uniform(max(hi[2] - lo[2] + 1, 0));
+  B.ncand = B.rx * B.ry * B.rz;
+  B.lo0 = uniform(lo[0]);
+  B.lo1 = uniform(lo[1]);
+  B.lo2 = uniform(lo[2]);
+  return B;
+}
+
+// candidate cell t of the box: its key, first source and count (0 if the
+// cell is empty or out of reach of the cluster sphere)
+__device__ __forceinline__ void cand_cell(const GridInfo& g, const CandBox& B, const int* __restrict__ cs, int t,
+                                          int& key, int& first, int& cnt, int* packed = nullptr) {
+  key = 0;
+  first = 0;
+  cnt = 0;
+  if (t < B.ncand) {
+    const int ix = t % B.rx, iy = (t / B.rx) % B.ry, iz = t / (B.rx * B.ry);
+    key = ((B.lo2 + iz) * g.ny + (B.lo1 + iy)) * g.nx + (B.lo0 + ix);
+    if (packed) *packed = (B.lo0 + ix) | ((B.lo1 + iy) << 11) | ((B.lo2 + iz) << 22);
+    if (cell_reachable(g, B.lo0 + ix, B.lo1 + iy, B.lo2 + iz, B.cc, B.reach2)) {
+      first = cs[key];
+      cnt = cs[key + 1] - first;
+    }
+  }
+}
+
+// Kernel A: per target cluster, the compacted list of reachable non-empty
+// source cells and the candidate count.
+__global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ reqs, const int* __restrict__ clus_end,
+                                                 int nreq, int total_clusters) {
+  const int lc = uniform(logical_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
+  if (lc >= total_clusters) return;
+  const int r = uniform(find_request(clus_end, nreq, lc));
+  const ReqStatic& R = reqs[r];
+  ReqState* S = R.state;
+  if (uniform(S->done)) return;
+  const int c = lc - (r > 0 ? clus_end[r - 1] : 0);
+  const int l = lane_id();
+  const int s0 = uniform(R.clus_start[c]);
+  const int cn = uniform(R.clus_count[c]);
+  const bool valid = l < cn;
+  double zt[3];
+  float mdummy[1];
+  load_targets<float, 1>(R, S->T, s0, valid, zt, mdummy);
+  const int stage = uniform(S->stage);
+  const GridInfo g = R.grid[stage];
+  const int* __restrict__ cs = uniform_ptr(R.cstart[stage]);
+  const CandBox B = cand_box(g, zt, valid);
+  CellEntry* list = R.cells + (size_t)c * kCellCap;
+  int nl = 0, total = 0;
+  for (int c0 = 0; c0 < B.ncand; c0 += kWave) {
+    int key, first, cnt, packed = 0;
+    cand_cell(g, B, cs, c0 + l, key, first, cnt, &packed);
+    const unsigned long long ne = __ballot(cnt > 0);
+    const int rank = __popcll(ne & ((1ull << l) - 1ull));
+    const int incl = wave_incl_scan(cnt);
+    if (cnt > 0 && nl + rank < kCellCap) {
+      CellEntry e;
+      e.cell = packed;
+      e.first = first;
+      e.count = cnt;
+      e.end = total + incl;
+      list[nl + rank] = e;
+    }
+    nl += __popcll(ne);
+    total += uniform(__shfl(incl, kWave - 1, kWave));
+  }
+  if (l == 0) {
+    ClusInfo ci;
+    ci.total = total;
+    ci.ncells = nl;
+    ci.overflow = nl > kCellCap ? 1 : 0;
+    ci.pad = 0;
+    R.cinfo[c] = ci;
+  }
+}
+
+// first list entry whose inclusive end exceeds pos (entries 0..nl-1, nl <= kCellCap)
+__device__ __forceinline__ int locate_entry(const CellEntry* __restrict__ list, int nl, long long pos) {
+  const int l = lane_id();
+  const int stride = (nl + kWave - 1) / kWave;  // <= kCellCap / 64
+  int idx = min(nl - 1, (l + 1) * stride - 1);
+  unsigned long long hit = __ballot(l * stride < nl && list[idx].end > pos);
+  if (hit == 0ull) return nl;
+  const int blk = __builtin_ctzll(hit);
+  idx = blk * stride + l;
+  hit = __ballot(l < stride && idx < nl && list[min(idx, nl - 1)].end > pos);
+  return hit == 0ull ? nl : blk * stride + __builtin_ctzll(hit);
+}
+
+template <typename CT, int FD, bool CUT>
+__device__ __forceinline__ void run_cell(const GridInfo& g, cptr<CT> xr, int xs, int key, int a, int b,
+                                         const double (&zt)[3], bool valid, const CT (&mj)[FD], CT rc2, Acc<CT>& acc,
+                                         unsigned long long& within) {
+  const int cx = key % g.nx, cy = (key / g.nx) % g.ny, cz = key / (g.nx * g.ny);
+  // lanes past the end of the cluster sit far outside every cell: their
+  // pairs fail the cutoff test and their kernel values underflow to 0
+  const CT far = (CT)1e30;
+  const CT zx = valid ? (CT)((zt[0] - (g.ox + cx * g.h)) * g.sq) : far;
+  const CT zy = valid ? (CT)((zt[1] - (g.oy + cy * g.h)) * g.sq) : far;
+  const CT zz = valid ? (CT)((zt[2] - (g.oz + cz * g.h)) * g.sq) : far;
+  cell_segment<CT, FD, CUT>(xr, xs, a, b, zx, zy, zz, mj, rc2, acc, within);
+}
+
+// sum of kSlot doubles over the first n lanes' rows p[lane*kSlot..], fixed order
+__device__ __forceinline__ void wave_reduce_rows(const double* __restrict__ p, int n, double (&out)[kSlot]) {
+  const int l = lane_id();
+  for (int q = 0; q < kSlot; q++) out[q] = 0.0;
+  for (int it = l; it < n; it += kWave) {
+    const double* row = p + (size_t)it * kSlot;
+    double v[kSlot];
+#pragma unroll
+    for (int q = 0; q < kSlot; q++) v[q] = row[q];
+#pragma unroll
+    for (int q = 0; q < kSlot; q++) out[q] += v[q];
+  }
+#pragma unroll
+  for (int q = 0; q < kSlot; q++) out[q] = wave_sum(out[q]);
+}
+
+// The request's final reduction and step (one wave per request).
+__device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S) {
+  double acc[kSlot];
+  wave_reduce_rows(R.rslots, R.nclus, acc);
+  if (lane_id() != 0) return;
   const int stage = S->stage;
   const double ell = R.stage_ell[stage];
   const double il2 = 1.0 / (ell * ell);
@@ -514,7 +849,7 @@ __device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S) {
   for (int q = 0; q < 7; q++) S->g[q] = g[q];
   const unsigned long long pairs = (unsigned long long)acc[7];
   S->pairs_within += pairs;
-  S->arrive = 0;
+  S->pairs_examined += (unsigned long long)acc[8];
 
   if (R.mode != kModeRegister) {
     S->done = 1;
@@ -559,131 +894,194 @@ __device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S) {
   if (stage < R.n_stages - 1 && kn >= R.stage_end[stage]) S->stage = stage + 1;
 }
 
+// wave-local LDS ordering: the stores of one phase are complete (and the
+// compiler keeps them in place) before another lane of the wave reads them
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <int FD>
+struct RecStride {
+  static constexpr int value = (3 + FD + 3) / 4 * 4;
+};
+
+// Candidate sources [lo_s, hi_s) of the cluster's list, staged round by round
+// into the wave's LDS area as coordinates relative to the cluster origin (the
+// first target, FP64), rounded once to CT, then paired with every lane's
+// target.  The pair loop reads each source at a wave-uniform LDS address.
 template <typename CT, int FD, bool CUT>
-__global__ __launch_bounds__(256) void k_iterate(const ReqStatic* __restrict__ reqs, const int* __restrict__ item_end,
-                                                 int nreq, int total_items) {
-  // XCD-aware block order: consecutive logical blocks share an XCD (L2).
-  const int nb = gridDim.x;
-  const int full = (nb / 8) * 8;
-  const int b = blockIdx.x;
-  const int lb = (b < full) ? (b % 8) * (full / 8) + b / 8 : b;
-  const int item = uniform(lb * kItemsPerBlock + (int)(threadIdx.x >> 6));
-  if (item >= total_items) return;
-  const int r = uniform(find_request(item_end, nreq, item));
+__device__ __forceinline__ void pairs_from_list(const ReqStatic& R, const GridInfo& g, const ClusInfo& ci, int c,
+                                                long long lo_s, long long hi_s, const double (&zt)[3], bool valid,
+                                                const CT (&mj)[FD], CT rc2, Acc<CT>& acc,
+                                                unsigned long long& within, cptr<CT> xr, int xs, CT* recs,
+                                                CellEntry* ents) {
+  constexpr int RS = RecStride<FD>::value;
+  constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
+  const int l = lane_id();
+  const CellEntry* __restrict__ list = uniform_ptr(R.cells + (size_t)c * kCellCap);
+  const int nl = uniform(ci.ncells);
+  // cluster origin: the first target (lane 0 always holds a target)
+  const double O[3] = {__shfl(zt[0], 0, kWave), __shfl(zt[1], 0, kWave), __shfl(zt[2], 0, kWave)};
+  const CT far = (CT)1e30;
+  const CT zx = valid ? (CT)((zt[0] - O[0]) * g.sq) : far;
+  const CT zy = valid ? (CT)((zt[1] - O[1]) * g.sq) : far;
+  const CT zz = valid ? (CT)((zt[2] - O[2]) * g.sq) : far;
+  // offset of cell (0,0,0) from the origin, in scaled units
+  const double base[3] = {(g.ox - O[0]) * g.sq, (g.oy - O[1]) * g.sq, (g.oz - O[2]) * g.sq};
+  const double hs = g.h * g.sq;
+  int e0 = uniform(locate_entry(list, nl, lo_s));
+  long long pos = lo_s;
+  while (pos < hi_s && e0 < nl) {
+    const int navail = uniform(min(kWave, nl - e0));
+    CellEntry me;
+    if (l < navail) {
+      me = list[e0 + l];
+    } else {
+      me.cell = 0;
+      me.first = 0;
+      me.count = 0;
+      me.end = 0x7fffffff;
+    }
+    ents[l] = me;
+    const long long last_end = uniform(__shfl(me.end, navail - 1, kWave));
+    long long rend = pos + NR;
+    if (rend > hi_s) rend = hi_s;
+    if (rend > last_end) rend = last_end;
+    const int nrec = (int)(rend - pos);
+    wave_lds_sync();
+    for (int s = l; s < nrec; s += kWave) {
+      const long long p = pos + s;
+      int lo = 0, hi = navail - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((long long)ents[mid].end > p) hi = mid;
+        else lo = mid + 1;
+      }
+      const CellEntry E = ents[lo];
+      const int src = E.first + (int)(p - ((long long)E.end - E.count));
+      const int cx = E.cell & 2047, cy = (E.cell >> 11) & 2047, cz = (E.cell >> 22) & 2047;
+      const CT* xg = (const CT*)xr + (size_t)src * xs;
+      CT* dst = recs + s * RS;
+      dst[0] = (CT)((double)xg[0] + (base[0] + cx * hs));
+      dst[1] = (CT)((double)xg[1] + (base[1] + cy * hs));
+      dst[2] = (CT)((double)xg[2] + (base[2] + cz * hs));
+#pragma unroll
+      for (int f = 0; f < FD; f++) dst[3 + f] = xg[3 + f];
+    }
+    wave_lds_sync();
+    // pairs: every lane's target against the staged sources
+    constexpr int U = 4;
+    for (int b0 = 0; b0 < nrec; b0 += kBlock) {
+      const int b1 = min(b0 + kBlock, nrec);
+      int i = b0;
+      for (; i + U <= b1; i += U) {
+        CT rec[U][3 + FD];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+          for (int q = 0; q < 3 + FD; q++) rec[u][q] = recs[(i + u) * RS + q];
+#pragma unroll
+        for (int u = 0; u < U; u++) one_pair<CT, FD, CUT>(rec[u], zx, zy, zz, mj, rc2, acc, within);
+      }
+      for (; i < b1; i++) {
+        CT rec[3 + FD];
+#pragma unroll
+        for (int q = 0; q < 3 + FD; q++) rec[q] = recs[i * RS + q];
+        one_pair<CT, FD, CUT>(rec, zx, zy, zz, mj, rc2, acc, within);
+      }
+      acc.fold();
+    }
+    wave_lds_sync();
+    // entries fully consumed by this round
+    const unsigned long long done_mask = __ballot(l < navail && (long long)me.end <= rend);
+    e0 += __popcll(done_mask);
+    pos = rend;
+  }
+}
+
+// Kernel B: one workgroup per target cluster, kPairWaves wavefronts, each
+// owning a contiguous slice of the cluster's candidate sources.  Wave partials
+// are combined through LDS in fixed order and the cluster partial goes to a
+// fixed slot; no device-scope synchronisation is needed inside the kernel.
+template <typename CT, int FD, bool CUT>
+__global__ __launch_bounds__(kPairWaves * kWave) void k_pairs(const ReqStatic* __restrict__ reqs,
+                                                              const int* __restrict__ clus_end, int nreq,
+                                                              int total_clusters) {
+  constexpr int RS = RecStride<FD>::value;
+  constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
+  __shared__ CT recs_all[kPairWaves][NR * RS];
+  __shared__ CellEntry ents_all[kPairWaves][kWave];
+  __shared__ double parts[kPairWaves][kSlot];
+  const int lc = logical_block();  // block-uniform
+  if (lc >= total_clusters) return;
+  const int r = find_request(clus_end, nreq, lc);
   const ReqStatic& R = reqs[r];
   ReqState* S = R.state;
-  if (S->done) return;
-  const int local = item - (r > 0 ? item_end[r - 1] : 0);
-  const int split = R.split;
-  const int clus = local / split;
-  const int part = local - clus * split;
+  if (S->done) return;  // block-uniform
+  const int c = lc - (r > 0 ? clus_end[r - 1] : 0);
+  const int w = threadIdx.x >> 6;
   const int l = lane_id();
-  const int j = clus * kWave + l;
-  const bool valid = j < R.m;
+  const ClusInfo ci = R.cinfo[c];
+  const int total = uniform(ci.total);
+  // per-target outputs need every source of a target in one wave
+  const int nslices = (R.mode == kModeEvalTargets) ? 1 : kPairWaves;
+  const long long lo_s = (w < nslices) ? (long long)total * w / nslices : 0;
+  const long long hi_s = (w < nslices) ? (long long)total * (w + 1) / nslices : 0;
 
-  // target point and labels
-  double zt[3] = {0.0, 0.0, 0.0};
+  const int s0 = uniform(R.clus_start[c]);
+  const int cn = uniform(R.clus_count[c]);
+  const bool valid = l < cn;
+  double zt[3];
   CT mj[FD];
-  {
-    const double* T = S->T;
-    const float* zr = R.zrec + (size_t)(valid ? j : 0) * R.zs;
-    const double z0 = zr[0], z1 = zr[1], z2 = zr[2];
-#pragma unroll
-    for (int f = 0; f < FD; f++) mj[f] = (CT)zr[3 + f];
-    for (int a = 0; a < 3; a++) zt[a] = T[4 * a] * z0 + T[4 * a + 1] * z1 + T[4 * a + 2] * z2 + T[4 * a + 3];
-  }
-  const unsigned long long vmask = __ballot(valid);
-  const int nvalid = __popcll(vmask);
+  load_targets<CT, FD>(R, S->T, s0, valid, zt, mj);
 
-  const int stage = S->stage;
+  // values read from the mutable request state are wave-uniform: keep them in
+  // scalar registers
+  const int stage = uniform(S->stage);
   const GridInfo g = R.grid[stage];
-  const CT* __restrict__ xr = (const CT*)R.xrec[stage];
-  const int* __restrict__ cs = R.cstart[stage];
-  const int xs = R.xs;
+  const cptr<CT> xr = (cptr<CT>)uniform_ptr(R.xrec[stage]);
+  const int xs = uniform(R.xs);
+  const CT rc2 = (CT)g.rc2s;
 
-  // candidate cell box
-  int lo[3], hi[3];
-  if (g.cutoff) {
-    const double o[3] = {g.ox, g.oy, g.oz};
-    const int dim[3] = {g.nx, g.ny, g.nz};
-    for (int a = 0; a < 3; a++) {
-      const double bmin = wave_min(valid ? zt[a] : INFINITY);
-      const double bmax = wave_max(valid ? zt[a] : -INFINITY);
-      const double fl = floor((bmin - g.reach - o[a]) / g.h);
-      const double fh = floor((bmax + g.reach - o[a]) / g.h);
-      // clamp in FP64 before the conversion so that far clusters give empty ranges
-      lo[a] = (int)fmin(fmax(fl, 0.0), (double)dim[a]);
-      hi[a] = (int)fmax(fmin(fh, (double)(dim[a] - 1)), -1.0);
-    }
-  } else {
-    lo[0] = lo[1] = lo[2] = 0;
-    hi[0] = g.nx - 1;
-    hi[1] = g.ny - 1;
-    hi[2] = g.nz - 1;
-  }
-  const int rx = uniform(max(hi[0] - lo[0] + 1, 0));
-  const int ry = uniform(max(hi[1] - lo[1] + 1, 0));
-  const int rz = uniform(max(hi[2] - lo[2] + 1, 0));
-  const int ncand = rx * ry * rz;
-  const int lo0 = uniform(lo[0]), lo1 = uniform(lo[1]), lo2 = uniform(lo[2]);
-
-  // pass 1: number of candidate sources
-  long long total = 0;
-  for (int c0 = 0; c0 < ncand; c0 += kWave) {
-    const int t = c0 + l;
-    int cnt = 0;
-    if (t < ncand) {
-      const int ix = t % rx, iy = (t / rx) % ry, iz = t / (rx * ry);
-      const int key = ((lo2 + iz) * g.ny + (lo1 + iy)) * g.nx + (lo0 + ix);
-      cnt = cs[key + 1] - cs[key];
-    }
-    total += uniform(wave_sum_int(cnt));
-  }
-  const long long s0 = total * part / split, s1 = total * (part + 1) / split;
-
-  // pass 2: my slice [s0, s1) of the concatenated candidate sources
   Acc<CT> acc;
   acc.init();
   unsigned long long within = 0;
-  unsigned long long examined = 0;
-  const CT rc2 = (CT)g.rc2s;
-  long long base = 0;
-  for (int c0 = 0; c0 < ncand && base < s1; c0 += kWave) {
-    const int t = c0 + l;
-    int key = 0, cnt = 0;
-    if (t < ncand) {
-      const int ix = t % rx, iy = (t / rx) % ry, iz = t / (rx * ry);
-      key = ((lo2 + iz) * g.ny + (lo1 + iy)) * g.nx + (lo0 + ix);
-      cnt = cs[key + 1] - cs[key];
+  long long span = 0;
+  if (lo_s < hi_s) {
+    if (!uniform(ci.overflow)) {
+      pairs_from_list<CT, FD, CUT>(R, g, ci, c, lo_s, hi_s, zt, valid, mj, rc2, acc, within, xr, xs, recs_all[w],
+                                   ents_all[w]);
+      span = hi_s - lo_s;
+    } else {
+      // the list overflowed: enumerate the candidate box again in the same order
+      const int* __restrict__ cs = uniform_ptr(R.cstart[stage]);
+      const CandBox B = cand_box(g, zt, valid);
+      long long base = 0;
+      for (int c0 = 0; c0 < B.ncand && base < hi_s; c0 += kWave) {
+        int key, first, cnt;
+        cand_cell(g, B, cs, c0 + l, key, first, cnt);
+        const int incl = wave_incl_scan(cnt);
+        const long long cb = base + incl - cnt, ce = base + incl;
+        unsigned long long todo = __ballot(cnt > 0 && ce > lo_s && cb < hi_s);
+        while (todo) {
+          const int src = __builtin_ctzll(todo);
+          todo &= todo - 1ull;
+          const int ckey = uniform(__shfl(key, src, kWave));
+          const int cfirst = uniform(__shfl(first, src, kWave));
+          const int ccnt = uniform(__shfl(cnt, src, kWave));
+          const long long cbeg = base + uniform(__shfl(incl - cnt, src, kWave));
+          const int a = cfirst + (int)(lo_s > cbeg ? lo_s - cbeg : 0);
+          const int b = cfirst + (int)((hi_s - cbeg) < ccnt ? (hi_s - cbeg) : ccnt);
+          run_cell<CT, FD, CUT>(g, xr, xs, ckey, a, b, zt, valid, mj, rc2, acc, within);
+          span += b - a;
+        }
+        base += uniform(__shfl(incl, kWave - 1, kWave));
+      }
     }
-    const int incl = wave_incl_scan(cnt);
-    const int chunk_total = uniform(__shfl(incl, kWave - 1, kWave));
-    // lanes whose cell intersects the slice
-    const long long cb = base + incl - cnt, ce = base + incl;
-    unsigned long long todo = __ballot(cnt > 0 && ce > s0 && cb < s1);
-    while (todo) {
-      const int src = __builtin_ctzll(todo);
-      todo &= todo - 1ull;
-      const int ckey = uniform(__shfl(key, src, kWave));
-      const long long cbeg = base + uniform(__shfl(incl - cnt, src, kWave));
-      const int ccnt = uniform(__shfl(cnt, src, kWave));
-      const int first = uniform(cs[ckey]);
-      const long long sb = cbeg > s0 ? cbeg : s0;
-      const long long se = (cbeg + ccnt) < s1 ? (cbeg + ccnt) : s1;
-      const int a = first + (int)(sb - cbeg);
-      const int bnd = first + (int)(se - cbeg);
-      const int cx = ckey % g.nx, cy = (ckey / g.nx) % g.ny, cz = ckey / (g.nx * g.ny);
-      // lanes past the end of the cloud sit far outside every cell: their
-      // pairs fail the cutoff test and their kernel values underflow to 0
-      const CT far = (CT)1e30;
-      const CT zx = valid ? (CT)((zt[0] - (g.ox + cx * g.h)) * g.sq) : far;
-      const CT zy = valid ? (CT)((zt[1] - (g.oy + cy * g.h)) * g.sq) : far;
-      const CT zz = valid ? (CT)((zt[2] - (g.oz + cz * g.h)) * g.sq) : far;
-      cell_segment<CT, FD, CUT>(xr, xs, a, bnd, zx, zy, zz, mj, rc2, acc, within);
-      examined += (unsigned long long)(bnd - a) * (unsigned long long)nvalid;
-    }
-    base += chunk_total;
   }
+  const unsigned long long examined = (unsigned long long)span * (unsigned long long)cn;
   if (!CUT) within = examined;
 
   double W, Dx, Dy, Dz;
@@ -693,16 +1091,15 @@ __global__ __launch_bounds__(256) void k_iterate(const ReqStatic* __restrict__ r
   Dx *= isq;
   Dy *= isq;
   Dz *= isq;
-  // omega contribution: sum_i w (x_i x z~_j) = z~_j x D_j with D_j = sum_i w (z~_j - x_i)
+  // sum_i w (x_i x z~_j) = z~_j x D_j with D_j = sum_i w (z~_j - x_i)
   const double ox = zt[1] * Dz - zt[2] * Dy;
   const double oy = zt[2] * Dx - zt[0] * Dz;
   const double oz = zt[0] * Dy - zt[1] * Dx;
 
-  if (R.mode == kModeEvalTargets && R.per_target && valid) {
-    const int stg = stage;
-    const double ell = R.stage_ell[stg];
+  if (R.mode == kModeEvalTargets && R.per_target && valid && w == 0) {
+    const double ell = R.stage_ell[stage];
     const double il2 = 1.0 / (ell * ell);
-    double* o = R.per_target + (size_t)R.zorig[j] * 7;
+    double* o = R.per_target + (size_t)R.zorig[s0 + l] * 7;
     o[0] = R.s2f * W;
     o[1] = R.s2f * ox * il2 / S->a2;
     o[2] = R.s2f * oy * il2 / S->a2;
@@ -712,28 +1109,34 @@ __global__ __launch_bounds__(256) void k_iterate(const ReqStatic* __restrict__ r
     o[6] = R.s2f * Dz * il2 / R.b2;
   }
 
-  const double sW = wave_sum(W), sox = wave_sum(ox), soy = wave_sum(oy), soz = wave_sum(oz);
-  const double sDx = wave_sum(Dx), sDy = wave_sum(Dy), sDz = wave_sum(Dz);
-  if (l == 0) {
-    double* sl = R.slots + (size_t)local * kSlot;
-    sl[0] = sW;
-    sl[1] = sox;
-    sl[2] = soy;
-    sl[3] = soz;
-    sl[4] = sDx;
-    sl[5] = sDy;
-    sl[6] = sDz;
-    sl[7] = (double)within;
-    atomicAdd(&S->pairs_examined, examined);
+  const double part[kSlot] = {wave_sum(W),  wave_sum(ox), wave_sum(oy),     wave_sum(oz),    wave_sum(Dx),
+                              wave_sum(Dy), wave_sum(Dz), (double)within, (double)examined};
+  if (l == 0)
+    for (int k = 0; k < kSlot; k++) parts[w][k] = part[k];
+  __syncthreads();
+  if (w == 0) {
+    // cluster partial: wave partials in fixed order
+    double cp[kSlot];
+#pragma unroll
+    for (int k = 0; k < kSlot; k++) cp[k] = (l < kPairWaves) ? parts[l][k] : 0.0;
+#pragma unroll
+    for (int k = 0; k < kSlot; k++) cp[k] = wave_sum(cp[k]);
+    if (l == 0) {
+      double* rs = R.rslots + (size_t)c * kSlot;
+      for (int k = 0; k < kSlot; k++) rs[k] = cp[k];
+    }
   }
-  __threadfence();
-  unsigned int old = 0;
-  if (l == 0) old = __hip_atomic_fetch_add(&S->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-  old = __shfl(old, 0, kWave);
-  if (old == (unsigned int)(R.n_items - 1)) {
-    __threadfence();
-    finish_request(R, S);
-  }
+}
+
+// Kernel C: one wave per request: the request's sum over its cluster partials
+// (fixed order, FP64), F, omega, v and the exponential-map step.
+__global__ __launch_bounds__(64) void k_step(const ReqStatic* __restrict__ reqs, int nreq) {
+  const int r = blockIdx.x;
+  if (r >= nreq) return;
+  const ReqStatic& R = reqs[r];
+  ReqState* S = R.state;
+  if (S->done) return;
+  finish_request(R, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -752,9 +1155,9 @@ __global__ void k_init_state(ReqState* __restrict__ S, const double* __restrict_
   S->done = 0;
   S->status = 0;
   S->converged = 0;
-  S->arrive = 0u;
+  S->reserved = 0u;
   S->bad_input = 0;
-  S->pad = 0;
+  S->nclus = 0;
 }
 
 __global__ __launch_bounds__(256) void k_check_finite(const float* __restrict__ p, long long count,
@@ -769,7 +1172,7 @@ __global__ __launch_bounds__(256) void k_check_finite(const float* __restrict__ 
 __global__ void k_setup_final(ReqState* __restrict__ S, const double* __restrict__ xbox, double a2_param) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (!(a2_param > 0.0)) S->a2 = xbox[6];
-  if (S->bad_input || !(S->a2 > 0.0) || !isfinite(S->a2)) {
+  if (S->bad_input || !(S->a2 > 0.0) || !isfinite(S->a2) || S->nclus < 1) {
     S->status = -1;  // invalid input
     S->done = 1;
   }
@@ -783,6 +1186,20 @@ static inline int blocks_for(long long work, int bs, int cap) {
   if (b < 1) b = 1;
   if (b > cap) b = cap;
   return (int)b;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const size_t words = bytes / 4;
+  if (words == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3(blocks_for((long long)words, 256, 4096)), dim3(256), 0, s, (unsigned*)p, words);
+  return hipGetLastError();
+}
+
+static void launch_scan(const ScanArgs* args, int nseg, long long maxlen, hipStream_t s) {
+  const int tiles = (int)((maxlen + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(k_scan_up, dim3(tiles, nseg), dim3(kScanBlock), 0, s, args);
+  hipLaunchKernelGGL(k_scan_mid, dim3(1, nseg), dim3(kScanBlock), 0, s, args);
+  hipLaunchKernelGGL(k_scan_down, dim3(tiles, nseg), dim3(kScanBlock), 0, s, args);
 }
 
 hipError_t launch_ingest(const IngestArgs& a, hipStream_t s) {
@@ -806,7 +1223,7 @@ hipError_t launch_ingest(const IngestArgs& a, hipStream_t s) {
   const int nseg = a.n_stages + 1;
   hipLaunchKernelGGL(k_sort_zero, dim3(blocks_for(a.max_kcap + 1LL, B, 2048), nseg), dim3(B), 0, s, a.segs);
   hipLaunchKernelGGL(k_sort_hist, dim3(blocks_for(a.max_seg_n, B, 1024), nseg), dim3(B), 0, s, a.segs);
-  hipLaunchKernelGGL(k_sort_scan, dim3(1, nseg), dim3(1024), 0, s, a.segs);
+  launch_scan(a.sort_scans, nseg, a.max_kcap + 1LL, s);
   hipLaunchKernelGGL(k_sort_scatter, dim3(blocks_for(a.max_seg_n, B, 1024), nseg), dim3(B), 0, s, a.segs);
   hipLaunchKernelGGL(k_sort_rank, dim3(blocks_for(a.max_seg_n, B, 1024), nseg), dim3(B), 0, s, a.segs);
   hipLaunchKernelGGL(k_tgt_records, dim3(blocks_for(a.m, B, 1024)), dim3(B), 0, s, a.tx, a.tfeat, a.m, a.fd, a.zs,
@@ -818,42 +1235,76 @@ hipError_t launch_ingest(const IngestArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_src_records<float>, dim3(blocks_for(a.n, B, 1024), a.n_stages), dim3(B), 0, s, a.sx,
                        a.sfeat, a.n, a.fd, a.xs, a.grid, a.src_keys, a.src_perm, (float* const*)a.xrec_dev);
   }
+  // target clusters
+  const int gm = blocks_for(a.m, B, 1024);
+  hipLaunchKernelGGL(k_cl_flags, dim3(gm), dim3(B), 0, s, a.zrec, a.zs, a.m, a.zbox, a.cl_flag, a.cl_scan);
+  launch_scan(a.cl_scan_args, 1, a.m, s);
+  hipLaunchKernelGGL(k_cl_segfirst, dim3(gm), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.m, a.cl_first);
+  hipLaunchKernelGGL(k_cl_cflags, dim3(gm), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.cl_first, a.m);
+  launch_scan(a.cl_scan_args, 1, a.m, s);
+  hipLaunchKernelGGL(k_cl_table, dim3(gm), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.m, a.clus_start, a.state);
+  hipLaunchKernelGGL(k_cl_count, dim3(gm), dim3(B), 0, s, a.clus_start, a.state, a.m, a.clus_count);
   hipLaunchKernelGGL(k_setup_final, dim3(1), dim3(1), 0, s, a.state, a.xbox, a.a2_param);
   return hipGetLastError();
 }
 
 template <typename CT, int FD>
-static void launch_it(bool cut, int blocks, const ReqStatic* reqs, const int* item_end, int nreq, int total,
-                      hipStream_t s) {
+static void launch_pairs(bool cut, int blocks, const ReqStatic* reqs, const int* clus_end, int nreq, int total,
+                         hipStream_t s) {
   if (cut)
-    hipLaunchKernelGGL((k_iterate<CT, FD, true>), dim3(blocks), dim3(256), 0, s, reqs, item_end, nreq, total);
+    hipLaunchKernelGGL((k_pairs<CT, FD, true>), dim3(blocks), dim3(kPairWaves * kWave), 0, s, reqs, clus_end, nreq,
+                       total);
   else
-    hipLaunchKernelGGL((k_iterate<CT, FD, false>), dim3(blocks), dim3(256), 0, s, reqs, item_end, nreq, total);
+    hipLaunchKernelGGL((k_pairs<CT, FD, false>), dim3(blocks), dim3(kPairWaves * kWave), 0, s, reqs, clus_end, nreq,
+                       total);
 }
 
 template <typename CT>
-static void launch_fd(int fd, bool cut, int blocks, const ReqStatic* reqs, const int* item_end, int nreq,
-                      int total, hipStream_t s) {
+static void launch_pairs_fd(int fd, bool cut, int blocks, const ReqStatic* reqs, const int* clus_end, int nreq,
+                            int total, hipStream_t s) {
   switch (fd) {
-    case 1: launch_it<CT, 1>(cut, blocks, reqs, item_end, nreq, total, s); break;
-    case 2: launch_it<CT, 2>(cut, blocks, reqs, item_end, nreq, total, s); break;
-    case 3: launch_it<CT, 3>(cut, blocks, reqs, item_end, nreq, total, s); break;
-    case 4: launch_it<CT, 4>(cut, blocks, reqs, item_end, nreq, total, s); break;
-    case 5: launch_it<CT, 5>(cut, blocks, reqs, item_end, nreq, total, s); break;
-    case 6: launch_it<CT, 6>(cut, blocks, reqs, item_end, nreq, total, s); break;
-    case 7: launch_it<CT, 7>(cut, blocks, reqs, item_end, nreq, total, s); break;
-    default: launch_it<CT, 8>(cut, blocks, reqs, item_end, nreq, total, s); break;
+    case 1: launch_pairs<CT, 1>(cut, blocks, reqs, clus_end, nreq, total, s); break;
+    case 2: launch_pairs<CT, 2>(cut, blocks, reqs, clus_end, nreq, total, s); break;
+    case 3: launch_pairs<CT, 3>(cut, blocks, reqs, clus_end, nreq, total, s); break;
+    case 4: launch_pairs<CT, 4>(cut, blocks, reqs, clus_end, nreq, total, s); break;
+    case 5: launch_pairs<CT, 5>(cut, blocks, reqs, clus_end, nreq, total, s); break;
+    case 6: launch_pairs<CT, 6>(cut, blocks, reqs, clus_end, nreq, total, s); break;
+    case 7: launch_pairs<CT, 7>(cut, blocks, reqs, clus_end, nreq, total, s); break;
+    default: launch_pairs<CT, 8>(cut, blocks, reqs, clus_end, nreq, total, s); break;
   }
 }
 
-hipError_t launch_iterate(int precision, int fd, bool cutoff, int blocks, const ReqStatic* reqs,
-                          const int* item_end, int nreq, int total_items, hipStream_t s) {
-  if (fd < 1 || fd > kMaxFeat || blocks < 1) return hipErrorInvalidValue;
-  if (precision == 1)
-    launch_fd<double>(fd, cutoff, blocks, reqs, item_end, nreq, total_items, s);
-  else
-    launch_fd<float>(fd, cutoff, blocks, reqs, item_end, nreq, total_items, s);
+hipError_t launch_prepare(const ReqStatic* reqs, const int* clus_end, int nreq, int total_clusters, hipStream_t s) {
+  if (total_clusters < 1) return hipErrorInvalidValue;
+  const int blocks = (total_clusters + kWavesPerBlock - 1) / kWavesPerBlock;
+  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, s, reqs, clus_end, nreq, total_clusters);
   return hipGetLastError();
+}
+
+hipError_t launch_pair_kernel(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end, int nreq,
+                              int total_clusters, hipStream_t s) {
+  if (fd < 1 || fd > kMaxFeat || total_clusters < 1) return hipErrorInvalidValue;
+  const int blocks = total_clusters;
+  if (precision == 1)
+    launch_pairs_fd<double>(fd, cutoff, blocks, reqs, clus_end, nreq, total_clusters, s);
+  else
+    launch_pairs_fd<float>(fd, cutoff, blocks, reqs, clus_end, nreq, total_clusters, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const ReqStatic* reqs, int nreq, hipStream_t s) {
+  if (nreq < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_step, dim3(nreq), dim3(64), 0, s, reqs, nreq);
+  return hipGetLastError();
+}
+
+hipError_t launch_iteration(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end, int nreq,
+                            int total_clusters, hipStream_t s) {
+  hipError_t e = launch_prepare(reqs, clus_end, nreq, total_clusters, s);
+  if (e != hipSuccess) return e;
+  e = launch_pair_kernel(precision, fd, cutoff, reqs, clus_end, nreq, total_clusters, s);
+  if (e != hipSuccess) return e;
+  return launch_step(reqs, nreq, s);
 }
 
 }  // namespace cvo
