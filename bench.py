@@ -36,6 +36,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-oracle", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--n", type=int, default=30000)
+    ap.add_argument("--no-events", action="store_true", help="time without the per-kernel HIP events")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -60,7 +61,7 @@ def main():
     torch.cuda.synchronize()
 
     ctx.kernel_stats(reset=True)
-    ctx.set_profiling(True)
+    ctx.set_profiling(not args.no_events)
     lat = []
     pairs = 0
     examined = 0

@@ -83,7 +83,7 @@ struct Layout {
 
 // per-cluster iteration buffers, sized once the cluster count is known
 struct LayoutB {
-  size_t off_cinfo, off_cells, off_rslots, off_trace, off_pt;
+  size_t off_cinfo, off_cells, off_sslots, off_trace, off_pt;
   size_t total;
 };
 
@@ -162,7 +162,7 @@ LayoutB plan_b(const Request& q, int nclus) {
   const size_t nc = (size_t)nclus;
   L.off_cinfo = take(sizeof(ClusInfo) * nc);
   L.off_cells = take(sizeof(CellEntry) * nc * kCellCap);
-  L.off_rslots = take(8 * nc * kSlot);
+  L.off_sslots = take(8 * nc * (kSlices / kWavesPerBlock) * kSlot);
   L.off_trace = q.trace_on ? take((size_t)q.max_iters * kTraceCols * 8) : 0;
   L.off_pt = (q.mode == kModeEvalTargets) ? take((size_t)q.m * 7 * 8) : 0;
   L.total = o;
@@ -435,7 +435,7 @@ static int finish_setup(cvo_ctx* c, Request& q, const Layout& L, const LayoutB& 
   st.grid = (const GridInfo*)(A + L.off_grid);
   st.cinfo = (ClusInfo*)(Bp + LB.off_cinfo);
   st.cells = (CellEntry*)(Bp + LB.off_cells);
-  st.rslots = (double*)(Bp + LB.off_rslots);
+  st.sslots = (double*)(Bp + LB.off_sslots);
   st.trace = q.trace_on ? (double*)(Bp + LB.off_trace) : nullptr;
   st.per_target = (q.mode == kModeEvalTargets) ? (double*)(Bp + LB.off_pt) : nullptr;
   st.m = q.m;

@@ -14,7 +14,8 @@ constexpr int kSlot = 9;            // doubles per partial: W, omega[3], D[3], p
 constexpr int kTraceCols = 26;      // F, omega[3], v[3], tau, ell, pairs, T[16] after the step
 constexpr int kZBits = 6;           // Morton bits per axis for the target spatial order
 constexpr int kZBuckets = 1 << (3 * kZBits);
-constexpr int kPairWaves = 8;       // wavefronts (candidate slices) per target cluster in the pair kernel
+constexpr int kSlices = 16;         // candidate slices (one wavefront each) per target cluster, at most
+constexpr int kSliceMin = 256;      // candidate sources per slice below which slices are merged
 constexpr int kCellCap = 512;       // cell-list entries per cluster; beyond: box enumeration
 constexpr int kMaxDim = 2047;       // cells per grid axis (packed coordinates use 11 bits)
 constexpr int kStage32 = 128;       // sources staged in LDS per round and wave (FP32 path)
@@ -51,7 +52,7 @@ struct ClusInfo {
   int total;     // candidate sources of the cluster
   int ncells;    // list entries (may exceed kCellCap: then overflow)
   int overflow;  // 1: the pair kernel enumerates the candidate box itself
-  int pad;
+  int nslices;   // wavefronts sharing the cluster's candidates (1..kSlices)
 };
 
 struct ReqState;
@@ -68,7 +69,7 @@ struct ReqStatic {
   const GridInfo* grid;              // [n_stages]
   ClusInfo* cinfo;                   // [nclus]
   CellEntry* cells;                  // [nclus][kCellCap]
-  double* rslots;                    // [nclus][kSlot] cluster partials
+  double* sslots;                    // [nclus][kSlices / kWavesPerBlock][kSlot] block partials
   double* trace;                     // [max_iters][kTraceCols] or null
   double* per_target;                // [m][7] or null (per-target terms, eval-targets mode)
   int m, n, fd, zs, xs, nclus;

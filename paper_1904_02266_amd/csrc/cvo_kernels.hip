@@ -5,17 +5,18 @@
 //              z~_j = T z_j in FP64, cluster bounding box and sphere, the
 //              compacted list of reachable non-empty source cells of the
 //              current length-scale grid, candidate count, work chunks.
-//   k_pairs    one workgroup per cluster; each wavefront stages its slice of
-//              the cluster's candidate sources in LDS (cluster-relative FP32
-//              coordinates) and pairs them, at a wave-uniform LDS address,
-//              with the cluster's targets (one per lane), FP32 pair terms
+//   k_pairs    one wavefront per (cluster, slice of the cluster's candidate
+//              sources, up to 16 slices): the slice is staged in the wave's
+//              LDS area (cluster-relative FP32 coordinates) and paired, at a
+//              wave-uniform LDS address, with the cluster's targets (one per
+//              lane), FP32 pair terms
 //                  d = z~_j - x_i, r^2, e = exp(-r^2/(2 l^2)), c = <l_i, m_j>,
 //                  W_j += c e, D_j += c e d          (eq. scalar, eq. 3_gradient)
-//              with compensated (Kahan) FP32 partials per lane, FP64 wave
-//              reductions and a fixed-order combination of the wave partials
-//              in LDS into one slot per cluster.
-//   k_step     one wavefront per request: fixed-order FP64 sum of the cluster
-//              partials, F, omega, v and the FP64 exponential-map step
+//              with compensated (Kahan) FP32 partials per lane, an FP64
+//              wave reduction, and the block's four slices summed in order
+//              into one slot per (cluster, block).
+//   k_step     one block per request: a fixed FP64 reduction tree over the
+//              block slots, F, omega, v and the FP64 exponential-map step
 //              (eq. step, eq. newstep) applied to the pose.
 //
 // Set-up kernels (once per registration): bounding boxes and the default
@@ -739,7 +740,7 @@ __device__ __forceinline__ void cand_cell(const GridInfo& g, const CandBox& B, c
 }
 
 // Kernel A: per target cluster, the compacted list of reachable non-empty
-// source cells and the candidate count.
+// source cells, the candidate count and the number of slices.
 __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ reqs, const int* __restrict__ clus_end,
                                                  int nreq, int total_clusters) {
   const int lc = uniform(logical_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
@@ -779,12 +780,15 @@ __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ r
     nl += __popcll(ne);
     total += uniform(__shfl(incl, kWave - 1, kWave));
   }
+  int ns = (total + kSliceMin - 1) / kSliceMin;
+  ns = ns < 1 ? 1 : (ns > kSlices ? kSlices : ns);
+  if (R.mode == kModeEvalTargets) ns = 1;  // per-target outputs need all sources of a target in one wave
   if (l == 0) {
     ClusInfo ci;
     ci.total = total;
     ci.ncells = nl;
     ci.overflow = nl > kCellCap ? 1 : 0;
-    ci.pad = 0;
+    ci.nslices = ns;
     R.cinfo[c] = ci;
   }
 }
@@ -816,27 +820,9 @@ __device__ __forceinline__ void run_cell(const GridInfo& g, cptr<CT> xr, int xs,
   cell_segment<CT, FD, CUT>(xr, xs, a, b, zx, zy, zz, mj, rc2, acc, within);
 }
 
-// sum of kSlot doubles over the first n lanes' rows p[lane*kSlot..], fixed order
-__device__ __forceinline__ void wave_reduce_rows(const double* __restrict__ p, int n, double (&out)[kSlot]) {
-  const int l = lane_id();
-  for (int q = 0; q < kSlot; q++) out[q] = 0.0;
-  for (int it = l; it < n; it += kWave) {
-    const double* row = p + (size_t)it * kSlot;
-    double v[kSlot];
-#pragma unroll
-    for (int q = 0; q < kSlot; q++) v[q] = row[q];
-#pragma unroll
-    for (int q = 0; q < kSlot; q++) out[q] += v[q];
-  }
-#pragma unroll
-  for (int q = 0; q < kSlot; q++) out[q] = wave_sum(out[q]);
-}
-
-// The request's final reduction and step (one wave per request).
-__device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S) {
-  double acc[kSlot];
-  wave_reduce_rows(R.rslots, R.nclus, acc);
-  if (lane_id() != 0) return;
+// F, omega, v from the request's summed terms, and the exponential-map step
+// (one thread).
+__device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S, const double (&acc)[kSlot]) {
   const int stage = S->stage;
   const double ell = R.stage_ell[stage];
   const double il2 = 1.0 / (ell * ell);
@@ -1001,34 +987,39 @@ __device__ __forceinline__ void pairs_from_list(const ReqStatic& R, const GridIn
   }
 }
 
-// Kernel B: one workgroup per target cluster, kPairWaves wavefronts, each
-// owning a contiguous slice of the cluster's candidate sources.  Wave partials
-// are combined through LDS in fixed order and the cluster partial goes to a
-// fixed slot; no device-scope synchronisation is needed inside the kernel.
+// Kernel B: one wavefront per (cluster, slice): the slice's contiguous range
+// of the cluster's candidate sources, staged in the wave's LDS area, against
+// the cluster's targets (one per lane).  The four slices of a block are summed
+// in slice order into a fixed slot; no synchronisation across workgroups is
+// needed inside the kernel.
 template <typename CT, int FD, bool CUT>
-__global__ __launch_bounds__(kPairWaves * kWave) void k_pairs(const ReqStatic* __restrict__ reqs,
-                                                              const int* __restrict__ clus_end, int nreq,
-                                                              int total_clusters) {
+__global__ __launch_bounds__(kWavesPerBlock* kWave) void k_pairs(const ReqStatic* __restrict__ reqs,
+                                                                 const int* __restrict__ clus_end, int nreq,
+                                                                 int total_clusters) {
   constexpr int RS = RecStride<FD>::value;
   constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
-  __shared__ CT recs_all[kPairWaves][NR * RS];
-  __shared__ CellEntry ents_all[kPairWaves][kWave];
-  __shared__ double parts[kPairWaves][kSlot];
-  const int lc = logical_block();  // block-uniform
+  constexpr int BPC = kSlices / kWavesPerBlock;  // blocks per cluster
+  __shared__ CT recs_all[kWavesPerBlock][NR * RS];
+  __shared__ CellEntry ents_all[kWavesPerBlock][kWave];
+  __shared__ double parts[kWavesPerBlock][kSlot];
+  const int lb = logical_block();
+  const int lc = lb / BPC;  // block-uniform
   if (lc >= total_clusters) return;
+  const int bq = lb - lc * BPC;
+  const int w = threadIdx.x >> 6;
+  const int q = uniform(bq * kWavesPerBlock + w);
   const int r = find_request(clus_end, nreq, lc);
   const ReqStatic& R = reqs[r];
   ReqState* S = R.state;
   if (S->done) return;  // block-uniform
   const int c = lc - (r > 0 ? clus_end[r - 1] : 0);
-  const int w = threadIdx.x >> 6;
   const int l = lane_id();
   const ClusInfo ci = R.cinfo[c];
+  const int ns = uniform(ci.nslices);
+  // slices past the cluster's count do no work but join the block reduction
   const int total = uniform(ci.total);
-  // per-target outputs need every source of a target in one wave
-  const int nslices = (R.mode == kModeEvalTargets) ? 1 : kPairWaves;
-  const long long lo_s = (w < nslices) ? (long long)total * w / nslices : 0;
-  const long long hi_s = (w < nslices) ? (long long)total * (w + 1) / nslices : 0;
+  const long long lo_s = (q < ns) ? (long long)total * q / ns : 0;
+  const long long hi_s = (q < ns) ? (long long)total * (q + 1) / ns : 0;
 
   const int s0 = uniform(R.clus_start[c]);
   const int cn = uniform(R.clus_count[c]);
@@ -1096,7 +1087,7 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pairs(const ReqStatic* _
   const double oy = zt[2] * Dx - zt[0] * Dz;
   const double oz = zt[0] * Dy - zt[1] * Dx;
 
-  if (R.mode == kModeEvalTargets && R.per_target && valid && w == 0) {
+  if (R.mode == kModeEvalTargets && R.per_target && valid) {
     const double ell = R.stage_ell[stage];
     const double il2 = 1.0 / (ell * ell);
     double* o = R.per_target + (size_t)R.zorig[s0 + l] * 7;
@@ -1114,29 +1105,63 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pairs(const ReqStatic* _
   if (l == 0)
     for (int k = 0; k < kSlot; k++) parts[w][k] = part[k];
   __syncthreads();
-  if (w == 0) {
-    // cluster partial: wave partials in fixed order
-    double cp[kSlot];
-#pragma unroll
-    for (int k = 0; k < kSlot; k++) cp[k] = (l < kPairWaves) ? parts[l][k] : 0.0;
-#pragma unroll
-    for (int k = 0; k < kSlot; k++) cp[k] = wave_sum(cp[k]);
-    if (l == 0) {
-      double* rs = R.rslots + (size_t)c * kSlot;
-      for (int k = 0; k < kSlot; k++) rs[k] = cp[k];
-    }
+  if (threadIdx.x < kSlot) {
+    // the block's slices in slice order
+    double t = 0.0;
+    for (int ww = 0; ww < kWavesPerBlock; ww++) t += parts[ww][threadIdx.x];
+    R.sslots[((size_t)c * BPC + bq) * kSlot + threadIdx.x] = t;
   }
 }
 
-// Kernel C: one wave per request: the request's sum over its cluster partials
-// (fixed order, FP64), F, omega, v and the exponential-map step.
-__global__ __launch_bounds__(64) void k_step(const ReqStatic* __restrict__ reqs, int nreq) {
+// Kernel C: one 512-thread block per request.  Thread t sums the block rows
+// t, t + 512, ... in order; the 512 thread sums are combined by a fixed
+// tree (wave butterflies, then waves in order): a deterministic FP64
+// reduction, then the step.
+constexpr int kStepThreads = 512;
+__global__ __launch_bounds__(kStepThreads) void k_step(const ReqStatic* __restrict__ reqs, int nreq) {
   const int r = blockIdx.x;
   if (r >= nreq) return;
   const ReqStatic& R = reqs[r];
   ReqState* S = R.state;
-  if (S->done) return;
-  finish_request(R, S);
+  if (S->done) return;  // block-uniform
+  constexpr int NW = kStepThreads / kWave;
+  constexpr int BPC = kSlices / kWavesPerBlock;
+  __shared__ double wsum[NW][kSlot];
+  const int w = threadIdx.x >> 6;
+  const int l = lane_id();
+  const int nrows = R.nclus * BPC;
+  double acc[kSlot];
+#pragma unroll
+  for (int k = 0; k < kSlot; k++) acc[k] = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * kStepThreads < nrows; i += 4 * kStepThreads) {
+    double v[4][kSlot];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+      for (int k = 0; k < kSlot; k++) v[u][k] = R.sslots[(size_t)(i + u * kStepThreads) * kSlot + k];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+      for (int k = 0; k < kSlot; k++) acc[k] += v[u][k];
+  }
+  for (; i < nrows; i += kStepThreads)
+#pragma unroll
+    for (int k = 0; k < kSlot; k++) acc[k] += R.sslots[(size_t)i * kSlot + k];
+#pragma unroll
+  for (int k = 0; k < kSlot; k++) acc[k] = wave_sum(acc[k]);
+  if (l == 0)
+    for (int k = 0; k < kSlot; k++) wsum[w][k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot[kSlot];
+    for (int k = 0; k < kSlot; k++) {
+      double t = 0.0;
+      for (int ww = 0; ww < NW; ww++) t += wsum[ww][k];
+      tot[k] = t;
+    }
+    finish_request(R, S, tot);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1252,11 +1277,11 @@ template <typename CT, int FD>
 static void launch_pairs(bool cut, int blocks, const ReqStatic* reqs, const int* clus_end, int nreq, int total,
                          hipStream_t s) {
   if (cut)
-    hipLaunchKernelGGL((k_pairs<CT, FD, true>), dim3(blocks), dim3(kPairWaves * kWave), 0, s, reqs, clus_end, nreq,
+    hipLaunchKernelGGL((k_pairs<CT, FD, true>), dim3(blocks), dim3(kWavesPerBlock * kWave), 0, s, reqs, clus_end, nreq,
                        total);
   else
-    hipLaunchKernelGGL((k_pairs<CT, FD, false>), dim3(blocks), dim3(kPairWaves * kWave), 0, s, reqs, clus_end, nreq,
-                       total);
+    hipLaunchKernelGGL((k_pairs<CT, FD, false>), dim3(blocks), dim3(kWavesPerBlock * kWave), 0, s, reqs, clus_end,
+                       nreq, total);
 }
 
 template <typename CT>
@@ -1284,7 +1309,9 @@ hipError_t launch_prepare(const ReqStatic* reqs, const int* clus_end, int nreq, 
 hipError_t launch_pair_kernel(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end, int nreq,
                               int total_clusters, hipStream_t s) {
   if (fd < 1 || fd > kMaxFeat || total_clusters < 1) return hipErrorInvalidValue;
-  const int blocks = total_clusters;
+  const long long nb = (long long)total_clusters * (kSlices / kWavesPerBlock);
+  if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+  const int blocks = (int)nb;
   if (precision == 1)
     launch_pairs_fd<double>(fd, cutoff, blocks, reqs, clus_end, nreq, total_clusters, s);
   else
@@ -1294,7 +1321,7 @@ hipError_t launch_pair_kernel(int precision, int fd, bool cutoff, const ReqStati
 
 hipError_t launch_step(const ReqStatic* reqs, int nreq, hipStream_t s) {
   if (nreq < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_step, dim3(nreq), dim3(64), 0, s, reqs, nreq);
+  hipLaunchKernelGGL(k_step, dim3(nreq), dim3(kStepThreads), 0, s, reqs, nreq);
   return hipGetLastError();
 }
 
