@@ -1,0 +1,183 @@
+"""GPU parity at the benchmark's full sizes and on the batched serving path.
+
+* RGB-D 30k (the benchmark workload): full F, omega, v against the oracle at
+  poses of the GPU trajectory, in the launch configuration bench.py times.
+* Dense 300k: per-target terms of sampled targets against the oracle (each
+  sampled target's sum over all sources), with the cutoff and by brute force;
+  properties that hold at any size (swap symmetry, determinism).
+* Batched submit/poll: every request's result equals the synchronous path's
+  bitwise, alone and mixed with other requests; error paths.
+Tolerances as in test_gpu_parity (reading C12): 1e-5 relative on F,
+1e-5 of sum|terms| on omega and v; per-target F_j 2e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1904_02266_amd import (CVO_ENOMEM, CVO_ENOTFOUND, CVO_EINVAL, Context, CvoError, Params,
+                                  params_planes, params_rgbd, synth)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def check(g, ref, rtol=1e-5, what=""):
+    r, A = ref["g"], ref["abs"]
+    assert abs(g[0] - r[0]) <= rtol * r[0], (what, "F", g[0], r[0])
+    for k in range(1, 7):
+        assert abs(g[k] - r[k]) <= rtol * A[k], (what, k, g[k], r[k], (g[k] - r[k]) / A[k])
+
+
+@pytest.fixture(scope="module")
+def rgbd30k():
+    return synth.rgbd_pair(30000, 30000, seed=2)
+
+
+@pytest.fixture(scope="module")
+def dense300k():
+    return synth.rgbd_pair(300000, 300000, seed=3, select="random")
+
+
+def test_rgbd30k_full_eval_along_trajectory(ctx, rgbd30k):
+    import torch
+    p = rgbd30k
+    dev = torch.device("cuda:0")
+    t = [torch.from_numpy(a).to(dev) for a in (p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat)]
+    prm = params_rgbd(trace=True)
+    out = ctx.register(*t, prm)
+    tr = ctx.trace()
+    assert out["iters"] == 100 and tr.shape[0] == 100
+    a2 = oracle.mean_sqnorm(p.src_xyz)
+    for k in (0, 30, 60, 99):
+        Tk = np.eye(4) if k == 0 else tr[k - 1, 10:26].reshape(4, 4)
+        ref = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, Tk, ell=tr[k, 8], kappa=3.0, a2=a2)
+        check(tr[k, :7], ref, what=f"iter {k}")
+        assert abs(tr[k, 9] - ref["within"]) <= 1e-6 * ref["within"] + 50
+
+
+def test_dense300k_sampled_targets_cutoff(ctx, dense300k):
+    p = dense300k
+    T = p.T_true
+    prm = Params(stage_ell=(0.05,), cutoff_mult=3.0)
+    sel = np.random.default_rng(7).choice(p.tgt_xyz.shape[0], 48, replace=False).astype(np.int32)
+    out = ctx.eval_targets(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, prm, sel=sel)
+    ref = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=0.05, kappa=3.0, sel=sel,
+                      per_target=True)["per_target"]
+    nz = ref[:, 0] > 0
+    assert nz.sum() > 40
+    np.testing.assert_allclose(out[nz, 0], ref[nz, 0], rtol=2e-5)
+    # the gradient terms of a target: error against the target's own magnitude
+    scale = np.abs(ref[:, 1:]).max(axis=1, keepdims=True) + 1e-300
+    assert (np.abs(out[:, 1:] - ref[:, 1:]) <= 2e-5 * scale + 1e-12).all()
+
+
+def test_dense300k_sampled_targets_brute_force(ctx, dense300k):
+    p = dense300k
+    T = p.T_true
+    prm = Params(stage_ell=(0.1,), cutoff_mult=0.0)
+    sel = np.random.default_rng(8).choice(p.tgt_xyz.shape[0], 16, replace=False).astype(np.int32)
+    out = ctx.eval_targets(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, prm, sel=sel)
+    ref = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=0.1, kappa=0.0, sel=sel,
+                      per_target=True)["per_target"]
+    np.testing.assert_allclose(out[:, 0], ref[:, 0], rtol=2e-5)
+
+
+def test_dense300k_swap_symmetry_and_determinism(ctx, dense300k):
+    """F(T; X, Z) = F(T^-1; Z, X) at full size (the oracle cannot afford the
+    9e10-pair brute-force sum; the property holds at any size)."""
+    p = dense300k
+    T = p.T_true
+    prm = Params(stage_ell=(0.08,), cutoff_mult=3.0)
+    a = ctx.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, prm)
+    b = ctx.eval(p.tgt_xyz, p.tgt_feat, p.src_xyz, p.src_feat, synth.invert_rigid(T), prm)
+    assert abs(a[0] - b[0]) <= 2e-5 * a[0]
+    a2 = ctx.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, prm)
+    assert np.array_equal(a, a2)
+
+
+def _small_requests(k0, count):
+    reqs = []
+    for k in range(count):
+        n = 3000 + 1700 * k
+        m = 2500 + 1300 * ((k * 7) % count)
+        reqs.append(synth.rgbd_pair(n, m, seed=6000 + k0 + k))
+    return reqs
+
+
+def test_batched_equals_sync_alone_and_mixed():
+    prm = params_rgbd(max_iters=20, stage_iters=(5, 5, 5))
+    reqs = _small_requests(0, 6)
+    ctx = Context(0, max_slots=8)
+    try:
+        sync = [ctx.register(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm) for q in reqs]
+        # alone: one request at a time through the scheduler
+        alone = []
+        for q in reqs:
+            tk, keep = ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)
+            alone.append(ctx.poll(tk))
+        # mixed: all at once, plus unrelated traffic in between
+        extra = _small_requests(100, 3)
+        tks = []
+        for i, q in enumerate(reqs):
+            tks.append(ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)[0])
+            if i < len(extra):
+                e = extra[i]
+                ctx.submit(e.src_xyz, e.src_feat, e.tgt_xyz, e.tgt_feat,
+                           params_rgbd(max_iters=33, stage_iters=(3, 3, 3)))
+        mixed = [ctx.poll(t) for t in tks]
+    finally:
+        ctx.close()
+    for s, a, m in zip(sync, alone, mixed):
+        assert a["rc"] == 0 and m["rc"] == 0
+        assert a["iters"] == 20 and m["iters"] == 20
+        assert np.array_equal(s["T"], a["T"]) and np.array_equal(a["T"], m["T"])
+        assert s["F"] == a["F"] == m["F"]
+
+
+def test_serving_convergence_and_errors():
+    ctx = Context(0, hbm_budget=64 << 20, max_slots=4)
+    try:
+        q = synth.planes_pair(2000, seed=1)
+        prm = params_planes(max_iters=200, tol=1e-5)
+        tk, _ = ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)
+        out = ctx.poll(tk)
+        assert out["rc"] == 0 and out["converged"] and 5 < out["iters"] < 200
+        ref = ctx.register(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)
+        assert ref["iters"] == out["iters"] and np.array_equal(ref["T"], out["T"])
+        # the ticket is released once its terminal status has been reported
+        assert ctx.poll(tk)["rc"] == CVO_ENOTFOUND
+        # a request larger than the device-memory budget fails alone; the
+        # scheduler keeps serving the others
+        big = synth.rgbd_pair(200000, 200000, seed=6101, select="random")
+        tk2, _ = ctx.submit(big.src_xyz, big.src_feat, big.tgt_xyz, big.tgt_feat, prm)
+        tk3, _ = ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)
+        assert ctx.poll(tk2)["rc"] == CVO_ENOMEM
+        again = ctx.poll(tk3)
+        assert again["rc"] == 0 and np.array_equal(again["T"], out["T"])
+    finally:
+        ctx.close()
+
+
+def test_poll_unknown_ticket_and_pending():
+    ctx = Context(0)
+    try:
+        assert ctx.L.cvo_poll(ctx.h, 12345, 0, None, None) == CVO_ENOTFOUND
+        q = synth.rgbd_pair(20000, 20000, seed=6200)
+        prm = params_rgbd()
+        tk, _ = ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)
+        first = ctx.poll(tk, wait_us=0)  # usually still running
+        out = first if first is not None else ctx.poll(tk)
+        assert out["rc"] == 0 and out["iters"] == 100
+        bad = q.src_xyz.copy()
+        bad[0, 0] = np.nan
+        with pytest.raises(CvoError) as e:
+            ctx.submit(bad, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)
+        assert e.value.code == CVO_EINVAL
+    finally:
+        ctx.close()
