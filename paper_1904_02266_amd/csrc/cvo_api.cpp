@@ -162,7 +162,7 @@ LayoutB plan_b(const Request& q, int nclus) {
   const size_t nc = (size_t)nclus;
   L.off_cinfo = take(sizeof(ClusInfo) * nc);
   L.off_cells = take(sizeof(CellEntry) * nc * kCellCap);
-  L.off_sslots = take(8 * nc * (kSlices / kWavesPerBlock) * kSlot);
+  L.off_sslots = take(8 * nc * kBlocksPerCluster * kSlot);
   L.off_trace = q.trace_on ? take((size_t)q.max_iters * kTraceCols * 8) : 0;
   L.off_pt = (q.mode == kModeEvalTargets) ? take((size_t)q.m * 7 * 8) : 0;
   L.total = o;

@@ -16,6 +16,9 @@ constexpr int kZBits = 6;           // Morton bits per axis for the target spati
 constexpr int kZBuckets = 1 << (3 * kZBits);
 constexpr int kSlices = 16;         // candidate slices (one wavefront each) per target cluster, at most
 constexpr int kSliceMin = 256;      // candidate sources per slice below which slices are merged
+constexpr int kPairBlockWaves = 4;  // slices per pair-kernel workgroup
+constexpr int kBlocksPerCluster = kSlices / kPairBlockWaves;
+constexpr int kXcds = 8;            // accelerator complex dies; workgroup b runs on die b mod 8
 constexpr int kCellCap = 512;       // cell-list entries per cluster; beyond: box enumeration
 constexpr int kMaxDim = 2047;       // cells per grid axis (packed coordinates use 11 bits)
 constexpr int kStage32 = 128;       // sources staged in LDS per round and wave (FP32 path)
@@ -69,7 +72,7 @@ struct ReqStatic {
   const GridInfo* grid;              // [n_stages]
   ClusInfo* cinfo;                   // [nclus]
   CellEntry* cells;                  // [nclus][kCellCap]
-  double* sslots;                    // [nclus][kSlices / kWavesPerBlock][kSlot] block partials
+  double* sslots;                    // [nclus][kBlocksPerCluster][kSlot] block partials
   double* trace;                     // [max_iters][kTraceCols] or null
   double* per_target;                // [m][7] or null (per-target terms, eval-targets mode)
   int m, n, fd, zs, xs, nclus;

@@ -893,18 +893,44 @@ struct RecStride {
   static constexpr int value = (3 + FD + 3) / 4 * 4;
 };
 
-// Candidate sources [lo_s, hi_s) of the cluster's list, staged round by round
-// into the wave's LDS area as coordinates relative to the cluster origin (the
-// first target, FP64), rounded once to CT, then paired with every lane's
-// target.  The pair loop reads each source at a wave-uniform LDS address.
+__device__ __forceinline__ unsigned long long wave_or(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned lo = __shfl_xor((unsigned)v, o, kWave), hi = __shfl_xor((unsigned)(v >> 32), o, kWave);
+    v |= ((unsigned long long)hi << 32) | lo;
+  }
+  return v;
+}
+
+// A batch of up to 64 consecutive candidate positions of a slice, one per
+// lane, with the lane's raw source record in flight.
+template <typename CT, int FD>
+struct Batch {
+  long long end;  // one past the batch's last position
+  bool live;      // this lane's position is inside the batch
+  int cell;       // packed cell coordinates of the lane's source
+  CT raw[3 + FD];
+};
+
+// Candidate sources [lo_s, hi_s) of the cluster's list, 64 at a time (one
+// per lane), software-pipelined: the records of the next batch are requested
+// before the current one is processed.  Each record is moved to coordinates
+// relative to the cluster origin (the first target; FP64 arithmetic, one
+// rounding to CT) and, with the cutoff, kept only if it lies within the
+// cutoff of the cluster's bounding box.  Survivors are compacted into the
+// wave's LDS area; every full round is paired with every lane's target,
+// reading each source at a wave-uniform LDS address.  The list window (64
+// cell entries, one per lane) stays in registers; a position's entry is
+// found from a bitmask of the entry boundaries inside the batch.  Returns the
+// number of sources paired.
 template <typename CT, int FD, bool CUT>
-__device__ __forceinline__ void pairs_from_list(const ReqStatic& R, const GridInfo& g, const ClusInfo& ci, int c,
-                                                long long lo_s, long long hi_s, const double (&zt)[3], bool valid,
-                                                const CT (&mj)[FD], CT rc2, Acc<CT>& acc,
-                                                unsigned long long& within, cptr<CT> xr, int xs, CT* recs,
-                                                CellEntry* ents) {
+__device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const GridInfo& g, const ClusInfo& ci, int c,
+                                                     long long lo_s, long long hi_s, const double (&zt)[3], bool valid,
+                                                     const CT (&mj)[FD], CT rc2, Acc<CT>& acc,
+                                                     unsigned long long& within, cptr<CT> xr, int xs, CT* recs) {
   constexpr int RS = RecStride<FD>::value;
   constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
+  static_assert(NR % kWave == 0 && NR >= kWave, "a staging round holds at least one batch");
   const int l = lane_id();
   const CellEntry* __restrict__ list = uniform_ptr(R.cells + (size_t)c * kCellCap);
   const int nl = uniform(ci.ncells);
@@ -914,77 +940,145 @@ __device__ __forceinline__ void pairs_from_list(const ReqStatic& R, const GridIn
   const CT zx = valid ? (CT)((zt[0] - O[0]) * g.sq) : far;
   const CT zy = valid ? (CT)((zt[1] - O[1]) * g.sq) : far;
   const CT zz = valid ? (CT)((zt[2] - O[2]) * g.sq) : far;
+  // cluster bounding box in the same coordinates; a source farther than the
+  // cutoff from it cannot pair with any target (threshold widened by a
+  // relative 1e-4 so that no pair the per-pair test accepts is dropped)
+  CT blo[3], bhi[3];
+  {
+    const CT zc[3] = {zx, zy, zz};
+    for (int a = 0; a < 3; a++) {
+      blo[a] = (CT)wave_min(valid ? (double)zc[a] : INFINITY);
+      bhi[a] = (CT)wave_max(valid ? (double)zc[a] : -INFINITY);
+    }
+  }
+  const CT cull2 = rc2 * (CT)1.0001 + (CT)1e-6;
   // offset of cell (0,0,0) from the origin, in scaled units
   const double base[3] = {(g.ox - O[0]) * g.sq, (g.oy - O[1]) * g.sq, (g.oz - O[2]) * g.sq};
   const double hs = g.h * g.sq;
-  int e0 = uniform(locate_entry(list, nl, lo_s));
-  long long pos = lo_s;
-  while (pos < hi_s && e0 < nl) {
-    const int navail = uniform(min(kWave, nl - e0));
-    CellEntry me;
+  const CT* xg0 = (const CT*)xr;
+
+  // entry window: lane k holds entry we0 + k
+  int we0 = uniform(locate_entry(list, nl, lo_s));
+  int navail = 0;
+  long long win_end = 0;
+  CellEntry me;
+  auto load_window = [&]() {
+    navail = uniform(min(kWave, nl - we0));
     if (l < navail) {
-      me = list[e0 + l];
+      me = list[we0 + l];
     } else {
       me.cell = 0;
       me.first = 0;
       me.count = 0;
       me.end = 0x7fffffff;
     }
-    ents[l] = me;
-    const long long last_end = uniform(__shfl(me.end, navail - 1, kWave));
-    long long rend = pos + NR;
-    if (rend > hi_s) rend = hi_s;
-    if (rend > last_end) rend = last_end;
-    const int nrec = (int)(rend - pos);
-    wave_lds_sync();
-    for (int s = l; s < nrec; s += kWave) {
-      const long long p = pos + s;
-      int lo = 0, hi = navail - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((long long)ents[mid].end > p) hi = mid;
-        else lo = mid + 1;
-      }
-      const CellEntry E = ents[lo];
-      const int src = E.first + (int)(p - ((long long)E.end - E.count));
-      const int cx = E.cell & 2047, cy = (E.cell >> 11) & 2047, cz = (E.cell >> 22) & 2047;
-      const CT* xg = (const CT*)xr + (size_t)src * xs;
-      CT* dst = recs + s * RS;
-      dst[0] = (CT)((double)xg[0] + (base[0] + cx * hs));
-      dst[1] = (CT)((double)xg[1] + (base[1] + cy * hs));
-      dst[2] = (CT)((double)xg[2] + (base[2] + cz * hs));
+    win_end = (navail > 0) ? (long long)uniform(__shfl(me.end, navail - 1, kWave)) : hi_s;
+  };
+  // request the records of the batch starting at pos
+  auto start_batch = [&](long long pos, Batch<CT, FD>& B) {
+    long long bend = pos + kWave;
+    if (bend > hi_s) bend = hi_s;
+    if (bend > win_end) bend = win_end;
+    B.end = bend;
+    const long long p = pos + l;
+    B.live = p < bend;
+    // entries of the window that end at or before pos, and the entry
+    // boundaries inside the batch
+    const long long bk = (long long)me.end - pos;
+    const int eoff = __popcll(__ballot(l < navail && bk <= 0));
+    const unsigned long long M = wave_or((l < navail && bk >= 1 && bk <= kWave - 1) ? (1ull << bk) : 0ull);
+    const unsigned long long upto = (l == kWave - 1) ? ~1ull : ((2ull << l) - 2ull);  // bits 1..l
+    int ei = eoff + __popcll(M & upto);
+    ei = ei < navail - 1 ? ei : navail - 1;
+    const int efirst = __shfl(me.first, ei, kWave);
+    const int ecount = __shfl(me.count, ei, kWave);
+    const int eend = __shfl(me.end, ei, kWave);
+    B.cell = __shfl(me.cell, ei, kWave);
+    if (B.live) {
+      const int src = efirst + (int)(p - ((long long)eend - ecount));
+      const CT* xg = xg0 + (size_t)src * xs;
 #pragma unroll
-      for (int f = 0; f < FD; f++) dst[3 + f] = xg[3 + f];
+      for (int q = 0; q < 3 + FD; q++) B.raw[q] = xg[q];
     }
+  };
+
+  long long paired = 0;
+  int count = 0;  // staged survivors
+  auto flush = [&]() {
     wave_lds_sync();
-    // pairs: every lane's target against the staged sources
     constexpr int U = 4;
-    for (int b0 = 0; b0 < nrec; b0 += kBlock) {
-      const int b1 = min(b0 + kBlock, nrec);
+    for (int b0 = 0; b0 < count; b0 += kBlock) {
+      const int b1 = min(b0 + kBlock, count);
       int i = b0;
       for (; i + U <= b1; i += U) {
-        CT rec[U][3 + FD];
+        CT r4[U][3 + FD];
 #pragma unroll
         for (int u = 0; u < U; u++)
 #pragma unroll
-          for (int q = 0; q < 3 + FD; q++) rec[u][q] = recs[(i + u) * RS + q];
+          for (int q = 0; q < 3 + FD; q++) r4[u][q] = recs[(i + u) * RS + q];
 #pragma unroll
-        for (int u = 0; u < U; u++) one_pair<CT, FD, CUT>(rec[u], zx, zy, zz, mj, rc2, acc, within);
+        for (int u = 0; u < U; u++) one_pair<CT, FD, CUT>(r4[u], zx, zy, zz, mj, rc2, acc, within);
       }
       for (; i < b1; i++) {
-        CT rec[3 + FD];
+        CT r1[3 + FD];
 #pragma unroll
-        for (int q = 0; q < 3 + FD; q++) rec[q] = recs[i * RS + q];
-        one_pair<CT, FD, CUT>(rec, zx, zy, zz, mj, rc2, acc, within);
+        for (int q = 0; q < 3 + FD; q++) r1[q] = recs[i * RS + q];
+        one_pair<CT, FD, CUT>(r1, zx, zy, zz, mj, rc2, acc, within);
       }
       acc.fold();
     }
+    paired += count;
+    count = 0;
     wave_lds_sync();
-    // entries fully consumed by this round
-    const unsigned long long done_mask = __ballot(l < navail && (long long)me.end <= rend);
-    e0 += __popcll(done_mask);
-    pos = rend;
+  };
+
+  load_window();
+  if (navail <= 0) return 0;
+  Batch<CT, FD> A, B;
+  start_batch(lo_s, A);
+  long long pos = A.end;
+  for (;;) {
+    const bool more = pos < hi_s;
+    if (more) {
+      if (pos >= win_end) {
+        we0 += navail;
+        load_window();
+      }
+      start_batch(pos, B);
+      pos = B.end;
+    }
+    // cull and stage batch A
+    bool keep = false;
+    CT rec[3 + FD];
+    if (A.live) {
+      const int cx = A.cell & 2047, cy = (A.cell >> 11) & 2047, cz = (A.cell >> 22) & 2047;
+      rec[0] = (CT)((double)A.raw[0] + (base[0] + cx * hs));
+      rec[1] = (CT)((double)A.raw[1] + (base[1] + cy * hs));
+      rec[2] = (CT)((double)A.raw[2] + (base[2] + cz * hs));
+#pragma unroll
+      for (int f = 0; f < FD; f++) rec[3 + f] = A.raw[3 + f];
+      keep = true;
+      if (CUT) {
+        CT d2 = 0;
+        for (int a = 0; a < 3; a++) {
+          const CT d = rec[a] < blo[a] ? blo[a] - rec[a] : (rec[a] > bhi[a] ? rec[a] - bhi[a] : (CT)0);
+          d2 += d * d;
+        }
+        keep = d2 <= cull2;
+      }
+    }
+    const unsigned long long km = __ballot(keep);
+    if (keep) {
+      CT* dst = recs + (count + __popcll(km & ((1ull << l) - 1ull))) * RS;
+#pragma unroll
+      for (int q = 0; q < 3 + FD; q++) dst[q] = rec[q];
+    }
+    count += __popcll(km);
+    if (count > NR - kWave || (!more && count > 0)) flush();
+    if (!more) break;
+    A = B;
   }
+  return paired;
 }
 
 // Kernel B: one wavefront per (cluster, slice): the slice's contiguous range
@@ -993,21 +1087,25 @@ __device__ __forceinline__ void pairs_from_list(const ReqStatic& R, const GridIn
 // in slice order into a fixed slot; no synchronisation across workgroups is
 // needed inside the kernel.
 template <typename CT, int FD, bool CUT>
-__global__ __launch_bounds__(kWavesPerBlock* kWave) void k_pairs(const ReqStatic* __restrict__ reqs,
-                                                                 const int* __restrict__ clus_end, int nreq,
-                                                                 int total_clusters) {
+__global__ __launch_bounds__(kPairBlockWaves* kWave) void k_pairs(const ReqStatic* __restrict__ reqs,
+                                                                  const int* __restrict__ clus_end, int nreq,
+                                                                  int total_clusters) {
   constexpr int RS = RecStride<FD>::value;
   constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
-  constexpr int BPC = kSlices / kWavesPerBlock;  // blocks per cluster
-  __shared__ CT recs_all[kWavesPerBlock][NR * RS];
-  __shared__ CellEntry ents_all[kWavesPerBlock][kWave];
-  __shared__ double parts[kWavesPerBlock][kSlot];
-  const int lb = logical_block();
-  const int lc = lb / BPC;  // block-uniform
-  if (lc >= total_clusters) return;
-  const int bq = lb - lc * BPC;
+  __shared__ CT recs_all[kPairBlockWaves][NR * RS];
+  __shared__ double parts[kPairBlockWaves][kSlot];
+  // Block placement: workgroup b runs on die b mod 8.  Cluster c goes to die
+  // c mod 8, so dense regions (contiguous in the Morton order) spread over
+  // all dies; on each die, blocks are ordered slice-block-major, so the first
+  // block of every cluster (always in use) is dispatched before any second
+  // block (in use only for clusters with many candidates).
+  const int die = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+  const int per_die = (total_clusters + kXcds - 1) / kXcds;
+  const int bq = j / per_die;
+  const int lc = (j - bq * per_die) * kXcds + die;  // block-uniform
+  if (lc >= total_clusters || bq >= kBlocksPerCluster) return;
   const int w = threadIdx.x >> 6;
-  const int q = uniform(bq * kWavesPerBlock + w);
+  const int q = uniform(bq * kPairBlockWaves + w);
   const int r = find_request(clus_end, nreq, lc);
   const ReqStatic& R = reqs[r];
   ReqState* S = R.state;
@@ -1016,6 +1114,11 @@ __global__ __launch_bounds__(kWavesPerBlock* kWave) void k_pairs(const ReqStatic
   const int l = lane_id();
   const ClusInfo ci = R.cinfo[c];
   const int ns = uniform(ci.nslices);
+  if (bq * kPairBlockWaves >= ns) {
+    // no slice of this block is in use: its row is zero
+    if (threadIdx.x < kSlot) R.sslots[((size_t)c * kBlocksPerCluster + bq) * kSlot + threadIdx.x] = 0.0;
+    return;
+  }
   // slices past the cluster's count do no work but join the block reduction
   const int total = uniform(ci.total);
   const long long lo_s = (q < ns) ? (long long)total * q / ns : 0;
@@ -1042,9 +1145,8 @@ __global__ __launch_bounds__(kWavesPerBlock* kWave) void k_pairs(const ReqStatic
   long long span = 0;
   if (lo_s < hi_s) {
     if (!uniform(ci.overflow)) {
-      pairs_from_list<CT, FD, CUT>(R, g, ci, c, lo_s, hi_s, zt, valid, mj, rc2, acc, within, xr, xs, recs_all[w],
-                                   ents_all[w]);
-      span = hi_s - lo_s;
+      span = pairs_from_list<CT, FD, CUT>(R, g, ci, c, lo_s, hi_s, zt, valid, mj, rc2, acc, within, xr, xs,
+                                          recs_all[w]);
     } else {
       // the list overflowed: enumerate the candidate box again in the same order
       const int* __restrict__ cs = uniform_ptr(R.cstart[stage]);
@@ -1108,8 +1210,8 @@ __global__ __launch_bounds__(kWavesPerBlock* kWave) void k_pairs(const ReqStatic
   if (threadIdx.x < kSlot) {
     // the block's slices in slice order
     double t = 0.0;
-    for (int ww = 0; ww < kWavesPerBlock; ww++) t += parts[ww][threadIdx.x];
-    R.sslots[((size_t)c * BPC + bq) * kSlot + threadIdx.x] = t;
+    for (int ww = 0; ww < kPairBlockWaves; ww++) t += parts[ww][threadIdx.x];
+    R.sslots[((size_t)c * kBlocksPerCluster + bq) * kSlot + threadIdx.x] = t;
   }
 }
 
@@ -1125,7 +1227,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const ReqStatic* __restri
   ReqState* S = R.state;
   if (S->done) return;  // block-uniform
   constexpr int NW = kStepThreads / kWave;
-  constexpr int BPC = kSlices / kWavesPerBlock;
+  constexpr int BPC = kBlocksPerCluster;
   __shared__ double wsum[NW][kSlot];
   const int w = threadIdx.x >> 6;
   const int l = lane_id();
@@ -1277,10 +1379,10 @@ template <typename CT, int FD>
 static void launch_pairs(bool cut, int blocks, const ReqStatic* reqs, const int* clus_end, int nreq, int total,
                          hipStream_t s) {
   if (cut)
-    hipLaunchKernelGGL((k_pairs<CT, FD, true>), dim3(blocks), dim3(kWavesPerBlock * kWave), 0, s, reqs, clus_end, nreq,
-                       total);
+    hipLaunchKernelGGL((k_pairs<CT, FD, true>), dim3(blocks), dim3(kPairBlockWaves * kWave), 0, s, reqs, clus_end,
+                       nreq, total);
   else
-    hipLaunchKernelGGL((k_pairs<CT, FD, false>), dim3(blocks), dim3(kWavesPerBlock * kWave), 0, s, reqs, clus_end,
+    hipLaunchKernelGGL((k_pairs<CT, FD, false>), dim3(blocks), dim3(kPairBlockWaves * kWave), 0, s, reqs, clus_end,
                        nreq, total);
 }
 
@@ -1309,7 +1411,7 @@ hipError_t launch_prepare(const ReqStatic* reqs, const int* clus_end, int nreq, 
 hipError_t launch_pair_kernel(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end, int nreq,
                               int total_clusters, hipStream_t s) {
   if (fd < 1 || fd > kMaxFeat || total_clusters < 1) return hipErrorInvalidValue;
-  const long long nb = (long long)total_clusters * (kSlices / kWavesPerBlock);
+  const long long nb = (long long)(total_clusters + kXcds - 1) / kXcds * kXcds * kBlocksPerCluster;
   if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
   const int blocks = (int)nb;
   if (precision == 1)
