@@ -83,7 +83,7 @@ struct Layout {
 
 // per-cluster iteration buffers, sized once the cluster count is known
 struct LayoutB {
-  size_t off_cinfo, off_cells, off_sslots, off_trace, off_pt;
+  size_t off_cinfo, off_cells, off_sslots, off_csum, off_trace, off_pt;
   size_t total;
 };
 
@@ -162,7 +162,8 @@ LayoutB plan_b(const Request& q, int nclus) {
   const size_t nc = (size_t)nclus;
   L.off_cinfo = take(sizeof(ClusInfo) * nc);
   L.off_cells = take(sizeof(CellEntry) * nc * kCellCap);
-  L.off_sslots = take(8 * nc * kBlocksPerCluster * kSlot);
+  L.off_sslots = take(8 * nc * kChunksMax * kSlot);
+  L.off_csum = take(8 * nc * kSlot);
   L.off_trace = q.trace_on ? take((size_t)q.max_iters * kTraceCols * 8) : 0;
   L.off_pt = (q.mode == kModeEvalTargets) ? take((size_t)q.m * 7 * 8) : 0;
   L.total = o;
@@ -177,6 +178,45 @@ size_t footprint(const Request& q) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// work queue of the iteration launches on one stream
+// ---------------------------------------------------------------------------
+struct DevQueue {
+  WorkQueue* q = nullptr;
+  unsigned int* items = nullptr;
+  unsigned int cap = 0;
+  QueueRef ref() const { return QueueRef{q, items, cap}; }
+  // capacity for a launch over total_clusters clusters; false if out of memory
+  bool ensure(int total_clusters) {
+    if (!q && hipMalloc(&q, sizeof(WorkQueue)) != hipSuccess) {
+      q = nullptr;
+      return false;
+    }
+    const unsigned long long need = (unsigned long long)std::max(total_clusters, 1) * kChunksMax;
+    if (need > 0xffffffffull) return false;
+    if (need <= cap) return true;
+    const unsigned long long want = std::min<unsigned long long>(std::max<unsigned long long>(need, 2ull * cap), 0xffffffffull);
+    if (items) (void)hipFree(items);
+    items = nullptr;
+    cap = 0;
+    if (hipMalloc(&items, want * sizeof(unsigned int)) != hipSuccess) {
+      items = nullptr;
+      return false;
+    }
+    cap = (unsigned int)want;
+    return true;
+  }
+  // both counters to zero (before the first launch of a run on this stream)
+  hipError_t reset(hipStream_t s) const { return hipMemsetAsync(q, 0, sizeof(WorkQueue), s); }
+  void release() {
+    if (q) (void)hipFree(q);
+    if (items) (void)hipFree(items);
+    q = nullptr;
+    items = nullptr;
+    cap = 0;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // context
@@ -201,6 +241,7 @@ struct cvo_ctx {
   size_t sync_arena_b_bytes = 0;
   ReqStatic* d_reqs_sync = nullptr;
   int* d_clus_end_sync = nullptr;
+  DevQueue queue_sync;
   Request last_register;
   bool have_last = false;
 
@@ -436,6 +477,7 @@ static int finish_setup(cvo_ctx* c, Request& q, const Layout& L, const LayoutB& 
   st.cinfo = (ClusInfo*)(Bp + LB.off_cinfo);
   st.cells = (CellEntry*)(Bp + LB.off_cells);
   st.sslots = (double*)(Bp + LB.off_sslots);
+  st.csum = (double*)(Bp + LB.off_csum);
   st.trace = q.trace_on ? (double*)(Bp + LB.off_trace) : nullptr;
   st.per_target = (q.mode == kModeEvalTargets) ? (double*)(Bp + LB.off_pt) : nullptr;
   st.m = q.m;
@@ -557,6 +599,9 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
   HIPCHK(c, hipMemcpyAsync(c->d_reqs_sync, hst, sizeof(ReqStatic), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->d_clus_end_sync, hend, sizeof(int), hipMemcpyHostToDevice, s));
 
+  if (!c->queue_sync.ensure(q.nclus)) return CVO_ENOMEM;
+  HIPCHK(c, c->queue_sync.reset(s));
+  const QueueRef QR = c->queue_sync.ref();
   const bool cut = q.kappa > 0.0;
   const bool prof = c->profile && q.mode == kModeRegister;
   if (prof && (int)c->ev_pool.size() < 3 * q.max_iters) {
@@ -573,13 +618,13 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
     for (; k < kend; k++) {
       if (prof) {
         HIPCHK(c, hipEventRecord(c->ev_pool[3 * k], s));
-        HIPCHK(c, launch_prepare(c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, s));
+        HIPCHK(c, launch_prepare(c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR, s));
         HIPCHK(c, hipEventRecord(c->ev_pool[3 * k + 1], s));
-        HIPCHK(c, launch_pair_kernel(q.precision, q.fd, cut, c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, s));
+        HIPCHK(c, launch_pair_kernel(q.precision, q.fd, cut, c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR, s));
         HIPCHK(c, hipEventRecord(c->ev_pool[3 * k + 2], s));
-        HIPCHK(c, launch_step(c->d_reqs_sync, 1, s));
+        HIPCHK(c, launch_step(c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR, s));
       } else {
-        HIPCHK(c, launch_iteration(q.precision, q.fd, cut, c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, s));
+        HIPCHK(c, launch_iteration(q.precision, q.fd, cut, c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR, s));
       }
       launched++;
     }
@@ -681,6 +726,7 @@ void scheduler(cvo_ctx* c) {
   ReqStatic* h_reqs = nullptr;
   int* h_end = nullptr;
   ReqState* h_states = nullptr;
+  DevQueue queue;
   void* h_stage = nullptr;
   (void)hipHostMalloc(&h_stage, 64 * 1024, hipHostMallocDefault);
   const int chunk = 8;
@@ -754,13 +800,16 @@ void scheduler(cvo_ctx* c) {
       g.clusters = cl;
       gl.push_back(g);
     }
-    bool dev_ok = d_reqs && d_end && h_reqs && h_end && h_states &&
+    int most_clusters = 1;
+    for (const G& g : gl) most_clusters = std::max(most_clusters, g.clusters);
+    bool dev_ok = d_reqs && d_end && h_reqs && h_end && h_states && queue.ensure(most_clusters) &&
+                  queue.reset(s) == hipSuccess &&
                   hipMemcpyAsync(d_reqs, h_reqs, sizeof(ReqStatic) * nreq, hipMemcpyHostToDevice, s) == hipSuccess &&
                   hipMemcpyAsync(d_end, h_end, sizeof(int) * nreq, hipMemcpyHostToDevice, s) == hipSuccess;
     for (int it = 0; it < chunk && dev_ok; it++) {
       for (const G& g : gl) {
         if (launch_iteration(g.precision, g.fd, g.cut != 0, d_reqs + g.first, d_end + g.first, g.count, g.clusters,
-                             s) != hipSuccess)
+                             queue.ref(), s) != hipSuccess)
           dev_ok = false;
       }
     }
@@ -794,6 +843,7 @@ void scheduler(cvo_ctx* c) {
   if (h_end) (void)hipHostFree(h_end);
   if (h_states) (void)hipHostFree(h_states);
   if (h_stage) (void)hipHostFree(h_stage);
+  queue.release();
 }
 
 }  // namespace
@@ -841,6 +891,7 @@ int cvo_destroy(cvo_ctx* c) {
   if (c->sync_arena) (void)hipFree(c->sync_arena);
   if (c->d_reqs_sync) (void)hipFree(c->d_reqs_sync);
   if (c->d_clus_end_sync) (void)hipFree(c->d_clus_end_sync);
+  c->queue_sync.release();
   if (c->sync_arena_b) (void)hipFree(c->sync_arena_b);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);

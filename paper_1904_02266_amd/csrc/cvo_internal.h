@@ -14,11 +14,12 @@ constexpr int kSlot = 9;            // doubles per partial: W, omega[3], D[3], p
 constexpr int kTraceCols = 26;      // F, omega[3], v[3], tau, ell, pairs, T[16] after the step
 constexpr int kZBits = 6;           // Morton bits per axis for the target spatial order
 constexpr int kZBuckets = 1 << (3 * kZBits);
-constexpr int kSlices = 16;         // candidate slices (one wavefront each) per target cluster, at most
-constexpr int kSliceMin = 256;      // candidate sources per slice below which slices are merged
-constexpr int kPairBlockWaves = 4;  // slices per pair-kernel workgroup
-constexpr int kBlocksPerCluster = kSlices / kPairBlockWaves;
-constexpr int kXcds = 8;            // accelerator complex dies; workgroup b runs on die b mod 8
+constexpr int kChunkMin = 256;      // candidate sources per work item (chunk), at least
+constexpr int kChunksMax = 64;      // work items per target cluster, at most
+constexpr int kItemShift = 6;       // work item = launch-wide cluster index << kItemShift | chunk
+static_assert((1 << kItemShift) >= kChunksMax, "chunk index fits the item encoding");
+constexpr int kMaxLaunchClusters = 1 << (32 - kItemShift);
+constexpr int kPairBlockWaves = 8;  // wavefronts per pair-kernel workgroup (two workgroups per CU)
 constexpr int kCellCap = 512;       // cell-list entries per cluster; beyond: box enumeration
 constexpr int kMaxDim = 2047;       // cells per grid axis (packed coordinates use 11 bits)
 constexpr int kStage32 = 128;       // sources staged in LDS per round and wave (FP32 path)
@@ -55,7 +56,22 @@ struct ClusInfo {
   int total;     // candidate sources of the cluster
   int ncells;    // list entries (may exceed kCellCap: then overflow)
   int overflow;  // 1: the pair kernel enumerates the candidate box itself
-  int nslices;   // wavefronts sharing the cluster's candidates (1..kSlices)
+  int nchunks;   // work items of the cluster (1..kChunksMax)
+  int chunk;     // candidate sources per work item (the last one may hold fewer)
+  int pad[3];
+};
+
+// Work list of one iteration launch: the prepare kernel appends items, each
+// persistent workgroup of the pair kernel takes an equal share of the list,
+// the step kernel resets the count for the next launch.
+struct WorkQueue {
+  unsigned int nitems;  // items appended
+  unsigned int pad;
+};
+struct QueueRef {
+  WorkQueue* q;
+  unsigned int* items;  // [cap]
+  unsigned int cap;     // >= total clusters * kChunksMax
 };
 
 struct ReqState;
@@ -72,7 +88,8 @@ struct ReqStatic {
   const GridInfo* grid;              // [n_stages]
   ClusInfo* cinfo;                   // [nclus]
   CellEntry* cells;                  // [nclus][kCellCap]
-  double* sslots;                    // [nclus][kBlocksPerCluster][kSlot] block partials
+  double* sslots;                    // [nclus][kChunksMax][kSlot] work-item partials
+  double* csum;                      // [nclus][kSlot] per-cluster sums of the partials
   double* trace;                     // [max_iters][kTraceCols] or null
   double* per_target;                // [m][7] or null (per-target terms, eval-targets mode)
   int m, n, fd, zs, xs, nclus;
@@ -154,12 +171,16 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // One gradient-flow iteration (or one evaluation) for a batch of requests that
 // share precision, label dimension and cutoff mode.  clus_end[r] is the
 // cumulative cluster count of requests 0..r.
+// The queue's count must be zero before the first launch on it (the step
+// kernel leaves it zero); one queue serves one stream.
 hipError_t launch_iteration(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end,
-                            int nreq, int total_clusters, hipStream_t s);
-// the three kernels of an iteration, separately (for event timing)
-hipError_t launch_step(const ReqStatic* reqs, int nreq, hipStream_t s);
-hipError_t launch_prepare(const ReqStatic* reqs, const int* clus_end, int nreq, int total_clusters, hipStream_t s);
+                            int nreq, int total_clusters, const QueueRef& Q, hipStream_t s);
+// the kernels of an iteration, separately (for event timing)
+hipError_t launch_step(const ReqStatic* reqs, const int* clus_end, int nreq, int total_clusters, const QueueRef& Q,
+                       hipStream_t s);
+hipError_t launch_prepare(const ReqStatic* reqs, const int* clus_end, int nreq, int total_clusters, const QueueRef& Q,
+                          hipStream_t s);
 hipError_t launch_pair_kernel(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end, int nreq,
-                              int total_clusters, hipStream_t s);
+                              int total_clusters, const QueueRef& Q, hipStream_t s);
 
 }  // namespace cvo

@@ -26,6 +26,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "cvo_internal.h"
 
 namespace cvo {
@@ -739,57 +741,93 @@ __device__ __forceinline__ void cand_cell(const GridInfo& g, const CandBox& B, c
   }
 }
 
-// Kernel A: per target cluster, the compacted list of reachable non-empty
-// source cells, the candidate count and the number of slices.
+// Kernel A: per target cluster (one wavefront each), the compacted list of
+// reachable non-empty source cells and the candidate count; the candidates
+// are cut into work items of at least kChunkMin sources (at most kChunksMax
+// items per cluster) that are appended to the launch's work queue, one
+// atomic per workgroup.  The order of the items in the queue varies from run
+// to run; results do not depend on it (every item has its own output row).
 __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ reqs, const int* __restrict__ clus_end,
-                                                 int nreq, int total_clusters) {
-  const int lc = uniform(logical_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
-  if (lc >= total_clusters) return;
-  const int r = uniform(find_request(clus_end, nreq, lc));
-  const ReqStatic& R = reqs[r];
-  ReqState* S = R.state;
-  if (uniform(S->done)) return;
-  const int c = lc - (r > 0 ? clus_end[r - 1] : 0);
+                                                 int nreq, int total_clusters, QueueRef Q) {
+  __shared__ int wcount[kWavesPerBlock];
+  __shared__ unsigned int wbase;
+  const int w = threadIdx.x >> 6;
+  const int lc = uniform(logical_block() * kWavesPerBlock + w);
   const int l = lane_id();
-  const int s0 = uniform(R.clus_start[c]);
-  const int cn = uniform(R.clus_count[c]);
-  const bool valid = l < cn;
-  double zt[3];
-  float mdummy[1];
-  load_targets<float, 1>(R, S->T, s0, valid, zt, mdummy);
-  const int stage = uniform(S->stage);
-  const GridInfo g = R.grid[stage];
-  const int* __restrict__ cs = uniform_ptr(R.cstart[stage]);
-  const CandBox B = cand_box(g, zt, valid);
-  CellEntry* list = R.cells + (size_t)c * kCellCap;
-  int nl = 0, total = 0;
-  for (int c0 = 0; c0 < B.ncand; c0 += kWave) {
-    int key, first, cnt, packed = 0;
-    cand_cell(g, B, cs, c0 + l, key, first, cnt, &packed);
-    const unsigned long long ne = __ballot(cnt > 0);
-    const int rank = __popcll(ne & ((1ull << l) - 1ull));
-    const int incl = wave_incl_scan(cnt);
-    if (cnt > 0 && nl + rank < kCellCap) {
-      CellEntry e;
-      e.cell = packed;
-      e.first = first;
-      e.count = cnt;
-      e.end = total + incl;
-      list[nl + rank] = e;
+  int nchunks = 0;
+  if (lc < total_clusters) {
+    const int r = uniform(find_request(clus_end, nreq, lc));
+    const ReqStatic& R = reqs[r];
+    ReqState* S = R.state;
+    if (!uniform(S->done)) {
+      const int c = lc - (r > 0 ? clus_end[r - 1] : 0);
+      const int s0 = uniform(R.clus_start[c]);
+      const int cn = uniform(R.clus_count[c]);
+      const bool valid = l < cn;
+      double zt[3];
+      float mdummy[1];
+      load_targets<float, 1>(R, S->T, s0, valid, zt, mdummy);
+      const int stage = uniform(S->stage);
+      const GridInfo g = R.grid[stage];
+      const int* __restrict__ cs = uniform_ptr(R.cstart[stage]);
+      const CandBox B = cand_box(g, zt, valid);
+      CellEntry* list = R.cells + (size_t)c * kCellCap;
+      int nl = 0, total = 0;
+      for (int c0 = 0; c0 < B.ncand; c0 += kWave) {
+        int key, first, cnt, packed = 0;
+        cand_cell(g, B, cs, c0 + l, key, first, cnt, &packed);
+        const unsigned long long ne = __ballot(cnt > 0);
+        const int rank = __popcll(ne & ((1ull << l) - 1ull));
+        const int incl = wave_incl_scan(cnt);
+        if (cnt > 0 && nl + rank < kCellCap) {
+          CellEntry e;
+          e.cell = packed;
+          e.first = first;
+          e.count = cnt;
+          e.end = total + incl;
+          list[nl + rank] = e;
+        }
+        nl += __popcll(ne);
+        total += uniform(__shfl(incl, kWave - 1, kWave));
+      }
+      int chunk;
+      if (R.mode == kModeEvalTargets) {
+        // per-target outputs need all sources of a target in one wavefront
+        chunk = total > 0 ? total : 1;
+        nchunks = 1;
+      } else {
+        chunk = (int)(((long long)total + kChunksMax - 1) / kChunksMax);
+        chunk = chunk < kChunkMin ? kChunkMin : chunk;
+        nchunks = (int)(((long long)total + chunk - 1) / chunk);
+        nchunks = nchunks < 1 ? 1 : nchunks;
+      }
+      if (l == 0) {
+        ClusInfo ci;
+        ci.total = total;
+        ci.ncells = nl;
+        ci.overflow = nl > kCellCap ? 1 : 0;
+        ci.nchunks = nchunks;
+        ci.chunk = chunk;
+        ci.pad[0] = ci.pad[1] = ci.pad[2] = 0;
+        R.cinfo[c] = ci;
+      }
     }
-    nl += __popcll(ne);
-    total += uniform(__shfl(incl, kWave - 1, kWave));
   }
-  int ns = (total + kSliceMin - 1) / kSliceMin;
-  ns = ns < 1 ? 1 : (ns > kSlices ? kSlices : ns);
-  if (R.mode == kModeEvalTargets) ns = 1;  // per-target outputs need all sources of a target in one wave
-  if (l == 0) {
-    ClusInfo ci;
-    ci.total = total;
-    ci.ncells = nl;
-    ci.overflow = nl > kCellCap ? 1 : 0;
-    ci.nslices = ns;
-    R.cinfo[c] = ci;
+  if (l == 0) wcount[w] = nchunks;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int ww = 0; ww < kWavesPerBlock; ww++) t += wcount[ww];
+    wbase = t > 0 ? atomicAdd(&Q.q->nitems, (unsigned)t) : 0u;
+  }
+  __syncthreads();
+  if (nchunks > 0) {
+    unsigned int base = wbase;
+    for (int ww = 0; ww < w; ww++) base += (unsigned)wcount[ww];
+    for (int q = l; q < nchunks; q += kWave) {
+      const unsigned int it = base + (unsigned)q;
+      if (it < Q.cap) Q.items[it] = ((unsigned)lc << kItemShift) | (unsigned)q;
+    }
   }
 }
 
@@ -880,12 +918,15 @@ __device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S, con
   if (stage < R.n_stages - 1 && kn >= R.stage_end[stage]) S->stage = stage + 1;
 }
 
-// wave-local LDS ordering: the stores of one phase are complete (and the
-// compiler keeps them in place) before another lane of the wave reads them
+// Wave-local LDS ordering between the lanes of one wavefront.  The LDS
+// executes the DS instructions of a wavefront in issue order, so a read issued
+// after a write sees it; only the compiler must keep LDS accesses on their side
+// of this point.  A wavefront-scope fence does that without waiting for the
+// wave's outstanding global loads (a workgroup-scope fence would, and would
+// stall the prefetch of the next batch).
 __device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 template <int FD>
@@ -902,7 +943,18 @@ __device__ __forceinline__ unsigned long long wave_or(unsigned long long v) {
   return v;
 }
 
-// A batch of up to 64 consecutive candidate positions of a slice, one per
+__device__ __forceinline__ double uniform_d(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <typename CT>
+__device__ __forceinline__ CT uniform_ct(CT v) {
+  return (CT)uniform_d((double)v);
+}
+
+// A batch of up to 64 consecutive candidate positions of a work item, one per
 // lane, with the lane's raw source record in flight.
 template <typename CT, int FD>
 struct Batch {
@@ -912,49 +964,46 @@ struct Batch {
   CT raw[3 + FD];
 };
 
-// Candidate sources [lo_s, hi_s) of the cluster's list, 64 at a time (one
-// per lane), software-pipelined: the records of the next batch are requested
-// before the current one is processed.  Each record is moved to coordinates
-// relative to the cluster origin (the first target; FP64 arithmetic, one
-// rounding to CT) and, with the cutoff, kept only if it lies within the
-// cutoff of the cluster's bounding box.  Survivors are compacted into the
-// wave's LDS area; every full round is paired with every lane's target,
-// reading each source at a wave-uniform LDS address.  The list window (64
-// cell entries, one per lane) stays in registers; a position's entry is
+// Candidate sources [lo_s, hi_s) of the cluster's list, 64 at a time (one per
+// lane), software-pipelined: the records of the next batch are requested
+// before the current one is culled, staged and paired; the two batches
+// alternate between two register sets, so no copy waits for a load in
+// flight.  Each record is moved to coordinates relative to the cluster origin
+// O (FP64 arithmetic, one rounding to CT) and, with the cutoff, kept only if
+// it lies within the cutoff of the cluster's bounding box.  Survivors are
+// compacted into the wave's LDS area; a full area is paired with every lane's
+// target, each source read at a wave-uniform LDS address.  The list window
+// (64 cell entries, one per lane) stays in registers; a position's entry is
 // found from a bitmask of the entry boundaries inside the batch.  Returns the
 // number of sources paired.
 template <typename CT, int FD, bool CUT>
 __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const GridInfo& g, const ClusInfo& ci, int c,
-                                                     long long lo_s, long long hi_s, const double (&zt)[3], bool valid,
-                                                     const CT (&mj)[FD], CT rc2, Acc<CT>& acc,
-                                                     unsigned long long& within, cptr<CT> xr, int xs, CT* recs) {
+                                                     long long lo_s, long long hi_s, const double (&O)[3], CT zx,
+                                                     CT zy, CT zz, bool valid, const CT (&mj)[FD], CT rc2,
+                                                     Acc<CT>& acc, unsigned long long& within, cptr<CT> xr, int xs,
+                                                     CT* recs) {
   constexpr int RS = RecStride<FD>::value;
   constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
   static_assert(NR % kWave == 0 && NR >= kWave, "a staging round holds at least one batch");
   const int l = lane_id();
   const CellEntry* __restrict__ list = uniform_ptr(R.cells + (size_t)c * kCellCap);
   const int nl = uniform(ci.ncells);
-  // cluster origin: the first target (lane 0 always holds a target)
-  const double O[3] = {__shfl(zt[0], 0, kWave), __shfl(zt[1], 0, kWave), __shfl(zt[2], 0, kWave)};
-  const CT far = (CT)1e30;
-  const CT zx = valid ? (CT)((zt[0] - O[0]) * g.sq) : far;
-  const CT zy = valid ? (CT)((zt[1] - O[1]) * g.sq) : far;
-  const CT zz = valid ? (CT)((zt[2] - O[2]) * g.sq) : far;
-  // cluster bounding box in the same coordinates; a source farther than the
-  // cutoff from it cannot pair with any target (threshold widened by a
-  // relative 1e-4 so that no pair the per-pair test accepts is dropped)
+  // cluster bounding box in the scaled relative coordinates; a source farther
+  // than the cutoff from it cannot pair with any target (threshold widened by
+  // a relative 1e-4 so that no pair the per-pair test accepts is dropped)
   CT blo[3], bhi[3];
   {
     const CT zc[3] = {zx, zy, zz};
     for (int a = 0; a < 3; a++) {
-      blo[a] = (CT)wave_min(valid ? (double)zc[a] : INFINITY);
-      bhi[a] = (CT)wave_max(valid ? (double)zc[a] : -INFINITY);
+      blo[a] = uniform_ct<CT>((CT)wave_min(valid ? (double)zc[a] : INFINITY));
+      bhi[a] = uniform_ct<CT>((CT)wave_max(valid ? (double)zc[a] : -INFINITY));
     }
   }
   const CT cull2 = rc2 * (CT)1.0001 + (CT)1e-6;
   // offset of cell (0,0,0) from the origin, in scaled units
-  const double base[3] = {(g.ox - O[0]) * g.sq, (g.oy - O[1]) * g.sq, (g.oz - O[2]) * g.sq};
-  const double hs = g.h * g.sq;
+  const double base[3] = {uniform_d((g.ox - O[0]) * g.sq), uniform_d((g.oy - O[1]) * g.sq),
+                          uniform_d((g.oz - O[2]) * g.sq)};
+  const double hs = uniform_d(g.h * g.sq);
   const CT* xg0 = (const CT*)xr;
 
   // entry window: lane k holds entry we0 + k
@@ -962,20 +1011,32 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const G
   int navail = 0;
   long long win_end = 0;
   CellEntry me;
+  // Loads below are issued by every lane (dead lanes read a valid clamped
+  // address): a load under a branch would make the compiler's wait counts
+  // assume it might not have been issued, and wait for the batch in flight.
+  // The window load is consumed by selects (no branch) right away, so no
+  // path leaves it in flight.
+  static_assert(sizeof(CellEntry) == 4 * sizeof(int), "a cell entry is four ints");
+  const __attribute__((address_space(1))) int* glist = (const __attribute__((address_space(1))) int*)list;
   auto load_window = [&]() {
     navail = uniform(min(kWave, nl - we0));
-    if (l < navail) {
-      me = list[we0 + l];
-    } else {
-      me.cell = 0;
-      me.first = 0;
-      me.count = 0;
-      me.end = 0x7fffffff;
-    }
-    win_end = (navail > 0) ? (long long)uniform(__shfl(me.end, navail - 1, kWave)) : hi_s;
+    const bool in = l < navail;
+    const int idx = we0 + (in ? l : 0);
+    const int e4 = 4 * (idx < nl && idx >= 0 ? idx : 0);
+    const int ecell = glist[e4], efirst = glist[e4 + 1], ecount = glist[e4 + 2], eend = glist[e4 + 3];
+    me.cell = in ? ecell : 0;
+    me.first = in ? efirst : 0;
+    me.count = in ? ecount : 0;
+    me.end = in ? eend : 0x7fffffff;
+    const int last_end = uniform(__shfl(me.end, navail > 0 ? navail - 1 : 0, kWave));
+    win_end = navail > 0 ? (long long)last_end : hi_s;
   };
   // request the records of the batch starting at pos
   auto start_batch = [&](long long pos, Batch<CT, FD>& B) {
+    if (pos >= win_end) {
+      we0 += navail;
+      load_window();
+    }
     long long bend = pos + kWave;
     if (bend > hi_s) bend = hi_s;
     if (bend > win_end) bend = win_end;
@@ -990,16 +1051,15 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const G
     const unsigned long long upto = (l == kWave - 1) ? ~1ull : ((2ull << l) - 2ull);  // bits 1..l
     int ei = eoff + __popcll(M & upto);
     ei = ei < navail - 1 ? ei : navail - 1;
+    ei = ei < 0 ? 0 : ei;
     const int efirst = __shfl(me.first, ei, kWave);
     const int ecount = __shfl(me.count, ei, kWave);
     const int eend = __shfl(me.end, ei, kWave);
     B.cell = __shfl(me.cell, ei, kWave);
-    if (B.live) {
-      const int src = efirst + (int)(p - ((long long)eend - ecount));
-      const CT* xg = xg0 + (size_t)src * xs;
+    const int src = B.live ? efirst + (int)(p - ((long long)eend - ecount)) : 0;
+    const CT* xg = xg0 + (size_t)src * xs;
 #pragma unroll
-      for (int q = 0; q < 3 + FD; q++) B.raw[q] = xg[q];
-    }
+    for (int q = 0; q < 3 + FD; q++) B.raw[q] = xg[q];
   };
 
   long long paired = 0;
@@ -1031,41 +1091,31 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const G
     count = 0;
     wave_lds_sync();
   };
-
-  load_window();
-  if (navail <= 0) return 0;
-  Batch<CT, FD> A, B;
-  start_batch(lo_s, A);
-  long long pos = A.end;
-  for (;;) {
-    const bool more = pos < hi_s;
-    if (more) {
-      if (pos >= win_end) {
-        we0 += navail;
-        load_window();
-      }
-      start_batch(pos, B);
-      pos = B.end;
-    }
-    // cull and stage batch A
-    bool keep = false;
+  // cull batch B, append its survivors to the staging area, pair a full area
+  // (or everything, after the last batch)
+  // (every lane computes its record, live or not, so that no path skips the
+  // use of the batch's loads)
+  auto stage = [&](const Batch<CT, FD>& B, bool last) {
     CT rec[3 + FD];
-    if (A.live) {
-      const int cx = A.cell & 2047, cy = (A.cell >> 11) & 2047, cz = (A.cell >> 22) & 2047;
-      rec[0] = (CT)((double)A.raw[0] + (base[0] + cx * hs));
-      rec[1] = (CT)((double)A.raw[1] + (base[1] + cy * hs));
-      rec[2] = (CT)((double)A.raw[2] + (base[2] + cz * hs));
+    const int cx = B.cell & 2047, cy = (B.cell >> 11) & 2047, cz = (B.cell >> 22) & 2047;
+    rec[0] = (CT)((double)B.raw[0] + (base[0] + cx * hs));
+    rec[1] = (CT)((double)B.raw[1] + (base[1] + cy * hs));
+    rec[2] = (CT)((double)B.raw[2] + (base[2] + cz * hs));
+    // (the first label is passed through an add so that the staged record's
+    // first four words are formed here, not moved out of the load's registers
+    // at the loop's back edge; x + 0 only turns -0 into +0)
+    rec[3] = B.raw[3] + (CT)0;
 #pragma unroll
-      for (int f = 0; f < FD; f++) rec[3 + f] = A.raw[3 + f];
-      keep = true;
-      if (CUT) {
-        CT d2 = 0;
-        for (int a = 0; a < 3; a++) {
-          const CT d = rec[a] < blo[a] ? blo[a] - rec[a] : (rec[a] > bhi[a] ? rec[a] - bhi[a] : (CT)0);
-          d2 += d * d;
-        }
-        keep = d2 <= cull2;
+    for (int f = 1; f < FD; f++) rec[3 + f] = B.raw[3 + f];
+    bool keep = B.live;
+    if (CUT) {
+      CT d2 = 0;
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        const CT d = fmax(fmax(blo[a] - rec[a], rec[a] - bhi[a]), (CT)0);
+        d2 += d * d;
       }
+      keep = keep && d2 <= cull2;
     }
     const unsigned long long km = __ballot(keep);
     if (keep) {
@@ -1074,55 +1124,54 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const G
       for (int q = 0; q < 3 + FD; q++) dst[q] = rec[q];
     }
     count += __popcll(km);
-    if (count > NR - kWave || (!more && count > 0)) flush();
-    if (!more) break;
-    A = B;
+    if (count > NR - kWave || (last && count > 0)) flush();
+  };
+
+  load_window();
+  if (navail <= 0) return 0;
+  // A starts as an empty batch (no loads), so both batches enter the loop in
+  // the registers the loop keeps them in.  The next batch is always requested
+  // (past the end it is empty: no live lane, loads of record 0), so the loads
+  // in flight are the same on every path and the waits before staging count
+  // only the older batch.
+  Batch<CT, FD> A, B;
+  A.end = lo_s;
+  A.live = false;
+  A.cell = 0;
+#pragma unroll
+  for (int q = 0; q < 3 + FD; q++) A.raw[q] = (CT)0;
+  long long pos = lo_s;
+  for (;;) {
+    const bool moreB = pos < hi_s;
+    start_batch(pos, B);
+    pos = B.end > pos ? B.end : pos;
+    stage(A, !moreB);
+    if (!moreB) break;
+    const bool moreA = pos < hi_s;
+    start_batch(pos, A);
+    pos = A.end > pos ? A.end : pos;
+    stage(B, !moreA);
+    if (!moreA) break;
   }
   return paired;
 }
 
-// Kernel B: one wavefront per (cluster, slice): the slice's contiguous range
-// of the cluster's candidate sources, staged in the wave's LDS area, against
-// the cluster's targets (one per lane).  The four slices of a block are summed
-// in slice order into a fixed slot; no synchronisation across workgroups is
-// needed inside the kernel.
+// One work item: candidate sources [k chunk, (k + 1) chunk) of cluster c
+// against the cluster's targets (one per lane).  The item's sums (W, the
+// torque and translation terms, pair counts) go to its own row.
 template <typename CT, int FD, bool CUT>
-__global__ __launch_bounds__(kPairBlockWaves* kWave) void k_pairs(const ReqStatic* __restrict__ reqs,
-                                                                  const int* __restrict__ clus_end, int nreq,
-                                                                  int total_clusters) {
-  constexpr int RS = RecStride<FD>::value;
-  constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
-  __shared__ CT recs_all[kPairBlockWaves][NR * RS];
-  __shared__ double parts[kPairBlockWaves][kSlot];
-  // Block placement: workgroup b runs on die b mod 8.  Cluster c goes to die
-  // c mod 8, so dense regions (contiguous in the Morton order) spread over
-  // all dies; on each die, blocks are ordered slice-block-major, so the first
-  // block of every cluster (always in use) is dispatched before any second
-  // block (in use only for clusters with many candidates).
-  const int die = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
-  const int per_die = (total_clusters + kXcds - 1) / kXcds;
-  const int bq = j / per_die;
-  const int lc = (j - bq * per_die) * kXcds + die;  // block-uniform
-  if (lc >= total_clusters || bq >= kBlocksPerCluster) return;
-  const int w = threadIdx.x >> 6;
-  const int q = uniform(bq * kPairBlockWaves + w);
-  const int r = find_request(clus_end, nreq, lc);
+__device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs, const int* __restrict__ clus_end,
+                                             int nreq, int lc, int k, CT* recs) {
+  const int r = uniform(find_request(clus_end, nreq, lc));
   const ReqStatic& R = reqs[r];
   ReqState* S = R.state;
-  if (S->done) return;  // block-uniform
   const int c = lc - (r > 0 ? clus_end[r - 1] : 0);
   const int l = lane_id();
   const ClusInfo ci = R.cinfo[c];
-  const int ns = uniform(ci.nslices);
-  if (bq * kPairBlockWaves >= ns) {
-    // no slice of this block is in use: its row is zero
-    if (threadIdx.x < kSlot) R.sslots[((size_t)c * kBlocksPerCluster + bq) * kSlot + threadIdx.x] = 0.0;
-    return;
-  }
-  // slices past the cluster's count do no work but join the block reduction
   const int total = uniform(ci.total);
-  const long long lo_s = (q < ns) ? (long long)total * q / ns : 0;
-  const long long hi_s = (q < ns) ? (long long)total * (q + 1) / ns : 0;
+  const int chunk = uniform(ci.chunk);
+  const long long lo_s = (long long)k * chunk;
+  const long long hi_s = min(lo_s + chunk, (long long)total);
 
   const int s0 = uniform(R.clus_start[c]);
   const int cn = uniform(R.clus_count[c]);
@@ -1143,36 +1192,49 @@ __global__ __launch_bounds__(kPairBlockWaves* kWave) void k_pairs(const ReqStati
   acc.init();
   unsigned long long within = 0;
   long long span = 0;
-  if (lo_s < hi_s) {
-    if (!uniform(ci.overflow)) {
-      span = pairs_from_list<CT, FD, CUT>(R, g, ci, c, lo_s, hi_s, zt, valid, mj, rc2, acc, within, xr, xs,
-                                          recs_all[w]);
-    } else {
-      // the list overflowed: enumerate the candidate box again in the same order
-      const int* __restrict__ cs = uniform_ptr(R.cstart[stage]);
-      const CandBox B = cand_box(g, zt, valid);
-      long long base = 0;
-      for (int c0 = 0; c0 < B.ncand && base < hi_s; c0 += kWave) {
-        int key, first, cnt;
-        cand_cell(g, B, cs, c0 + l, key, first, cnt);
-        const int incl = wave_incl_scan(cnt);
-        const long long cb = base + incl - cnt, ce = base + incl;
-        unsigned long long todo = __ballot(cnt > 0 && ce > lo_s && cb < hi_s);
-        while (todo) {
-          const int src = __builtin_ctzll(todo);
-          todo &= todo - 1ull;
-          const int ckey = uniform(__shfl(key, src, kWave));
-          const int cfirst = uniform(__shfl(first, src, kWave));
-          const int ccnt = uniform(__shfl(cnt, src, kWave));
-          const long long cbeg = base + uniform(__shfl(incl - cnt, src, kWave));
-          const int a = cfirst + (int)(lo_s > cbeg ? lo_s - cbeg : 0);
-          const int b = cfirst + (int)((hi_s - cbeg) < ccnt ? (hi_s - cbeg) : ccnt);
-          run_cell<CT, FD, CUT>(g, xr, xs, ckey, a, b, zt, valid, mj, rc2, acc, within);
-          span += b - a;
-        }
-        base += uniform(__shfl(incl, kWave - 1, kWave));
+  double lever[3];  // the target position z~_j used for the torque
+  if (!uniform(ci.overflow)) {
+    // cluster origin: the first target (lane 0 always holds a target)
+    const double O[3] = {uniform_d(zt[0]), uniform_d(zt[1]), uniform_d(zt[2])};
+    const CT far = (CT)1e30;
+    const CT zx = valid ? (CT)((zt[0] - O[0]) * g.sq) : far;
+    const CT zy = valid ? (CT)((zt[1] - O[1]) * g.sq) : far;
+    const CT zz = valid ? (CT)((zt[2] - O[2]) * g.sq) : far;
+    if (lo_s < hi_s)
+      span = pairs_from_list<CT, FD, CUT>(R, g, ci, c, lo_s, hi_s, O, zx, zy, zz, valid, mj, rc2, acc, within, xr,
+                                          xs, recs);
+    const double isq0 = 1.0 / g.sq;
+    lever[0] = O[0] + (double)zx * isq0;
+    lever[1] = O[1] + (double)zy * isq0;
+    lever[2] = O[2] + (double)zz * isq0;
+  } else {
+    // the list overflowed: enumerate the candidate box again in the same order
+    const int* __restrict__ cs = uniform_ptr(R.cstart[stage]);
+    const CandBox B = cand_box(g, zt, valid);
+    long long base = 0;
+    for (int c0 = 0; c0 < B.ncand && base < hi_s; c0 += kWave) {
+      int key, first, cnt;
+      cand_cell(g, B, cs, c0 + l, key, first, cnt);
+      const int incl = wave_incl_scan(cnt);
+      const long long cb = base + incl - cnt, ce = base + incl;
+      unsigned long long todo = __ballot(cnt > 0 && ce > lo_s && cb < hi_s);
+      while (todo) {
+        const int src = __builtin_ctzll(todo);
+        todo &= todo - 1ull;
+        const int ckey = uniform(__shfl(key, src, kWave));
+        const int cfirst = uniform(__shfl(first, src, kWave));
+        const int ccnt = uniform(__shfl(cnt, src, kWave));
+        const long long cbeg = base + uniform(__shfl(incl - cnt, src, kWave));
+        const int a = cfirst + (int)(lo_s > cbeg ? lo_s - cbeg : 0);
+        const int b = cfirst + (int)((hi_s - cbeg) < ccnt ? (hi_s - cbeg) : ccnt);
+        run_cell<CT, FD, CUT>(g, xr, xs, ckey, a, b, zt, valid, mj, rc2, acc, within);
+        span += b - a;
       }
+      base += uniform(__shfl(incl, kWave - 1, kWave));
     }
+    lever[0] = zt[0];
+    lever[1] = zt[1];
+    lever[2] = zt[2];
   }
   const unsigned long long examined = (unsigned long long)span * (unsigned long long)cn;
   if (!CUT) within = examined;
@@ -1185,9 +1247,9 @@ __global__ __launch_bounds__(kPairBlockWaves* kWave) void k_pairs(const ReqStati
   Dy *= isq;
   Dz *= isq;
   // sum_i w (x_i x z~_j) = z~_j x D_j with D_j = sum_i w (z~_j - x_i)
-  const double ox = zt[1] * Dz - zt[2] * Dy;
-  const double oy = zt[2] * Dx - zt[0] * Dz;
-  const double oz = zt[0] * Dy - zt[1] * Dx;
+  const double ox = lever[1] * Dz - lever[2] * Dy;
+  const double oy = lever[2] * Dx - lever[0] * Dz;
+  const double oz = lever[0] * Dy - lever[1] * Dx;
 
   if (R.mode == kModeEvalTargets && R.per_target && valid) {
     const double ell = R.stage_ell[stage];
@@ -1204,21 +1266,82 @@ __global__ __launch_bounds__(kPairBlockWaves* kWave) void k_pairs(const ReqStati
 
   const double part[kSlot] = {wave_sum(W),  wave_sum(ox), wave_sum(oy),     wave_sum(oz),    wave_sum(Dx),
                               wave_sum(Dy), wave_sum(Dz), (double)within, (double)examined};
-  if (l == 0)
-    for (int k = 0; k < kSlot; k++) parts[w][k] = part[k];
+  // every lane holds the same butterfly sums: all lanes store them (same
+  // address, same value), so the persistent loop has no lane-dependent branch
+  double* row = R.sslots + ((size_t)c * kChunksMax + k) * kSlot;
+#pragma unroll
+  for (int q = 0; q < kSlot; q++) row[q] = part[q];
+}
+
+// Kernel B: persistent workgroups, as many as are resident at once (two per
+// compute unit).  Workgroup b takes the b-th equal share of the launch's work
+// items; its wavefronts take the items of the share one at a time from a
+// counter in LDS, so the compute unit stays busy until its share is done and
+// no device-wide atomic is needed (one same-address device atomic per item
+// costs more than the items' arithmetic at this granularity).  Results do not
+// depend on which wavefront takes an item.  Every wavefront reaches the exit:
+// the counter grows by one per take and the share is finite.
+template <typename CT, int FD, bool CUT>
+__global__ __launch_bounds__(kPairBlockWaves* kWave) void k_pairs(const ReqStatic* __restrict__ reqs,
+                                                                  const int* __restrict__ clus_end, int nreq,
+                                                                  QueueRef Q) {
+  constexpr int RS = RecStride<FD>::value;
+  constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
+  __shared__ CT recs_all[kPairBlockWaves][NR * RS];
+  __shared__ unsigned int next;
+  CT* recs = recs_all[threadIdx.x >> 6];
+  const unsigned int nitems = (unsigned)uniform((int)min(Q.q->nitems, Q.cap));
+  const unsigned long long G = gridDim.x;
+  const unsigned int lo = (unsigned)((unsigned long long)nitems * blockIdx.x / G);
+  const unsigned int hi = (unsigned)((unsigned long long)nitems * (blockIdx.x + 1) / G);
+  if (threadIdx.x == 0) next = lo;
   __syncthreads();
-  if (threadIdx.x < kSlot) {
-    // the block's slices in slice order
-    double t = 0.0;
-    for (int ww = 0; ww < kPairBlockWaves; ww++) t += parts[ww][threadIdx.x];
-    R.sslots[((size_t)c * kBlocksPerCluster + bq) * kSlot + threadIdx.x] = t;
+  // No branch on the lane index may sit in this loop: the compiler may thread
+  // the loop's back edge on such a branch, which splits the wavefront so that
+  // lanes 1..63 re-enter the body without lane 0 and never see a new ticket.
+  // Every lane takes part in the atomic (lane 0 adds one, the others zero)
+  // and the ticket is lane 0's result.
+  for (;;) {
+    const unsigned int mine = atomicAdd(&next, lane_id() == 0 ? 1u : 0u);
+    const unsigned int it = (unsigned)uniform((int)mine);
+    if (it >= hi) break;
+    const unsigned int item = uniform((int)Q.items[it]);
+    process_item<CT, FD, CUT>(reqs, clus_end, nreq, (int)(item >> kItemShift),
+                              (int)(item & ((1u << kItemShift) - 1u)), recs);
   }
 }
 
-// Kernel C: one 512-thread block per request.  Thread t sums the block rows
-// t, t + 512, ... in order; the 512 thread sums are combined by a fixed
-// tree (wave butterflies, then waves in order): a deterministic FP64
-// reduction, then the step.
+// Kernel C1: per target cluster (one wavefront each), the sum of its work-item
+// rows: lane j holds chunk j (zero past the cluster's count), summed by the
+// fixed xor butterfly, so the result does not depend on the order in which the
+// items ran.  Block 0 also resets the work list for the next launch.
+__global__ __launch_bounds__(256) void k_reduce(const ReqStatic* __restrict__ reqs, const int* __restrict__ clus_end,
+                                                int nreq, int total_clusters, QueueRef Q) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) Q.q->nitems = 0u;
+  const int lc = uniform(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
+  if (lc >= total_clusters) return;
+  const int r = uniform(find_request(clus_end, nreq, lc));
+  const ReqStatic& R = reqs[r];
+  if (uniform(R.state->done)) return;
+  const int c = lc - (r > 0 ? clus_end[r - 1] : 0);
+  const int l = lane_id();
+  const int nch = uniform(R.cinfo[c].nchunks);
+  const double* row = R.sslots + ((size_t)c * kChunksMax + (l < nch ? l : 0)) * kSlot;
+  double v[kSlot];
+#pragma unroll
+  for (int q = 0; q < kSlot; q++) v[q] = row[q];
+#pragma unroll
+  for (int q = 0; q < kSlot; q++) v[q] = wave_sum(l < nch ? v[q] : 0.0);
+  // every lane holds the sums; all store them (same address, same value)
+  double* out = R.csum + (size_t)c * kSlot;
+#pragma unroll
+  for (int q = 0; q < kSlot; q++) out[q] = v[q];
+}
+
+// Kernel C2: one 512-thread block per request.  Thread t sums the cluster rows
+// t, t + 512, ... in order; the 512 thread sums are combined by a fixed tree
+// (wave butterflies, then waves in order): a deterministic FP64 reduction,
+// then the step.
 constexpr int kStepThreads = 512;
 __global__ __launch_bounds__(kStepThreads) void k_step(const ReqStatic* __restrict__ reqs, int nreq) {
   const int r = blockIdx.x;
@@ -1227,40 +1350,39 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const ReqStatic* __restri
   ReqState* S = R.state;
   if (S->done) return;  // block-uniform
   constexpr int NW = kStepThreads / kWave;
-  constexpr int BPC = kBlocksPerCluster;
   __shared__ double wsum[NW][kSlot];
   const int w = threadIdx.x >> 6;
   const int l = lane_id();
-  const int nrows = R.nclus * BPC;
   double acc[kSlot];
 #pragma unroll
-  for (int k = 0; k < kSlot; k++) acc[k] = 0.0;
+  for (int q = 0; q < kSlot; q++) acc[q] = 0.0;
+  const int nrows = R.nclus;
   int i = threadIdx.x;
   for (; i + 3 * kStepThreads < nrows; i += 4 * kStepThreads) {
     double v[4][kSlot];
 #pragma unroll
     for (int u = 0; u < 4; u++)
 #pragma unroll
-      for (int k = 0; k < kSlot; k++) v[u][k] = R.sslots[(size_t)(i + u * kStepThreads) * kSlot + k];
+      for (int q = 0; q < kSlot; q++) v[u][q] = R.csum[(size_t)(i + u * kStepThreads) * kSlot + q];
 #pragma unroll
     for (int u = 0; u < 4; u++)
 #pragma unroll
-      for (int k = 0; k < kSlot; k++) acc[k] += v[u][k];
+      for (int q = 0; q < kSlot; q++) acc[q] += v[u][q];
   }
   for (; i < nrows; i += kStepThreads)
 #pragma unroll
-    for (int k = 0; k < kSlot; k++) acc[k] += R.sslots[(size_t)i * kSlot + k];
+    for (int q = 0; q < kSlot; q++) acc[q] += R.csum[(size_t)i * kSlot + q];
 #pragma unroll
-  for (int k = 0; k < kSlot; k++) acc[k] = wave_sum(acc[k]);
+  for (int q = 0; q < kSlot; q++) acc[q] = wave_sum(acc[q]);
   if (l == 0)
-    for (int k = 0; k < kSlot; k++) wsum[w][k] = acc[k];
+    for (int q = 0; q < kSlot; q++) wsum[w][q] = acc[q];
   __syncthreads();
   if (threadIdx.x == 0) {
     double tot[kSlot];
-    for (int k = 0; k < kSlot; k++) {
+    for (int q = 0; q < kSlot; q++) {
       double t = 0.0;
-      for (int ww = 0; ww < NW; ww++) t += wsum[ww][k];
-      tot[k] = t;
+      for (int ww = 0; ww < NW; ww++) t += wsum[ww][q];
+      tot[q] = t;
     }
     finish_request(R, S, tot);
   }
@@ -1375,65 +1497,93 @@ hipError_t launch_ingest(const IngestArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Persistent grid of the pair kernel: as many workgroups as are resident at
+// once (occupancy of this instance times the compute units), capped by the
+// largest item count the launch can have.
+static int resident_blocks(const void* kernel) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kPairBlockWaves * kWave, 0) != hipSuccess)
+    return -1;
+  return (per_cu < 1 ? 1 : per_cu) * (cus < 1 ? 1 : cus);
+}
+
+template <typename CT, int FD, bool CUT>
+static hipError_t launch_pairs3(const ReqStatic* reqs, const int* clus_end, int nreq, int total,
+                                const QueueRef& Q, hipStream_t s) {
+  static std::atomic<int> resident_cache{0};  // per instance; every device of a process is the same part
+  int resident = resident_cache.load(std::memory_order_relaxed);
+  if (resident <= 0) {
+    resident = resident_blocks((const void*)k_pairs<CT, FD, CUT>);
+    if (resident <= 0) return hipErrorInvalidValue;
+    resident_cache.store(resident, std::memory_order_relaxed);
+  }
+  const long long most = (long long)total * kChunksMax;
+  const int blocks = (int)(most < resident ? most : resident);
+  hipLaunchKernelGGL((k_pairs<CT, FD, CUT>), dim3(blocks), dim3(kPairBlockWaves * kWave), 0, s, reqs, clus_end,
+                     nreq, Q);
+  return hipGetLastError();
+}
+
 template <typename CT, int FD>
-static void launch_pairs(bool cut, int blocks, const ReqStatic* reqs, const int* clus_end, int nreq, int total,
-                         hipStream_t s) {
-  if (cut)
-    hipLaunchKernelGGL((k_pairs<CT, FD, true>), dim3(blocks), dim3(kPairBlockWaves * kWave), 0, s, reqs, clus_end,
-                       nreq, total);
-  else
-    hipLaunchKernelGGL((k_pairs<CT, FD, false>), dim3(blocks), dim3(kPairBlockWaves * kWave), 0, s, reqs, clus_end,
-                       nreq, total);
+static hipError_t launch_pairs(bool cut, const ReqStatic* reqs, const int* clus_end, int nreq, int total,
+                               const QueueRef& Q, hipStream_t s) {
+  return cut ? launch_pairs3<CT, FD, true>(reqs, clus_end, nreq, total, Q, s)
+             : launch_pairs3<CT, FD, false>(reqs, clus_end, nreq, total, Q, s);
 }
 
 template <typename CT>
-static void launch_pairs_fd(int fd, bool cut, int blocks, const ReqStatic* reqs, const int* clus_end, int nreq,
-                            int total, hipStream_t s) {
+static hipError_t launch_pairs_fd(int fd, bool cut, const ReqStatic* reqs, const int* clus_end, int nreq, int total,
+                                  const QueueRef& Q, hipStream_t s) {
   switch (fd) {
-    case 1: launch_pairs<CT, 1>(cut, blocks, reqs, clus_end, nreq, total, s); break;
-    case 2: launch_pairs<CT, 2>(cut, blocks, reqs, clus_end, nreq, total, s); break;
-    case 3: launch_pairs<CT, 3>(cut, blocks, reqs, clus_end, nreq, total, s); break;
-    case 4: launch_pairs<CT, 4>(cut, blocks, reqs, clus_end, nreq, total, s); break;
-    case 5: launch_pairs<CT, 5>(cut, blocks, reqs, clus_end, nreq, total, s); break;
-    case 6: launch_pairs<CT, 6>(cut, blocks, reqs, clus_end, nreq, total, s); break;
-    case 7: launch_pairs<CT, 7>(cut, blocks, reqs, clus_end, nreq, total, s); break;
-    default: launch_pairs<CT, 8>(cut, blocks, reqs, clus_end, nreq, total, s); break;
+    case 1: return launch_pairs<CT, 1>(cut, reqs, clus_end, nreq, total, Q, s);
+    case 2: return launch_pairs<CT, 2>(cut, reqs, clus_end, nreq, total, Q, s);
+    case 3: return launch_pairs<CT, 3>(cut, reqs, clus_end, nreq, total, Q, s);
+    case 4: return launch_pairs<CT, 4>(cut, reqs, clus_end, nreq, total, Q, s);
+    case 5: return launch_pairs<CT, 5>(cut, reqs, clus_end, nreq, total, Q, s);
+    case 6: return launch_pairs<CT, 6>(cut, reqs, clus_end, nreq, total, Q, s);
+    case 7: return launch_pairs<CT, 7>(cut, reqs, clus_end, nreq, total, Q, s);
+    default: return launch_pairs<CT, 8>(cut, reqs, clus_end, nreq, total, Q, s);
   }
 }
 
-hipError_t launch_prepare(const ReqStatic* reqs, const int* clus_end, int nreq, int total_clusters, hipStream_t s) {
-  if (total_clusters < 1) return hipErrorInvalidValue;
+static bool queue_fits(int total_clusters, const QueueRef& Q) {
+  return Q.q && Q.items && total_clusters >= 1 && total_clusters < kMaxLaunchClusters &&
+         (unsigned long long)total_clusters * kChunksMax <= Q.cap;
+}
+
+hipError_t launch_prepare(const ReqStatic* reqs, const int* clus_end, int nreq, int total_clusters, const QueueRef& Q,
+                          hipStream_t s) {
+  if (!queue_fits(total_clusters, Q)) return hipErrorInvalidValue;
   const int blocks = (total_clusters + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, s, reqs, clus_end, nreq, total_clusters);
+  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, s, reqs, clus_end, nreq, total_clusters, Q);
   return hipGetLastError();
 }
 
 hipError_t launch_pair_kernel(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end, int nreq,
-                              int total_clusters, hipStream_t s) {
-  if (fd < 1 || fd > kMaxFeat || total_clusters < 1) return hipErrorInvalidValue;
-  const long long nb = (long long)(total_clusters + kXcds - 1) / kXcds * kXcds * kBlocksPerCluster;
-  if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
-  const int blocks = (int)nb;
-  if (precision == 1)
-    launch_pairs_fd<double>(fd, cutoff, blocks, reqs, clus_end, nreq, total_clusters, s);
-  else
-    launch_pairs_fd<float>(fd, cutoff, blocks, reqs, clus_end, nreq, total_clusters, s);
-  return hipGetLastError();
+                              int total_clusters, const QueueRef& Q, hipStream_t s) {
+  if (fd < 1 || fd > kMaxFeat || !queue_fits(total_clusters, Q)) return hipErrorInvalidValue;
+  if (precision == 1) return launch_pairs_fd<double>(fd, cutoff, reqs, clus_end, nreq, total_clusters, Q, s);
+  return launch_pairs_fd<float>(fd, cutoff, reqs, clus_end, nreq, total_clusters, Q, s);
 }
 
-hipError_t launch_step(const ReqStatic* reqs, int nreq, hipStream_t s) {
-  if (nreq < 1) return hipErrorInvalidValue;
+hipError_t launch_step(const ReqStatic* reqs, const int* clus_end, int nreq, int total_clusters, const QueueRef& Q,
+                       hipStream_t s) {
+  if (nreq < 1 || !queue_fits(total_clusters, Q)) return hipErrorInvalidValue;
+  const int blocks = (total_clusters + kWavesPerBlock - 1) / kWavesPerBlock;
+  hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(256), 0, s, reqs, clus_end, nreq, total_clusters, Q);
   hipLaunchKernelGGL(k_step, dim3(nreq), dim3(kStepThreads), 0, s, reqs, nreq);
   return hipGetLastError();
 }
 
 hipError_t launch_iteration(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end, int nreq,
-                            int total_clusters, hipStream_t s) {
-  hipError_t e = launch_prepare(reqs, clus_end, nreq, total_clusters, s);
+                            int total_clusters, const QueueRef& Q, hipStream_t s) {
+  hipError_t e = launch_prepare(reqs, clus_end, nreq, total_clusters, Q, s);
   if (e != hipSuccess) return e;
-  e = launch_pair_kernel(precision, fd, cutoff, reqs, clus_end, nreq, total_clusters, s);
+  e = launch_pair_kernel(precision, fd, cutoff, reqs, clus_end, nreq, total_clusters, Q, s);
   if (e != hipSuccess) return e;
-  return launch_step(reqs, nreq, s);
+  return launch_step(reqs, clus_end, nreq, total_clusters, Q, s);
 }
 
 }  // namespace cvo
