@@ -46,36 +46,75 @@ __device__ __forceinline__ P* uniform_ptr(P* p) {
   return (P*)(((unsigned long long)hi << 32) | lo);
 }
 
+// Cross-lane reductions on DPP row operations (no LDS traffic): within each
+// row of 16 lanes, xor-1 and xor-2 quad permutations, then the half-row and
+// row mirrors give every lane its row's result; the four row results are
+// read as scalars and combined in a fixed order.  Every lane returns the same
+// value, and the association is fixed, so results are reproducible.
+template <int CTRL>
+__device__ __forceinline__ int dpp32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)dpp32<CTRL>((int)(unsigned)u);
+  const unsigned hi = (unsigned)dpp32<CTRL>((int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+constexpr int kDppRowShr = 0x110;     // + n: row_shr:n
+constexpr int kDppBcast15 = 0x142;
+constexpr int kDppBcast31 = 0x143;
+
+template <typename Op>
+__device__ __forceinline__ double wave_reduce_d(double v, Op op) {
+  v = op(v, dpp64<kDppXor1>(v));
+  v = op(v, dpp64<kDppXor2>(v));
+  v = op(v, dpp64<kDppHalfMirror>(v));
+  v = op(v, dpp64<kDppMirror>(v));
+  return op(op(readlane_d(v, 0), readlane_d(v, 16)), op(readlane_d(v, 32), readlane_d(v, 48)));
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  return wave_reduce_d(v, [](double a, double b) { return a + b; });
 }
 __device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
-  return v;
+  return wave_reduce_d(v, [](double a, double b) { return fmin(a, b); });
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-  return v;
+  return wave_reduce_d(v, [](double a, double b) { return fmax(a, b); });
 }
 __device__ __forceinline__ int wave_sum_int(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp32<kDppXor1>(v);
+  v += dpp32<kDppXor2>(v);
+  v += dpp32<kDppHalfMirror>(v);
+  v += dpp32<kDppMirror>(v);
+  return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+         (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
-// inclusive prefix sum over the wave (Hillis-Steele with shuffles)
+// inclusive prefix sum over the wave: Hillis-Steele inside each row of 16
+// (row shifts, zero fill), then the row totals are carried by the row
+// broadcasts of lanes 15 and 31
 __device__ __forceinline__ int wave_incl_scan(int v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    int u = __shfl_up(v, o, kWave);
-    if (l >= o) v += u;
-  }
+  v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr + 1, 0xF, 0xF, true);
+  v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr + 2, 0xF, 0xF, true);
+  v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr + 4, 0xF, 0xF, true);
+  v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr + 8, 0xF, 0xF, true);
+  v += __builtin_amdgcn_update_dpp(0, v, kDppBcast15, 0xA, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, kDppBcast31, 0xC, 0xF, false);
   return v;
 }
+// value of a wave-uniform lane index, as a scalar
+__device__ __forceinline__ int lane_value(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
 // ---------------------------------------------------------------------------
 // 1) bounding box and mean squared norm (FP64), two passes
@@ -788,7 +827,7 @@ __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ r
           list[nl + rank] = e;
         }
         nl += __popcll(ne);
-        total += uniform(__shfl(incl, kWave - 1, kWave));
+        total += lane_value(incl, kWave - 1);
       }
       int chunk;
       if (R.mode == kModeEvalTargets) {
@@ -935,12 +974,20 @@ struct RecStride {
 };
 
 __device__ __forceinline__ unsigned long long wave_or(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const unsigned lo = __shfl_xor((unsigned)v, o, kWave), hi = __shfl_xor((unsigned)(v >> 32), o, kWave);
-    v |= ((unsigned long long)hi << 32) | lo;
-  }
-  return v;
+  unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+  lo |= (unsigned)dpp32<kDppXor1>((int)lo);
+  hi |= (unsigned)dpp32<kDppXor1>((int)hi);
+  lo |= (unsigned)dpp32<kDppXor2>((int)lo);
+  hi |= (unsigned)dpp32<kDppXor2>((int)hi);
+  lo |= (unsigned)dpp32<kDppHalfMirror>((int)lo);
+  hi |= (unsigned)dpp32<kDppHalfMirror>((int)hi);
+  lo |= (unsigned)dpp32<kDppMirror>((int)lo);
+  hi |= (unsigned)dpp32<kDppMirror>((int)hi);
+  lo = (unsigned)lane_value((int)lo, 0) | (unsigned)lane_value((int)lo, 16) | (unsigned)lane_value((int)lo, 32) |
+       (unsigned)lane_value((int)lo, 48);
+  hi = (unsigned)lane_value((int)hi, 0) | (unsigned)lane_value((int)hi, 16) | (unsigned)lane_value((int)hi, 32) |
+       (unsigned)lane_value((int)hi, 48);
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 __device__ __forceinline__ double uniform_d(double v) {
@@ -1028,7 +1075,7 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const G
     me.first = in ? efirst : 0;
     me.count = in ? ecount : 0;
     me.end = in ? eend : 0x7fffffff;
-    const int last_end = uniform(__shfl(me.end, navail > 0 ? navail - 1 : 0, kWave));
+    const int last_end = lane_value(me.end, navail > 0 ? navail - 1 : 0);
     win_end = navail > 0 ? (long long)last_end : hi_s;
   };
   // request the records of the batch starting at pos
@@ -1221,16 +1268,16 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
       while (todo) {
         const int src = __builtin_ctzll(todo);
         todo &= todo - 1ull;
-        const int ckey = uniform(__shfl(key, src, kWave));
-        const int cfirst = uniform(__shfl(first, src, kWave));
-        const int ccnt = uniform(__shfl(cnt, src, kWave));
-        const long long cbeg = base + uniform(__shfl(incl - cnt, src, kWave));
+        const int ckey = lane_value(key, src);
+        const int cfirst = lane_value(first, src);
+        const int ccnt = lane_value(cnt, src);
+        const long long cbeg = base + lane_value(incl - cnt, src);
         const int a = cfirst + (int)(lo_s > cbeg ? lo_s - cbeg : 0);
         const int b = cfirst + (int)((hi_s - cbeg) < ccnt ? (hi_s - cbeg) : ccnt);
         run_cell<CT, FD, CUT>(g, xr, xs, ckey, a, b, zt, valid, mj, rc2, acc, within);
         span += b - a;
       }
-      base += uniform(__shfl(incl, kWave - 1, kWave));
+      base += lane_value(incl, kWave - 1);
     }
     lever[0] = zt[0];
     lever[1] = zt[1];
