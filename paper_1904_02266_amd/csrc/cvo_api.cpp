@@ -83,7 +83,7 @@ struct Layout {
 
 // per-cluster iteration buffers, sized once the cluster count is known
 struct LayoutB {
-  size_t off_cinfo, off_cells, off_sslots, off_csum, off_trace, off_pt;
+  size_t off_cinfo, off_cells, off_centry, off_tblk, off_sslots, off_csum, off_trace, off_pt;
   size_t total;
 };
 
@@ -162,6 +162,8 @@ LayoutB plan_b(const Request& q, int nclus) {
   const size_t nc = (size_t)nclus;
   L.off_cinfo = take(sizeof(ClusInfo) * nc);
   L.off_cells = take(sizeof(CellEntry) * nc * kCellCap);
+  L.off_centry = take(sizeof(int) * nc * kChunksMax);
+  L.off_tblk = take((q.precision == CVO_FP64 ? 8 : 4) * nc * (3 + (size_t)q.fd) * kWave);
   L.off_sslots = take(8 * nc * kChunksMax * kSlot);
   L.off_csum = take(8 * nc * kSlot);
   L.off_trace = q.trace_on ? take((size_t)q.max_iters * kTraceCols * 8) : 0;
@@ -476,6 +478,8 @@ static int finish_setup(cvo_ctx* c, Request& q, const Layout& L, const LayoutB& 
   st.grid = (const GridInfo*)(A + L.off_grid);
   st.cinfo = (ClusInfo*)(Bp + LB.off_cinfo);
   st.cells = (CellEntry*)(Bp + LB.off_cells);
+  st.centry = (int*)(Bp + LB.off_centry);
+  st.tblk = (void*)(Bp + LB.off_tblk);
   st.sslots = (double*)(Bp + LB.off_sslots);
   st.csum = (double*)(Bp + LB.off_csum);
   st.trace = q.trace_on ? (double*)(Bp + LB.off_trace) : nullptr;

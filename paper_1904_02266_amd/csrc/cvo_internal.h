@@ -51,14 +51,23 @@ struct CellEntry {
   int end;    // inclusive prefix of counts along the list
 };
 
-// Per target cluster, rebuilt every iteration by the prepare kernel.
+// Per target cluster, rebuilt every iteration by the prepare kernel: the
+// frame in which the pair kernel works on the cluster, and its candidates.
 struct ClusInfo {
-  int total;     // candidate sources of the cluster
-  int ncells;    // list entries (may exceed kCellCap: then overflow)
-  int overflow;  // 1: the pair kernel enumerates the candidate box itself
-  int nchunks;   // work items of the cluster (1..kChunksMax)
-  int chunk;     // candidate sources per work item (the last one may hold fewer)
-  int pad[3];
+  double O[3];        // origin: the first target's transformed position (m)
+  double base[3];     // position of source cell (0,0,0) relative to O, scaled units
+  double hs;          // cell edge, scaled units
+  double isq;         // 1 / (scale): scaled units -> m
+  float blo[3];       // bounding box of the cluster's targets relative to O, scaled units
+  float bhi[3];
+  const void* xrec;   // source records of the current stage
+  int total;          // candidate sources of the cluster
+  int ncells;         // list entries (may exceed kCellCap: then overflow)
+  int overflow;       // 1: the pair kernel enumerates the candidate box itself
+  int nchunks;        // work items of the cluster (1..kChunksMax)
+  int chunk;          // candidate sources per work item (the last one may hold fewer)
+  int s0, cn;         // first sorted target and target count
+  int stage;
 };
 
 // Work list of one iteration launch: the prepare kernel appends items, each
@@ -88,6 +97,9 @@ struct ReqStatic {
   const GridInfo* grid;              // [n_stages]
   ClusInfo* cinfo;                   // [nclus]
   CellEntry* cells;                  // [nclus][kCellCap]
+  int* centry;                       // [nclus][kChunksMax] list entry holding each chunk's first candidate
+  void* tblk;                        // [nclus][3 + fd][kWave] targets in the cluster frame (scaled, relative
+                                     // to O; far away for lanes past the cluster) and labels, pair type
   double* sslots;                    // [nclus][kChunksMax][kSlot] work-item partials
   double* csum;                      // [nclus][kSlot] per-cluster sums of the partials
   double* trace;                     // [max_iters][kTraceCols] or null

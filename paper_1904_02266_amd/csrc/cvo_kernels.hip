@@ -46,6 +46,13 @@ __device__ __forceinline__ P* uniform_ptr(P* p) {
   return (P*)(((unsigned long long)hi << 32) | lo);
 }
 
+__device__ __forceinline__ double uniform_d(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Cross-lane reductions on DPP row operations (no LDS traffic): within each
 // row of 16 lanes, xor-1 and xor-2 quad permutations, then the half-row and
 // row mirrors give every lane its row's result; the four row results are
@@ -780,12 +787,35 @@ __device__ __forceinline__ void cand_cell(const GridInfo& g, const CandBox& B, c
   }
 }
 
-// Kernel A: per target cluster (one wavefront each), the compacted list of
-// reachable non-empty source cells and the candidate count; the candidates
-// are cut into work items of at least kChunkMin sources (at most kChunksMax
-// items per cluster) that are appended to the launch's work queue, one
-// atomic per workgroup.  The order of the items in the queue varies from run
-// to run; results do not depend on it (every item has its own output row).
+// Kernel A: per target cluster (one wavefront each).
+//  * The cluster frame: origin O (the first target, FP64), the targets
+//    relative to O in scaled units (one rounding to the pair type) with their
+//    labels, their bounding box, and the source-grid offsets in the same
+//    frame, so that a work item needs no FP64 transform and no dependent
+//    look-ups before its first pair.
+//  * The compacted list of reachable non-empty source cells in box order, the
+//    candidate count, and the cut into work items of at least kChunkMin
+//    sources (at most kChunksMax per cluster) with the list entry that holds
+//    each item's first candidate.  The cells of a round (up to 8 per lane,
+//    lane-major, so that the list keeps box order) are looked up together.
+//  * The items are appended to the launch's work list, one atomic per
+//    workgroup; their order there varies from run to run and results do not
+//    depend on it (every item has its own output row).
+constexpr int kPrepCells = 8;  // candidate cells per lane and round
+template <typename CT>
+__device__ __forceinline__ void write_frame(const ReqStatic& R, int c, int s0, int cn, const double (&zt)[3],
+                                            const GridInfo& g, const double (&O)[3]) {
+  const int l = lane_id();
+  const bool valid = l < cn;
+  const int fd = R.fd;
+  CT* blk = (CT*)R.tblk + (size_t)c * (3 + fd) * kWave;
+  const CT far = (CT)1e30;
+#pragma unroll
+  for (int a = 0; a < 3; a++) blk[a * kWave + l] = valid ? (CT)((zt[a] - O[a]) * g.sq) : far;
+  const float* zr = R.zrec + (size_t)(s0 + (valid ? l : 0)) * R.zs;
+  for (int f = 0; f < fd; f++) blk[(3 + f) * kWave + l] = valid ? (CT)zr[3 + f] : (CT)0;
+}
+
 __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ reqs, const int* __restrict__ clus_end,
                                                  int nreq, int total_clusters, QueueRef Q) {
   __shared__ int wcount[kWavesPerBlock];
@@ -809,25 +839,47 @@ __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ r
       const int stage = uniform(S->stage);
       const GridInfo g = R.grid[stage];
       const int* __restrict__ cs = uniform_ptr(R.cstart[stage]);
+
+      // cluster frame (lane 0 always holds a target)
+      const double O[3] = {uniform_d(zt[0]), uniform_d(zt[1]), uniform_d(zt[2])};
+      double blo[3], bhi[3];
+      for (int a = 0; a < 3; a++) {
+        const double zr = valid ? (zt[a] - O[a]) * g.sq : 0.0;
+        blo[a] = wave_min(valid ? zr : INFINITY);
+        bhi[a] = wave_max(valid ? zr : -INFINITY);
+      }
+      if (R.precision == 1)
+        write_frame<double>(R, c, s0, cn, zt, g, O);
+      else
+        write_frame<float>(R, c, s0, cn, zt, g, O);
+
+      // candidate cells, rounds of 64 x kPrepCells in box order (cell
+      // t = round base + q * 64 + lane; slots past the box are skipped)
       const CandBox B = cand_box(g, zt, valid);
       CellEntry* list = R.cells + (size_t)c * kCellCap;
-      int nl = 0, total = 0;
-      for (int c0 = 0; c0 < B.ncand; c0 += kWave) {
-        int key, first, cnt, packed = 0;
-        cand_cell(g, B, cs, c0 + l, key, first, cnt, &packed);
-        const unsigned long long ne = __ballot(cnt > 0);
-        const int rank = __popcll(ne & ((1ull << l) - 1ull));
-        const int incl = wave_incl_scan(cnt);
-        if (cnt > 0 && nl + rank < kCellCap) {
-          CellEntry e;
-          e.cell = packed;
-          e.first = first;
-          e.count = cnt;
-          e.end = total + incl;
-          list[nl + rank] = e;
+      int* centry = R.centry + (size_t)c * kChunksMax;
+      constexpr int PR = kWave * kPrepCells;
+      const int rounds = (B.ncand + PR - 1) / PR;
+      int ccnt[kPrepCells], cfirst[kPrepCells], cpack[kPrepCells];
+      auto load_round = [&](int rd) {
+#pragma unroll
+        for (int q = 0; q < kPrepCells; q++) {
+          int key;
+          cpack[q] = 0;
+          cfirst[q] = 0;
+          ccnt[q] = 0;
+          if (rd * PR + q * kWave < B.ncand)  // wave-uniform
+            cand_cell(g, B, cs, rd * PR + q * kWave + l, key, cfirst[q], ccnt[q], &cpack[q]);
         }
-        nl += __popcll(ne);
-        total += lane_value(incl, kWave - 1);
+      };
+      // pass 1: the candidate count fixes the chunk size
+      int total = 0;
+      for (int rd = 0; rd < rounds; rd++) {
+        load_round(rd);
+        int lt = 0;
+#pragma unroll
+        for (int q = 0; q < kPrepCells; q++) lt += ccnt[q];
+        total += wave_sum_int(lt);
       }
       int chunk;
       if (R.mode == kModeEvalTargets) {
@@ -840,16 +892,57 @@ __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ r
         nchunks = (int)(((long long)total + chunk - 1) / chunk);
         nchunks = nchunks < 1 ? 1 : nchunks;
       }
-      if (l == 0) {
-        ClusInfo ci;
-        ci.total = total;
-        ci.ncells = nl;
-        ci.overflow = nl > kCellCap ? 1 : 0;
-        ci.nchunks = nchunks;
-        ci.chunk = chunk;
-        ci.pad[0] = ci.pad[1] = ci.pad[2] = 0;
-        R.cinfo[c] = ci;
+      // pass 2: list entries and the entry of each chunk's first candidate
+      // (the cells of a single round are still in registers)
+      int nl = 0, pos0 = 0;
+      for (int rd = 0; rd < rounds; rd++) {
+        if (rounds > 1) load_round(rd);
+#pragma unroll
+        for (int q = 0; q < kPrepCells; q++) {
+          if (rd * PR + q * kWave >= B.ncand) break;  // wave-uniform
+          const int cnt = ccnt[q];
+          const unsigned long long ne = __ballot(cnt > 0);
+          const int idx = nl + __popcll(ne & ((1ull << l) - 1ull));
+          const int incl = wave_incl_scan(cnt);
+          const int pos = pos0 + incl - cnt;
+          if (cnt > 0) {
+            if (idx < kCellCap) {
+              CellEntry e;
+              e.cell = cpack[q];
+              e.first = cfirst[q];
+              e.count = cnt;
+              e.end = pos + cnt;
+              list[idx] = e;
+            }
+            // chunks whose first candidate falls in [pos, pos + count)
+            for (int kq = (pos + chunk - 1) / chunk; kq < nchunks && (long long)kq * chunk < pos + cnt; kq++)
+              centry[kq] = idx < kCellCap ? idx : kCellCap - 1;
+          }
+          pos0 += lane_value(incl, kWave - 1);
+          nl += __popcll(ne);
+        }
       }
+      // the frame and the counts (all lanes store the same values)
+      ClusInfo* ci = R.cinfo + c;
+      for (int a = 0; a < 3; a++) {
+        ci->O[a] = O[a];
+        ci->blo[a] = (float)blo[a];
+        ci->bhi[a] = (float)bhi[a];
+      }
+      ci->base[0] = (g.ox - O[0]) * g.sq;
+      ci->base[1] = (g.oy - O[1]) * g.sq;
+      ci->base[2] = (g.oz - O[2]) * g.sq;
+      ci->hs = g.h * g.sq;
+      ci->isq = 1.0 / g.sq;
+      ci->xrec = R.xrec[stage];
+      ci->total = total;
+      ci->ncells = nl;
+      ci->overflow = nl > kCellCap ? 1 : 0;
+      ci->nchunks = nchunks;
+      ci->chunk = chunk;
+      ci->s0 = s0;
+      ci->cn = cn;
+      ci->stage = stage;
     }
   }
   if (l == 0) wcount[w] = nchunks;
@@ -868,19 +961,6 @@ __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ r
       if (it < Q.cap) Q.items[it] = ((unsigned)lc << kItemShift) | (unsigned)q;
     }
   }
-}
-
-// first list entry whose inclusive end exceeds pos (entries 0..nl-1, nl <= kCellCap)
-__device__ __forceinline__ int locate_entry(const CellEntry* __restrict__ list, int nl, long long pos) {
-  const int l = lane_id();
-  const int stride = (nl + kWave - 1) / kWave;  // <= kCellCap / 64
-  int idx = min(nl - 1, (l + 1) * stride - 1);
-  unsigned long long hit = __ballot(l * stride < nl && list[idx].end > pos);
-  if (hit == 0ull) return nl;
-  const int blk = __builtin_ctzll(hit);
-  idx = blk * stride + l;
-  hit = __ballot(l < stride && idx < nl && list[min(idx, nl - 1)].end > pos);
-  return hit == 0ull ? nl : blk * stride + __builtin_ctzll(hit);
 }
 
 template <typename CT, int FD, bool CUT>
@@ -990,17 +1070,6 @@ __device__ __forceinline__ unsigned long long wave_or(unsigned long long v) {
   return ((unsigned long long)hi << 32) | lo;
 }
 
-__device__ __forceinline__ double uniform_d(double v) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
-  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-template <typename CT>
-__device__ __forceinline__ CT uniform_ct(CT v) {
-  return (CT)uniform_d((double)v);
-}
-
 // A batch of up to 64 consecutive candidate positions of a work item, one per
 // lane, with the lane's raw source record in flight.
 template <typename CT, int FD>
@@ -1024,37 +1093,30 @@ struct Batch {
 // found from a bitmask of the entry boundaries inside the batch.  Returns the
 // number of sources paired.
 template <typename CT, int FD, bool CUT>
-__device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const GridInfo& g, const ClusInfo& ci, int c,
-                                                     long long lo_s, long long hi_s, const double (&O)[3], CT zx,
-                                                     CT zy, CT zz, bool valid, const CT (&mj)[FD], CT rc2,
-                                                     Acc<CT>& acc, unsigned long long& within, cptr<CT> xr, int xs,
-                                                     CT* recs) {
+__device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const ClusInfo& ci, int c, int k,
+                                                     long long lo_s, long long hi_s, CT zx, CT zy, CT zz,
+                                                     const CT (&mj)[FD], CT rc2, Acc<CT>& acc,
+                                                     unsigned long long& within, cptr<CT> xr, int xs, CT* recs) {
   constexpr int RS = RecStride<FD>::value;
   constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
   static_assert(NR % kWave == 0 && NR >= kWave, "a staging round holds at least one batch");
   const int l = lane_id();
   const CellEntry* __restrict__ list = uniform_ptr(R.cells + (size_t)c * kCellCap);
   const int nl = uniform(ci.ncells);
-  // cluster bounding box in the scaled relative coordinates; a source farther
+  // cluster bounding box in the frame's scaled coordinates; a source farther
   // than the cutoff from it cannot pair with any target (threshold widened by
   // a relative 1e-4 so that no pair the per-pair test accepts is dropped)
-  CT blo[3], bhi[3];
-  {
-    const CT zc[3] = {zx, zy, zz};
-    for (int a = 0; a < 3; a++) {
-      blo[a] = uniform_ct<CT>((CT)wave_min(valid ? (double)zc[a] : INFINITY));
-      bhi[a] = uniform_ct<CT>((CT)wave_max(valid ? (double)zc[a] : -INFINITY));
-    }
-  }
+  const CT blo[3] = {(CT)ci.blo[0], (CT)ci.blo[1], (CT)ci.blo[2]};
+  const CT bhi[3] = {(CT)ci.bhi[0], (CT)ci.bhi[1], (CT)ci.bhi[2]};
   const CT cull2 = rc2 * (CT)1.0001 + (CT)1e-6;
   // offset of cell (0,0,0) from the origin, in scaled units
-  const double base[3] = {uniform_d((g.ox - O[0]) * g.sq), uniform_d((g.oy - O[1]) * g.sq),
-                          uniform_d((g.oz - O[2]) * g.sq)};
-  const double hs = uniform_d(g.h * g.sq);
+  const double base[3] = {ci.base[0], ci.base[1], ci.base[2]};
+  const double hs = ci.hs;
   const CT* xg0 = (const CT*)xr;
 
-  // entry window: lane k holds entry we0 + k
-  int we0 = uniform(locate_entry(list, nl, lo_s));
+  // entry window: lane k holds entry we0 + k (the entry holding the item's
+  // first candidate was found by the prepare kernel)
+  int we0 = uniform(R.centry[(size_t)c * kChunksMax + k]);
   int navail = 0;
   long long win_end = 0;
   CellEntry me;
@@ -1204,36 +1266,33 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const G
 }
 
 // One work item: candidate sources [k chunk, (k + 1) chunk) of cluster c
-// against the cluster's targets (one per lane).  The item's sums (W, the
-// torque and translation terms, pair counts) go to its own row.
+// against the cluster's targets (one per lane), in the frame the prepare
+// kernel set up.  The item's sums (W, the torque and translation terms, pair
+// counts) go to its own row.
 template <typename CT, int FD, bool CUT>
 __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs, const int* __restrict__ clus_end,
                                              int nreq, int lc, int k, CT* recs) {
   const int r = uniform(find_request(clus_end, nreq, lc));
   const ReqStatic& R = reqs[r];
-  ReqState* S = R.state;
   const int c = lc - (r > 0 ? clus_end[r - 1] : 0);
   const int l = lane_id();
-  const ClusInfo ci = R.cinfo[c];
+  const ClusInfo& ci = R.cinfo[c];
   const int total = uniform(ci.total);
   const int chunk = uniform(ci.chunk);
+  const int cn = uniform(ci.cn);
   const long long lo_s = (long long)k * chunk;
   const long long hi_s = min(lo_s + chunk, (long long)total);
-
-  const int s0 = uniform(R.clus_start[c]);
-  const int cn = uniform(R.clus_count[c]);
   const bool valid = l < cn;
-  double zt[3];
+  // targets in the cluster frame, and labels
+  const CT* blk = (const CT*)R.tblk + (size_t)c * (3 + FD) * kWave;
+  const CT zx = blk[l], zy = blk[kWave + l], zz = blk[2 * kWave + l];
   CT mj[FD];
-  load_targets<CT, FD>(R, S->T, s0, valid, zt, mj);
-
-  // values read from the mutable request state are wave-uniform: keep them in
-  // scalar registers
-  const int stage = uniform(S->stage);
-  const GridInfo g = R.grid[stage];
-  const cptr<CT> xr = (cptr<CT>)uniform_ptr(R.xrec[stage]);
+#pragma unroll
+  for (int f = 0; f < FD; f++) mj[f] = blk[(3 + f) * kWave + l];
+  const CT rc2 = (CT)R.grid[0].rc2s;  // the same for every stage
+  const cptr<CT> xr = (cptr<CT>)uniform_ptr(ci.xrec);
   const int xs = uniform(R.xs);
-  const CT rc2 = (CT)g.rc2s;
+  const double isq = ci.isq;
 
   Acc<CT> acc;
   acc.init();
@@ -1241,22 +1300,21 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
   long long span = 0;
   double lever[3];  // the target position z~_j used for the torque
   if (!uniform(ci.overflow)) {
-    // cluster origin: the first target (lane 0 always holds a target)
-    const double O[3] = {uniform_d(zt[0]), uniform_d(zt[1]), uniform_d(zt[2])};
-    const CT far = (CT)1e30;
-    const CT zx = valid ? (CT)((zt[0] - O[0]) * g.sq) : far;
-    const CT zy = valid ? (CT)((zt[1] - O[1]) * g.sq) : far;
-    const CT zz = valid ? (CT)((zt[2] - O[2]) * g.sq) : far;
     if (lo_s < hi_s)
-      span = pairs_from_list<CT, FD, CUT>(R, g, ci, c, lo_s, hi_s, O, zx, zy, zz, valid, mj, rc2, acc, within, xr,
-                                          xs, recs);
-    const double isq0 = 1.0 / g.sq;
-    lever[0] = O[0] + (double)zx * isq0;
-    lever[1] = O[1] + (double)zy * isq0;
-    lever[2] = O[2] + (double)zz * isq0;
+      span = pairs_from_list<CT, FD, CUT>(R, ci, c, k, lo_s, hi_s, zx, zy, zz, mj, rc2, acc, within, xr, xs, recs);
+    lever[0] = ci.O[0] + (double)zx * isq;
+    lever[1] = ci.O[1] + (double)zy * isq;
+    lever[2] = ci.O[2] + (double)zz * isq;
   } else {
-    // the list overflowed: enumerate the candidate box again in the same order
-    const int* __restrict__ cs = uniform_ptr(R.cstart[stage]);
+    // the list overflowed: enumerate the candidate box again in the same
+    // order, from the FP64 target positions
+    ReqState* S = R.state;
+    const int s0 = uniform(ci.s0);
+    const GridInfo g = R.grid[uniform(ci.stage)];
+    const int* __restrict__ cs = uniform_ptr(R.cstart[uniform(ci.stage)]);
+    double zt[3];
+    CT mdummy[FD];
+    load_targets<CT, FD>(R, S->T, s0, valid, zt, mdummy);
     const CandBox B = cand_box(g, zt, valid);
     long long base = 0;
     for (int c0 = 0; c0 < B.ncand && base < hi_s; c0 += kWave) {
@@ -1289,7 +1347,6 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
   double W, Dx, Dy, Dz;
   acc.result(W, Dx, Dy, Dz);
   if (!valid) W = Dx = Dy = Dz = 0.0;
-  const double isq = 1.0 / g.sq;
   Dx *= isq;
   Dy *= isq;
   Dz *= isq;
@@ -1299,13 +1356,14 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
   const double oz = lever[0] * Dy - lever[1] * Dx;
 
   if (R.mode == kModeEvalTargets && R.per_target && valid) {
-    const double ell = R.stage_ell[stage];
+    const double ell = R.stage_ell[uniform(ci.stage)];
     const double il2 = 1.0 / (ell * ell);
-    double* o = R.per_target + (size_t)R.zorig[s0 + l] * 7;
+    const double a2 = R.state->a2;
+    double* o = R.per_target + (size_t)R.zorig[uniform(ci.s0) + l] * 7;
     o[0] = R.s2f * W;
-    o[1] = R.s2f * ox * il2 / S->a2;
-    o[2] = R.s2f * oy * il2 / S->a2;
-    o[3] = R.s2f * oz * il2 / S->a2;
+    o[1] = R.s2f * ox * il2 / a2;
+    o[2] = R.s2f * oy * il2 / a2;
+    o[3] = R.s2f * oz * il2 / a2;
     o[4] = R.s2f * Dx * il2 / R.b2;
     o[5] = R.s2f * Dy * il2 / R.b2;
     o[6] = R.s2f * Dz * il2 / R.b2;
@@ -1313,8 +1371,8 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
 
   const double part[kSlot] = {wave_sum(W),  wave_sum(ox), wave_sum(oy),     wave_sum(oz),    wave_sum(Dx),
                               wave_sum(Dy), wave_sum(Dz), (double)within, (double)examined};
-  // every lane holds the same butterfly sums: all lanes store them (same
-  // address, same value), so the persistent loop has no lane-dependent branch
+  // every lane holds the same sums: all lanes store them (same address, same
+  // value), so the persistent loop has no lane-dependent branch
   double* row = R.sslots + ((size_t)c * kChunksMax + k) * kSlot;
 #pragma unroll
   for (int q = 0; q < kSlot; q++) row[q] = part[q];
