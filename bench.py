@@ -10,14 +10,18 @@ Workload (one step = one full registration, inputs resident in HBM):
 value = pairs inside the cutoff evaluated over the timed registrations / wall time.
 
 Also reported: the iteration kernel against the FP32 ALU roofline (event-timed
-on the launch stream), per-registration latency p50/p99, and the FP64 CPU
-oracle on a bounded teacher-forced sample (which doubles as a parity check).
+on the launch stream), per-registration latency p50/p99, a batched run through
+the continuous-batching scheduler (regs/s, per-request latency), and the FP64
+CPU oracle on a bounded teacher-forced sample (which doubles as a parity check).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
 import time
+
+from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 
@@ -27,6 +31,83 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_PAIR = 26          # d:3, r^2:5, exponent scale:1, label product (5 ch):9, weight:1, W:1, D:6
 PEAK_TFLOPS = 78.6           # FP32 VALU issue peak without packed FP32
 METRIC = "pair-evals/s per registration + batched regs/s, p50/p99 latency @1e-5 rel"
+KERNEL_SRC = os.path.join(ROOT, "paper_1904_02266_amd", "csrc", "cvo_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_rgbd30k_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per pair-kernel launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None when
+    the kernel source has changed since the counters were taken."""
+    try:
+        with open(KERNEL_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        fields = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line and line.startswith("- "):
+                    key, val = line[2:].split(":", 1)
+                    fields[key.strip()] = val.strip().strip("`")
+        if fields.get("kernel_source_sha256") != sha:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def _gen_request(args):
+    seed, ns, nt = args
+    from paper_1904_02266_amd import synth
+    p = synth.rgbd_pair(ns, nt, seed=seed)
+    return p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat
+
+
+def gen_batch(nreq):
+    """The batched run's inputs, drawn in worker processes.  Called before this
+    process touches the GPU (the workers are forked)."""
+    if nreq <= 0:
+        return []
+    from paper_1904_02266_amd import synth
+    with ProcessPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
+        return list(ex.map(_gen_request, synth.batched_sizes(nreq)))
+
+
+def batched(clouds, repeats=2):
+    """The registrations of `clouds` (the RGB-D generator, per-request seeds
+    4000 + k, cloud sizes uniform in 5000..60000, 100 iterations each)
+    submitted at once to the continuous-batching scheduler; inputs already on
+    the device."""
+    import torch
+    from paper_1904_02266_amd import Context, params_rgbd
+    nreq = len(clouds)
+    dev = torch.device("cuda:0")
+    dclouds = [[torch.from_numpy(a).to(dev) for a in c] for c in clouds]
+    torch.cuda.synchronize()
+    ctx = Context(0, max_slots=max(nreq, 1))
+    prm = params_rgbd()
+
+    def run():
+        t0 = time.perf_counter()
+        tks = [ctx.submit(*c, prm) for c in dclouds]
+        outs = [ctx.poll(tk) for tk, _ in tks]
+        return time.perf_counter() - t0, outs
+
+    run()  # warm-up
+    best = None
+    for _ in range(repeats):
+        el, outs = run()
+        if any(o["rc"] != 0 for o in outs):
+            raise RuntimeError("a batched registration failed: " + str([o["rc"] for o in outs]))
+        if best is None or el < best[0]:
+            best = (el, outs)
+    el, outs = best
+    ctx.close()
+    lat = [o["wall_ms"] for o in outs]
+    pairs = sum(o["pairs_within"] for o in outs)
+    return {"requests": nreq, "sizes": "n_src, n_tgt uniform in 5000..60000 (seeds 4000+k)", "iterations": 100,
+            "wall_s": el, "regs_per_s": nreq / el, "pair_evals_per_s": pairs / el,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+            "note": "all requests submitted at once; latency = submission to completion"}
 
 
 def main():
@@ -36,11 +117,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-oracle", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--n", type=int, default=30000)
+    ap.add_argument("--batch", type=int, default=64, help="requests in the batched run (0: skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the measurement, copy a MIB-MiB device buffer once (reference dispatch "
+                         "of known size for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    batch_clouds = gen_batch(args.batch)
 
     import torch
     from paper_1904_02266_amd import Context, params_rgbd, synth
@@ -124,6 +210,8 @@ def main():
                          f"at the GPU trajectory's poses of iterations {its}, {t_cpu:.1f} s"}
         parity = {"max_rel_err": worst, "criterion": "F rel; omega,v abs/sum|terms|", "iters": its}
 
+    batch = batched(batch_clouds) if batch_clouds else None
+
     line = {
         "metric": METRIC,
         "value": pairs / elapsed,
@@ -143,7 +231,7 @@ def main():
                    "points_src": int(pair.src_xyz.shape[0]), "points_tgt": int(pair.tgt_xyz.shape[0]),
                    "iterations": 100, "precision": "fp32 pair terms, kahan fp32 partials, fp64 reduce+step"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "k_pairs<float,5,true>", "kernel_ms_avg": kern_ms_avg,
                      "launches": ks["launches"], "flops_per_pair": FLOPS_PER_PAIR,
                      "prepare_kernel_ms_avg": ks["prepare_ms"] / max(1, ks["launches"]),
@@ -154,9 +242,16 @@ def main():
         "pairs_examined_per_registration": examined / args.steps,
         "pose_error": {"rot_deg": rot_err_deg, "trans_m": trans_err},
         "parity": parity,
+        "batched": batch,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+    if args.copy_calibration > 0:
+        a = torch.ones(args.copy_calibration * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

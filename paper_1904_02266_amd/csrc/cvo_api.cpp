@@ -524,6 +524,9 @@ static int ensure_pinned(cvo_ctx* c, size_t bytes) {
   return CVO_OK;
 }
 
+// Results of a finished request.  Does not publish the status: on the batched
+// path a poller may delete the request as soon as it sees a terminal status,
+// so only complete() sets it, under the queue lock, after every other field.
 static void fill_result(Request& q, const ReqState& hs) {
   q.res.status = hs.status;
   q.res.iters = hs.iter;
@@ -538,7 +541,6 @@ static void fill_result(Request& q, const ReqState& hs) {
   for (int k = 0; k < 12; k++) q.T_out[k] = hs.T[k];
   q.T_out[12] = q.T_out[13] = q.T_out[14] = 0.0;
   q.T_out[15] = 1.0;
-  q.status = hs.status;
 }
 
 static int grow(cvo_ctx* c, char** buf, size_t* have, size_t need, hipStream_t s) {
@@ -586,6 +588,7 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
   q.nclus = hs->nclus;
   if (hs->done) {  // invalid input detected on the device
     fill_result(q, *hs);
+    q.status = hs->status;
     q.res.wall_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
     return CVO_OK;
   }
@@ -646,6 +649,7 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
   }
   HIPCHK(c, hipStreamSynchronize(s));
   fill_result(q, *hs);
+  q.status = hs->status;
   if (q.trace_on) {
     const int rows = std::min(hs->iter, q.max_iters);
     q.trace.resize((size_t)rows * kTraceCols);

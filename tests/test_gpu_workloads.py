@@ -140,6 +140,24 @@ def test_batched_equals_sync_alone_and_mixed():
         assert s["F"] == a["F"] == m["F"]
 
 
+def test_batched_results_are_complete_when_polled():
+    """A ticket is reported only after every field of its result is written
+    (status is published last, under the queue lock): polling a batch in
+    submission order must never see a terminal status with a partial result."""
+    prm = params_rgbd(max_iters=12, stage_iters=(3, 3, 3))
+    reqs = _small_requests(200, 12)
+    ctx = Context(0, max_slots=16)
+    try:
+        tks = [ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)[0] for q in reqs]
+        outs = [ctx.poll(t) for t in tks]
+    finally:
+        ctx.close()
+    for o in outs:
+        assert o["rc"] == 0 and o["iters"] == 12
+        assert o["wall_ms"] > 0.0 and o["pairs_within"] > 0 and o["F"] > 0.0
+        assert abs(np.linalg.det(o["T"][:3, :3]) - 1.0) < 1e-9
+
+
 def test_serving_convergence_and_errors():
     ctx = Context(0, hbm_budget=64 << 20, max_slots=4)
     try:
