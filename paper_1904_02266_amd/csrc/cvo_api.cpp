@@ -144,8 +144,8 @@ Layout plan(const Request& q) {
   L.off_clscan = take(4 * m);
   L.off_clfirst = take(4 * m);
   L.off_clsums = take(4 * (size_t)(scan_tiles((long long)m) + 1));
-  L.off_clstart = take(4 * m);
-  L.off_clcount = take(4 * m);
+  L.off_clstart = take(4 * m * S);
+  L.off_clcount = take(4 * m * S);
   L.off_state = take(sizeof(ReqState));
   L.total = o;
   return L;
@@ -469,8 +469,11 @@ static int finish_setup(cvo_ctx* c, Request& q, const Layout& L, const LayoutB& 
   st.state = (ReqState*)(A + L.off_state);
   st.zrec = (const float*)(A + L.off_zrec);
   st.zorig = (const int*)(A + L.off_zorig);
-  st.clus_start = (const int*)(A + L.off_clstart);
-  st.clus_count = (const int*)(A + L.off_clcount);
+  for (int s = 0; s < kMaxStages; s++) {
+    const int ss = s < q.n_stages ? s : 0;
+    st.clus_start[s] = (const int*)(A + L.off_clstart) + (size_t)ss * q.m;
+    st.clus_count[s] = (const int*)(A + L.off_clcount) + (size_t)ss * q.m;
+  }
   for (int k = 0; k < S; k++) {
     st.xrec[k] = A + L.off_xrec[k];
     st.cstart[k] = (const int*)(A + L.off_count[k]);

@@ -90,8 +90,8 @@ struct ReqStatic {
   ReqState* state;                   // this request's mutable state
   const float* zrec;                 // [m][zs] target xyz (raw FP32) + labels, spatially sorted
   const int* zorig;                  // [m] original index of each sorted target
-  const int* clus_start;             // [nclus] first sorted target of each cluster
-  const int* clus_count;             // [nclus] targets in each cluster (1..64)
+  const int* clus_start[kMaxStages]; // per stage: [nclus_s] first sorted target of each cluster
+  const int* clus_count[kMaxStages]; // per stage: [nclus_s] targets in each cluster (1..64)
   const void* xrec[kMaxStages];      // per stage: [n][xs] scaled cell-local offsets + labels
   const int* cstart[kMaxStages];     // per stage: [ncell+1] first sorted source of each cell
   const GridInfo* grid;              // [n_stages]
@@ -104,7 +104,7 @@ struct ReqStatic {
   double* csum;                      // [nclus][kSlot] per-cluster sums of the partials
   double* trace;                     // [max_iters][kTraceCols] or null
   double* per_target;                // [m][7] or null (per-target terms, eval-targets mode)
-  int m, n, fd, zs, xs, nclus;
+  int m, n, fd, zs, xs, nclus;        // nclus: the largest cluster count over the stages
   int n_stages, max_iters, mode, precision;
   int stage_end[kMaxStages];         // iteration index where stage s ends; last = INT_MAX
   double stage_ell[kMaxStages];
@@ -122,7 +122,8 @@ struct ReqState {
   int iter, stage, done, status, converged;
   unsigned int reserved;
   int bad_input;                     // set by the finiteness check
-  int nclus;                         // target clusters (device-computed at ingest)
+  int nclus;                         // target clusters, the largest over the stages (device-computed at ingest)
+  int nclus_s[kMaxStages];           // target clusters of each stage
 };
 
 // Descriptor of a counting sort over one key segment (one per stage for the
@@ -172,7 +173,8 @@ struct IngestArgs {
   float* zrec;
   int* zorig;
   void* const* xrec_dev;     // device array [n_stages] of record pointers
-  // target clustering: scratch [m] each (cl_sums: [m/kScanTile + 1]), outputs [m]
+  // target clustering (one per stage): scratch [m] each (cl_sums: [m/kScanTile + 1]),
+  // outputs [n_stages][m]
   int *cl_flag, *cl_scan, *cl_first, *cl_sums;
   int *clus_start, *clus_count;
   ReqState* state;

@@ -462,16 +462,21 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const ScanArgs* __rest
 }
 
 // ---------------------------------------------------------------------------
-// target clusters: runs of at most 64 consecutive Morton-ordered targets, cut
-// wherever two consecutive targets are farther apart than D (2.5 Morton
-// bucket edges), so that no cluster straddles a jump of the Morton curve.
+// target clusters, one clustering per length-scale stage: runs of at most 64
+// consecutive Morton-ordered targets, cut wherever two consecutive targets are
+// farther apart than D = max(2.5 Morton bucket edges, 2 x the stage's cutoff
+// radius), so that no cluster straddles a large jump of the Morton curve.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_cl_flags(const float* __restrict__ zrec, int zs, int m,
-                                                  const double* __restrict__ zbox, int* __restrict__ flag,
-                                                  int* __restrict__ scan) {
+                                                  const double* __restrict__ zbox, double kappa,
+                                                  const double* __restrict__ stage_ell, int stage,
+                                                  int* __restrict__ flag, int* __restrict__ scan) {
   double e = 0.0;
   for (int a = 0; a < 3; a++) e = fmax(e, zbox[3 + a] - zbox[a]);
-  const double D = 2.5 * e / (double)(1 << kZBits);
+  // with a cutoff, a gap up to twice the cutoff radius stays inside a cluster:
+  // fuller clusters (fewer idle lanes) cost fewer candidate slots than the
+  // larger boxes add, while the cutoff is large against the Morton buckets
+  const double D = fmax(2.5 * e / (double)(1 << kZBits), 2.0 * kappa * stage_ell[stage]);
   const double D2 = isfinite(D) ? D * D : 0.0;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
     int f = 1;
@@ -506,16 +511,17 @@ __global__ __launch_bounds__(256) void k_cl_cflags(int* __restrict__ flag, int* 
 }
 
 __global__ __launch_bounds__(256) void k_cl_table(const int* __restrict__ cflag, const int* __restrict__ cscan, int m,
-                                                  int* __restrict__ clus_start, ReqState* __restrict__ S) {
+                                                  int stage, int* __restrict__ clus_start,
+                                                  ReqState* __restrict__ S) {
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
     if (cflag[p]) clus_start[cscan[p]] = p;
-    if (p == m - 1) S->nclus = cscan[p] + cflag[p];
+    if (p == m - 1) S->nclus_s[stage] = cscan[p] + cflag[p];
   }
 }
 
 __global__ __launch_bounds__(256) void k_cl_count(const int* __restrict__ clus_start, const ReqState* __restrict__ S,
-                                                  int m, int* __restrict__ clus_count) {
-  const int nc = S->nclus;
+                                                  int m, int stage, int* __restrict__ clus_count) {
+  const int nc = S->nclus_s[stage];
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x)
     clus_count[c] = ((c + 1 < nc) ? clus_start[c + 1] : m) - clus_start[c];
 }
@@ -828,15 +834,16 @@ __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ r
     const int r = uniform(find_request(clus_end, nreq, lc));
     const ReqStatic& R = reqs[r];
     ReqState* S = R.state;
-    if (!uniform(S->done)) {
-      const int c = lc - (r > 0 ? clus_end[r - 1] : 0);
-      const int s0 = uniform(R.clus_start[c]);
-      const int cn = uniform(R.clus_count[c]);
+    const int stage = uniform(S->stage);
+    const int c = lc - (r > 0 ? clus_end[r - 1] : 0);
+    // launches cover the largest cluster count over the stages
+    if (!uniform(S->done) && c < uniform(S->nclus_s[stage])) {
+      const int s0 = uniform(R.clus_start[stage][c]);
+      const int cn = uniform(R.clus_count[stage][c]);
       const bool valid = l < cn;
       double zt[3];
       float mdummy[1];
       load_targets<float, 1>(R, S->T, s0, valid, zt, mdummy);
-      const int stage = uniform(S->stage);
       const GridInfo g = R.grid[stage];
       const int* __restrict__ cs = uniform_ptr(R.cstart[stage]);
 
@@ -1430,7 +1437,8 @@ __global__ __launch_bounds__(256) void k_reduce(const ReqStatic* __restrict__ re
   if (uniform(R.state->done)) return;
   const int c = lc - (r > 0 ? clus_end[r - 1] : 0);
   const int l = lane_id();
-  const int nch = uniform(R.cinfo[c].nchunks);
+  // clusters past the current stage's count hold no items: a zero row
+  const int nch = c < uniform(R.state->nclus_s[uniform(R.state->stage)]) ? uniform(R.cinfo[c].nchunks) : 0;
   const double* row = R.sslots + ((size_t)c * kChunksMax + (l < nch ? l : 0)) * kSlot;
   double v[kSlot];
 #pragma unroll
@@ -1512,6 +1520,7 @@ __global__ void k_init_state(ReqState* __restrict__ S, const double* __restrict_
   S->reserved = 0u;
   S->bad_input = 0;
   S->nclus = 0;
+  for (int st = 0; st < kMaxStages; st++) S->nclus_s[st] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_check_finite(const float* __restrict__ p, long long count,
@@ -1523,10 +1532,17 @@ __global__ __launch_bounds__(256) void k_check_finite(const float* __restrict__ 
   if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&S->bad_input, 1);
 }
 
-__global__ void k_setup_final(ReqState* __restrict__ S, const double* __restrict__ xbox, double a2_param) {
+__global__ void k_setup_final(ReqState* __restrict__ S, const double* __restrict__ xbox, double a2_param,
+                              int n_stages) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (!(a2_param > 0.0)) S->a2 = xbox[6];
-  if (S->bad_input || !(S->a2 > 0.0) || !isfinite(S->a2) || S->nclus < 1) {
+  int most = 0, least = 0x7fffffff;
+  for (int st = 0; st < n_stages; st++) {
+    most = max(most, S->nclus_s[st]);
+    least = min(least, S->nclus_s[st]);
+  }
+  S->nclus = most;
+  if (S->bad_input || !(S->a2 > 0.0) || !isfinite(S->a2) || least < 1) {
     S->status = -1;  // invalid input
     S->done = 1;
   }
@@ -1589,16 +1605,21 @@ hipError_t launch_ingest(const IngestArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_src_records<float>, dim3(blocks_for(a.n, B, 1024), a.n_stages), dim3(B), 0, s, a.sx,
                        a.sfeat, a.n, a.fd, a.xs, a.grid, a.src_keys, a.src_perm, (float* const*)a.xrec_dev);
   }
-  // target clusters
+  // target clusters, one clustering per stage
   const int gm = blocks_for(a.m, B, 1024);
-  hipLaunchKernelGGL(k_cl_flags, dim3(gm), dim3(B), 0, s, a.zrec, a.zs, a.m, a.zbox, a.cl_flag, a.cl_scan);
-  launch_scan(a.cl_scan_args, 1, a.m, s);
-  hipLaunchKernelGGL(k_cl_segfirst, dim3(gm), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.m, a.cl_first);
-  hipLaunchKernelGGL(k_cl_cflags, dim3(gm), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.cl_first, a.m);
-  launch_scan(a.cl_scan_args, 1, a.m, s);
-  hipLaunchKernelGGL(k_cl_table, dim3(gm), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.m, a.clus_start, a.state);
-  hipLaunchKernelGGL(k_cl_count, dim3(gm), dim3(B), 0, s, a.clus_start, a.state, a.m, a.clus_count);
-  hipLaunchKernelGGL(k_setup_final, dim3(1), dim3(1), 0, s, a.state, a.xbox, a.a2_param);
+  for (int st = 0; st < a.n_stages; st++) {
+    int* cstart = a.clus_start + (size_t)st * a.m;
+    int* ccount = a.clus_count + (size_t)st * a.m;
+    hipLaunchKernelGGL(k_cl_flags, dim3(gm), dim3(B), 0, s, a.zrec, a.zs, a.m, a.zbox, a.kappa, a.stage_ell, st,
+                       a.cl_flag, a.cl_scan);
+    launch_scan(a.cl_scan_args, 1, a.m, s);
+    hipLaunchKernelGGL(k_cl_segfirst, dim3(gm), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.m, a.cl_first);
+    hipLaunchKernelGGL(k_cl_cflags, dim3(gm), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.cl_first, a.m);
+    launch_scan(a.cl_scan_args, 1, a.m, s);
+    hipLaunchKernelGGL(k_cl_table, dim3(gm), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.m, st, cstart, a.state);
+    hipLaunchKernelGGL(k_cl_count, dim3(gm), dim3(B), 0, s, cstart, a.state, a.m, st, ccount);
+  }
+  hipLaunchKernelGGL(k_setup_final, dim3(1), dim3(1), 0, s, a.state, a.xbox, a.a2_param, a.n_stages);
   return hipGetLastError();
 }
 
