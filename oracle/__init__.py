@@ -56,9 +56,15 @@ def _load():
         L.cvo_oracle_mean_sqnorm.restype = c_double
         L.cvo_oracle_register.argtypes = [c_int, f32p, f32p, c_int, f32p, f32p, c_int,
                                           c_double, c_double, c_double, c_double, c_double, c_double,
-                                          c_int, i32p, f64p, c_int, c_double, f64p, c_int, f64p, f64p,
-                                          i32p, i32p]
+                                          c_int, i32p, f64p, c_int, c_double, c_int, f64p, c_int, f64p,
+                                          f64p, i32p, i32p]
         L.cvo_oracle_register.restype = c_int
+        L.cvo_oracle_quartic.argtypes = [c_int, f32p, f32p, c_int, f32p, f32p, c_int,
+                                         c_double, c_double, c_double, c_double, f64p, f64p, f64p, c_int,
+                                         f64p, f64p]
+        L.cvo_oracle_quartic.restype = c_int
+        L.cvo_oracle_quartic_step.argtypes = [f64p, f64p]
+        L.cvo_oracle_quartic_step.restype = c_int
         _lib = L
     return _lib
 
@@ -145,13 +151,52 @@ def expmap(w, u):
     return E
 
 
+def quartic(src_xyz, src_feat, tgt_xyz, tgt_feat, T, w, u, *, sigma=0.1, feat_scale=0.2, ell=0.1,
+            kappa=0.0, nthreads=None):
+    """Taylor coefficients of G(t) = F(h exp(t (w^, u))) at t = 0 (eq. fourth),
+    T = h^-1: returns (coef[5] = F, A1..A4, abs[5] = sums of |terms|)."""
+    L = _load()
+    x = _f32(src_xyz, 3)
+    fd = np.asarray(src_feat).shape[1]
+    lx = _f32(src_feat, fd)
+    z = _f32(tgt_xyz, 3)
+    lz = _f32(tgt_feat, fd)
+    T = np.ascontiguousarray(T, dtype=np.float64).reshape(16)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(5)
+    absout = np.zeros(5)
+    rc = L.cvo_oracle_quartic(x.shape[0], _ptr(x, ctypes.c_float), _ptr(lx, ctypes.c_float),
+                              z.shape[0], _ptr(z, ctypes.c_float), _ptr(lz, ctypes.c_float), fd,
+                              sigma, feat_scale, ell, kappa, _ptr(T, ctypes.c_double), _ptr(w, ctypes.c_double),
+                              _ptr(u, ctypes.c_double), nthreads or default_threads(),
+                              _ptr(out, ctypes.c_double), _ptr(absout, ctypes.c_double))
+    if rc != 0:
+        raise OracleError(rc)
+    return out, absout
+
+
+def quartic_step(coef):
+    """t > 0 maximising P(t) = A1 t + A2 t^2 + A3 t^3 + A4 t^4 (coef[1:5]) among
+    its local maxima, or None when P has none on t > 0."""
+    A = np.ascontiguousarray(coef, dtype=np.float64)
+    assert A.shape == (5,)
+    t = np.zeros(1)
+    ok = _load().cvo_oracle_quartic_step(_ptr(A, ctypes.c_double), _ptr(t, ctypes.c_double))
+    return float(t[0]) if ok else None
+
+
 TRACE_COLS = 26
+STEP_RULES = {"fixed": 0, "quartic": 1}
 
 
 def register(src_xyz, src_feat, tgt_xyz, tgt_feat, *, sigma=0.1, feat_scale=0.2, a2=None, b2=1.0,
              eta=1.0, kappa=0.0, stage_iters=(), stage_ell=(0.1,), max_iters=50, tol=0.0,
-             T0=None, nthreads=None):
-    """Run the registration iteration; returns dict(T, iters, converged, trace[iters,26], rc)."""
+             step_rule="fixed", T0=None, nthreads=None):
+    """Run the registration iteration; returns dict(T, iters, converged, trace[iters,26], rc).
+    step_rule "fixed": tau = eta ell^2 / F; "quartic": the maximiser of the
+    fourth-order model (eq. fourth), falling back to the fixed rule when the
+    model has no maximum on t > 0."""
     L = _load()
     x = _f32(src_xyz, 3)
     fd = np.asarray(src_feat).shape[1]
@@ -171,7 +216,7 @@ def register(src_xyz, src_feat, tgt_xyz, tgt_feat, *, sigma=0.1, feat_scale=0.2,
                                z.shape[0], _ptr(z, ctypes.c_float), _ptr(lz, ctypes.c_float), fd,
                                sigma, feat_scale, -1.0 if a2 is None else a2, b2, eta, kappa, ns,
                                _ptr(si, ctypes.c_int), _ptr(se, ctypes.c_double), max_iters, tol,
-                               _ptr(T0, ctypes.c_double), nthreads or default_threads(),
+                               STEP_RULES[step_rule], _ptr(T0, ctypes.c_double), nthreads or default_threads(),
                                _ptr(Tout, ctypes.c_double), _ptr(trace, ctypes.c_double),
                                _ptr(it, ctypes.c_int), _ptr(cv, ctypes.c_int))
     return dict(T=Tout.reshape(4, 4), iters=int(it[0]), converged=bool(cv[0]),

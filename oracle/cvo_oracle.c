@@ -25,8 +25,10 @@
  *           x_i - z~_j has the opposite sign, see the reading list)
  *   step:  h <- h exp(t (omega^, v)), i.e. R <- R dR, t <- R dT + t
  *          (eq. newstep), dR, dT from the closed-form SE(3) exponential
- *          (eq. step), with the step length t = eta ell^2 / F (project rule;
- *          the paper's quartic line search is a separate later stage).
+ *          (eq. step), with the step length either t = eta ell^2 / F (project
+ *          rule) or the maximiser of the fourth-order Taylor model of
+ *          G(t) = F(h exp(t xi)) (Sec. VI-B, eq. fourth; see the quartic
+ *          section below for the coefficients used).
  *
  * parity pins: see the oracle tests (finite differences along the six
  * generators, rigid-motion invariance, zero gradient at identical clouds,
@@ -262,11 +264,183 @@ int cvo_oracle_eval(int n, const float* x, const float* lx, int m, const float* 
 }
 
 /*
+ * Fourth-order Taylor model of the line G(t) = F(h exp(t xi)) (Sec. VI-B,
+ * eq. fourth), xi = (w^, u) in the paper's convention.  Along the line the
+ * transformed target moves as z~(t) = exp(-t Xi) z~, so with d = x - z~,
+ * u1 = w x z~ + u and u_{k+1} = w x u_k,
+ *   x - z~(t) = d + t u1 - t^2/2 u2 + t^3/6 u3 - t^4/24 u4 + O(t^5),
+ * and the exponent -|x - z~(t)|^2 / (2 ell^2) = alpha + beta t + gamma t^2
+ * + delta t^3 + eps t^4 + O(t^5) with
+ *   alpha = -|d|^2/(2 ell^2)           beta  = -<d,u1>/ell^2
+ *   gamma = -(|u1|^2 - <d,u2>)/(2 ell^2)
+ *   delta =  (<u1,u2> - <d,u3>/3)/(2 ell^2)
+ *   eps   = -(|u2|^2/4 + <u1,u3>/3 - <d,u4>/12)/(2 ell^2)
+ * (the printed gamma, delta, eps expand |x - (z - t u1 - ... - t^4 u4)|^2
+ * instead; the g^1..g^4 compositions below are the paper's).  Then
+ *   G(t) ~ F + A1 t + A2 t^2 + A3 t^3 + A4 t^4,
+ *   A_k = sigma^2 sum_ij c_ij e^alpha g^k_ij,
+ *   g1 = beta, g2 = gamma + beta^2/2, g3 = delta + beta gamma + beta^3/6,
+ *   g4 = eps + beta delta + beta^2 gamma/2 + gamma^2/2 + beta^4/24,
+ * summed over the pairs inside the cutoff at t = 0.
+ * out[5] = F, A1..A4; absout[5] the sums of absolute terms.
+ */
+typedef struct {
+    int n, fd;
+    const float *x, *lx, *z, *lz;
+    double sigma, sf, ell, kappa;
+    double Rt[9], tt[3], w[3], u[3];
+    int j0, j1;
+    double sum[5], abs_sum[5];
+} qjob_t;
+
+static void cross3(const double a[3], const double b[3], double c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void* run_qjob(void* arg) {
+    qjob_t* J = (qjob_t*)arg;
+    const double il2 = 1.0 / (J->ell * J->ell);
+    const double rc2 = (J->kappa > 0.0) ? (J->kappa * J->ell) * (J->kappa * J->ell) : INFINITY;
+    const double s2 = J->sigma * J->sigma;
+    for (int q = 0; q < 5; q++) { J->sum[q] = 0.0; J->abs_sum[q] = 0.0; }
+    for (int j = J->j0; j < J->j1; j++) {
+        double zt[3], u1[3], u2[3], u3[3], u4[3];
+        for (int r = 0; r < 3; r++)
+            zt[r] = J->Rt[3 * r] * J->z[3 * j] + J->Rt[3 * r + 1] * J->z[3 * j + 1] +
+                    J->Rt[3 * r + 2] * J->z[3 * j + 2] + J->tt[r];
+        cross3(J->w, zt, u1);
+        for (int r = 0; r < 3; r++) u1[r] += J->u[r];
+        cross3(J->w, u1, u2);
+        cross3(J->w, u2, u3);
+        cross3(J->w, u3, u4);
+        for (int i = 0; i < J->n; i++) {
+            double d[3];
+            for (int r = 0; r < 3; r++) d[r] = (double)J->x[3 * i + r] - zt[r];
+            const double r2 = dot3(d, d);
+            if (!(r2 <= rc2)) continue;
+            double lm = 0.0;
+            for (int f = 0; f < J->fd; f++) lm += (double)J->lx[J->fd * i + f] * (double)J->lz[J->fd * j + f];
+            const double cw = J->sf * lm * s2 * exp(-0.5 * r2 * il2);
+            const double be = -dot3(d, u1) * il2;
+            const double ga = -(dot3(u1, u1) - dot3(d, u2)) * 0.5 * il2;
+            const double de = (dot3(u1, u2) - dot3(d, u3) / 3.0) * 0.5 * il2;
+            const double ep = -(dot3(u2, u2) / 4.0 + dot3(u1, u3) / 3.0 - dot3(d, u4) / 12.0) * 0.5 * il2;
+            const double g1 = be;
+            const double g2 = ga + be * be / 2.0;
+            const double g3 = de + be * ga + be * be * be / 6.0;
+            const double g4 = ep + be * de + be * be * ga / 2.0 + ga * ga / 2.0 + be * be * be * be / 24.0;
+            const double t5[5] = {cw, cw * g1, cw * g2, cw * g3, cw * g4};
+            for (int q = 0; q < 5; q++) { J->sum[q] += t5[q]; J->abs_sum[q] += fabs(t5[q]); }
+        }
+    }
+    return NULL;
+}
+
+int cvo_oracle_quartic(int n, const float* x, const float* lx, int m, const float* z, const float* lz,
+                       int fd, double sigma, double feat_scale, double ell, double kappa,
+                       const double T[16], const double w[3], const double u[3], int nthreads,
+                       double out[5], double absout[5]) {
+    if (!check_cloud(n, fd, x, lx) || !check_cloud(m, fd, z, lz)) return OR_EINVAL;
+    if (!(ell > 0.0) || kappa < 0.0) return OR_EINVAL;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > m) nthreads = m;
+    qjob_t* jobs = (qjob_t*)calloc((size_t)nthreads, sizeof(qjob_t));
+    pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!jobs || !th) { free(jobs); free(th); return OR_EINVAL; }
+    double h[16];
+    rigid_inverse(T, h);
+    for (int k2 = 0; k2 < nthreads; k2++) {
+        qjob_t* J = &jobs[k2];
+        J->n = n; J->fd = fd; J->x = x; J->lx = lx; J->z = z; J->lz = lz;
+        J->sigma = sigma; J->sf = feat_scale; J->ell = ell; J->kappa = kappa;
+        pose_to_inverse_action(h, J->Rt, J->tt);
+        for (int r = 0; r < 3; r++) { J->w[r] = w[r]; J->u[r] = u[r]; }
+        J->j0 = (int)((long long)m * k2 / nthreads);
+        J->j1 = (int)((long long)m * (k2 + 1) / nthreads);
+    }
+    for (int k2 = 1; k2 < nthreads; k2++) pthread_create(&th[k2], NULL, run_qjob, &jobs[k2]);
+    run_qjob(&jobs[0]);
+    for (int k2 = 1; k2 < nthreads; k2++) pthread_join(th[k2], NULL);
+    for (int q = 0; q < 5; q++) { out[q] = 0.0; absout[q] = 0.0; }
+    for (int k2 = 0; k2 < nthreads; k2++)
+        for (int q = 0; q < 5; q++) { out[q] += jobs[k2].sum[q]; absout[q] += jobs[k2].abs_sum[q]; }
+    free(jobs); free(th);
+    return OR_OK;
+}
+
+/*
+ * Step of the quartic model P(t) = A1 t + A2 t^2 + A3 t^3 + A4 t^4 (eq.
+ * fourth, "the value of t > 0 that maximises the quartic"): among the real
+ * roots t > 0 of P'(t) = A1 + 2 A2 t + 3 A3 t^2 + 4 A4 t^3 with P''(t) < 0,
+ * the one with the largest P; the roots come from the cubic in closed form
+ * (trigonometric case for three real roots).  Returns 1 and *t on success,
+ * 0 when P has no local maximum on t > 0 (then the caller falls back).
+ */
+static double poly4(const double A[5], double t) { return t * (A[1] + t * (A[2] + t * (A[3] + t * A[4]))); }
+static double dd4(const double A[5], double t) { return 2.0 * A[2] + 6.0 * A[3] * t + 12.0 * A[4] * t * t; }
+
+int cvo_oracle_quartic_step(const double A[5], double* t_out) {
+    /* P'(t) = a t^3 + b t^2 + c t + d */
+    const double a = 4.0 * A[4], b = 3.0 * A[3], c = 2.0 * A[2], d = A[1];
+    double roots[3];
+    int nr = 0;
+    const double scale = fabs(b) + fabs(c) + fabs(d) + 1e-300;
+    if (fabs(a) <= 1e-14 * scale) {
+        if (fabs(b) <= 1e-14 * (fabs(c) + fabs(d) + 1e-300)) {
+            if (c != 0.0) roots[nr++] = -d / c;
+        } else {
+            const double disc = c * c - 4.0 * b * d;
+            if (disc >= 0.0) {
+                const double s = sqrt(disc);
+                const double q = -0.5 * (c + (c >= 0.0 ? s : -s));
+                roots[nr++] = q / b;
+                if (q != 0.0) roots[nr++] = d / q;
+            }
+        }
+    } else {
+        /* depressed cubic t = y - b/(3a): y^3 + p y + q = 0 */
+        const double B = b / a, C = c / a, D = d / a;
+        const double p = C - B * B / 3.0;
+        const double q = 2.0 * B * B * B / 27.0 - B * C / 3.0 + D;
+        const double disc = q * q / 4.0 + p * p * p / 27.0;
+        if (disc > 0.0) {
+            const double s = sqrt(disc);
+            roots[nr++] = cbrt(-q / 2.0 + s) + cbrt(-q / 2.0 - s) - B / 3.0;
+        } else {
+            const double r = sqrt(-p / 3.0);
+            const double arg = (r > 0.0) ? fmax(-1.0, fmin(1.0, (-q / 2.0) / (r * r * r))) : 0.0;
+            const double phi = acos(arg);
+            for (int kk = 0; kk < 3; kk++)
+                roots[nr++] = 2.0 * r * cos((phi - 2.0 * 3.14159265358979323846 * kk) / 3.0) - B / 3.0;
+        }
+    }
+    int found = 0;
+    double best_t = 0.0, best_p = -INFINITY;
+    for (int i = 0; i < nr; i++) {
+        /* one Newton polish on P' */
+        double t = roots[i];
+        const double f = A[1] + t * (2.0 * A[2] + t * (3.0 * A[3] + t * 4.0 * A[4]));
+        const double fp = dd4(A, t);
+        if (fp != 0.0) t -= f / fp;
+        if (!(t > 0.0) || !(dd4(A, t) < 0.0)) continue;
+        const double pv = poly4(A, t);
+        if (!found || pv > best_p) { found = 1; best_t = t; best_p = pv; }
+    }
+    if (found) *t_out = best_t;
+    return found;
+}
+
+/*
  * The registration iteration (Section VI): at every iteration k,
  *   ell   = schedule length-scale of the stage containing k
  *   (F, omega, v) at the current h
  *   F <= 1e-300 -> no overlap (error)
- *   tau = eta ell^2 / F,  h <- h exp(tau (omega^, v))
+ *   tau = eta ell^2 / F (step_rule 0), or (step_rule 1) the maximiser of the
+ *         quartic model when it has one on t > 0, else eta ell^2 / F;
+ *   h <- h exp(tau (omega^, v))
  *   stop when the last stage is reached and |tau (omega, v)|_2 < tol.
  * Stage s spans stage_iters[s] iterations; the last stage runs to max_iters.
  * T0 and T_out use the library convention T = h^-1.
@@ -276,8 +450,8 @@ int cvo_oracle_eval(int n, const float* x, const float* lx, int m, const float* 
 int cvo_oracle_register(int n, const float* x, const float* lx, int m, const float* z, const float* lz,
                         int fd, double sigma, double feat_scale, double a2, double b2, double eta,
                         double kappa, int n_stages, const int* stage_iters, const double* stage_ell,
-                        int max_iters, double tol, const double T0[16], int nthreads, double T_out[16],
-                        double* trace, int* iters_out, int* converged_out) {
+                        int max_iters, double tol, int step_rule, const double T0[16], int nthreads,
+                        double T_out[16], double* trace, int* iters_out, int* converged_out) {
     if (n_stages < 1 || !stage_ell || max_iters < 1 || !(eta > 0.0)) return OR_EINVAL;
     for (int s = 0; s < n_stages; s++) {
         if (!(stage_ell[s] > 0.0)) return OR_EINVAL;
@@ -300,7 +474,16 @@ int cvo_oracle_register(int n, const float* x, const float* lx, int m, const flo
                                NULL, nthreads, g, ga, cnt, NULL);
         if (rc != OR_OK) break;
         if (!(g[0] > 1e-300)) { rc = OR_ENOOVERLAP; break; }
-        const double tau = eta * ell * ell / g[0];
+        double tau = eta * ell * ell / g[0];
+        if (step_rule == 1) {
+            /* quartic model along xi = (omega, v) at the current pose */
+            double Tcur[16], A[5], Aa[5], tq;
+            rigid_inverse(h, Tcur);
+            rc = cvo_oracle_quartic(n, x, lx, m, z, lz, fd, sigma, feat_scale, ell, kappa, Tcur, g + 1, g + 4,
+                                    nthreads, A, Aa);
+            if (rc != OR_OK) break;
+            if (cvo_oracle_quartic_step(A, &tq)) tau = tq;
+        }
         newstep(h, g + 1, g + 4, tau);
         double sq = 0.0;
         for (int q = 1; q < 7; q++) sq += (tau * g[q]) * (tau * g[q]);

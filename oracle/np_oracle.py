@@ -89,3 +89,44 @@ def evaluate(x, lx, z, lz, T, *, sigma=0.1, feat_scale=0.2, ell=0.1, kappa=0.0, 
 def objective(x, lx, z, lz, T, **kw):
     w, _, _, _ = terms(x, lx, z, lz, T, **kw)
     return w.sum()
+
+
+def quartic(x, lx, z, lz, T, w, u, *, sigma=0.1, feat_scale=0.2, ell=0.1, kappa=0.0):
+    """Taylor coefficients [F, A1, A2, A3, A4] of G(t) = F(h exp(t xi)) at t = 0
+    (Sec. VI-B, eq. fourth), xi = (w^, u), T = h^-1 acting on targets.
+
+    Computed here without the paper's alpha..epsilon / g^k formulas, by power
+    series: the moved target is z~(t) = exp(-t Xi) z~ = sum_k (-t Xi)^k z~ / k!
+    (4x4 twist Xi, homogeneous coordinates), the exponent
+    e(t) = -|x - z~(t)|^2 / (2 ell^2) is truncated to degree 4 by polynomial
+    products, and exp(e(t)) follows from the series recurrence
+    k f_k = sum_{j=1..k} j e_j f_{k-j}.  The pair set is the one inside the
+    cutoff at t = 0.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    c = feat_scale * (np.asarray(lx, dtype=np.float64) @ np.asarray(lz, dtype=np.float64).T)
+    T = np.asarray(T, dtype=np.float64)
+    Xi = twist_matrix(np.asarray(w, dtype=np.float64), np.asarray(u, dtype=np.float64))
+    zh = np.concatenate([z, np.ones((z.shape[0], 1))], axis=1) @ T.T      # z~ (homogeneous)
+    # coefficient k of x - z~(t): delta_k0 x - (-Xi)^k z~ / k!
+    P = []
+    Mk = np.eye(4)
+    fact = 1.0
+    for k in range(5):
+        if k > 0:
+            Mk = Mk @ (-Xi)
+            fact *= k
+        zk = (zh @ Mk.T)[:, :3] / fact                                       # [M, 3]
+        P.append((x[:, None, :] if k == 0 else 0.0) - zk[None, :, :])      # [N, M, 3]
+    e = []
+    for k in range(5):
+        s = sum((P[i] * P[k - i]).sum(axis=2) for i in range(k + 1))
+        e.append(-s / (2.0 * ell * ell))
+    f = [np.ones_like(e[0])]
+    for k in range(1, 5):
+        f.append(sum(j * e[j] * f[k - j] for j in range(1, k + 1)) / k)
+    wgt = c * sigma ** 2 * np.exp(e[0])
+    if kappa > 0:
+        wgt = np.where(-2.0 * ell * ell * e[0] <= (kappa * ell) ** 2, wgt, 0.0)
+    return np.array([(wgt * f[k]).sum() for k in range(5)])

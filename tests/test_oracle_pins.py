@@ -256,3 +256,159 @@ def test_error_codes():
     r = oracle.register(p.src_xyz, p.src_feat, far, p.tgt_feat, kappa=3.0, stage_ell=(0.1,),
                         max_iters=5)
     assert r["rc"] == oracle.ENOOVERLAP and r["iters"] == 0
+
+
+# --------------------------------------------------------------------------
+# Fourth-order step model (Sec. VI-B, eq. fourth)
+def _quartic_case(seed=3):
+    p = small_pair()
+    rng = np.random.default_rng(seed)
+    T = oracle.expmap(rng.normal(size=3) * 0.05, rng.normal(size=3) * 0.03)
+    w = rng.normal(size=3) * 2.0
+    u = rng.normal(size=3) * 0.5
+    return p, T, w, u
+
+
+def _G(p, T, w, u, t, ell):
+    """Exact G(t) = F(h exp(t xi)); with T = h^-1 the pose is exp(-t Xi) T."""
+    Tt = oracle.expmap(-t * w, -t * u) @ T
+    return oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, Tt, ell=ell, a2=7.0)["g"][0]
+
+
+def test_quartic_model_error_is_fifth_order():
+    # G(t) - (F + A1 t + ... + A4 t^4) = O(t^5): halving t divides the
+    # residual by 32.  A dropped or mis-signed term in any coefficient leaves
+    # a residual of lower order (ratio 16, 8 or 4).
+    p, T, w, u = _quartic_case()
+    ell = 0.2
+    c, _ = oracle.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, w, u, ell=ell)
+    res = []
+    for t in (0.0025, 0.00125, 0.000625):
+        g = _G(p, T, w, u, t, ell)
+        res.append(g - sum(c[k] * t ** k for k in range(5)))
+    assert abs(res[0]) > 1e-9
+    for a, b in zip(res, res[1:]):
+        assert 28.0 < a / b < 36.0, res
+
+
+def test_quartic_coefficients_match_central_differences():
+    p, T, w, u = _quartic_case(seed=5)
+    ell = 0.2
+    c, _ = oracle.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, w, u, ell=ell)
+    h = 2e-4          # truncation A4 h^2 ~ 1e-3 relative 2e-5
+    fd2 = (_G(p, T, w, u, h, ell) - 2.0 * c[0] + _G(p, T, w, u, -h, ell)) / (2.0 * h * h)
+    h = 3e-4
+    fd3 = (_G(p, T, w, u, 2 * h, ell) - 2 * _G(p, T, w, u, h, ell) + 2 * _G(p, T, w, u, -h, ell)
+           - _G(p, T, w, u, -2 * h, ell)) / (12.0 * h ** 3)
+    np.testing.assert_allclose(c[2], fd2, rtol=3e-5)
+    np.testing.assert_allclose(c[3], fd3, rtol=3e-4)
+
+
+@pytest.mark.parametrize("kappa", [0.0, 3.0])
+def test_quartic_first_coefficient_is_gradient_metric_norm(kappa):
+    # Along the gradient itself, G'(0) = <grad F, xi> = a^2 |omega|^2 + b^2 |v|^2
+    # (the metric of Sec. IV-B), over the same pair set.
+    p = small_pair(seed=13)
+    T = oracle.expmap([0.02, -0.03, 0.01], [0.01, 0.0, -0.02])
+    a2, b2, ell = 7.0, 1.5, 0.15
+    r = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=ell, kappa=kappa, a2=a2, b2=b2)
+    w, u = r["g"][1:4], r["g"][4:7]
+    c, _ = oracle.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, w, u, ell=ell, kappa=kappa)
+    np.testing.assert_allclose(c[0], r["g"][0], rtol=1e-13)
+    np.testing.assert_allclose(c[1], a2 * w @ w + b2 * u @ u, rtol=1e-11)
+
+
+@pytest.mark.parametrize("kappa", [0.0, 2.5])
+def test_quartic_c_and_numpy_agree(kappa):
+    p, T, w, u = _quartic_case(seed=7)
+    c, a = oracle.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, w, u, ell=0.12, kappa=kappa)
+    n = npo.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, w, u, ell=0.12, kappa=kappa)
+    np.testing.assert_allclose(c, n, rtol=0, atol=1e-12 * a.max())
+
+
+def test_printed_coefficients_are_only_first_order():
+    # The coefficients as printed (x - z~(t) expanded as d + t u1 + t^2 u2 +
+    # t^3 u3 + t^4 u4, no factorials or alternating signs) agree with G in
+    # F and A1 only; the residual falls off as t^2.  This is why the oracle
+    # uses the exact expansion (see the readings of eq. fourth).
+    p, T, w, u = _quartic_case(seed=3)
+    ell = 0.2
+    x = p.src_xyz.astype(np.float64)
+    zt = p.tgt_xyz.astype(np.float64) @ T[:3, :3].T + T[:3, 3]
+    W = hat(w)
+    u1 = zt @ W.T + u
+    u2 = u1 @ W.T
+    u3 = u2 @ W.T
+    u4 = u3 @ W.T
+    d = x[:, None, :] - zt[None, :, :]
+    cc = 0.2 * (p.src_feat.astype(np.float64) @ p.tgt_feat.astype(np.float64).T)
+    il = 1.0 / ell ** 2
+    dot = lambda a, b: (a * b).sum(-1)
+    al = -0.5 * il * dot(d, d)
+    be = -il * dot(u1[None], d)
+    ga = -0.5 * il * (dot(u1, u1)[None] + 2 * dot(u2[None], d))
+    de = il * (-dot(u1, u2)[None] - dot(u3[None], d))
+    ep = -0.5 * il * (dot(u2, u2)[None] + 2 * dot(u1, u3)[None] + 2 * dot(u4[None], d))
+    g = [be, ga + be ** 2 / 2, de + be * ga + be ** 3 / 6,
+         ep + be * de + be ** 2 * ga / 2 + ga ** 2 / 2 + be ** 4 / 24]
+    k = 0.01 * cc * np.exp(al)
+    Ap = [float((k * gk).sum()) for gk in g]
+    c, _ = oracle.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, w, u, ell=ell)
+    np.testing.assert_allclose(Ap[0], c[1], rtol=1e-12)
+    assert abs(Ap[1] - c[2]) > 1e-3 * abs(c[2])
+    res = [_G(p, T, w, u, t, ell) - c[0] - sum(Ap[k - 1] * t ** k for k in range(1, 5))
+           for t in (0.0025, 0.00125)]
+    assert 3.0 < res[0] / res[1] < 5.0, res
+
+
+def _grid_best(A, tmax):
+    t = np.linspace(tmax * 1e-6, tmax, 400001)
+    P = t * (A[1] + t * (A[2] + t * (A[3] + t * A[4])))
+    inner = (P[1:-1] > P[:-2]) & (P[1:-1] >= P[2:])
+    if not inner.any():
+        return None
+    idx = np.nonzero(inner)[0] + 1
+    return t[idx[np.argmax(P[idx])]]
+
+
+@pytest.mark.parametrize("A", [
+    [0, 5.1, 5.0, -96.9, -601.2],        # one maximum (a regular step)
+    [0, 1.0, -1.0, 0.0, 0.0],            # quadratic: t = 1/2
+    [0, 1.0, 0.0, -1.0, 0.0],            # cubic: t = 1/sqrt(3)
+    [0, 1.0, -4.5, 6.0, -2.0],           # P' = -8 (t - 0.25)(t - 1)(t - ... ): two maxima
+    [0, 2.0, -7.0, 7.0, -2.0],
+    [0, 1.0, -3.0, 2.0, 0.25],           # local max then unbounded growth
+])
+def test_quartic_step_picks_best_local_maximum(A):
+    t = oracle.quartic_step(A)
+    ref = _grid_best(A, 5.0)
+    assert ref is not None and t is not None
+    assert abs(t - ref) < 2e-5 * 5.0
+    dP = A[1] + 2 * A[2] * t + 3 * A[3] * t * t + 4 * A[4] * t ** 3
+    assert abs(dP) < 1e-9 * (abs(A[1]) + abs(A[2]) + abs(A[3]) + abs(A[4]))
+
+
+@pytest.mark.parametrize("A", [
+    [0, 1.0, 1.0, 1.0, 1.0],             # increasing for all t > 0
+    [0, 1.0, 0.0, 0.0, 0.0],             # linear
+    [0, -1.0, -1.0, 0.0, -1.0],          # decreasing from t = 0
+])
+def test_quartic_step_without_maximum(A):
+    assert oracle.quartic_step(A) is None
+
+
+def test_quartic_step_rule_registration():
+    # The quartic rule takes the model's maximiser each iteration; with it
+    # the registration recovers the motion and G never falls.
+    p = synth.planes_pair(600, seed=21, theta_max_deg=6.0, t_max=0.06)
+    r = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, stage_ell=(0.15,), max_iters=40,
+                        step_rule="quartic", a2=7.0)
+    assert r["rc"] == 0
+    tr = r["trace"]
+    F = tr[:, 0]
+    assert np.all(np.diff(F) > -1e-9 * F[1:])
+    assert rot_angle_deg(r["T"], p.T_true) < 0.5 and trans_err(r["T"], p.T_true) < 0.01
+    # the first step is the model's maximiser along the first gradient
+    c, _ = oracle.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, np.eye(4), tr[0, 1:4], tr[0, 4:7],
+                          ell=0.15)
+    np.testing.assert_allclose(tr[0, 7], oracle.quartic_step(c), rtol=1e-12)
