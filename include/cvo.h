@@ -24,8 +24,18 @@
  *   - v carries the sign obtained by differentiating the kernel (z~ - x); the
  *     paper prints the opposite sign in eq. 3_gradient while its own
  *     differential and Taylor coefficients imply this one.
- *   - Step length (project rule, not the paper's quartic line search):
- *     tau = eta * ell^2 / F.
+ *   - Step length, by params->step_rule:
+ *     CVO_STEP_FIXED    tau = eta * ell^2 / F (a project rule);
+ *     CVO_STEP_QUARTIC  the paper's rule (Sec. VI-B, eq. fourth): tau is the
+ *       t > 0 that maximises the fourth-order Taylor model
+ *       P(t) = F + A1 t + A2 t^2 + A3 t^3 + A4 t^4 of G(t) = F(h exp(t xi))
+ *       along the gradient xi = (omega, v) (the local maximum with the
+ *       largest P when there are two); when P has no maximum on t > 0 the
+ *       fixed rule's tau is taken.  A second pass over the same pairs sums
+ *       A_k = sigma^2 s_f sum_ij <l_i, m_j> e^alpha_ij g^k_ij with the
+ *       exponent's exact Taylor coefficients (alpha .. eps of the moving
+ *       target exp(-t Xi) z~; the printed gamma, delta, eps omit the
+ *       exponential's factorials and signs) and the paper's g^1..g^4.
  *   - With cutoff_mult = kappa > 0 a pair contributes only if
  *     |x_i - z~_j| <= kappa * ell (the paper sparsifies small kernel values,
  *     Section VII-B; here in distance form); kappa = 0 sums all pairs.
@@ -67,6 +77,7 @@ enum {
 };
 
 enum { CVO_FP32_KAHAN = 0, CVO_FP64 = 1 };
+enum { CVO_STEP_FIXED = 0, CVO_STEP_QUARTIC = 1 };
 
 /* One labelled point cloud (Section III-A: points x_i with labels l(x_i) in R^feat_dim). */
 typedef struct {
@@ -93,6 +104,7 @@ typedef struct {
   int32_t precision;        /* CVO_FP32_KAHAN (FP32 pair terms, Kahan FP32 partials, FP64
                                reduction and step) or CVO_FP64 (every pair term in FP64) */
   int32_t trace;            /* 1: keep the per-iteration trace (cvo_trace) */
+  int32_t step_rule;        /* CVO_STEP_FIXED or CVO_STEP_QUARTIC (see the step length above) */
 } cvo_params;
 
 typedef struct {
@@ -124,6 +136,20 @@ int cvo_set_stream(cvo_ctx* ctx, void* hip_stream);
 int cvo_eval(cvo_ctx* ctx, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* params,
              const double T[16], double* F, double omega[3], double v[3]);
 
+/* The fourth-order model of the line G(t) = F(h exp(t xi)) at pose T along
+ * xi = (omega, v) (Sec. VI-B, eq. fourth; h = T^-1), ell = params->stage_ell[0]:
+ * coef = F, A1, A2, A3, A4 with G(t) = coef . (1, t, t^2, t^3, t^4) + O(t^5),
+ * over the pairs inside the cutoff at t = 0.  Along the gradient
+ * A1 = a^2 |omega|^2 + b^2 |v|^2.  omega and v must be finite. */
+int cvo_quartic(cvo_ctx* ctx, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* params,
+                const double T[16], const double omega[3], const double v[3], double coef[5]);
+
+/* The step of CVO_STEP_QUARTIC for given coefficients (host code, the same
+ * rule the step kernel applies): returns 1 and *t = the maximiser over t > 0
+ * of A1 t + A2 t^2 + A3 t^3 + A4 t^4 (coef[1..4]), 0 when it has no local
+ * maximum on t > 0, CVO_EINVAL for null or non-finite input. */
+int cvo_quartic_step(const double coef[5], double* t);
+
 /* Per-target terms of the same double sum: for each selected original target
  * index sel[k] (0 <= sel[k] < tgt->n), out[7k..7k+6] = (F_j, omega_j, v_j),
  * the sums over sources i of the terms of eq. scalar and eq. 3_gradient.
@@ -154,15 +180,16 @@ int cvo_poll(cvo_ctx* ctx, uint64_t ticket, int32_t wait_us, double T_out[16], c
  * of rows written (<= cap) or a negative code. */
 int cvo_trace(cvo_ctx* ctx, uint64_t ticket, double* buf, int32_t cap);
 
-/* Event timing of the two kernels of each iteration (the per-cluster
- * candidate-list kernel and the pair kernel): when enabled, every iteration of
- * cvo_register brackets them with HIP events on the launch stream. */
+/* Event timing of the kernels of each iteration (the per-cluster
+ * candidate-list kernel, the pair kernel and, with the quartic rule, the pair
+ * kernel's second pass): when enabled, every iteration of cvo_register
+ * brackets them with HIP events on the launch stream. */
 int cvo_set_profiling(cvo_ctx* ctx, int32_t enable);
 /* Totals since the last reset: iterations timed, summed device milliseconds of
- * the pair kernel and of the candidate-list kernel, and the pairs within the
- * cutoff evaluated. */
+ * the pair kernel (gradient pass), of the candidate-list kernel and of the
+ * quartic pass, and the pairs within the cutoff evaluated (gradient pass). */
 int cvo_kernel_stats(cvo_ctx* ctx, int32_t reset, int64_t* iterations, double* pair_ms, double* prepare_ms,
-                     uint64_t* pairs);
+                     double* quartic_ms, uint64_t* pairs);
 
 /* Static text for a return code; cvo_last_error gives the last HIP message. */
 const char* cvo_strerror(int code);

@@ -373,61 +373,64 @@ int cvo_oracle_quartic(int n, const float* x, const float* lx, int m, const floa
 
 /*
  * Step of the quartic model P(t) = A1 t + A2 t^2 + A3 t^3 + A4 t^4 (eq.
- * fourth, "the value of t > 0 that maximises the quartic"): among the real
- * roots t > 0 of P'(t) = A1 + 2 A2 t + 3 A3 t^2 + 4 A4 t^3 with P''(t) < 0,
- * the one with the largest P; the roots come from the cubic in closed form
- * (trigonometric case for three real roots).  Returns 1 and *t on success,
- * 0 when P has no local maximum on t > 0 (then the caller falls back).
+ * fourth: the value of t > 0 that maximises the quartic), read as: among the
+ * local maxima of P on t > 0 (points where P' = A1 + 2 A2 t + 3 A3 t^2 +
+ * 4 A4 t^3 changes sign from + to -), the one with the largest P.  P' is
+ * monotone between consecutive roots of P'' (a quadratic), so the real line
+ * t > 0 is cut at those roots and at a bound beyond which P' has no root
+ * (Cauchy's bound); each piece where P' goes from > 0 to <= 0 holds exactly
+ * one such point, found by plain bisection to the last bit.  Returns 1 and
+ * *t on success, 0 when P has no local maximum on t > 0 (then the caller
+ * falls back).  Coefficients whose size is below 1e-14 of the largest are
+ * treated as zero when the degree of P' is decided.
  */
 static double poly4(const double A[5], double t) { return t * (A[1] + t * (A[2] + t * (A[3] + t * A[4]))); }
-static double dd4(const double A[5], double t) { return 2.0 * A[2] + 6.0 * A[3] * t + 12.0 * A[4] * t * t; }
+static double dpoly3(const double c[4], double t) { return c[0] + t * (c[1] + t * (c[2] + t * c[3])); }
 
 int cvo_oracle_quartic_step(const double A[5], double* t_out) {
-    /* P'(t) = a t^3 + b t^2 + c t + d */
-    const double a = 4.0 * A[4], b = 3.0 * A[3], c = 2.0 * A[2], d = A[1];
-    double roots[3];
+    const double c[4] = {A[1], 2.0 * A[2], 3.0 * A[3], 4.0 * A[4]}; /* P' coefficients */
+    double big = 0.0;
+    for (int i = 0; i < 4; i++) big = fmax(big, fabs(c[i]));
+    if (!(big > 0.0) || !isfinite(big)) return 0;
+    int deg = 3;
+    while (deg > 0 && fabs(c[deg]) <= 1e-14 * big) deg--;
+    if (deg == 0) return 0;
+    double cc[4] = {c[0], c[1], deg >= 2 ? c[2] : 0.0, deg >= 3 ? c[3] : 0.0};
+    double bound = 0.0;
+    for (int i = 0; i < deg; i++) bound = fmax(bound, fabs(cc[i] / cc[deg]));
+    bound = 1.0 + bound;
+    /* cut points: 0, the positive roots of P'' = cc1 + 2 cc2 t + 3 cc3 t^2, bound */
+    double cut[4];
+    int nc = 0;
+    cut[nc++] = 0.0;
+    const double qa = 3.0 * cc[3], qb = 2.0 * cc[2], qc = cc[1];
+    double r[2];
     int nr = 0;
-    const double scale = fabs(b) + fabs(c) + fabs(d) + 1e-300;
-    if (fabs(a) <= 1e-14 * scale) {
-        if (fabs(b) <= 1e-14 * (fabs(c) + fabs(d) + 1e-300)) {
-            if (c != 0.0) roots[nr++] = -d / c;
-        } else {
-            const double disc = c * c - 4.0 * b * d;
-            if (disc >= 0.0) {
-                const double s = sqrt(disc);
-                const double q = -0.5 * (c + (c >= 0.0 ? s : -s));
-                roots[nr++] = q / b;
-                if (q != 0.0) roots[nr++] = d / q;
-            }
-        }
-    } else {
-        /* depressed cubic t = y - b/(3a): y^3 + p y + q = 0 */
-        const double B = b / a, C = c / a, D = d / a;
-        const double p = C - B * B / 3.0;
-        const double q = 2.0 * B * B * B / 27.0 - B * C / 3.0 + D;
-        const double disc = q * q / 4.0 + p * p * p / 27.0;
+    if (qa != 0.0) {
+        const double disc = qb * qb - 4.0 * qa * qc;
         if (disc > 0.0) {
-            const double s = sqrt(disc);
-            roots[nr++] = cbrt(-q / 2.0 + s) + cbrt(-q / 2.0 - s) - B / 3.0;
-        } else {
-            const double r = sqrt(-p / 3.0);
-            const double arg = (r > 0.0) ? fmax(-1.0, fmin(1.0, (-q / 2.0) / (r * r * r))) : 0.0;
-            const double phi = acos(arg);
-            for (int kk = 0; kk < 3; kk++)
-                roots[nr++] = 2.0 * r * cos((phi - 2.0 * 3.14159265358979323846 * kk) / 3.0) - B / 3.0;
+            r[nr++] = (-qb - sqrt(disc)) / (2.0 * qa);
+            r[nr++] = (-qb + sqrt(disc)) / (2.0 * qa);
         }
+    } else if (qb != 0.0) {
+        r[nr++] = -qc / qb;
     }
+    if (nr == 2 && r[0] > r[1]) { const double tmp = r[0]; r[0] = r[1]; r[1] = tmp; }
+    for (int i = 0; i < nr; i++)
+        if (r[i] > 0.0 && r[i] < bound) cut[nc++] = r[i];
+    cut[nc++] = bound;
     int found = 0;
-    double best_t = 0.0, best_p = -INFINITY;
-    for (int i = 0; i < nr; i++) {
-        /* one Newton polish on P' */
-        double t = roots[i];
-        const double f = A[1] + t * (2.0 * A[2] + t * (3.0 * A[3] + t * 4.0 * A[4]));
-        const double fp = dd4(A, t);
-        if (fp != 0.0) t -= f / fp;
-        if (!(t > 0.0) || !(dd4(A, t) < 0.0)) continue;
-        const double pv = poly4(A, t);
-        if (!found || pv > best_p) { found = 1; best_t = t; best_p = pv; }
+    double best_t = 0.0, best_p = 0.0;
+    for (int i = 0; i + 1 < nc; i++) {
+        double lo = cut[i], hi = cut[i + 1];
+        if (!(dpoly3(cc, lo) > 0.0 && dpoly3(cc, hi) <= 0.0)) continue;
+        for (;;) {
+            const double mid = lo + 0.5 * (hi - lo);
+            if (!(mid > lo && mid < hi)) break;
+            if (dpoly3(cc, mid) > 0.0) lo = mid; else hi = mid;
+        }
+        const double pv = poly4(A, hi);
+        if (!found || pv > best_p) { found = 1; best_t = hi; best_p = pv; }
     }
     if (found) *t_out = best_t;
     return found;

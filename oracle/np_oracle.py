@@ -130,3 +130,42 @@ def quartic(x, lx, z, lz, T, w, u, *, sigma=0.1, feat_scale=0.2, ell=0.1, kappa=
     if kappa > 0:
         wgt = np.where(-2.0 * ell * ell * e[0] <= (kappa * ell) ** 2, wgt, 0.0)
     return np.array([(wgt * f[k]).sum() for k in range(5)])
+
+
+def quartic_step(A):
+    """t > 0 maximising P(t) = A1 t + A2 t^2 + A3 t^3 + A4 t^4 among its local
+    maxima (largest P), or None.  Roots of P' from the companion-matrix
+    eigenvalues (numpy.roots), polished by Newton's method; a root is a local
+    maximum where P'' < 0 (a simple root).  Leading coefficients below 1e-14
+    of the largest are dropped, as in the C oracle."""
+    c = np.array([A[1], 2.0 * A[2], 3.0 * A[3], 4.0 * A[4]], dtype=np.float64)  # P', ascending
+    big = np.abs(c).max()
+    if not big > 0:
+        return None
+    deg = 3
+    while deg > 0 and abs(c[deg]) <= 1e-14 * big:
+        deg -= 1
+    if deg == 0:
+        return None
+    c = c[: deg + 1]
+    dP = np.polynomial.polynomial.Polynomial(c)
+    ddP = dP.deriv()
+    best = None
+    for z in np.roots(c[::-1]):
+        if abs(z.imag) > 1e-9 * max(1.0, abs(z.real)):
+            continue
+        t = z.real
+        for _ in range(50):
+            f, fp = dP(t), ddP(t)
+            if fp == 0:
+                break
+            tn = t - f / fp
+            if tn == t:
+                break
+            t = tn
+        if not t > 0 or not ddP(t) < 0:
+            continue
+        p = t * (A[1] + t * (A[2] + t * (A[3] + t * A[4])))
+        if best is None or p > best[1]:
+            best = (t, p)
+    return None if best is None else float(best[0])

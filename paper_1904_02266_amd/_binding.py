@@ -26,6 +26,9 @@ CVO_EDEVICE = -5
 CVO_ENOTFOUND = -6
 CVO_FP32_KAHAN = 0
 CVO_FP64 = 1
+CVO_STEP_FIXED = 0
+CVO_STEP_QUARTIC = 1
+STEP_RULES = {"fixed": CVO_STEP_FIXED, "quartic": CVO_STEP_QUARTIC}
 TRACE_COLS = 26
 
 
@@ -42,7 +45,7 @@ class cvo_params(ctypes.Structure):
                 ("stage_iters", ctypes.POINTER(ctypes.c_int32)),
                 ("stage_ell", ctypes.POINTER(ctypes.c_double)),
                 ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("trace", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("trace", ctypes.c_int32), ("step_rule", ctypes.c_int32)]
 
 
 class cvo_result(ctypes.Structure):
@@ -92,14 +95,16 @@ def load():
     L.cvo_poll.argtypes = [vp, u64, i32, P(dbl), P(cvo_result)]
     L.cvo_trace.argtypes = [vp, u64, P(dbl), i32]
     L.cvo_set_profiling.argtypes = [vp, i32]
-    L.cvo_kernel_stats.argtypes = [vp, i32, P(ctypes.c_int64), P(dbl), P(dbl), P(u64)]
+    L.cvo_kernel_stats.argtypes = [vp, i32, P(ctypes.c_int64), P(dbl), P(dbl), P(dbl), P(u64)]
+    L.cvo_quartic.argtypes = [vp, P(cvo_cloud), P(cvo_cloud), P(cvo_params), P(dbl), P(dbl), P(dbl), P(dbl)]
+    L.cvo_quartic_step.argtypes = [P(dbl), P(dbl)]
     L.cvo_strerror.argtypes = [ctypes.c_int]
     L.cvo_strerror.restype = ctypes.c_char_p
     L.cvo_last_error.argtypes = [vp]
     L.cvo_last_error.restype = ctypes.c_char_p
     for name in ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
                  "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
-                 "cvo_kernel_stats"):
+                 "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -107,7 +112,7 @@ def load():
 
 EXPORTED = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
             "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
-            "cvo_kernel_stats", "cvo_strerror", "cvo_last_error")
+            "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_strerror", "cvo_last_error")
 
 
 class CvoError(RuntimeError):
@@ -132,6 +137,7 @@ class Params:
     tol: float = 0.0
     precision: str = "fp32"
     trace: bool = False
+    step_rule: str = "fixed"
 
     def to_c(self):
         ns = len(self.stage_ell)
@@ -140,7 +146,8 @@ class Params:
         p = cvo_params(self.sigma, self.feat_scale, self.a2, self.b2, self.eta, self.cutoff_mult, ns,
                        ctypes.cast(si, ctypes.POINTER(ctypes.c_int32)),
                        ctypes.cast(se, ctypes.POINTER(ctypes.c_double)), self.max_iters, self.tol,
-                       CVO_FP64 if self.precision == "fp64" else CVO_FP32_KAHAN, 1 if self.trace else 0)
+                       CVO_FP64 if self.precision == "fp64" else CVO_FP32_KAHAN, 1 if self.trace else 0,
+                       STEP_RULES[self.step_rule])
         return p, (si, se)
 
 
@@ -196,6 +203,19 @@ def _pose(T):
     return T, T.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def quartic_step(coef):
+    """The quartic rule's step for coefficients (F, A1..A4): the maximiser over
+    t > 0 of A1 t + ... + A4 t^4, or None when it has no local maximum there
+    (host code of the library, the rule the step kernel applies)."""
+    L = load()
+    c = (ctypes.c_double * 5)(*[float(a) for a in coef])
+    t = ctypes.c_double()
+    rc = L.cvo_quartic_step(c, ctypes.byref(t))
+    if rc < 0:
+        raise CvoError(rc, "cvo_quartic_step")
+    return t.value if rc == 1 else None
+
+
 class Context:
     """One library context on one HIP device."""
 
@@ -238,10 +258,13 @@ class Context:
         n = ctypes.c_int64()
         ms = ctypes.c_double()
         prep = ctypes.c_double()
+        quart = ctypes.c_double()
         pairs = ctypes.c_uint64()
         self._check(self.L.cvo_kernel_stats(self.h, 1 if reset else 0, ctypes.byref(n), ctypes.byref(ms),
-                                            ctypes.byref(prep), ctypes.byref(pairs)), "kernel_stats")
-        return dict(launches=n.value, ms=ms.value, prepare_ms=prep.value, pairs=pairs.value)
+                                            ctypes.byref(prep), ctypes.byref(quart), ctypes.byref(pairs)),
+                    "kernel_stats")
+        return dict(launches=n.value, ms=ms.value, prepare_ms=prep.value, quartic_ms=quart.value,
+                    pairs=pairs.value)
 
     def eval(self, src_xyz, src_feat, tgt_xyz, tgt_feat, T, params: Params):
         s, t = _Cloud(src_xyz, src_feat), _Cloud(tgt_xyz, tgt_feat)
@@ -254,6 +277,19 @@ class Context:
         self._check(self.L.cvo_eval(self.h, ctypes.byref(s.c), ctypes.byref(t.c), ctypes.byref(p), Tp,
                                     ctypes.byref(F), w, v), "cvo_eval")
         return np.array([F.value, *w[:], *v[:]])
+
+    def quartic(self, src_xyz, src_feat, tgt_xyz, tgt_feat, T, omega, v, params: Params):
+        """F, A1..A4 of the fourth-order model of G(t) = F(h exp(t (omega, v))) at T."""
+        s, t = _Cloud(src_xyz, src_feat), _Cloud(tgt_xyz, tgt_feat)
+        self._sync_stream([s, t])
+        p, keep = params.to_c()
+        Ta, Tp = _pose(T)
+        w = (ctypes.c_double * 3)(*[float(a) for a in omega])
+        u = (ctypes.c_double * 3)(*[float(a) for a in v])
+        coef = (ctypes.c_double * 5)()
+        self._check(self.L.cvo_quartic(self.h, ctypes.byref(s.c), ctypes.byref(t.c), ctypes.byref(p), Tp, w, u,
+                                       coef), "cvo_quartic")
+        return np.array(coef[:])
 
     def eval_targets(self, src_xyz, src_feat, tgt_xyz, tgt_feat, T, params: Params, sel=None):
         s, t = _Cloud(src_xyz, src_feat), _Cloud(tgt_xyz, tgt_feat)

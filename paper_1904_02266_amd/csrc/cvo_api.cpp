@@ -25,6 +25,7 @@
 
 #include "../../include/cvo.h"
 #include "cvo_internal.h"
+#include "cvo_step.h"
 
 using namespace cvo;
 
@@ -43,6 +44,8 @@ struct Request {
   uint64_t ticket = 0;
   int mode = kModeRegister;
   int n = 0, m = 0, fd = 0, n_stages = 1, max_iters = 1, precision = 0, trace_on = 0;
+  int step_rule = kStepFixed;
+  double xi0[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // direction of the coefficient evaluation
   double sigma = 0.1, sf = 0.2, a2 = -1.0, b2 = 1.0, eta = 1.0, kappa = 0.0, tol = 0.0;
   int stage_iters[kMaxStages] = {0};
   double stage_ell[kMaxStages] = {0.0};
@@ -65,6 +68,7 @@ struct Request {
   int status = CVO_PENDING;
   cvo_result res{};
   double T_out[16];
+  double coef[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // coefficient evaluation: F, A1..A4
   std::vector<double> trace;
   Clock::time_point t_submit;
 };
@@ -116,7 +120,7 @@ Layout plan(const Request& q) {
   L.off_zpart = take(kBboxBlocks * 7 * 8);
   L.off_xbox = take(8 * 8);
   L.off_zbox = take(8 * 8);
-  L.off_T0 = take(16 * 8);
+  L.off_T0 = take(24 * 8);  // T0[16], then the direction xi0[6]
   L.off_ell = take(kMaxStages * 8);
   L.off_grid = take(sizeof(GridInfo) * kMaxStages);
   L.off_ncell = take(4 * (kMaxStages + 1));
@@ -253,6 +257,7 @@ struct cvo_ctx {
   int64_t prof_launches = 0;
   double prof_ms = 0.0;          // pair kernel
   double prof_prep_ms = 0.0;     // prepare kernel
+  double prof_quart_ms = 0.0;    // pair kernel, quartic pass
   uint64_t prof_pairs = 0;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
 
@@ -308,6 +313,7 @@ static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
   if (p->n_stages > 1 && !p->stage_iters) return CVO_EINVAL;
   if (p->max_iters < 1 || !(p->tol >= 0.0)) return CVO_EINVAL;
   if (p->precision != CVO_FP32_KAHAN && p->precision != CVO_FP64) return CVO_EINVAL;
+  if (p->step_rule != CVO_STEP_FIXED && p->step_rule != CVO_STEP_QUARTIC) return CVO_EINVAL;
   for (int s = 0; s < p->n_stages; s++) {
     if (!(p->stage_ell[s] > 0.0) || !std::isfinite(p->stage_ell[s])) return CVO_EINVAL;
     if (s < p->n_stages - 1 && p->stage_iters[s] < 1) return CVO_EINVAL;
@@ -322,6 +328,7 @@ static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
   q.max_iters = (mode == kModeRegister) ? p->max_iters : 1;
   q.precision = p->precision;
   q.trace_on = (mode == kModeRegister) ? (p->trace ? 1 : 0) : 0;
+  q.step_rule = (mode == kModeRegister) ? p->step_rule : (mode == kModeQuartic ? kStepQuartic : kStepFixed);
   q.sigma = p->sigma;
   q.sf = p->feat_scale;
   q.a2 = p->a2;
@@ -352,7 +359,7 @@ static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
 static int enqueue_ingest(cvo_ctx* c, Request& q, const Layout& L, hipStream_t s, void* pinned_scratch) {
   char* A = q.arena;
   struct Staging {
-    double T0[16];
+    double T0[24];
     double ell[kMaxStages];
     SortSeg segs[kMaxStages + 1];
     ScanArgs scans[kMaxStages + 1];
@@ -361,7 +368,9 @@ static int enqueue_ingest(cvo_ctx* c, Request& q, const Layout& L, hipStream_t s
   };
   static_assert(sizeof(Staging) < 16384, "staging area");
   Staging* h = (Staging*)pinned_scratch;
-  memcpy(h->T0, q.T0, sizeof(h->T0));
+  memset(h->T0, 0, sizeof(h->T0));
+  memcpy(h->T0, q.T0, sizeof(q.T0));
+  memcpy(h->T0 + 16, q.xi0, sizeof(q.xi0));
   for (int k = 0; k < kMaxStages; k++) h->ell[k] = (k < q.n_stages) ? q.stage_ell[k] : 1.0;
   const int S = q.n_stages;
   int* ncell = (int*)(A + L.off_ncell);
@@ -425,6 +434,7 @@ static int enqueue_ingest(cvo_ctx* c, Request& q, const Layout& L, hipStream_t s
   a.kcap = L.kcap;
   a.a2_param = q.a2;
   a.T0 = (const double*)(A + L.off_T0);
+  a.xi0 = (q.mode == kModeQuartic) ? (const double*)(A + L.off_T0) + 16 : nullptr;
   a.stage_ell = (const double*)(A + L.off_ell);
   a.xpart = (double*)(A + L.off_xpart);
   a.zpart = (double*)(A + L.off_zpart);
@@ -497,6 +507,7 @@ static int finish_setup(cvo_ctx* c, Request& q, const Layout& L, const LayoutB& 
   st.max_iters = q.max_iters;
   st.mode = q.mode;
   st.precision = q.precision;
+  st.step_rule = q.step_rule;
   int end = 0;
   for (int k = 0; k < kMaxStages; k++) {
     if (k < S - 1) {
@@ -539,6 +550,7 @@ static void fill_result(Request& q, const ReqState& hs) {
     q.res.omega[a] = hs.g[1 + a];
     q.res.v[a] = hs.g[4 + a];
   }
+  for (int i = 0; i < 5; i++) q.coef[i] = hs.A[i];
   q.res.pairs_within = hs.pairs_within;
   q.res.pairs_examined = hs.pairs_examined;
   for (int k = 0; k < 12; k++) q.T_out[k] = hs.T[k];
@@ -614,8 +626,9 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
   const QueueRef QR = c->queue_sync.ref();
   const bool cut = q.kappa > 0.0;
   const bool prof = c->profile && q.mode == kModeRegister;
-  if (prof && (int)c->ev_pool.size() < 3 * q.max_iters) {
-    while ((int)c->ev_pool.size() < 3 * q.max_iters) {
+  constexpr int kEv = 5;  // events per timed iteration
+  if (prof && (int)c->ev_pool.size() < kEv * q.max_iters) {
+    while ((int)c->ev_pool.size() < kEv * q.max_iters) {
       hipEvent_t e;
       HIPCHK(c, hipEventCreate(&e));
       c->ev_pool.push_back(e);
@@ -627,14 +640,25 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
     const int kend = std::min(q.max_iters, k + chunk);
     for (; k < kend; k++) {
       if (prof) {
-        HIPCHK(c, hipEventRecord(c->ev_pool[3 * k], s));
+        hipEvent_t* ev = &c->ev_pool[kEv * k];
+        HIPCHK(c, hipEventRecord(ev[0], s));
         HIPCHK(c, launch_prepare(c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR, s));
-        HIPCHK(c, hipEventRecord(c->ev_pool[3 * k + 1], s));
+        HIPCHK(c, hipEventRecord(ev[1], s));
         HIPCHK(c, launch_pair_kernel(q.precision, q.fd, cut, c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR, s));
-        HIPCHK(c, hipEventRecord(c->ev_pool[3 * k + 2], s));
-        HIPCHK(c, launch_step(c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR, s));
+        HIPCHK(c, hipEventRecord(ev[2], s));
+        if (q.step_rule == kStepQuartic) {
+          HIPCHK(c, launch_step(c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR, s, kPhaseGradient, false));
+          HIPCHK(c, hipEventRecord(ev[3], s));
+          HIPCHK(c, launch_quartic_pairs(q.precision, q.fd, cut, c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR,
+                                         s));
+          HIPCHK(c, hipEventRecord(ev[4], s));
+          HIPCHK(c, launch_step(c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR, s, kPhaseQuartic, true));
+        } else {
+          HIPCHK(c, launch_step(c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR, s));
+        }
       } else {
-        HIPCHK(c, launch_iteration(q.precision, q.fd, cut, c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR, s));
+        HIPCHK(c, launch_iteration_rule(q.step_rule, q.precision, q.fd, cut, c->d_reqs_sync, c->d_clus_end_sync, 1,
+                                        q.nclus, QR, s));
       }
       launched++;
     }
@@ -663,17 +687,21 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
   q.res.gpu_ms = ms;
   if (prof) {
-    double tot = 0.0, prep = 0.0;
+    double tot = 0.0, prep = 0.0, quart = 0.0;
     for (int k = 0; k < launched; k++) {
-      float e1 = 0.f, e2 = 0.f;
-      HIPCHK(c, hipEventElapsedTime(&e1, c->ev_pool[3 * k], c->ev_pool[3 * k + 1]));
-      HIPCHK(c, hipEventElapsedTime(&e2, c->ev_pool[3 * k + 1], c->ev_pool[3 * k + 2]));
+      const hipEvent_t* ev = &c->ev_pool[kEv * k];
+      float e1 = 0.f, e2 = 0.f, e3 = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&e1, ev[0], ev[1]));
+      HIPCHK(c, hipEventElapsedTime(&e2, ev[1], ev[2]));
+      if (q.step_rule == kStepQuartic) HIPCHK(c, hipEventElapsedTime(&e3, ev[3], ev[4]));
       prep += e1;
       tot += e2;
+      quart += e3;
     }
     c->prof_launches += launched;
     c->prof_ms += tot;
     c->prof_prep_ms += prep;
+    c->prof_quart_ms += quart;
     c->prof_pairs += hs->pairs_within;
   }
   q.res.wall_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
@@ -776,8 +804,9 @@ void scheduler(cvo_ctx* c) {
     if (active.empty()) continue;
 
     // one launch pair per iteration per kernel variant, for all active requests
-    std::map<std::tuple<int, int, int>, std::vector<Request*>> groups;
-    for (Request* q : active) groups[std::make_tuple(q->precision, q->fd, q->kappa > 0.0 ? 1 : 0)].push_back(q);
+    std::map<std::tuple<int, int, int, int>, std::vector<Request*>> groups;
+    for (Request* q : active)
+      groups[std::make_tuple(q->precision, q->fd, q->kappa > 0.0 ? 1 : 0, q->step_rule)].push_back(q);
     const int nreq = (int)active.size();
     if (nreq > cap_reqs) {
       if (d_reqs) (void)hipFree(d_reqs);
@@ -793,13 +822,14 @@ void scheduler(cvo_ctx* c) {
       (void)hipHostMalloc(&h_states, sizeof(ReqState) * cap_reqs, hipHostMallocDefault);
     }
     struct G {
-      int precision, fd, cut, first, count, clusters;
+      int precision, fd, cut, rule, first, count, clusters;
     };
     std::vector<G> gl;
     int pos = 0;
     std::vector<Request*> order;
     for (auto& kv : groups) {
-      G g{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), pos, (int)kv.second.size(), 0};
+      G g{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first), pos,
+          (int)kv.second.size(), 0};
       int cl = 0;
       for (Request* q : kv.second) {
         h_reqs[pos] = q->st;
@@ -819,8 +849,8 @@ void scheduler(cvo_ctx* c) {
                   hipMemcpyAsync(d_end, h_end, sizeof(int) * nreq, hipMemcpyHostToDevice, s) == hipSuccess;
     for (int it = 0; it < chunk && dev_ok; it++) {
       for (const G& g : gl) {
-        if (launch_iteration(g.precision, g.fd, g.cut != 0, d_reqs + g.first, d_end + g.first, g.count, g.clusters,
-                             queue.ref(), s) != hipSuccess)
+        if (launch_iteration_rule(g.rule, g.precision, g.fd, g.cut != 0, d_reqs + g.first, d_end + g.first, g.count,
+                                  g.clusters, queue.ref(), s) != hipSuccess)
           dev_ok = false;
       }
     }
@@ -930,17 +960,19 @@ int cvo_set_profiling(cvo_ctx* c, int32_t enable) {
 }
 
 int cvo_kernel_stats(cvo_ctx* c, int32_t reset, int64_t* launches, double* pair_ms, double* prepare_ms,
-                     uint64_t* pairs) {
+                     double* quartic_ms, uint64_t* pairs) {
   if (!c) return CVO_EINVAL;
   std::lock_guard<std::mutex> g(c->call_mu);
   if (launches) *launches = c->prof_launches;
   if (pair_ms) *pair_ms = c->prof_ms;
   if (prepare_ms) *prepare_ms = c->prof_prep_ms;
+  if (quartic_ms) *quartic_ms = c->prof_quart_ms;
   if (pairs) *pairs = c->prof_pairs;
   if (reset) {
     c->prof_launches = 0;
     c->prof_ms = 0.0;
     c->prof_prep_ms = 0.0;
+    c->prof_quart_ms = 0.0;
     c->prof_pairs = 0;
   }
   return CVO_OK;
@@ -962,6 +994,33 @@ int cvo_eval(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
     if (v) v[a] = q.res.v[a];
   }
   return CVO_OK;
+}
+
+int cvo_quartic(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* p, const double T[16],
+                const double omega[3], const double v[3], double coef[5]) {
+  if (!c || !omega || !v || !coef) return CVO_EINVAL;
+  for (int a = 0; a < 3; a++)
+    if (!std::isfinite(omega[a]) || !std::isfinite(v[a])) return CVO_EINVAL;
+  Request q;
+  int rc = build_request(src, tgt, p, T, kModeQuartic, q);
+  if (rc) return rc;
+  for (int a = 0; a < 3; a++) {
+    q.xi0[a] = omega[a];
+    q.xi0[3 + a] = v[a];
+  }
+  std::lock_guard<std::mutex> g(c->call_mu);
+  rc = run_sync(c, q, nullptr);
+  if (rc) return rc;
+  if (q.status) return q.status;
+  for (int i = 0; i < 5; i++) coef[i] = q.coef[i];
+  return CVO_OK;
+}
+
+int cvo_quartic_step(const double coef[5], double* t) {
+  if (!coef || !t) return CVO_EINVAL;
+  for (int i = 1; i < 5; i++)
+    if (!std::isfinite(coef[i])) return CVO_EINVAL;
+  return quartic_argmax(coef, t) ? 1 : 0;
 }
 
 int cvo_eval_targets(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* p,

@@ -28,7 +28,14 @@ constexpr int kScanPerThread = 16;  // multi-block scan: elements per thread
 constexpr int kScanBlock = 1024;    // multi-block scan: threads per block
 constexpr int kScanTile = kScanPerThread * kScanBlock;
 
-enum Mode : int { kModeRegister = 0, kModeEval = 1, kModeEvalTargets = 2 };
+enum Mode : int { kModeRegister = 0, kModeEval = 1, kModeEvalTargets = 2, kModeQuartic = 3 };
+// Step rules: tau = eta ell^2 / F, or the maximiser of the fourth-order model
+// of G(t) = F(h exp(t xi)) along the gradient (second pair pass).
+enum StepRule : int { kStepFixed = 0, kStepQuartic = 1 };
+// Phases of the step kernel: the whole step (fixed rule); the gradient only
+// (first pass of the quartic rule, or of a coefficient evaluation); the
+// quartic step from the second pass's sums.
+enum StepPhase : int { kPhaseFixed = 0, kPhaseGradient = 1, kPhaseQuartic = 2 };
 
 // Geometry of one source grid (one per length-scale stage), written on the device.
 struct GridInfo {
@@ -106,6 +113,7 @@ struct ReqStatic {
   double* per_target;                // [m][7] or null (per-target terms, eval-targets mode)
   int m, n, fd, zs, xs, nclus;        // nclus: the largest cluster count over the stages
   int n_stages, max_iters, mode, precision;
+  int step_rule, pad_rule;
   int stage_end[kMaxStages];         // iteration index where stage s ends; last = INT_MAX
   double stage_ell[kMaxStages];
   double s2f;                        // sigma^2 * s_f
@@ -116,6 +124,9 @@ struct ReqStatic {
 struct ReqState {
   double T[12];                      // rows 0..2 of the pose acting on target points
   double g[7];                       // F, omega, v at the last evaluated pose
+  double xi[6];                      // direction (omega, v) of the second (quartic) pass
+  double A[5];                       // F and the model coefficients A1..A4 of the last quartic pass
+  unsigned long long last_pairs;     // pairs within the cutoff of the last gradient pass
   double a2;                         // rotational metric weight (device-computed default)
   double tau;
   unsigned long long pairs_within, pairs_examined;
@@ -158,6 +169,7 @@ struct IngestArgs {
   int cells_per_reach, brute_div, kcap;
   double a2_param;
   const double* T0;          // device [16]
+  const double* xi0;         // device [6] direction of the quartic pass (kModeQuartic) or null
   const double* stage_ell;   // device [n_stages]
   double *xpart, *zpart, *xbox, *zbox;
   GridInfo* grid;
@@ -189,9 +201,16 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // kernel leaves it zero); one queue serves one stream.
 hipError_t launch_iteration(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end,
                             int nreq, int total_clusters, const QueueRef& Q, hipStream_t s);
-// the kernels of an iteration, separately (for event timing)
+// With step_rule == kStepQuartic (all requests of the launch) the iteration
+// is prepare, pairs, reduce, gradient, quartic pairs, reduce, quartic step.
+hipError_t launch_iteration_rule(int step_rule, int precision, int fd, bool cutoff, const ReqStatic* reqs,
+                                 const int* clus_end, int nreq, int total_clusters, const QueueRef& Q, hipStream_t s);
+// the kernels of an iteration, separately (for event timing).  reset: the
+// reduce kernel clears the work list (the last reduce of an iteration).
 hipError_t launch_step(const ReqStatic* reqs, const int* clus_end, int nreq, int total_clusters, const QueueRef& Q,
-                       hipStream_t s);
+                       hipStream_t s, int phase = kPhaseFixed, bool reset = true);
+hipError_t launch_quartic_pairs(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end,
+                                int nreq, int total_clusters, const QueueRef& Q, hipStream_t s);
 hipError_t launch_prepare(const ReqStatic* reqs, const int* clus_end, int nreq, int total_clusters, const QueueRef& Q,
                           hipStream_t s);
 hipError_t launch_pair_kernel(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end, int nreq,

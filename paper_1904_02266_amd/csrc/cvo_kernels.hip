@@ -1,23 +1,28 @@
 // HIP kernels (gfx950) for continuous sensor registration.
 //
-// Hot path, per gradient-flow iteration (three launches for all active requests):
+// Hot path, per gradient-flow iteration (launches shared by all active
+// requests of one kernel variant):
 //   k_prepare  one wavefront per cluster of <= 64 spatially sorted targets:
-//              z~_j = T z_j in FP64, cluster bounding box and sphere, the
-//              compacted list of reachable non-empty source cells of the
-//              current length-scale grid, candidate count, work chunks.
-//   k_pairs    one wavefront per (cluster, slice of the cluster's candidate
-//              sources, up to 16 slices): the slice is staged in the wave's
-//              LDS area (cluster-relative FP32 coordinates) and paired, at a
-//              wave-uniform LDS address, with the cluster's targets (one per
-//              lane), FP32 pair terms
+//              z~_j = T z_j in FP64, the cluster frame (origin, scaled
+//              relative targets, bounding box), the compacted list of
+//              reachable non-empty source cells of the current length-scale
+//              grid, and the cut of the cluster's candidates into work items.
+//   k_pairs    persistent workgroups over the work items: each item's
+//              candidate sources are culled against the cluster box, staged
+//              in the wave's LDS area and paired with the cluster's targets
+//              (one per lane), FP32 pair terms
 //                  d = z~_j - x_i, r^2, e = exp(-r^2/(2 l^2)), c = <l_i, m_j>,
 //                  W_j += c e, D_j += c e d          (eq. scalar, eq. 3_gradient)
-//              with compensated (Kahan) FP32 partials per lane, an FP64
-//              wave reduction, and the block's four slices summed in order
-//              into one slot per (cluster, block).
+//              with compensated (Kahan) FP32 partials per lane and an FP64
+//              wave reduction into the item's row.
+//   k_reduce   one wavefront per cluster: the cluster's item rows, in order.
 //   k_step     one block per request: a fixed FP64 reduction tree over the
-//              block slots, F, omega, v and the FP64 exponential-map step
+//              cluster rows, F, omega, v and the FP64 exponential-map step
 //              (eq. step, eq. newstep) applied to the pose.
+// With the quartic step rule (Sec. VI-B, eq. fourth) k_step first stores the
+// gradient only; a second k_pairs pass over the same items sums the Taylor
+// coefficients A1..A4 of G(t) = F(h exp(t xi)) along it, and a second
+// k_reduce / k_step pair takes the maximiser of the quartic as the step.
 //
 // Set-up kernels (once per registration): bounding boxes and the default
 // a^2 (FP64), one source grid per length-scale stage (deterministic counting
@@ -27,8 +32,10 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <type_traits>
 
 #include "cvo_internal.h"
+#include "cvo_step.h"
 
 namespace cvo {
 
@@ -614,10 +621,133 @@ __device__ __forceinline__ void one_pair(const CT* __restrict__ r, CT zx, CT zy,
   acc.dz += w * dz;
 }
 
-// All sources of one cell segment [a, b) against the lane's target.
+// The gradient pass's per-lane state: the lane's target (frame
+// coordinates, labels), the cutoff and the accumulators.
 template <typename CT, int FD, bool CUT>
-__device__ __forceinline__ void cell_segment(cptr<CT> xr, int xs, int a, int b, CT zx, CT zy, CT zz,
-                                             const CT (&mj)[FD], CT rc2, Acc<CT>& acc, unsigned long long& within) {
+struct GradOp {
+  CT zx, zy, zz;
+  CT mj[FD];
+  CT rc2;
+  Acc<CT> acc;
+  unsigned long long within;
+  __device__ __forceinline__ void pair(const CT* r) { one_pair<CT, FD, CUT>(r, zx, zy, zz, mj, rc2, acc, within); }
+  __device__ __forceinline__ void fold() { acc.fold(); }
+};
+
+// Accumulators of the quartic pass: the four coefficient sums.
+template <typename CT>
+struct Acc4;
+template <>
+struct Acc4<float> {
+  float a[4], s[4], c[4];
+  __device__ void init() {
+#pragma unroll
+    for (int q = 0; q < 4; q++) a[q] = s[q] = c[q] = 0.0f;
+  }
+  __device__ void fold() {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      Acc<float>::kahan(s[q], c[q], a[q]);
+      a[q] = 0.0f;
+    }
+  }
+  __device__ void result(double (&out)[4]) {
+    fold();
+#pragma unroll
+    for (int q = 0; q < 4; q++) out[q] = (double)s[q] - (double)c[q];
+  }
+};
+template <>
+struct Acc4<double> {
+  double a[4];
+  __device__ void init() {
+#pragma unroll
+    for (int q = 0; q < 4; q++) a[q] = 0.0;
+  }
+  __device__ void fold() {}
+  __device__ void result(double (&out)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) out[q] = a[q];
+  }
+};
+
+// The quartic pass (Sec. VI-B, eq. fourth) in the frame's scaled units
+// (d^ = s d with s^2 = 1 / (2 ell^2 ln 2), so that -|d|^2/(2 ell^2) =
+// -ln2 |d^|^2).  With dk = z~ - x (scaled) and per target
+//   u1 = w x z~ + v, u_{k+1} = w x u_k   (the moving target's derivatives),
+//   p1 = 2 ln2 u1^, p2 = -ln2 u2^, p3 = ln2/3 u3^, p4 = -ln2/12 u4^,
+//   c2 = -ln2 |u1^|^2, c3 = ln2 <u1^,u2^>, c4 = -ln2 (|u2^|^2/4 + <u1^,u3^>/3),
+// the exponent of the kernel along the line is
+//   alpha + beta t + gamma t^2 + delta t^3 + eps t^4 + O(t^5),
+//   beta = <dk,p1>, gamma = c2 + <dk,p2>, delta = c3 + <dk,p3>, eps = c4 + <dk,p4>,
+// and the pair adds w g^k with
+//   g1 = beta, g2 = gamma + beta^2/2, g3 = delta + beta gamma + beta^3/6,
+//   g4 = eps + beta delta + beta^2 gamma/2 + gamma^2/2 + beta^4/24
+//      = eps + beta delta + g2^2/2 - beta^4/12.
+template <typename CT, int FD, bool CUT>
+struct QuartOp {
+  CT zx, zy, zz;
+  CT mj[FD];
+  CT rc2;
+  CT p[4][3];
+  CT c2, c3, c4;
+  Acc4<CT> acc;
+  __device__ __forceinline__ void pair(const CT* r) {
+    const CT dx = zx - r[0];
+    const CT dy = zy - r[1];
+    const CT dz = zz - r[2];
+    const CT r2 = dx * dx + dy * dy + dz * dz;
+    const CT e = kexp2(-r2);
+    CT c = r[3] * mj[0];
+#pragma unroll
+    for (int f = 1; f < FD; f++) c += r[3 + f] * mj[f];
+    CT w = c * e;
+    if (CUT) w = (r2 <= rc2) ? w : (CT)0;
+    const CT be = dx * p[0][0] + dy * p[0][1] + dz * p[0][2];
+    const CT ga = c2 + dx * p[1][0] + dy * p[1][1] + dz * p[1][2];
+    const CT de = c3 + dx * p[2][0] + dy * p[2][1] + dz * p[2][2];
+    const CT ep = c4 + dx * p[3][0] + dy * p[3][1] + dz * p[3][2];
+    const CT b2 = be * be;
+    const CT g2 = b2 * (CT)0.5 + ga;
+    const CT g3 = be * (b2 * (CT)(1.0 / 6.0) + ga) + de;
+    const CT g4 = (be * de + ep) + g2 * ((CT)0.5 * g2) - b2 * (b2 * (CT)(1.0 / 12.0));
+    acc.a[0] += w * be;
+    acc.a[1] += w * g2;
+    acc.a[2] += w * g3;
+    acc.a[3] += w * g4;
+  }
+  __device__ __forceinline__ void fold() { acc.fold(); }
+  // per-target vectors from the direction (w, v) and the target's position
+  // zt (m), in FP64; lanes past the cluster get zero (their pairs have w = 0
+  // and finite g)
+  __device__ void setup(const double* __restrict__ xi, const double (&zt)[3], double s, bool valid) {
+    const double w0 = xi[0], w1 = xi[1], w2 = xi[2];
+    double u[4][3];
+    u[0][0] = w1 * zt[2] - w2 * zt[1] + xi[3];
+    u[0][1] = w2 * zt[0] - w0 * zt[2] + xi[4];
+    u[0][2] = w0 * zt[1] - w1 * zt[0] + xi[5];
+    for (int q = 1; q < 4; q++) {
+      u[q][0] = w1 * u[q - 1][2] - w2 * u[q - 1][1];
+      u[q][1] = w2 * u[q - 1][0] - w0 * u[q - 1][2];
+      u[q][2] = w0 * u[q - 1][1] - w1 * u[q - 1][0];
+    }
+    for (int q = 0; q < 4; q++)
+      for (int a = 0; a < 3; a++) u[q][a] = valid ? u[q][a] * s : 0.0;
+    const double ln2 = 0.69314718055994530942;
+    const double f[4] = {2.0 * ln2, -ln2, ln2 / 3.0, -ln2 / 12.0};
+    for (int q = 0; q < 4; q++)
+      for (int a = 0; a < 3; a++) p[q][a] = (CT)(f[q] * u[q][a]);
+    auto dot = [&](int i, int j) { return u[i][0] * u[j][0] + u[i][1] * u[j][1] + u[i][2] * u[j][2]; };
+    c2 = (CT)(-ln2 * dot(0, 0));
+    c3 = (CT)(ln2 * dot(0, 1));
+    c4 = (CT)(-ln2 * (0.25 * dot(1, 1) + dot(0, 2) / 3.0));
+    acc.init();
+  }
+};
+
+// All sources of one cell segment [a, b) against the lane's target.
+template <typename CT, int FD, typename Op>
+__device__ __forceinline__ void cell_segment(cptr<CT> xr, int xs, int a, int b, Op& op) {
   constexpr int NR = 3 + FD;
   constexpr int U = 4;
   for (int b0 = a; b0 < b; b0 += kBlock) {
@@ -630,15 +760,15 @@ __device__ __forceinline__ void cell_segment(cptr<CT> xr, int xs, int a, int b, 
 #pragma unroll
         for (int q = 0; q < NR; q++) rec[u][q] = xr[(size_t)(i + u) * xs + q];
 #pragma unroll
-      for (int u = 0; u < U; u++) one_pair<CT, FD, CUT>(rec[u], zx, zy, zz, mj, rc2, acc, within);
+      for (int u = 0; u < U; u++) op.pair(rec[u]);
     }
     for (; i < b1; i++) {
       CT rec[NR];
 #pragma unroll
       for (int q = 0; q < NR; q++) rec[q] = xr[(size_t)i * xs + q];
-      one_pair<CT, FD, CUT>(rec, zx, zy, zz, mj, rc2, acc, within);
+      op.pair(rec);
     }
-    acc.fold();
+    op.fold();
   }
 }
 
@@ -970,47 +1100,41 @@ __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ r
   }
 }
 
-template <typename CT, int FD, bool CUT>
+template <typename CT, int FD, typename Op>
 __device__ __forceinline__ void run_cell(const GridInfo& g, cptr<CT> xr, int xs, int key, int a, int b,
-                                         const double (&zt)[3], bool valid, const CT (&mj)[FD], CT rc2, Acc<CT>& acc,
-                                         unsigned long long& within) {
+                                         const double (&zt)[3], bool valid, Op& op) {
   const int cx = key % g.nx, cy = (key / g.nx) % g.ny, cz = key / (g.nx * g.ny);
   // lanes past the end of the cluster sit far outside every cell: their
   // pairs fail the cutoff test and their kernel values underflow to 0
   const CT far = (CT)1e30;
-  const CT zx = valid ? (CT)((zt[0] - (g.ox + cx * g.h)) * g.sq) : far;
-  const CT zy = valid ? (CT)((zt[1] - (g.oy + cy * g.h)) * g.sq) : far;
-  const CT zz = valid ? (CT)((zt[2] - (g.oz + cz * g.h)) * g.sq) : far;
-  cell_segment<CT, FD, CUT>(xr, xs, a, b, zx, zy, zz, mj, rc2, acc, within);
+  op.zx = valid ? (CT)((zt[0] - (g.ox + cx * g.h)) * g.sq) : far;
+  op.zy = valid ? (CT)((zt[1] - (g.oy + cy * g.h)) * g.sq) : far;
+  op.zz = valid ? (CT)((zt[2] - (g.oz + cz * g.h)) * g.sq) : far;
+  cell_segment<CT, FD, Op>(xr, xs, a, b, op);
 }
 
-// F, omega, v from the request's summed terms, and the exponential-map step
-// (one thread).
-__device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S, const double (&acc)[kSlot]) {
-  const int stage = S->stage;
-  const double ell = R.stage_ell[stage];
+// F, omega, v from the request's summed terms.
+__device__ void gradient_from_sums(const ReqStatic& R, ReqState* __restrict__ S, const double (&acc)[kSlot],
+                                   double (&g)[7]) {
+  const double ell = R.stage_ell[S->stage];
   const double il2 = 1.0 / (ell * ell);
-  double g[7];
   g[0] = R.s2f * acc[0];
   for (int a = 0; a < 3; a++) {
     g[1 + a] = R.s2f * acc[1 + a] * il2 / S->a2;
     g[4 + a] = R.s2f * acc[4 + a] * il2 / R.b2;
   }
   for (int q = 0; q < 7; q++) S->g[q] = g[q];
-  const unsigned long long pairs = (unsigned long long)acc[7];
-  S->pairs_within += pairs;
+  S->pairs_within += (unsigned long long)acc[7];
   S->pairs_examined += (unsigned long long)acc[8];
+}
 
-  if (R.mode != kModeRegister) {
-    S->done = 1;
-    return;
-  }
-  if (!(g[0] > 1e-300)) {
-    S->status = -4;  // no pairs in range
-    S->done = 1;
-    return;
-  }
-  const double tau = R.eta * ell * ell / g[0];
+// The exponential-map step h <- h exp(tau xi), xi = (omega, v) = S->g
+// (T <- Exp(-tau xi) T), the trace row, the stopping test and the stage
+// schedule.
+__device__ void take_step(const ReqStatic& R, ReqState* __restrict__ S, double tau, double pairs) {
+  const int stage = S->stage;
+  const double ell = R.stage_ell[stage];
+  const double* g = S->g;
   S->tau = tau;
   const double w[3] = {-tau * g[1], -tau * g[2], -tau * g[3]};
   const double u[3] = {-tau * g[4], -tau * g[5], -tau * g[6]};
@@ -1024,7 +1148,7 @@ __device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S, con
     for (int q = 0; q < 7; q++) tr[q] = g[q];
     tr[7] = tau;
     tr[8] = ell;
-    tr[9] = (double)pairs;
+    tr[9] = pairs;
     for (int q = 0; q < 12; q++) tr[10 + q] = T[q];
     tr[22] = 0.0;
     tr[23] = 0.0;
@@ -1042,6 +1166,59 @@ __device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S, con
     S->done = 1;
   }
   if (stage < R.n_stages - 1 && kn >= R.stage_end[stage]) S->stage = stage + 1;
+}
+
+// The step kernel's work for one request (one thread), by phase:
+//  kPhaseFixed     F, omega, v, then the step tau = eta ell^2 / F;
+//  kPhaseGradient  F, omega, v only; the direction of the quartic pass is the
+//                  gradient (register mode) or the caller's (coefficient mode);
+//  kPhaseQuartic   the quartic model's coefficients from the second pass's
+//                  sums, then the step at its maximiser (tau = eta ell^2 / F
+//                  when the model has no maximum on t > 0).
+__device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S, const double (&acc)[kSlot], int phase) {
+  if (phase == kPhaseQuartic) {
+    S->A[0] = S->g[0];
+    for (int q = 0; q < 4; q++) S->A[1 + q] = R.s2f * acc[q];
+    if (R.mode != kModeRegister) {
+      S->done = 1;
+      return;
+    }
+    // Along the gradient, A1 = G'(0) = <grad F, xi> = a^2 |omega|^2 + b^2 |v|^2
+    // over the same pairs.  Taken from this identity in FP64: near
+    // convergence the terms of the summed A1 cancel to a small remainder
+    // that the FP32 pair terms resolve only to their rounding, and the step
+    // is about -A1 / (2 A2).
+    const double* xi = S->xi;
+    S->A[1] = S->a2 * (xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]) +
+              R.b2 * (xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
+    const double ell = R.stage_ell[S->stage];
+    double tau = R.eta * ell * ell / S->g[0];
+    double t;
+    if (quartic_argmax(S->A, &t)) tau = t;
+    take_step(R, S, tau, (double)S->last_pairs);
+    return;
+  }
+  double g[7];
+  gradient_from_sums(R, S, acc, g);
+  if (R.mode == kModeQuartic) {
+    return;  // the caller's direction is already in S->xi
+  }
+  if (R.mode != kModeRegister) {
+    S->done = 1;
+    return;
+  }
+  if (!(g[0] > 1e-300)) {
+    S->status = -4;  // no pairs in range
+    S->done = 1;
+    return;
+  }
+  if (phase == kPhaseGradient) {
+    for (int q = 0; q < 6; q++) S->xi[q] = g[1 + q];
+    S->last_pairs = (unsigned long long)acc[7];
+    return;
+  }
+  const double ell = R.stage_ell[S->stage];
+  take_step(R, S, R.eta * ell * ell / g[0], acc[7]);
 }
 
 // Wave-local LDS ordering between the lanes of one wavefront.  The LDS
@@ -1099,11 +1276,10 @@ struct Batch {
 // (64 cell entries, one per lane) stays in registers; a position's entry is
 // found from a bitmask of the entry boundaries inside the batch.  Returns the
 // number of sources paired.
-template <typename CT, int FD, bool CUT>
+template <typename CT, int FD, bool CUT, typename Op>
 __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const ClusInfo& ci, int c, int k,
-                                                     long long lo_s, long long hi_s, CT zx, CT zy, CT zz,
-                                                     const CT (&mj)[FD], CT rc2, Acc<CT>& acc,
-                                                     unsigned long long& within, cptr<CT> xr, int xs, CT* recs) {
+                                                     long long lo_s, long long hi_s, CT rc2, Op& op, cptr<CT> xr,
+                                                     int xs, CT* recs) {
   constexpr int RS = RecStride<FD>::value;
   constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
   static_assert(NR % kWave == 0 && NR >= kWave, "a staging round holds at least one batch");
@@ -1193,15 +1369,15 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const C
 #pragma unroll
           for (int q = 0; q < 3 + FD; q++) r4[u][q] = recs[(i + u) * RS + q];
 #pragma unroll
-        for (int u = 0; u < U; u++) one_pair<CT, FD, CUT>(r4[u], zx, zy, zz, mj, rc2, acc, within);
+        for (int u = 0; u < U; u++) op.pair(r4[u]);
       }
       for (; i < b1; i++) {
         CT r1[3 + FD];
 #pragma unroll
         for (int q = 0; q < 3 + FD; q++) r1[q] = recs[i * RS + q];
-        one_pair<CT, FD, CUT>(r1, zx, zy, zz, mj, rc2, acc, within);
+        op.pair(r1);
       }
-      acc.fold();
+      op.fold();
     }
     paired += count;
     count = 0;
@@ -1274,9 +1450,10 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const C
 
 // One work item: candidate sources [k chunk, (k + 1) chunk) of cluster c
 // against the cluster's targets (one per lane), in the frame the prepare
-// kernel set up.  The item's sums (W, the torque and translation terms, pair
-// counts) go to its own row.
-template <typename CT, int FD, bool CUT>
+// kernel set up.  The item's sums go to its own row: W, the torque and
+// translation terms and the pair counts (gradient pass), or the four
+// quartic-model sums (QUART).
+template <typename CT, int FD, bool CUT, bool QUART>
 __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs, const int* __restrict__ clus_end,
                                              int nreq, int lc, int k, CT* recs) {
   const int r = uniform(find_request(clus_end, nreq, lc));
@@ -1293,35 +1470,48 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
   // targets in the cluster frame, and labels
   const CT* blk = (const CT*)R.tblk + (size_t)c * (3 + FD) * kWave;
   const CT zx = blk[l], zy = blk[kWave + l], zz = blk[2 * kWave + l];
-  CT mj[FD];
+  using Op = typename std::conditional<QUART, QuartOp<CT, FD, CUT>, GradOp<CT, FD, CUT>>::type;
+  Op op;
+  op.zx = zx;
+  op.zy = zy;
+  op.zz = zz;
 #pragma unroll
-  for (int f = 0; f < FD; f++) mj[f] = blk[(3 + f) * kWave + l];
+  for (int f = 0; f < FD; f++) op.mj[f] = blk[(3 + f) * kWave + l];
   const CT rc2 = (CT)R.grid[0].rc2s;  // the same for every stage
+  op.rc2 = rc2;
   const cptr<CT> xr = (cptr<CT>)uniform_ptr(ci.xrec);
   const int xs = uniform(R.xs);
   const double isq = ci.isq;
+  const bool overflow = uniform(ci.overflow) != 0;
 
-  Acc<CT> acc;
-  acc.init();
-  unsigned long long within = 0;
+  // the target position z~_j (m): the torque's lever, the quartic vectors'
+  // base point (FP64 from the pose when the list overflowed)
+  double zt[3] = {0.0, 0.0, 0.0};
+  if (overflow) {
+    CT mdummy[FD];
+    load_targets<CT, FD>(R, R.state->T, uniform(ci.s0), valid, zt, mdummy);
+  }
+  auto lever = [&](double (&p)[3]) {
+    p[0] = overflow ? zt[0] : ci.O[0] + (double)zx * isq;
+    p[1] = overflow ? zt[1] : ci.O[1] + (double)zy * isq;
+    p[2] = overflow ? zt[2] : ci.O[2] + (double)zz * isq;
+  };
+  if constexpr (QUART) {
+    double lv[3];
+    lever(lv);
+    op.setup(R.state->xi, lv, 1.0 / isq, valid);
+  } else {
+    op.acc.init();
+    op.within = 0;
+  }
   long long span = 0;
-  double lever[3];  // the target position z~_j used for the torque
-  if (!uniform(ci.overflow)) {
-    if (lo_s < hi_s)
-      span = pairs_from_list<CT, FD, CUT>(R, ci, c, k, lo_s, hi_s, zx, zy, zz, mj, rc2, acc, within, xr, xs, recs);
-    lever[0] = ci.O[0] + (double)zx * isq;
-    lever[1] = ci.O[1] + (double)zy * isq;
-    lever[2] = ci.O[2] + (double)zz * isq;
+  if (!overflow) {
+    if (lo_s < hi_s) span = pairs_from_list<CT, FD, CUT, Op>(R, ci, c, k, lo_s, hi_s, rc2, op, xr, xs, recs);
   } else {
     // the list overflowed: enumerate the candidate box again in the same
     // order, from the FP64 target positions
-    ReqState* S = R.state;
-    const int s0 = uniform(ci.s0);
     const GridInfo g = R.grid[uniform(ci.stage)];
     const int* __restrict__ cs = uniform_ptr(R.cstart[uniform(ci.stage)]);
-    double zt[3];
-    CT mdummy[FD];
-    load_targets<CT, FD>(R, S->T, s0, valid, zt, mdummy);
     const CandBox B = cand_box(g, zt, valid);
     long long base = 0;
     for (int c0 = 0; c0 < B.ncand && base < hi_s; c0 += kWave) {
@@ -1339,50 +1529,61 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
         const long long cbeg = base + lane_value(incl - cnt, src);
         const int a = cfirst + (int)(lo_s > cbeg ? lo_s - cbeg : 0);
         const int b = cfirst + (int)((hi_s - cbeg) < ccnt ? (hi_s - cbeg) : ccnt);
-        run_cell<CT, FD, CUT>(g, xr, xs, ckey, a, b, zt, valid, mj, rc2, acc, within);
+        run_cell<CT, FD, Op>(g, xr, xs, ckey, a, b, zt, valid, op);
         span += b - a;
       }
       base += lane_value(incl, kWave - 1);
     }
-    lever[0] = zt[0];
-    lever[1] = zt[1];
-    lever[2] = zt[2];
   }
-  const unsigned long long examined = (unsigned long long)span * (unsigned long long)cn;
-  if (!CUT) within = examined;
-
-  double W, Dx, Dy, Dz;
-  acc.result(W, Dx, Dy, Dz);
-  if (!valid) W = Dx = Dy = Dz = 0.0;
-  Dx *= isq;
-  Dy *= isq;
-  Dz *= isq;
-  // sum_i w (x_i x z~_j) = z~_j x D_j with D_j = sum_i w (z~_j - x_i)
-  const double ox = lever[1] * Dz - lever[2] * Dy;
-  const double oy = lever[2] * Dx - lever[0] * Dz;
-  const double oz = lever[0] * Dy - lever[1] * Dx;
-
-  if (R.mode == kModeEvalTargets && R.per_target && valid) {
-    const double ell = R.stage_ell[uniform(ci.stage)];
-    const double il2 = 1.0 / (ell * ell);
-    const double a2 = R.state->a2;
-    double* o = R.per_target + (size_t)R.zorig[uniform(ci.s0) + l] * 7;
-    o[0] = R.s2f * W;
-    o[1] = R.s2f * ox * il2 / a2;
-    o[2] = R.s2f * oy * il2 / a2;
-    o[3] = R.s2f * oz * il2 / a2;
-    o[4] = R.s2f * Dx * il2 / R.b2;
-    o[5] = R.s2f * Dy * il2 / R.b2;
-    o[6] = R.s2f * Dz * il2 / R.b2;
-  }
-
-  const double part[kSlot] = {wave_sum(W),  wave_sum(ox), wave_sum(oy),     wave_sum(oz),    wave_sum(Dx),
-                              wave_sum(Dy), wave_sum(Dz), (double)within, (double)examined};
-  // every lane holds the same sums: all lanes store them (same address, same
-  // value), so the persistent loop has no lane-dependent branch
   double* row = R.sslots + ((size_t)c * kChunksMax + k) * kSlot;
+  if constexpr (QUART) {
+    double a4[4];
+    op.acc.result(a4);
 #pragma unroll
-  for (int q = 0; q < kSlot; q++) row[q] = part[q];
+    for (int q = 0; q < 4; q++) a4[q] = valid ? a4[q] : 0.0;
+    const double part[kSlot] = {wave_sum(a4[0]), wave_sum(a4[1]), wave_sum(a4[2]), wave_sum(a4[3]), 0.0, 0.0,
+                                0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < kSlot; q++) row[q] = part[q];
+  } else {
+    unsigned long long within = op.within;
+    const unsigned long long examined = (unsigned long long)span * (unsigned long long)cn;
+    if (!CUT) within = examined;
+
+    double W, Dx, Dy, Dz;
+    op.acc.result(W, Dx, Dy, Dz);
+    if (!valid) W = Dx = Dy = Dz = 0.0;
+    Dx *= isq;
+    Dy *= isq;
+    Dz *= isq;
+    // sum_i w (x_i x z~_j) = z~_j x D_j with D_j = sum_i w (z~_j - x_i)
+    double lv[3];
+    lever(lv);
+    const double ox = lv[1] * Dz - lv[2] * Dy;
+    const double oy = lv[2] * Dx - lv[0] * Dz;
+    const double oz = lv[0] * Dy - lv[1] * Dx;
+
+    if (R.mode == kModeEvalTargets && R.per_target && valid) {
+      const double ell = R.stage_ell[uniform(ci.stage)];
+      const double il2 = 1.0 / (ell * ell);
+      const double a2 = R.state->a2;
+      double* o = R.per_target + (size_t)R.zorig[uniform(ci.s0) + l] * 7;
+      o[0] = R.s2f * W;
+      o[1] = R.s2f * ox * il2 / a2;
+      o[2] = R.s2f * oy * il2 / a2;
+      o[3] = R.s2f * oz * il2 / a2;
+      o[4] = R.s2f * Dx * il2 / R.b2;
+      o[5] = R.s2f * Dy * il2 / R.b2;
+      o[6] = R.s2f * Dz * il2 / R.b2;
+    }
+
+    const double part[kSlot] = {wave_sum(W),  wave_sum(ox), wave_sum(oy),     wave_sum(oz),    wave_sum(Dx),
+                                wave_sum(Dy), wave_sum(Dz), (double)within, (double)examined};
+    // every lane holds the same sums: all lanes store them (same address,
+    // same value), so the persistent loop has no lane-dependent branch
+#pragma unroll
+    for (int q = 0; q < kSlot; q++) row[q] = part[q];
+  }
 }
 
 // Kernel B: persistent workgroups, as many as are resident at once (two per
@@ -1393,7 +1594,7 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
 // costs more than the items' arithmetic at this granularity).  Results do not
 // depend on which wavefront takes an item.  Every wavefront reaches the exit:
 // the counter grows by one per take and the share is finite.
-template <typename CT, int FD, bool CUT>
+template <typename CT, int FD, bool CUT, bool QUART>
 __global__ __launch_bounds__(kPairBlockWaves* kWave) void k_pairs(const ReqStatic* __restrict__ reqs,
                                                                   const int* __restrict__ clus_end, int nreq,
                                                                   QueueRef Q) {
@@ -1418,7 +1619,7 @@ __global__ __launch_bounds__(kPairBlockWaves* kWave) void k_pairs(const ReqStati
     const unsigned int it = (unsigned)uniform((int)mine);
     if (it >= hi) break;
     const unsigned int item = uniform((int)Q.items[it]);
-    process_item<CT, FD, CUT>(reqs, clus_end, nreq, (int)(item >> kItemShift),
+    process_item<CT, FD, CUT, QUART>(reqs, clus_end, nreq, (int)(item >> kItemShift),
                               (int)(item & ((1u << kItemShift) - 1u)), recs);
   }
 }
@@ -1426,10 +1627,11 @@ __global__ __launch_bounds__(kPairBlockWaves* kWave) void k_pairs(const ReqStati
 // Kernel C1: per target cluster (one wavefront each), the sum of its work-item
 // rows: lane j holds chunk j (zero past the cluster's count), summed by the
 // fixed xor butterfly, so the result does not depend on the order in which the
-// items ran.  Block 0 also resets the work list for the next launch.
+// items ran.  After the iteration's last pass block 0 also resets the work
+// list for the next launch (the quartic pass reuses the gradient pass's items).
 __global__ __launch_bounds__(256) void k_reduce(const ReqStatic* __restrict__ reqs, const int* __restrict__ clus_end,
-                                                int nreq, int total_clusters, QueueRef Q) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) Q.q->nitems = 0u;
+                                                int nreq, int total_clusters, QueueRef Q, int reset) {
+  if (reset && blockIdx.x == 0 && threadIdx.x == 0) Q.q->nitems = 0u;
   const int lc = uniform(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
   if (lc >= total_clusters) return;
   const int r = uniform(find_request(clus_end, nreq, lc));
@@ -1456,7 +1658,7 @@ __global__ __launch_bounds__(256) void k_reduce(const ReqStatic* __restrict__ re
 // (wave butterflies, then waves in order): a deterministic FP64 reduction,
 // then the step.
 constexpr int kStepThreads = 512;
-__global__ __launch_bounds__(kStepThreads) void k_step(const ReqStatic* __restrict__ reqs, int nreq) {
+__global__ __launch_bounds__(kStepThreads) void k_step(const ReqStatic* __restrict__ reqs, int nreq, int phase) {
   const int r = blockIdx.x;
   if (r >= nreq) return;
   const ReqStatic& R = reqs[r];
@@ -1497,17 +1699,21 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const ReqStatic* __restri
       for (int ww = 0; ww < NW; ww++) t += wsum[ww][q];
       tot[q] = t;
     }
-    finish_request(R, S, tot);
+    finish_request(R, S, tot, phase);
   }
 }
 
 // ---------------------------------------------------------------------------
 // 7) request state set-up
 // ---------------------------------------------------------------------------
-__global__ void k_init_state(ReqState* __restrict__ S, const double* __restrict__ T0, double a2_param) {
+__global__ void k_init_state(ReqState* __restrict__ S, const double* __restrict__ T0, const double* __restrict__ xi0,
+                             double a2_param) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int q = 0; q < 12; q++) S->T[q] = T0[q];
   for (int q = 0; q < 7; q++) S->g[q] = 0.0;
+  for (int q = 0; q < 6; q++) S->xi[q] = xi0 ? xi0[q] : 0.0;
+  for (int q = 0; q < 5; q++) S->A[q] = 0.0;
+  S->last_pairs = 0ull;
   S->a2 = a2_param;
   S->tau = 0.0;
   S->pairs_within = 0ull;
@@ -1574,7 +1780,7 @@ static void launch_scan(const ScanArgs* args, int nseg, long long maxlen, hipStr
 
 hipError_t launch_ingest(const IngestArgs& a, hipStream_t s) {
   const int B = 256;
-  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, a.state, a.T0, a.a2_param);
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, a.state, a.T0, a.xi0, a.a2_param);
   hipLaunchKernelGGL(k_check_finite, dim3(blocks_for(3LL * a.n, B, 1024)), dim3(B), 0, s, a.sx, 3LL * a.n, a.state);
   hipLaunchKernelGGL(k_check_finite, dim3(blocks_for((long long)a.fd * a.n, B, 1024)), dim3(B), 0, s, a.sfeat,
                      (long long)a.fd * a.n, a.state);
@@ -1635,42 +1841,45 @@ static int resident_blocks(const void* kernel) {
   return (per_cu < 1 ? 1 : per_cu) * (cus < 1 ? 1 : cus);
 }
 
-template <typename CT, int FD, bool CUT>
+template <typename CT, int FD, bool CUT, bool QUART>
 static hipError_t launch_pairs3(const ReqStatic* reqs, const int* clus_end, int nreq, int total,
                                 const QueueRef& Q, hipStream_t s) {
   static std::atomic<int> resident_cache{0};  // per instance; every device of a process is the same part
   int resident = resident_cache.load(std::memory_order_relaxed);
   if (resident <= 0) {
-    resident = resident_blocks((const void*)k_pairs<CT, FD, CUT>);
+    resident = resident_blocks((const void*)k_pairs<CT, FD, CUT, QUART>);
     if (resident <= 0) return hipErrorInvalidValue;
     resident_cache.store(resident, std::memory_order_relaxed);
   }
   const long long most = (long long)total * kChunksMax;
   const int blocks = (int)(most < resident ? most : resident);
-  hipLaunchKernelGGL((k_pairs<CT, FD, CUT>), dim3(blocks), dim3(kPairBlockWaves * kWave), 0, s, reqs, clus_end,
-                     nreq, Q);
+  hipLaunchKernelGGL((k_pairs<CT, FD, CUT, QUART>), dim3(blocks), dim3(kPairBlockWaves * kWave), 0, s, reqs,
+                     clus_end, nreq, Q);
   return hipGetLastError();
 }
 
 template <typename CT, int FD>
-static hipError_t launch_pairs(bool cut, const ReqStatic* reqs, const int* clus_end, int nreq, int total,
+static hipError_t launch_pairs(bool cut, bool quart, const ReqStatic* reqs, const int* clus_end, int nreq, int total,
                                const QueueRef& Q, hipStream_t s) {
-  return cut ? launch_pairs3<CT, FD, true>(reqs, clus_end, nreq, total, Q, s)
-             : launch_pairs3<CT, FD, false>(reqs, clus_end, nreq, total, Q, s);
+  if (quart)
+    return cut ? launch_pairs3<CT, FD, true, true>(reqs, clus_end, nreq, total, Q, s)
+               : launch_pairs3<CT, FD, false, true>(reqs, clus_end, nreq, total, Q, s);
+  return cut ? launch_pairs3<CT, FD, true, false>(reqs, clus_end, nreq, total, Q, s)
+             : launch_pairs3<CT, FD, false, false>(reqs, clus_end, nreq, total, Q, s);
 }
 
 template <typename CT>
-static hipError_t launch_pairs_fd(int fd, bool cut, const ReqStatic* reqs, const int* clus_end, int nreq, int total,
-                                  const QueueRef& Q, hipStream_t s) {
+static hipError_t launch_pairs_fd(int fd, bool cut, bool quart, const ReqStatic* reqs, const int* clus_end, int nreq,
+                                  int total, const QueueRef& Q, hipStream_t s) {
   switch (fd) {
-    case 1: return launch_pairs<CT, 1>(cut, reqs, clus_end, nreq, total, Q, s);
-    case 2: return launch_pairs<CT, 2>(cut, reqs, clus_end, nreq, total, Q, s);
-    case 3: return launch_pairs<CT, 3>(cut, reqs, clus_end, nreq, total, Q, s);
-    case 4: return launch_pairs<CT, 4>(cut, reqs, clus_end, nreq, total, Q, s);
-    case 5: return launch_pairs<CT, 5>(cut, reqs, clus_end, nreq, total, Q, s);
-    case 6: return launch_pairs<CT, 6>(cut, reqs, clus_end, nreq, total, Q, s);
-    case 7: return launch_pairs<CT, 7>(cut, reqs, clus_end, nreq, total, Q, s);
-    default: return launch_pairs<CT, 8>(cut, reqs, clus_end, nreq, total, Q, s);
+    case 1: return launch_pairs<CT, 1>(cut, quart, reqs, clus_end, nreq, total, Q, s);
+    case 2: return launch_pairs<CT, 2>(cut, quart, reqs, clus_end, nreq, total, Q, s);
+    case 3: return launch_pairs<CT, 3>(cut, quart, reqs, clus_end, nreq, total, Q, s);
+    case 4: return launch_pairs<CT, 4>(cut, quart, reqs, clus_end, nreq, total, Q, s);
+    case 5: return launch_pairs<CT, 5>(cut, quart, reqs, clus_end, nreq, total, Q, s);
+    case 6: return launch_pairs<CT, 6>(cut, quart, reqs, clus_end, nreq, total, Q, s);
+    case 7: return launch_pairs<CT, 7>(cut, quart, reqs, clus_end, nreq, total, Q, s);
+    default: return launch_pairs<CT, 8>(cut, quart, reqs, clus_end, nreq, total, Q, s);
   }
 }
 
@@ -1690,26 +1899,45 @@ hipError_t launch_prepare(const ReqStatic* reqs, const int* clus_end, int nreq, 
 hipError_t launch_pair_kernel(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end, int nreq,
                               int total_clusters, const QueueRef& Q, hipStream_t s) {
   if (fd < 1 || fd > kMaxFeat || !queue_fits(total_clusters, Q)) return hipErrorInvalidValue;
-  if (precision == 1) return launch_pairs_fd<double>(fd, cutoff, reqs, clus_end, nreq, total_clusters, Q, s);
-  return launch_pairs_fd<float>(fd, cutoff, reqs, clus_end, nreq, total_clusters, Q, s);
+  if (precision == 1) return launch_pairs_fd<double>(fd, cutoff, false, reqs, clus_end, nreq, total_clusters, Q, s);
+  return launch_pairs_fd<float>(fd, cutoff, false, reqs, clus_end, nreq, total_clusters, Q, s);
+}
+
+hipError_t launch_quartic_pairs(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end,
+                                int nreq, int total_clusters, const QueueRef& Q, hipStream_t s) {
+  if (fd < 1 || fd > kMaxFeat || !queue_fits(total_clusters, Q)) return hipErrorInvalidValue;
+  if (precision == 1) return launch_pairs_fd<double>(fd, cutoff, true, reqs, clus_end, nreq, total_clusters, Q, s);
+  return launch_pairs_fd<float>(fd, cutoff, true, reqs, clus_end, nreq, total_clusters, Q, s);
 }
 
 hipError_t launch_step(const ReqStatic* reqs, const int* clus_end, int nreq, int total_clusters, const QueueRef& Q,
-                       hipStream_t s) {
+                       hipStream_t s, int phase, bool reset) {
   if (nreq < 1 || !queue_fits(total_clusters, Q)) return hipErrorInvalidValue;
+  if (phase != kPhaseFixed && phase != kPhaseGradient && phase != kPhaseQuartic) return hipErrorInvalidValue;
   const int blocks = (total_clusters + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(256), 0, s, reqs, clus_end, nreq, total_clusters, Q);
-  hipLaunchKernelGGL(k_step, dim3(nreq), dim3(kStepThreads), 0, s, reqs, nreq);
+  hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(256), 0, s, reqs, clus_end, nreq, total_clusters, Q,
+                     reset ? 1 : 0);
+  hipLaunchKernelGGL(k_step, dim3(nreq), dim3(kStepThreads), 0, s, reqs, nreq, phase);
   return hipGetLastError();
 }
 
 hipError_t launch_iteration(int precision, int fd, bool cutoff, const ReqStatic* reqs, const int* clus_end, int nreq,
                             int total_clusters, const QueueRef& Q, hipStream_t s) {
+  return launch_iteration_rule(kStepFixed, precision, fd, cutoff, reqs, clus_end, nreq, total_clusters, Q, s);
+}
+
+hipError_t launch_iteration_rule(int step_rule, int precision, int fd, bool cutoff, const ReqStatic* reqs,
+                                 const int* clus_end, int nreq, int total_clusters, const QueueRef& Q, hipStream_t s) {
   hipError_t e = launch_prepare(reqs, clus_end, nreq, total_clusters, Q, s);
   if (e != hipSuccess) return e;
   e = launch_pair_kernel(precision, fd, cutoff, reqs, clus_end, nreq, total_clusters, Q, s);
   if (e != hipSuccess) return e;
-  return launch_step(reqs, clus_end, nreq, total_clusters, Q, s);
+  if (step_rule != kStepQuartic) return launch_step(reqs, clus_end, nreq, total_clusters, Q, s);
+  e = launch_step(reqs, clus_end, nreq, total_clusters, Q, s, kPhaseGradient, false);
+  if (e != hipSuccess) return e;
+  e = launch_quartic_pairs(precision, fd, cutoff, reqs, clus_end, nreq, total_clusters, Q, s);
+  if (e != hipSuccess) return e;
+  return launch_step(reqs, clus_end, nreq, total_clusters, Q, s, kPhaseQuartic, true);
 }
 
 }  // namespace cvo

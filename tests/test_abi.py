@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -46,3 +47,51 @@ def test_create_without_device_fails_cleanly():
     from paper_1904_02266_amd import Context, CvoError
     with pytest.raises(CvoError):
         Context(0)
+
+
+def _P(A, t):
+    return t * (A[1] + t * (A[2] + t * (A[3] + t * A[4])))
+
+
+def test_quartic_step_host_rule_matches_oracle():
+    # The library's step rule for the quartic model (bracketed Newton on P')
+    # against the oracle's (closed-form roots of the cubic P'), on random
+    # coefficient sets of mixed signs and scales, A1 >= 0 as along a gradient.
+    import oracle
+    from paper_1904_02266_amd import quartic_step
+    rng = np.random.default_rng(5)
+    agree = none_both = 0
+    for _ in range(4000):
+        sc = 10.0 ** rng.uniform(-3, 3, size=4)
+        A = np.concatenate([[1.0], rng.normal(size=4) * sc])
+        A[1] = abs(A[1])
+        if rng.random() < 0.1:
+            A[4] = 0.0
+        t_lib = quartic_step(A)
+        t_or = oracle.quartic_step(A)
+        if t_or is None:
+            assert t_lib is None, A
+            none_both += 1
+            continue
+        assert t_lib is not None, A
+        if abs(t_lib - t_or) > 1e-9 * t_or:
+            # two maxima of (numerically) equal height: the values must agree
+            assert abs(_P(A, t_lib) - _P(A, t_or)) <= 1e-12 * max(abs(_P(A, t_or)), 1e-300), A
+        agree += 1
+    assert agree > 1000 and none_both > 100
+
+
+@pytest.mark.parametrize("A,t", [
+    ([0, 1.0, -1.0, 0.0, 0.0], 0.5),
+    ([0, 1.0, 0.0, -1.0, 0.0], 3 ** -0.5),
+    ([0, 1.0, 1.0, 1.0, 1.0], None),
+    ([0, 1.0, 0.0, 0.0, 0.0], None),
+    ([0, 0.0, 0.0, 0.0, 0.0], None),
+])
+def test_quartic_step_host_rule_special_cases(A, t):
+    from paper_1904_02266_amd import quartic_step
+    got = quartic_step(A)
+    if t is None:
+        assert got is None
+    else:
+        assert abs(got - t) < 1e-14

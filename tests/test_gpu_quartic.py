@@ -1,0 +1,190 @@
+"""The quartic step rule (Sec. VI-B, eq. fourth) on the GPU against the oracle.
+
+Coefficients F, A1..A4 of the fourth-order model of G(t) = F(h exp(t xi)):
+  F:      |F - F_ref| <= 1e-5 F_ref
+  A_k:    |A_k - A_ref,k| <= tol * S_k, S_k = sum_ij |term_k,ij| from the oracle
+          (A_k cancels between pairs; its error is measured against the size
+          of the summed terms), tol = 2e-5 on the FP32 path (the terms of g^3
+          and g^4 combine powers of beta computed in FP32), 1e-10 on FP64.
+Steps (teacher-forced): at the GPU's pose before iteration k the GPU's
+gradient matches the oracle's, and where that gradient is resolved the GPU's
+tau equals the oracle's quartic step (see _teacher_forced).  The step kernel
+takes A1 = a^2 |omega|^2 + b^2 |v|^2 from the identity along the gradient;
+the oracle sums it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1904_02266_amd import Context, Params, params_planes, params_rgbd, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def rgbd_small():
+    return synth.rgbd_pair(6000, 5000, seed=31)
+
+
+def check_coef(c, ref, absref, tol, what=""):
+    ftol = 1e-5 if tol > 1e-8 else tol
+    assert abs(c[0] - ref[0]) <= ftol * ref[0], (what, "F", c[0], ref[0])
+    for k in range(1, 5):
+        assert abs(c[k] - ref[k]) <= tol * absref[k], (what, k, c[k], ref[k], (c[k] - ref[k]) / absref[k])
+
+
+@pytest.mark.parametrize("ell", [0.2, 0.08, 0.05])
+def test_coefficients_rgbd_cutoff(ctx, rgbd_small, ell):
+    p = rgbd_small
+    rng = np.random.default_rng(int(ell * 1000))
+    a2 = oracle.mean_sqnorm(p.src_xyz)
+    for trial in range(3):
+        T = p.T_true if trial == 0 else synth.random_motion(rng, 3.0, 0.03) @ p.T_true
+        g = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=ell, kappa=3.0, a2=a2)["g"]
+        w, v = (g[1:4], g[4:7]) if trial < 2 else (rng.normal(size=3), rng.normal(size=3) * 0.1)
+        prm = Params(stage_ell=(ell,), cutoff_mult=3.0)
+        c = ctx.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, w, v, prm)
+        ref, absref = oracle.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, w, v, ell=ell, kappa=3.0)
+        check_coef(c, ref, absref, 2e-5, what=f"ell {ell} trial {trial}")
+
+
+def test_coefficients_planes_brute_force(ctx):
+    p = synth.planes_pair(2000, seed=1)
+    rng = np.random.default_rng(3)
+    for trial in range(3):
+        T = np.eye(4) if trial == 0 else synth.random_motion(rng, 8.0, 0.08)
+        g = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=0.1)["g"]
+        c = ctx.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, g[1:4], g[4:7], params_planes())
+        ref, absref = oracle.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, g[1:4], g[4:7], ell=0.1)
+        check_coef(c, ref, absref, 2e-5, what=f"trial {trial}")
+
+
+def test_coefficients_fp64_path(ctx, rgbd_small):
+    p = rgbd_small
+    T = p.T_true
+    g = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=0.08, kappa=3.0)["g"]
+    prm = Params(stage_ell=(0.08,), cutoff_mult=3.0, precision="fp64")
+    c = ctx.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, g[1:4], g[4:7], prm)
+    ref, absref = oracle.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, g[1:4], g[4:7], ell=0.08,
+                                 kappa=3.0)
+    check_coef(c, ref, absref, 1e-10)
+
+
+def test_first_coefficient_is_gradient_metric_norm(ctx, rgbd_small):
+    # along the GPU's own gradient, A1 = a^2 |omega|^2 + b^2 |v|^2
+    p = rgbd_small
+    prm = Params(stage_ell=(0.1,), cutoff_mult=3.0, a2=2.0, b2=0.5)
+    g = ctx.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, p.T_true, prm)
+    c = ctx.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, p.T_true, g[1:4], g[4:7], prm)
+    assert c[0] == g[0]
+    A1 = 2.0 * g[1:4] @ g[1:4] + 0.5 * g[4:7] @ g[4:7]
+    assert abs(c[1] - A1) <= 1e-4 * A1, (c[1], A1)
+
+
+def test_zero_direction(ctx, rgbd_small):
+    p = rgbd_small
+    prm = Params(stage_ell=(0.1,), cutoff_mult=3.0)
+    c = ctx.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, np.eye(4), [0, 0, 0], [0, 0, 0], prm)
+    F = ctx.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, np.eye(4), prm)[0]
+    assert c[0] == F and np.all(c[1:] == 0.0)
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (7, 63), (65, 64), (300, 130), (129, 1)])
+def test_coefficients_ragged_sizes(ctx, n, m):
+    rng = np.random.default_rng(n * 1000 + m + 7)
+    x = rng.uniform(-0.3, 0.3, size=(n, 3)).astype(np.float32)
+    z = rng.uniform(-0.3, 0.3, size=(m, 3)).astype(np.float32)
+    lx = rng.uniform(0, 1, size=(n, 5)).astype(np.float32)
+    lz = rng.uniform(0, 1, size=(m, 5)).astype(np.float32)
+    T = synth.random_motion(rng, 5.0, 0.02)
+    w, v = rng.normal(size=3), rng.normal(size=3) * 0.2
+    for kappa in (0.0, 3.0):
+        prm = Params(stage_ell=(0.2,), cutoff_mult=kappa, a2=1.0)
+        ref, absref = oracle.quartic(x, lx, z, lz, T, w, v, ell=0.2, kappa=kappa)
+        if ref[0] == 0.0:
+            continue
+        c = ctx.quartic(x, lx, z, lz, T, w, v, prm)
+        check_coef(c, ref, absref, 2e-5, what=f"{n}x{m} kappa {kappa}")
+
+
+def _teacher_forced(ctx, p, prm, kappa, iters, a2):
+    """Run the quartic rule on the GPU; at the GPU's pose before each listed
+    iteration check the gradient against the oracle, and the step against the
+    oracle's quartic step along the oracle's gradient wherever the gradient is
+    resolved (its FP32 error bound below 1e-3 of its size: near convergence
+    the direction is rounding noise and no step is comparable).  The step's
+    tolerance is 1e-4 plus 20 times the direction's relative error bound."""
+    out = ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, prm)
+    tr = ctx.trace()
+    assert out["rc"] == 0 and tr.shape[0] == prm.max_iters
+    checked = 0
+    for k in iters:
+        Tk = np.eye(4) if k == 0 else tr[k - 1, 10:26].reshape(4, 4)
+        ell = tr[k, 8]
+        r = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, Tk, ell=ell, kappa=kappa, a2=a2)
+        g = r["g"]
+        assert abs(tr[k, 0] - g[0]) <= 1e-5 * g[0]
+        for q in range(1, 7):
+            assert abs(tr[k, q] - g[q]) <= 1e-5 * r["abs"][q], (k, q)
+        rel = 1e-5 * np.linalg.norm(r["abs"][1:7]) / np.linalg.norm(g[1:7])
+        if rel > 1e-3:
+            continue
+        c, _ = oracle.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, Tk, g[1:4], g[4:7], ell=ell,
+                              kappa=kappa)
+        t = oracle.quartic_step(c)
+        if t is None:
+            t = ell * ell / g[0]
+        assert abs(tr[k, 7] - t) <= (1e-4 + 20 * rel) * t, (k, tr[k, 7], t, rel)
+        checked += 1
+    return out, tr, checked
+
+
+def test_register_quartic_planes_teacher_forced(ctx):
+    p = synth.planes_pair(2000, seed=1)
+    prm = params_planes(trace=True, step_rule="quartic", max_iters=30)
+    a2 = oracle.mean_sqnorm(p.src_xyz)
+    out, tr, checked = _teacher_forced(ctx, p, prm, 0.0, range(30), a2)
+    assert checked >= 3
+    ref = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, stage_ell=(0.1,), max_iters=30,
+                          step_rule="quartic")
+    E = out["T"][:3, :3] @ ref["T"][:3, :3].T
+    ang = np.arccos(np.clip((np.trace(E) - 1) / 2, -1, 1))
+    assert ang < 1e-4 and np.linalg.norm(out["T"][:3, 3] - E @ ref["T"][:3, 3]) < 1e-4
+    # each quartic step raises F
+    assert np.all(np.diff(tr[:, 0]) > -1e-6 * tr[1:, 0])
+
+
+def test_register_quartic_rgbd_schedule_teacher_forced(ctx):
+    p = synth.rgbd_pair(4000, 4000, seed=41)
+    prm = params_rgbd(max_iters=24, stage_iters=(6, 6, 6), trace=True, step_rule="quartic")
+    a2 = oracle.mean_sqnorm(p.src_xyz)
+    out, tr, checked = _teacher_forced(ctx, p, prm, 3.0, (0, 1, 6, 7, 12, 13, 18, 19, 23), a2)
+    assert checked >= 4
+    E = out["T"][:3, :3] @ p.T_true[:3, :3].T
+    assert np.degrees(np.arccos(np.clip((np.trace(E) - 1) / 2, -1, 1))) < 0.5
+
+
+def test_quartic_rule_batched_equals_sync():
+    reqs = [synth.rgbd_pair(3000 + 900 * k, 2800 + 700 * k, seed=7100 + k) for k in range(4)]
+    pq = params_rgbd(max_iters=12, stage_iters=(3, 3, 3), step_rule="quartic")
+    pf = params_rgbd(max_iters=12, stage_iters=(3, 3, 3))
+    ctx = Context(0, max_slots=8)
+    try:
+        sync = [ctx.register(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, pq if k % 2 == 0 else pf)
+                for k, q in enumerate(reqs)]
+        tks = [ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, pq if k % 2 == 0 else pf)[0]
+               for k, q in enumerate(reqs)]
+        bat = [ctx.poll(t) for t in tks]
+    finally:
+        ctx.close()
+    for s, b in zip(sync, bat):
+        assert b["rc"] == 0 and b["iters"] == 12
+        assert np.array_equal(s["T"], b["T"]) and s["F"] == b["F"]
+    assert not np.array_equal(sync[0]["T"], sync[1]["T"])

@@ -123,7 +123,8 @@ def lane_split_back_edges(ir):
 
         loops = {}  # header -> blocks of its natural loop(s)
         for latch, header in back:
-            body_, work = {header, latch}, [latch]
+            # (a self-loop's body is its header alone: never walk past it)
+            body_, work = {header, latch}, ([latch] if latch != header else [])
             while work:
                 n = work.pop()
                 for p in pred.get(n, []):

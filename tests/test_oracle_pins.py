@@ -412,3 +412,26 @@ def test_quartic_step_rule_registration():
     c, _ = oracle.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, np.eye(4), tr[0, 1:4], tr[0, 4:7],
                           ell=0.15)
     np.testing.assert_allclose(tr[0, 7], oracle.quartic_step(c), rtol=1e-12)
+
+
+def test_quartic_step_c_and_numpy_agree():
+    # bisection between the critical points of P' (C) against the
+    # companion-matrix roots of P' (NumPy), on mixed-scale coefficient sets,
+    # including ill-conditioned ones (one root of P' far from the others)
+    rng = np.random.default_rng(17)
+    P = lambda A, t: t * (A[1] + t * (A[2] + t * (A[3] + t * A[4])))
+    nones = 0
+    for _ in range(3000):
+        A = np.concatenate([[1.0], rng.normal(size=4) * 10.0 ** rng.uniform(-3, 3, size=4)])
+        A[1] = abs(A[1])
+        a, b = oracle.quartic_step(A), npo.quartic_step(A)
+        assert (a is None) == (b is None), A
+        if a is None:
+            nones += 1
+        elif abs(a - b) > 1e-9 * a:
+            assert abs(P(A, a) - P(A, b)) <= 1e-12 * abs(P(A, a)), A
+    assert 200 < nones < 2800
+    # the ill-conditioned case that a closed-form cubic solution gets wrong
+    A = [1.0, 4.02833482e-03, 8.71549933e-03, -7.21017475e+02, -1.91432643e-03]
+    t = oracle.quartic_step(A)
+    assert abs(t - npo.quartic_step(A)) < 1e-12 and 0.0013 < t < 0.0014
