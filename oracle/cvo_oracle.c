@@ -444,7 +444,9 @@ int cvo_oracle_quartic_step(const double A[5], double* t_out) {
  *   tau = eta ell^2 / F (step_rule 0), or (step_rule 1) the maximiser of the
  *         quartic model when it has one on t > 0, else eta ell^2 / F;
  *   h <- h exp(tau (omega^, v))
- *   stop when the last stage is reached and |tau (omega, v)|_2 < tol.
+ *   stop when the last stage is reached and |tau (omega, v)|_2 < tol (the
+ *   transformation threshold of Table 1) or |(omega, v)|_2 < grad_tol (the
+ *   gradient-norm threshold); a zero threshold is off.
  * Stage s spans stage_iters[s] iterations; the last stage runs to max_iters.
  * T0 and T_out use the library convention T = h^-1.
  * trace (optional) receives per iteration 26 doubles:
@@ -453,9 +455,11 @@ int cvo_oracle_quartic_step(const double A[5], double* t_out) {
 int cvo_oracle_register(int n, const float* x, const float* lx, int m, const float* z, const float* lz,
                         int fd, double sigma, double feat_scale, double a2, double b2, double eta,
                         double kappa, int n_stages, const int* stage_iters, const double* stage_ell,
-                        int max_iters, double tol, int step_rule, const double T0[16], int nthreads,
+                        int max_iters, double tol, double grad_tol, int step_rule, const double T0[16],
+                        int nthreads,
                         double T_out[16], double* trace, int* iters_out, int* converged_out) {
     if (n_stages < 1 || !stage_ell || max_iters < 1 || !(eta > 0.0)) return OR_EINVAL;
+    if (!(tol >= 0.0) || !(grad_tol >= 0.0)) return OR_EINVAL;
     for (int s = 0; s < n_stages; s++) {
         if (!(stage_ell[s] > 0.0)) return OR_EINVAL;
         if (s < n_stages - 1 && (!stage_iters || stage_iters[s] < 1)) return OR_EINVAL;
@@ -488,15 +492,18 @@ int cvo_oracle_register(int n, const float* x, const float* lx, int m, const flo
             if (cvo_oracle_quartic_step(A, &tq)) tau = tq;
         }
         newstep(h, g + 1, g + 4, tau);
-        double sq = 0.0;
-        for (int q = 1; q < 7; q++) sq += (tau * g[q]) * (tau * g[q]);
+        double sq = 0.0, gq = 0.0;
+        for (int q = 1; q < 7; q++) {
+            sq += (tau * g[q]) * (tau * g[q]);
+            gq += g[q] * g[q];
+        }
         if (trace) {
             double* tr = trace + 26 * (size_t)k;
             for (int q = 0; q < 7; q++) tr[q] = g[q];
             tr[7] = tau; tr[8] = ell; tr[9] = (double)cnt[0];
             rigid_inverse(h, tr + 10);
         }
-        if (stage == n_stages - 1 && sqrt(sq) < tol) { conv = 1; k++; break; }
+        if (stage == n_stages - 1 && (sqrt(sq) < tol || sqrt(gq) < grad_tol)) { conv = 1; k++; break; }
     }
     rigid_inverse(h, T_out);
     if (iters_out) *iters_out = k;

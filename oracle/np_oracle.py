@@ -48,10 +48,13 @@ def expm_series(A, terms=30):
     return E
 
 
-def terms(x, lx, z, lz, T, *, sigma=0.1, feat_scale=0.2, ell=0.1, kappa=0.0, a2=None, b2=1.0):
+def terms(x, lx, z, lz, T, *, sigma=0.1, feat_scale=0.2, ell=0.1, kappa=0.0, a2=None, b2=1.0,
+          kernel_floor=0.0):
     """Per-pair weights w_ij = c_ij k_ij, displacement z~_j - x_i and z~.
 
-    T acts on target points (T = h^-1).
+    T acts on target points (T = h^-1).  kernel_floor > 0 sparsifies by value
+    as in the TUM experiment (Sec. VII-B, Table 1): kernel values
+    k_ij = sigma^2 exp(-r^2 / (2 ell^2)) below the floor are set to zero.
     """
     x = np.asarray(x, dtype=np.float64)
     z = np.asarray(z, dtype=np.float64)
@@ -65,16 +68,19 @@ def terms(x, lx, z, lz, T, *, sigma=0.1, feat_scale=0.2, ell=0.1, kappa=0.0, a2=
     k = sigma ** 2 * np.exp(-r2 / (2.0 * ell * ell))
     if kappa > 0:
         k = np.where(r2 <= (kappa * ell) ** 2, k, 0.0)
+    if kernel_floor > 0:
+        k = np.where(k >= kernel_floor, k, 0.0)
     return c * k, d, zt, r2
 
 
-def evaluate(x, lx, z, lz, T, *, sigma=0.1, feat_scale=0.2, ell=0.1, kappa=0.0, a2=None, b2=1.0):
+def evaluate(x, lx, z, lz, T, *, sigma=0.1, feat_scale=0.2, ell=0.1, kappa=0.0, a2=None, b2=1.0,
+             kernel_floor=0.0):
     """Returns (F, omega[3], v[3])."""
     x = np.asarray(x, dtype=np.float64)
     if a2 is None:
         a2 = float((x * x).sum(axis=1).mean())
     w, d, zt, _ = terms(x, lx, z, lz, T, sigma=sigma, feat_scale=feat_scale, ell=ell,
-                        kappa=kappa)
+                        kappa=kappa, kernel_floor=kernel_floor)
     F = w.sum()
     W = np.zeros((3, 3))
     for p in range(3):
@@ -169,3 +175,36 @@ def quartic_step(A):
         if best is None or p > best[1]:
             best = (t, p)
     return None if best is None else float(best[0])
+
+
+def quartic_printed(x, lx, z, lz, T, w, u, *, sigma=0.1, feat_scale=0.2, ell=0.1):
+    """[F, A1..A4] from the coefficients exactly as printed with eq. fourth
+    (comparison mode only): alpha = -|d|^2/(2 ell^2) (the printed alpha lacks
+    the square), beta = -<u1, d>/ell^2, gamma = -(|u1|^2 + 2<u2, d>)/(2 ell^2),
+    delta = (<-u1, u2> + <-u3, d>)/ell^2,
+    eps = -(|u2|^2 + 2<u1, u3> + 2<u4, d>)/(2 ell^2), with d = x - z~,
+    u1 = w^ z~ + u, u_{k+1} = w^ u_k (the printed "w^2 z + v" read as
+    w^2 z + w^ v), and the paper's g^1..g^4.  These expand
+    |d + t u1 + t^2 u2 + t^3 u3 + t^4 u4|^2, which agrees with G(t) to first
+    order only."""
+    x = np.asarray(x, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    zt = np.asarray(z, dtype=np.float64) @ T[:3, :3].T + T[:3, 3]
+    W = hat(np.asarray(w, dtype=np.float64))
+    u1 = zt @ W.T + np.asarray(u, dtype=np.float64)
+    u2 = u1 @ W.T
+    u3 = u2 @ W.T
+    u4 = u3 @ W.T
+    d = x[:, None, :] - zt[None, :, :]
+    c = feat_scale * (np.asarray(lx, dtype=np.float64) @ np.asarray(lz, dtype=np.float64).T)
+    il = 1.0 / ell ** 2
+    dot = lambda a, b: (a * b).sum(-1)
+    al = -0.5 * il * dot(d, d)
+    be = -il * dot(u1[None], d)
+    ga = -0.5 * il * (dot(u1, u1)[None] + 2 * dot(u2[None], d))
+    de = il * (-dot(u1, u2)[None] - dot(u3[None], d))
+    ep = -0.5 * il * (dot(u2, u2)[None] + 2 * dot(u1, u3)[None] + 2 * dot(u4[None], d))
+    g = [be, ga + be ** 2 / 2, de + be * ga + be ** 3 / 6,
+         ep + be * de + be ** 2 * ga / 2 + ga ** 2 / 2 + be ** 4 / 24]
+    k = sigma ** 2 * c * np.exp(al)
+    return np.array([k.sum()] + [(k * gk).sum() for gk in g])

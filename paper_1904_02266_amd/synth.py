@@ -307,3 +307,65 @@ def default_schedule(n_stages=4, iters_per_stage=25, ell0=0.2, ell1=0.05):
         return [iters_per_stage], [ell0]
     ells = [ell0 * (ell1 / ell0) ** (s / (n_stages - 1)) for s in range(n_stages)]
     return [iters_per_stage] * n_stages, ells
+
+
+# --------------------------------------------------------------------------
+# RGB-D images (input of the device front end) and frame sequences
+# --------------------------------------------------------------------------
+@dataclass
+class RGBDFrame:
+    depth: np.ndarray          # [H, W] float32 metres, NaN where the ray has no valid return
+    rgb: np.ndarray            # [H, W, 3] float32 colour in [0, 1]
+    pose: np.ndarray           # camera-to-world 4x4 (ground truth)
+    fx: float = CAM_F
+    fy: float = CAM_F
+    cx: float = CAM_CX
+    cy: float = CAM_CY
+    dmin: float = 0.5
+    dmax: float = 5.0
+
+
+def render_images(room, G, rng, depth_noise=0.01, dmin=0.5, dmax=5.0):
+    """One VGA frame from camera pose G as images: depth along the optical
+    axis with 1% multiplicative noise (NaN outside [dmin, dmax] or without a
+    surface) and the colour of the world surface point."""
+    cam, _, valid, feat, _ = render(room, G, rng, depth_noise=depth_noise, dmin=dmin, dmax=dmax)
+    depth = np.where(valid, cam[:, 2], np.nan).astype(np.float32).reshape(CAM_H, CAM_W)
+    rgb = feat[:, :3].astype(np.float32).reshape(CAM_H, CAM_W, 3)
+    return RGBDFrame(depth, rgb, G.copy(), dmin=dmin, dmax=dmax)
+
+
+def rgbd_frame_pair(seed=2, theta_max_deg=5.0, t_max=0.05):
+    """The two frames of the RGB-D pair workload as images (same room and
+    motion draw order as rgbd_pair with the same seed: source camera at the
+    origin, target camera at G)."""
+    rng = np.random.default_rng(seed)
+    room = Room.draw(rng)
+    G = random_motion(rng, theta_max_deg, t_max)
+    return render_images(room, np.eye(4), rng), render_images(room, G, rng), G
+
+
+def rgbd_sequence(n_frames=30, seed=9, step_deg=1.0, step_m=0.02):
+    """A hand-held-like camera path through one seeded room: each frame moves
+    by a smooth random rotation (about step_deg) and translation (about
+    step_m) from the previous one.  Returns the frames (ground-truth poses in
+    .pose, camera-to-world)."""
+    rng = np.random.default_rng(seed)
+    room = Room.draw(rng)
+    frames = []
+    G = np.eye(4)
+    w = rng.normal(0.0, 1.0, 3)
+    v = rng.normal(0.0, 1.0, 3)
+    for k in range(n_frames):
+        frames.append(render_images(room, G, rng))
+        # slowly varying angular and linear velocity
+        w = 0.8 * w + 0.2 * rng.normal(0.0, 1.0, 3)
+        v = 0.8 * v + 0.2 * rng.normal(0.0, 1.0, 3)
+        ang = math.radians(step_deg) * w / max(np.linalg.norm(w), 1e-12)
+        R = rotation_axis_angle(ang / max(np.linalg.norm(ang), 1e-12), np.linalg.norm(ang))
+        t = step_m * v / max(np.linalg.norm(v), 1e-12)
+        M = np.eye(4)
+        M[:3, :3] = R
+        M[:3, 3] = t
+        G = G @ M
+    return frames

@@ -327,37 +327,16 @@ def test_quartic_c_and_numpy_agree(kappa):
 
 
 def test_printed_coefficients_are_only_first_order():
-    # The coefficients as printed (x - z~(t) expanded as d + t u1 + t^2 u2 +
-    # t^3 u3 + t^4 u4, no factorials or alternating signs) agree with G in
-    # F and A1 only; the residual falls off as t^2.  This is why the oracle
-    # uses the exact expansion (see the readings of eq. fourth).
+    # The coefficients as printed (comparison mode of the NumPy oracle) agree
+    # with G in F and A1 only; the residual falls off as t^2.  This is why the
+    # oracle uses the exact expansion of exp(-t Xi) z~ (readings of eq. fourth).
     p, T, w, u = _quartic_case(seed=3)
     ell = 0.2
-    x = p.src_xyz.astype(np.float64)
-    zt = p.tgt_xyz.astype(np.float64) @ T[:3, :3].T + T[:3, 3]
-    W = hat(w)
-    u1 = zt @ W.T + u
-    u2 = u1 @ W.T
-    u3 = u2 @ W.T
-    u4 = u3 @ W.T
-    d = x[:, None, :] - zt[None, :, :]
-    cc = 0.2 * (p.src_feat.astype(np.float64) @ p.tgt_feat.astype(np.float64).T)
-    il = 1.0 / ell ** 2
-    dot = lambda a, b: (a * b).sum(-1)
-    al = -0.5 * il * dot(d, d)
-    be = -il * dot(u1[None], d)
-    ga = -0.5 * il * (dot(u1, u1)[None] + 2 * dot(u2[None], d))
-    de = il * (-dot(u1, u2)[None] - dot(u3[None], d))
-    ep = -0.5 * il * (dot(u2, u2)[None] + 2 * dot(u1, u3)[None] + 2 * dot(u4[None], d))
-    g = [be, ga + be ** 2 / 2, de + be * ga + be ** 3 / 6,
-         ep + be * de + be ** 2 * ga / 2 + ga ** 2 / 2 + be ** 4 / 24]
-    k = 0.01 * cc * np.exp(al)
-    Ap = [float((k * gk).sum()) for gk in g]
+    Ap = npo.quartic_printed(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, w, u, ell=ell)
     c, _ = oracle.quartic(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, w, u, ell=ell)
-    np.testing.assert_allclose(Ap[0], c[1], rtol=1e-12)
-    assert abs(Ap[1] - c[2]) > 1e-3 * abs(c[2])
-    res = [_G(p, T, w, u, t, ell) - c[0] - sum(Ap[k - 1] * t ** k for k in range(1, 5))
-           for t in (0.0025, 0.00125)]
+    np.testing.assert_allclose(Ap[:2], c[:2], rtol=1e-12)
+    assert abs(Ap[2] - c[2]) > 1e-3 * abs(c[2])
+    res = [_G(p, T, w, u, t, ell) - sum(Ap[k] * t ** k for k in range(5)) for t in (0.0025, 0.00125)]
     assert 3.0 < res[0] / res[1] < 5.0, res
 
 
@@ -435,3 +414,33 @@ def test_quartic_step_c_and_numpy_agree():
     A = [1.0, 4.02833482e-03, 8.71549933e-03, -7.21017475e+02, -1.91432643e-03]
     t = oracle.quartic_step(A)
     assert abs(t - npo.quartic_step(A)) < 1e-12 and 0.0013 < t < 0.0014
+
+
+def test_kernel_value_floor_is_a_distance_cutoff():
+    # Table 1's sparsification (kernel values below 1e-3 set to zero) keeps
+    # exactly the pairs within r = ell sqrt(2 ln(sigma^2 / floor)) (2.146 ell at
+    # sigma = 0.1): the C oracle's distance cutoff at that kappa equals the
+    # NumPy oracle's value floor
+    p = small_pair(seed=19)
+    T = oracle.expmap([0.01, 0.02, -0.01], [0.02, -0.01, 0.0])
+    sigma, floor, ell = 0.1, 1e-3, 0.15
+    kappa = math.sqrt(2.0 * math.log(sigma ** 2 / floor))
+    assert abs(kappa - 2.1460) < 1e-4
+    r = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, sigma=sigma, ell=ell, kappa=kappa, a2=5.0)
+    F, w, v = npo.evaluate(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, sigma=sigma, ell=ell, a2=5.0,
+                           kernel_floor=floor)
+    np.testing.assert_allclose(r["g"], np.concatenate([[F], w, v]), rtol=1e-10, atol=1e-14)
+    F0, _, _ = npo.evaluate(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, sigma=sigma, ell=ell, a2=5.0)
+    assert F < F0
+
+
+def test_gradient_norm_threshold_stops():
+    p = small_pair(seed=23)
+    base = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, stage_ell=(0.15,), max_iters=60, a2=7.0)
+    gn = np.linalg.norm(base["trace"][:, 1:7], axis=1)
+    thr = float(gn[20])
+    r = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, stage_ell=(0.15,), max_iters=60, a2=7.0,
+                        grad_tol=thr * 1.0000001)
+    k = int(np.argmax(gn < thr * 1.0000001))
+    assert r["converged"] and r["iters"] == k + 1
+    np.testing.assert_array_equal(r["trace"], base["trace"][: k + 1])
