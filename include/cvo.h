@@ -105,7 +105,24 @@ typedef struct {
                                reduction and step) or CVO_FP64 (every pair term in FP64) */
   int32_t trace;            /* 1: keep the per-iteration trace (cvo_trace) */
   int32_t step_rule;        /* CVO_STEP_FIXED or CVO_STEP_QUARTIC (see the step length above) */
+  double grad_tol;          /* also stop once the last stage is reached and |(omega, v)|_2 < grad_tol
+                               (Table 1's gradient-norm threshold; 0: off) */
+  double kernel_floor;      /* > 0: sparsify by kernel value as in the TUM experiment (Table 1):
+                               pairs with sigma^2 exp(-r^2/(2 ell^2)) < kernel_floor are dropped,
+                               i.e. the cutoff r <= ell sqrt(2 ln(sigma^2 / kernel_floor)); needs
+                               cutoff_mult = 0 and sigma^2 > kernel_floor.  0: cutoff_mult applies */
 } cvo_params;
+
+/* One organised RGB-D frame (the input of the front end, Sec. VII-B). */
+typedef struct {
+  int32_t width, height;    /* pixels, 1..16384 each, width * height <= 16,777,216 */
+  const float* depth;       /* [height][width] depth along the optical axis (m); a pixel whose depth is
+                               not finite or outside [dmin, dmax] gives no point */
+  const float* rgb;         /* [height][width][3] colour, finite (EINVAL otherwise) */
+  double fx, fy, cx, cy;    /* pinhole intrinsics in pixels (fx, fy > 0) */
+  double dmin, dmax;        /* valid depth range (m), dmin <= dmax */
+  int32_t on_device;        /* 1: depth, rgb and the outputs are device pointers on the context's device */
+} cvo_rgbd_frame;
 
 typedef struct {
   int32_t status;           /* 0 or a negative code */
@@ -143,6 +160,22 @@ int cvo_eval(cvo_ctx* ctx, const cvo_cloud* src, const cvo_cloud* tgt, const cvo
  * A1 = a^2 |omega|^2 + b^2 |v|^2.  omega and v must be finite. */
 int cvo_quartic(cvo_ctx* ctx, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* params,
                 const double T[16], const double omega[3], const double v[3], double coef[5]);
+
+/* RGB-D front end (Sec. VII-B: the semi-dense cloud of high-gradient pixels
+ * taken from the organised depth image, one point per pixel, the pixel's
+ * colour as label).  Every step that decides the selection is FP32 in this
+ * order, without fused multiply-adds:
+ *   I = ((r + g) + b) / 3;  gu = (I[v][u+1] - I[v][u-1]) / 2 (one-sided
+ *   differences at the border: I[v][1] - I[v][0], I[v][W-1] - I[v][W-2]),
+ *   gv likewise along rows;  s = gu*gu + gv*gv;
+ * the k valid pixels of largest s are kept (ties to the smaller pixel index
+ * p = v * width + u; all valid pixels when there are at most k), in increasing
+ * pixel order.  Point p: (rx d, ry d, d) with rx = (float)((u - cx) / fx),
+ * ry = (float)((v - cy) / fy) (FP64 ray, one rounding, one FP32 product);
+ * label: (r, g, b, 0.5 + 0.5 tanh(gu / 0.05), 0.5 + 0.5 tanh(gv / 0.05)).
+ * xyz [k][3] and feat [k][5] receive the first *n_out rows (caller buffers,
+ * on the device when frame->on_device).  Synchronous. */
+int cvo_frontend(cvo_ctx* ctx, const cvo_rgbd_frame* frame, int32_t k, float* xyz, float* feat, int32_t* n_out);
 
 /* The step of CVO_STEP_QUARTIC for given coefficients (host code, the same
  * rule the step kernel applies): returns 1 and *t = the maximiser over t > 0

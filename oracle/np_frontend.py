@@ -14,7 +14,7 @@ can reproduce the selection exactly:
   gu     = (I[v, u+1] - I[v, u-1]) / 2  (interior),  I[v,1] - I[v,0],  I[v,W-1] - I[v,W-2]
   gv     = the same along v (rows)
   s      = gu*gu + gv*gv                             (two products, one sum; no fused multiply-add)
-  valid  = depth finite and dmin <= depth <= dmax
+  valid  = depth finite and fl32(dmin) <= depth <= fl32(dmax)
   keep   = the k valid pixels of largest s, ties to the smaller pixel index
            p = v W + u; all valid pixels when there are at most k
   order  = increasing p
@@ -59,7 +59,7 @@ def select(depth, s, dmin, dmax, k):
     d = np.asarray(depth, dtype=F32).reshape(-1)
     s = np.asarray(s, dtype=F32).reshape(-1)
     with np.errstate(invalid="ignore"):
-        valid = np.isfinite(d) & (d >= dmin) & (d <= dmax)
+        valid = np.isfinite(d) & (d >= F32(dmin)) & (d <= F32(dmax))
     idx = np.flatnonzero(valid)
     if idx.size <= k:
         return idx

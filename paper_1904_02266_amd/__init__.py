@@ -7,4 +7,4 @@ seeded synthetic inputs.
 """
 from ._binding import (CVO_EBUSY, CVO_EDEVICE, CVO_EINVAL, CVO_ENOMEM, CVO_ENOOVERLAP,  # noqa: F401
                        CVO_ENOTFOUND, CVO_OK, CVO_PENDING, Context, CvoError, Params, load,
-                       params_planes, params_rgbd, quartic_step)
+                       params_planes, params_rgbd, params_table1, quartic_step)

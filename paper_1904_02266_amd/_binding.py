@@ -45,7 +45,15 @@ class cvo_params(ctypes.Structure):
                 ("stage_iters", ctypes.POINTER(ctypes.c_int32)),
                 ("stage_ell", ctypes.POINTER(ctypes.c_double)),
                 ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("trace", ctypes.c_int32), ("step_rule", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("trace", ctypes.c_int32), ("step_rule", ctypes.c_int32),
+                ("grad_tol", ctypes.c_double), ("kernel_floor", ctypes.c_double)]
+
+
+class cvo_rgbd_frame(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("depth", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("dmin", ctypes.c_double), ("dmax", ctypes.c_double), ("on_device", ctypes.c_int32)]
 
 
 class cvo_result(ctypes.Structure):
@@ -98,13 +106,14 @@ def load():
     L.cvo_kernel_stats.argtypes = [vp, i32, P(ctypes.c_int64), P(dbl), P(dbl), P(dbl), P(u64)]
     L.cvo_quartic.argtypes = [vp, P(cvo_cloud), P(cvo_cloud), P(cvo_params), P(dbl), P(dbl), P(dbl), P(dbl)]
     L.cvo_quartic_step.argtypes = [P(dbl), P(dbl)]
+    L.cvo_frontend.argtypes = [vp, P(cvo_rgbd_frame), i32, vp, vp, P(i32)]
     L.cvo_strerror.argtypes = [ctypes.c_int]
     L.cvo_strerror.restype = ctypes.c_char_p
     L.cvo_last_error.argtypes = [vp]
     L.cvo_last_error.restype = ctypes.c_char_p
     for name in ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
                  "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
-                 "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step"):
+                 "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -112,7 +121,8 @@ def load():
 
 EXPORTED = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
             "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
-            "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_strerror", "cvo_last_error")
+            "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend", "cvo_strerror",
+            "cvo_last_error")
 
 
 class CvoError(RuntimeError):
@@ -138,6 +148,8 @@ class Params:
     precision: str = "fp32"
     trace: bool = False
     step_rule: str = "fixed"
+    grad_tol: float = 0.0
+    kernel_floor: float = 0.0
 
     def to_c(self):
         ns = len(self.stage_ell)
@@ -147,13 +159,25 @@ class Params:
                        ctypes.cast(si, ctypes.POINTER(ctypes.c_int32)),
                        ctypes.cast(se, ctypes.POINTER(ctypes.c_double)), self.max_iters, self.tol,
                        CVO_FP64 if self.precision == "fp64" else CVO_FP32_KAHAN, 1 if self.trace else 0,
-                       STEP_RULES[self.step_rule])
+                       STEP_RULES[self.step_rule], self.grad_tol, self.kernel_floor)
         return p, (si, se)
 
 
 def params_planes(**kw):
     """Three-plane brute-force workload: ell = 0.1 fixed, all pairs, 50 steps."""
     base = dict(stage_ell=(0.1,), max_iters=50, cutoff_mult=0.0)
+    base.update(kw)
+    return Params(**base)
+
+
+def params_table1(**kw):
+    """The TUM-experiment parameters of Table 1: ell 0.15, 0.10 after iteration
+    3, 0.06 after 10, 0.03 after 20; sigma 0.1; kernel values below 1e-3
+    dropped; transformation and gradient-norm thresholds 1e-5 and 5e-5; the
+    quartic step.  (The colour inner-product scale and the minimum step length
+    are not taken over: see the readings of the step rule and of the labels.)"""
+    base = dict(stage_ell=(0.15, 0.10, 0.06, 0.03), stage_iters=(4, 7, 10), max_iters=200, sigma=0.1,
+                kernel_floor=1e-3, tol=1e-5, grad_tol=5e-5, step_rule="quartic")
     base.update(kw)
     return Params(**base)
 
@@ -277,6 +301,42 @@ class Context:
         self._check(self.L.cvo_eval(self.h, ctypes.byref(s.c), ctypes.byref(t.c), ctypes.byref(p), Tp,
                                     ctypes.byref(F), w, v), "cvo_eval")
         return np.array([F.value, *w[:], *v[:]])
+
+    def frontend(self, depth, rgb, k, fx, fy, cx, cy, dmin=0.5, dmax=5.0):
+        """Semi-dense cloud of one RGB-D frame: (xyz [n,3], feat [n,5]) as float32,
+        NumPy arrays for host images, torch tensors on the device for device ones."""
+        try:
+            import torch
+            is_t = isinstance(depth, torch.Tensor) and depth.is_cuda
+        except ImportError:  # pragma: no cover
+            is_t = False
+        if is_t:
+            import torch
+            depth = depth.to(torch.float32).contiguous()
+            rgb = rgb.to(torch.float32).contiguous()
+            H, W = depth.shape
+            if tuple(rgb.shape) != (H, W, 3) or not rgb.is_cuda:
+                raise ValueError("rgb must be [H,W,3] on the same device as depth")
+            xyz = torch.empty((k, 3), dtype=torch.float32, device=depth.device)
+            feat = torch.empty((k, 5), dtype=torch.float32, device=depth.device)
+            self.L.cvo_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+            fr = cvo_rgbd_frame(W, H, depth.data_ptr(), rgb.data_ptr(), fx, fy, cx, cy, dmin, dmax, 1)
+            xp, fp = xyz.data_ptr(), feat.data_ptr()
+        else:
+            depth = np.ascontiguousarray(depth, dtype=np.float32)
+            rgb = np.ascontiguousarray(rgb, dtype=np.float32)
+            H, W = depth.shape
+            if rgb.shape != (H, W, 3):
+                raise ValueError("rgb must be [H,W,3]")
+            xyz = np.zeros((k, 3), np.float32)
+            feat = np.zeros((k, 5), np.float32)
+            self.L.cvo_set_stream(self.h, None)
+            fr = cvo_rgbd_frame(W, H, depth.ctypes.data, rgb.ctypes.data, fx, fy, cx, cy, dmin, dmax, 0)
+            xp, fp = xyz.ctypes.data, feat.ctypes.data
+        n = ctypes.c_int32()
+        self._check(self.L.cvo_frontend(self.h, ctypes.byref(fr), k, ctypes.c_void_p(xp), ctypes.c_void_p(fp),
+                                        ctypes.byref(n)), "cvo_frontend")
+        return xyz[: n.value], feat[: n.value]
 
     def quartic(self, src_xyz, src_feat, tgt_xyz, tgt_feat, T, omega, v, params: Params):
         """F, A1..A4 of the fourth-order model of G(t) = F(h exp(t (omega, v))) at T."""

@@ -46,7 +46,7 @@ struct Request {
   int n = 0, m = 0, fd = 0, n_stages = 1, max_iters = 1, precision = 0, trace_on = 0;
   int step_rule = kStepFixed;
   double xi0[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // direction of the coefficient evaluation
-  double sigma = 0.1, sf = 0.2, a2 = -1.0, b2 = 1.0, eta = 1.0, kappa = 0.0, tol = 0.0;
+  double sigma = 0.1, sf = 0.2, a2 = -1.0, b2 = 1.0, eta = 1.0, kappa = 0.0, tol = 0.0, grad_tol = 0.0;
   int stage_iters[kMaxStages] = {0};
   double stage_ell[kMaxStages] = {0.0};
   double T0[16];
@@ -248,6 +248,8 @@ struct cvo_ctx {
   ReqStatic* d_reqs_sync = nullptr;
   int* d_clus_end_sync = nullptr;
   DevQueue queue_sync;
+  char* fe_arena = nullptr;  // front-end buffers
+  size_t fe_arena_bytes = 0;
   Request last_register;
   bool have_last = false;
 
@@ -314,6 +316,11 @@ static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
   if (p->max_iters < 1 || !(p->tol >= 0.0)) return CVO_EINVAL;
   if (p->precision != CVO_FP32_KAHAN && p->precision != CVO_FP64) return CVO_EINVAL;
   if (p->step_rule != CVO_STEP_FIXED && p->step_rule != CVO_STEP_QUARTIC) return CVO_EINVAL;
+  if (!(p->grad_tol >= 0.0) || !(p->kernel_floor >= 0.0) || !std::isfinite(p->kernel_floor)) return CVO_EINVAL;
+  // value sparsification (Table 1): sigma^2 exp(-r^2 / (2 ell^2)) >= floor
+  // keeps exactly r <= ell sqrt(2 ln(sigma^2 / floor))
+  if (p->kernel_floor > 0.0 && (p->cutoff_mult > 0.0 || !(p->sigma * p->sigma > p->kernel_floor)))
+    return CVO_EINVAL;
   for (int s = 0; s < p->n_stages; s++) {
     if (!(p->stage_ell[s] > 0.0) || !std::isfinite(p->stage_ell[s])) return CVO_EINVAL;
     if (s < p->n_stages - 1 && p->stage_iters[s] < 1) return CVO_EINVAL;
@@ -334,8 +341,10 @@ static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
   q.a2 = p->a2;
   q.b2 = p->b2;
   q.eta = p->eta;
-  q.kappa = p->cutoff_mult;
+  q.kappa = p->kernel_floor > 0.0 ? std::sqrt(2.0 * std::log(p->sigma * p->sigma / p->kernel_floor))
+                                   : p->cutoff_mult;
   q.tol = p->tol;
+  q.grad_tol = p->grad_tol;
   for (int s = 0; s < q.n_stages; s++) {
     q.stage_ell[s] = p->stage_ell[s];
     q.stage_iters[s] = (s < q.n_stages - 1) ? p->stage_iters[s] : INT_MAX;
@@ -522,6 +531,7 @@ static int finish_setup(cvo_ctx* c, Request& q, const Layout& L, const LayoutB& 
   st.b2 = q.b2;
   st.eta = q.eta;
   st.tol = q.tol;
+  st.grad_tol = q.grad_tol;
   q.trace_dev = st.trace;
   q.per_target_dev = st.per_target;
   return CVO_OK;
@@ -635,7 +645,7 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
     }
   }
   int launched = 0;
-  const int chunk = (q.tol > 0.0) ? 16 : q.max_iters;
+  const int chunk = (q.tol > 0.0 || q.grad_tol > 0.0) ? 16 : q.max_iters;
   for (int k = 0; k < q.max_iters;) {
     const int kend = std::min(q.max_iters, k + chunk);
     for (; k < kend; k++) {
@@ -934,6 +944,7 @@ int cvo_destroy(cvo_ctx* c) {
   if (c->d_clus_end_sync) (void)hipFree(c->d_clus_end_sync);
   c->queue_sync.release();
   if (c->sync_arena_b) (void)hipFree(c->sync_arena_b);
+  if (c->fe_arena) (void)hipFree(c->fe_arena);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->ev_a) (void)hipEventDestroy(c->ev_a);
@@ -1013,6 +1024,98 @@ int cvo_quartic(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cv
   if (rc) return rc;
   if (q.status) return q.status;
   for (int i = 0; i < 5; i++) coef[i] = q.coef[i];
+  return CVO_OK;
+}
+
+int cvo_frontend(cvo_ctx* c, const cvo_rgbd_frame* f, int32_t k, float* xyz, float* feat, int32_t* n_out) {
+  if (!c || !f || !xyz || !feat || !n_out || k < 1) return CVO_EINVAL;
+  if (f->width < 1 || f->height < 1 || f->width > 16384 || f->height > 16384 || !f->depth || !f->rgb)
+    return CVO_EINVAL;
+  const long long P = (long long)f->width * f->height;
+  if (P > (long long)kScanTile * kScanBlock) return CVO_EINVAL;
+  if (!(f->fx > 0.0) || !(f->fy > 0.0) || !std::isfinite(f->fx) || !std::isfinite(f->fy) || !std::isfinite(f->cx) ||
+      !std::isfinite(f->cy) || !std::isfinite(f->dmin) || !std::isfinite(f->dmax) || !(f->dmin <= f->dmax))
+    return CVO_EINVAL;
+  std::lock_guard<std::mutex> g(c->call_mu);
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  // arena: depth, rgb (host frames), I, key, tie, pos, two histograms,
+  // control block, scan arguments and tile sums, outputs (host outputs)
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  const bool dev = f->on_device != 0;
+  const size_t o_depth = dev ? 0 : take(4 * (size_t)P);
+  const size_t o_rgb = dev ? 0 : take(12 * (size_t)P);
+  const size_t o_I = take(4 * (size_t)P), o_key = take(4 * (size_t)P), o_tie = take(4 * (size_t)P),
+               o_pos = take(4 * (size_t)P);
+  const size_t o_hh = take(4 << 16), o_hl = take(4 << 16), o_ctl = take(sizeof(FeCtl)),
+               o_scans = take(2 * sizeof(ScanArgs));
+  const size_t ntiles = (size_t)((P + kScanTile - 1) / kScanTile) + 1;
+  const size_t o_sums0 = take(4 * ntiles), o_sums1 = take(4 * ntiles);
+  const size_t o_xyz = dev ? 0 : take(12 * (size_t)k);
+  const size_t o_feat = dev ? 0 : take(20 * (size_t)k);
+  int rc = grow(c, &c->fe_arena, &c->fe_arena_bytes, off, s);
+  if (rc) return rc;
+  rc = ensure_pinned(c, 64 * 1024);
+  if (rc) return rc;
+  char* A = c->fe_arena;
+  FrontendArgs a{};
+  a.W = f->width;
+  a.H = f->height;
+  a.k = k;
+  a.dmin = (float)f->dmin;
+  a.dmax = (float)f->dmax;
+  a.fx = f->fx;
+  a.fy = f->fy;
+  a.cx = f->cx;
+  a.cy = f->cy;
+  if (dev) {
+    a.depth = f->depth;
+    a.rgb = f->rgb;
+    a.xyz = xyz;
+    a.feat = feat;
+  } else {
+    HIPCHK(c, hipMemcpyAsync(A + o_depth, f->depth, 4 * (size_t)P, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(A + o_rgb, f->rgb, 12 * (size_t)P, hipMemcpyHostToDevice, s));
+    a.depth = (const float*)(A + o_depth);
+    a.rgb = (const float*)(A + o_rgb);
+    a.xyz = (float*)(A + o_xyz);
+    a.feat = (float*)(A + o_feat);
+  }
+  a.I = (float*)(A + o_I);
+  a.key = (unsigned*)(A + o_key);
+  a.tie = (int*)(A + o_tie);
+  a.pos = (int*)(A + o_pos);
+  a.hist_hi = (unsigned*)(A + o_hh);
+  a.hist_lo = (unsigned*)(A + o_hl);
+  a.ctl = (FeCtl*)(A + o_ctl);
+  a.scans = (ScanArgs*)(A + o_scans);
+  ScanArgs* hs = (ScanArgs*)c->pinned;
+  hs[0].data = a.tie;
+  hs[0].lenp = nullptr;
+  hs[0].len0 = (int)P;
+  hs[0].sums = (int*)(A + o_sums0);
+  hs[1].data = a.pos;
+  hs[1].lenp = nullptr;
+  hs[1].len0 = (int)P;
+  hs[1].sums = (int*)(A + o_sums1);
+  HIPCHK(c, hipMemcpyAsync(a.scans, hs, 2 * sizeof(ScanArgs), hipMemcpyHostToDevice, s));
+  HIPCHK(c, launch_frontend(a, s));
+  FeCtl* hc = (FeCtl*)((char*)c->pinned + 1024);
+  HIPCHK(c, hipMemcpyAsync(hc, a.ctl, sizeof(FeCtl), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (hc->bad) return CVO_EINVAL;
+  const int n = hc->n_out;
+  if (!dev && n > 0) {
+    HIPCHK(c, hipMemcpyAsync(xyz, a.xyz, 12 * (size_t)n, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(feat, a.feat, 20 * (size_t)n, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  *n_out = n;
   return CVO_OK;
 }
 

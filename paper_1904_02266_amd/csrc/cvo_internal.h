@@ -118,6 +118,7 @@ struct ReqStatic {
   double stage_ell[kMaxStages];
   double s2f;                        // sigma^2 * s_f
   double b2, eta, tol;
+  double grad_tol;                   // stop when |(omega, v)| < grad_tol in the last stage (0: off)
 };
 
 // Per-request mutable state, device-resident for the whole registration.
@@ -193,6 +194,32 @@ struct IngestArgs {
   int nblk_bbox;
 };
 hipError_t launch_ingest(const IngestArgs& a, hipStream_t s);
+
+// RGB-D front end: control block of the selection (device) and arguments.
+struct FeCtl {
+  int valid;       // valid pixels
+  int all;         // 1: at most k valid pixels, all kept
+  int hi;          // high 16 bits of the k-th largest key
+  int above;       // keys above bin hi
+  unsigned thr;    // the k-th largest key
+  int need;        // pixels with key == thr to keep (the first ones in pixel order)
+  int n_out;       // points written
+  int bad;         // a colour value is not finite
+};
+struct FrontendArgs {
+  const float *depth, *rgb;  // device [H][W], [H][W][3]
+  int W, H, k;
+  float dmin, dmax;
+  double fx, fy, cx, cy;
+  float* I;                  // [P] intensity
+  unsigned* key;             // [P]
+  unsigned *hist_hi, *hist_lo;  // [65536] each
+  int *tie, *pos;            // [P] each (scanned in place)
+  ScanArgs* scans;           // device [2]: over tie, over pos
+  FeCtl* ctl;
+  float *xyz, *feat;         // device outputs [k][3], [k][5]
+};
+hipError_t launch_frontend(const FrontendArgs& a, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // One gradient-flow iteration (or one evaluation) for a batch of requests that
 // share precision, label dimension and cutoff mode.  clus_end[r] is the

@@ -1155,11 +1155,14 @@ __device__ void take_step(const ReqStatic& R, ReqState* __restrict__ S, double t
     tr[24] = 0.0;
     tr[25] = 1.0;
   }
-  double sq = 0.0;
-  for (int a = 0; a < 3; a++) sq += w[a] * w[a] + u[a] * u[a];
+  double sq = 0.0, gq = 0.0;
+  for (int a = 0; a < 3; a++) {
+    sq += w[a] * w[a] + u[a] * u[a];
+    gq += g[1 + a] * g[1 + a] + g[4 + a] * g[4 + a];
+  }
   const int kn = k + 1;
   S->iter = kn;
-  if (stage == R.n_stages - 1 && sqrt(sq) < R.tol) {
+  if (stage == R.n_stages - 1 && (sqrt(sq) < R.tol || sqrt(gq) < R.grad_tol)) {
     S->converged = 1;
     S->done = 1;
   } else if (kn >= R.max_iters) {
@@ -1755,6 +1758,195 @@ __global__ void k_setup_final(ReqState* __restrict__ S, const double* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// RGB-D front end (Sec. VII-B, TUM experiment): semi-dense selection of the
+// pixels of largest image gradient and their points from the organised depth
+// image.  Every floating-point step that decides the selection is fixed in
+// FP32 (no contraction), so the kept set is exact:
+//   I = ((r + g) + b) / 3;  gu, gv central differences (one-sided at the
+//   border);  s = gu*gu + gv*gv;  valid = finite depth in [dmin, dmax];
+//   keep the k valid pixels of largest s, ties to the smaller pixel index,
+//   in increasing pixel order.
+// Selection is a two-level radix select on key = bits(s) + 1 (0: invalid):
+// 16-bit histograms find the k-th largest key t; the pixels with key > t and
+// the first (k - #{key > t}) pixels with key == t in pixel order are kept.
+// ---------------------------------------------------------------------------
+constexpr int kFeBins = 1 << 16;
+
+__global__ __launch_bounds__(256) void k_fe_intensity(const float* __restrict__ rgb, long long P,
+                                                      float* __restrict__ I, FeCtl* __restrict__ ctl) {
+  bool bad = false;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
+    const float r = rgb[3 * p], g = rgb[3 * p + 1], b = rgb[3 * p + 2];
+    bad |= !(isfinite(r) && isfinite(g) && isfinite(b));
+    I[p] = ((r + g) + b) / 3.0f;
+  }
+  if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&ctl->bad, 1);
+}
+
+// gu, gv at pixel (u, v), the border rules of the definition
+__device__ __forceinline__ void fe_grad(const float* __restrict__ I, int W, int H, int u, int v, float& gu, float& gv) {
+  const float* row = I + (size_t)v * W;
+  if (W < 2) gu = 0.0f;
+  else if (u == 0) gu = row[1] - row[0];
+  else if (u == W - 1) gu = row[W - 1] - row[W - 2];
+  else gu = (row[u + 1] - row[u - 1]) / 2.0f;
+  if (H < 2) gv = 0.0f;
+  else if (v == 0) gv = I[(size_t)W + u] - I[u];
+  else if (v == H - 1) gv = I[(size_t)(H - 1) * W + u] - I[(size_t)(H - 2) * W + u];
+  else gv = (I[(size_t)(v + 1) * W + u] - I[(size_t)(v - 1) * W + u]) / 2.0f;
+}
+
+__device__ __forceinline__ float fe_score(float gu, float gv) {
+#pragma clang fp contract(off)
+  const float a = gu * gu;
+  const float b = gv * gv;
+  return a + b;
+}
+
+__global__ __launch_bounds__(256) void k_fe_score(const float* __restrict__ I, const float* __restrict__ depth, int W,
+                                                  int H, float dmin, float dmax, unsigned* __restrict__ key,
+                                                  unsigned* __restrict__ hist) {
+  const long long P = (long long)W * H;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
+    const int v = (int)(p / W), u = (int)(p - (long long)v * W);
+    float gu, gv;
+    fe_grad(I, W, H, u, v, gu, gv);
+    const float s = fe_score(gu, gv);
+    const float d = depth[p];
+    const bool valid = isfinite(d) && d >= dmin && d <= dmax;
+    const unsigned kk = valid ? __float_as_uint(s) + 1u : 0u;  // s >= 0 and finite: bits are monotone
+    key[p] = kk;
+    if (kk) atomicAdd(&hist[kk >> 16], 1u);
+  }
+}
+
+// One 1024-thread block: the high-16-bit bin holding the k-th largest key
+// (thread t holds bins 64t .. 64t + 63, scanned from the top), and the number
+// of keys in the bins above it.  When at most k pixels are valid all are kept.
+__global__ __launch_bounds__(1024) void k_fe_find(const unsigned* __restrict__ hist, int k, FeCtl* __restrict__ ctl) {
+  constexpr int per = kFeBins / 1024;
+  __shared__ int sh[33];
+  const int t = threadIdx.x;
+  const int rt = 1023 - t;  // reversed order: thread 0 holds the top bins
+  int sum = 0;
+  for (int q = 0; q < per; q++) sum += (int)hist[rt * per + q];
+  int total;
+  int above = block_excl_scan(sum, sh, total);  // keys in the bins above this thread's range
+  if (t == 0) {
+    ctl->valid = total;
+    ctl->all = total <= k ? 1 : 0;
+  }
+  if (total <= k) return;  // block-uniform
+  if (above < k && above + sum >= k) {
+    for (int q = per - 1; q >= 0; q--) {
+      const int b = rt * per + q;
+      const int c = (int)hist[b];
+      if (above + c >= k) {
+        ctl->hi = b;
+        ctl->above = above;
+        break;
+      }
+      above += c;
+    }
+  }
+}
+
+// level 1 of the search, skipped when every valid pixel is kept
+__global__ __launch_bounds__(1024) void k_fe_find_lo_gate(const unsigned* __restrict__ hist, int k,
+                                                          FeCtl* __restrict__ ctl);
+
+__global__ __launch_bounds__(256) void k_fe_hist_lo(const unsigned* __restrict__ key, long long P,
+                                                    const FeCtl* __restrict__ ctl, unsigned* __restrict__ hist) {
+  if (ctl->all) return;
+  const unsigned hi = (unsigned)ctl->hi;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
+    const unsigned kk = key[p];
+    if (kk && (kk >> 16) == hi) atomicAdd(&hist[kk & 0xFFFFu], 1u);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_fe_find_lo_gate(const unsigned* __restrict__ hist, int k,
+                                                          FeCtl* __restrict__ ctl) {
+  if (ctl->all) return;  // block-uniform
+  constexpr int per = kFeBins / 1024;
+  __shared__ int sh[33];
+  const int t = threadIdx.x;
+  const int rt = 1023 - t;
+  int sum = 0;
+  for (int q = 0; q < per; q++) sum += (int)hist[rt * per + q];
+  int total;
+  int above = block_excl_scan(sum, sh, total);
+  const int want = k - ctl->above;
+  if (above < want && above + sum >= want) {
+    for (int q = per - 1; q >= 0; q--) {
+      const int b = rt * per + q;
+      const int c = (int)hist[b];
+      if (above + c >= want) {
+        ctl->thr = ((unsigned)ctl->hi << 16) | (unsigned)b;
+        ctl->need = want - above;
+        break;
+      }
+      above += c;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fe_ties(const unsigned* __restrict__ key, long long P,
+                                                 const FeCtl* __restrict__ ctl, int* __restrict__ tie) {
+  const bool all = ctl->all != 0;
+  const unsigned thr = ctl->thr;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x)
+    tie[p] = (!all && key[p] == thr) ? 1 : 0;
+}
+
+__device__ __forceinline__ bool fe_kept(unsigned kk, int tie_rank, const FeCtl& c) {
+  if (c.all) return kk != 0u;
+  return kk > c.thr || (kk == c.thr && tie_rank < c.need);
+}
+
+__global__ __launch_bounds__(256) void k_fe_keep(const unsigned* __restrict__ key, const int* __restrict__ tie_rank,
+                                                 long long P, const FeCtl* __restrict__ ctl, int* __restrict__ keep) {
+  const FeCtl c = *ctl;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x)
+    keep[p] = fe_kept(key[p], tie_rank[p], c) ? 1 : 0;
+}
+
+// The kept pixels' points and labels, at their rank in pixel order.
+__global__ __launch_bounds__(256) void k_fe_emit(const float* __restrict__ I, const float* __restrict__ depth,
+                                                 const float* __restrict__ rgb, const unsigned* __restrict__ key,
+                                                 const int* __restrict__ tie_rank, const int* __restrict__ pos, int W,
+                                                 int H, double fx, double fy, double cx, double cy, int k,
+                                                 const FeCtl* __restrict__ ctl, float* __restrict__ xyz,
+                                                 float* __restrict__ feat) {
+  const FeCtl c = *ctl;
+  const long long P = (long long)W * H;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
+    if (!fe_kept(key[p], tie_rank[p], c)) continue;
+    const int o = pos[p];
+    if (o < 0 || o >= k) continue;  // cannot happen: at most k pixels are kept
+    const int v = (int)(p / W), u = (int)(p - (long long)v * W);
+    const float d = depth[p];
+    const float rx = (float)(((double)u - cx) / fx);
+    const float ry = (float)(((double)v - cy) / fy);
+    xyz[3 * (size_t)o] = rx * d;
+    xyz[3 * (size_t)o + 1] = ry * d;
+    xyz[3 * (size_t)o + 2] = d;
+    float gu, gv;
+    fe_grad(I, W, H, u, v, gu, gv);
+    float* f = feat + 5 * (size_t)o;
+    f[0] = rgb[3 * p];
+    f[1] = rgb[3 * p + 1];
+    f[2] = rgb[3 * p + 2];
+    f[3] = (float)(0.5 + 0.5 * tanh((double)gu / 0.05));
+    f[4] = (float)(0.5 + 0.5 * tanh((double)gv / 0.05));
+  }
+}
+
+__global__ void k_fe_count(FeCtl* __restrict__ ctl, int k) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->n_out = ctl->all ? ctl->valid : k;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline int blocks_for(long long work, int bs, int cap) {
@@ -1938,6 +2130,32 @@ hipError_t launch_iteration_rule(int step_rule, int precision, int fd, bool cuto
   e = launch_quartic_pairs(precision, fd, cutoff, reqs, clus_end, nreq, total_clusters, Q, s);
   if (e != hipSuccess) return e;
   return launch_step(reqs, clus_end, nreq, total_clusters, Q, s, kPhaseQuartic, true);
+}
+
+hipError_t launch_frontend(const FrontendArgs& a, hipStream_t s) {
+  const long long P = (long long)a.W * a.H;
+  if (a.W < 1 || a.H < 1 || P > (long long)kScanTile * kScanBlock || a.k < 1) return hipErrorInvalidValue;
+  const int B = 256;
+  const int g = blocks_for(P, B, 2048);
+  hipError_t e = launch_zero(a.hist_hi, sizeof(unsigned) * kFeBins, s);
+  if (e != hipSuccess) return e;
+  e = launch_zero(a.hist_lo, sizeof(unsigned) * kFeBins, s);
+  if (e != hipSuccess) return e;
+  e = launch_zero(a.ctl, sizeof(FeCtl), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fe_intensity, dim3(g), dim3(B), 0, s, a.rgb, P, a.I, a.ctl);
+  hipLaunchKernelGGL(k_fe_score, dim3(g), dim3(B), 0, s, a.I, a.depth, a.W, a.H, a.dmin, a.dmax, a.key, a.hist_hi);
+  hipLaunchKernelGGL(k_fe_find, dim3(1), dim3(1024), 0, s, a.hist_hi, a.k, a.ctl);
+  hipLaunchKernelGGL(k_fe_hist_lo, dim3(g), dim3(B), 0, s, a.key, P, a.ctl, a.hist_lo);
+  hipLaunchKernelGGL(k_fe_find_lo_gate, dim3(1), dim3(1024), 0, s, a.hist_lo, a.k, a.ctl);
+  hipLaunchKernelGGL(k_fe_ties, dim3(g), dim3(B), 0, s, a.key, P, a.ctl, a.tie);
+  launch_scan(a.scans, 1, P, s);
+  hipLaunchKernelGGL(k_fe_keep, dim3(g), dim3(B), 0, s, a.key, a.tie, P, a.ctl, a.pos);
+  launch_scan(a.scans + 1, 1, P, s);
+  hipLaunchKernelGGL(k_fe_emit, dim3(g), dim3(B), 0, s, a.I, a.depth, a.rgb, a.key, a.tie, a.pos, a.W, a.H, a.fx,
+                     a.fy, a.cx, a.cy, a.k, a.ctl, a.xyz, a.feat);
+  hipLaunchKernelGGL(k_fe_count, dim3(1), dim3(1), 0, s, a.ctl, a.k);
+  return hipGetLastError();
 }
 
 }  // namespace cvo

@@ -345,7 +345,7 @@ def rgbd_frame_pair(seed=2, theta_max_deg=5.0, t_max=0.05):
     return render_images(room, np.eye(4), rng), render_images(room, G, rng), G
 
 
-def rgbd_sequence(n_frames=30, seed=9, step_deg=1.0, step_m=0.02):
+def rgbd_sequence(n_frames=30, seed=9, step_deg=1.0, step_m=0.02, depth_noise=0.01):
     """A hand-held-like camera path through one seeded room: each frame moves
     by a smooth random rotation (about step_deg) and translation (about
     step_m) from the previous one.  Returns the frames (ground-truth poses in
@@ -357,7 +357,7 @@ def rgbd_sequence(n_frames=30, seed=9, step_deg=1.0, step_m=0.02):
     w = rng.normal(0.0, 1.0, 3)
     v = rng.normal(0.0, 1.0, 3)
     for k in range(n_frames):
-        frames.append(render_images(room, G, rng))
+        frames.append(render_images(room, G, rng, depth_noise=depth_noise))
         # slowly varying angular and linear velocity
         w = 0.8 * w + 0.2 * rng.normal(0.0, 1.0, 3)
         v = 0.8 * v + 0.2 * rng.normal(0.0, 1.0, 3)
