@@ -623,14 +623,51 @@ __device__ __forceinline__ void one_pair(const CT* __restrict__ r, CT zx, CT zy,
 
 // The gradient pass's per-lane state: the lane's target (frame
 // coordinates, labels), the cutoff and the accumulators.
+//
+// FP32 staged sources (kExpanded) carry |x|^2 after the labels, and the pair
+// uses r^2 = |x|^2 + |z|^2 - 2 x.z (one add and three fma instead of three
+// subtractions, a product and two fma) and accumulates S = sum w x; the
+// item's D = sum w (z - x) is z W - S.  Frame coordinates are relative to the
+// cluster's centre, so |x|^2 and |z|^2 stay within a few tens (scaled units)
+// and the expansion costs a few ulp of r^2.  pair_cell (the overflow path,
+// cell-local coordinates) keeps the difference form and accumulates D.
 template <typename CT, int FD, bool CUT>
 struct GradOp {
+  static constexpr bool kExpanded = std::is_same<CT, float>::value;
   CT zx, zy, zz;
   CT mj[FD];
   CT rc2;
+  CT m0, m1, m2, z2;  // -2 z, |z|^2 (expanded form)
   Acc<CT> acc;
   unsigned long long within;
-  __device__ __forceinline__ void pair(const CT* r) { one_pair<CT, FD, CUT>(r, zx, zy, zz, mj, rc2, acc, within); }
+  __device__ __forceinline__ void expand() {
+    m0 = (CT)-2 * zx;
+    m1 = (CT)-2 * zy;
+    m2 = (CT)-2 * zz;
+    z2 = zx * zx + zy * zy + zz * zz;
+  }
+  __device__ __forceinline__ void pair(const CT* r) {
+    if constexpr (kExpanded) {
+      const CT r2 = fmaf(r[0], m0, fmaf(r[1], m1, fmaf(r[2], m2, r[3 + FD] + z2)));
+      const CT e = kexp2(-r2);
+      CT c = r[3] * mj[0];
+#pragma unroll
+      for (int f = 1; f < FD; f++) c += r[3 + f] * mj[f];
+      CT w = c * e;
+      if (CUT) {
+        const bool in = r2 <= rc2;
+        within += (unsigned long long)__popcll(__ballot(in));
+        w = in ? w : (CT)0;
+      }
+      acc.w += w;
+      acc.dx += w * r[0];
+      acc.dy += w * r[1];
+      acc.dz += w * r[2];
+    } else {
+      one_pair<CT, FD, CUT>(r, zx, zy, zz, mj, rc2, acc, within);
+    }
+  }
+  __device__ __forceinline__ void pair_cell(const CT* r) { one_pair<CT, FD, CUT>(r, zx, zy, zz, mj, rc2, acc, within); }
   __device__ __forceinline__ void fold() { acc.fold(); }
 };
 
@@ -686,6 +723,7 @@ struct Acc4<double> {
 //      = eps + beta delta + g2^2/2 - beta^4/12.
 template <typename CT, int FD, bool CUT>
 struct QuartOp {
+  static constexpr bool kExpanded = false;
   CT zx, zy, zz;
   CT mj[FD];
   CT rc2;
@@ -716,6 +754,7 @@ struct QuartOp {
     acc.a[2] += w * g3;
     acc.a[3] += w * g4;
   }
+  __device__ __forceinline__ void pair_cell(const CT* r) { pair(r); }
   __device__ __forceinline__ void fold() { acc.fold(); }
   // per-target vectors from the direction (w, v) and the target's position
   // zt (m), in FP64; lanes past the cluster get zero (their pairs have w = 0
@@ -760,13 +799,13 @@ __device__ __forceinline__ void cell_segment(cptr<CT> xr, int xs, int a, int b, 
 #pragma unroll
         for (int q = 0; q < NR; q++) rec[u][q] = xr[(size_t)(i + u) * xs + q];
 #pragma unroll
-      for (int u = 0; u < U; u++) op.pair(rec[u]);
+      for (int u = 0; u < U; u++) op.pair_cell(rec[u]);
     }
     for (; i < b1; i++) {
       CT rec[NR];
 #pragma unroll
       for (int q = 0; q < NR; q++) rec[q] = xr[(size_t)i * xs + q];
-      op.pair(rec);
+      op.pair_cell(rec);
     }
     op.fold();
   }
@@ -977,13 +1016,19 @@ __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ r
       const GridInfo g = R.grid[stage];
       const int* __restrict__ cs = uniform_ptr(R.cstart[stage]);
 
-      // cluster frame (lane 0 always holds a target)
-      const double O[3] = {uniform_d(zt[0]), uniform_d(zt[1]), uniform_d(zt[2])};
-      double blo[3], bhi[3];
+      // cluster frame: origin at the centre of the targets' bounding box
+      // (found relative to the first target, which lane 0 always holds), so
+      // that frame coordinates stay small
+      const double O0[3] = {uniform_d(zt[0]), uniform_d(zt[1]), uniform_d(zt[2])};
+      double blo[3], bhi[3], O[3];
       for (int a = 0; a < 3; a++) {
-        const double zr = valid ? (zt[a] - O[a]) * g.sq : 0.0;
+        const double zr = valid ? (zt[a] - O0[a]) * g.sq : 0.0;
         blo[a] = wave_min(valid ? zr : INFINITY);
         bhi[a] = wave_max(valid ? zr : -INFINITY);
+        const double mid = 0.5 * (blo[a] + bhi[a]);
+        O[a] = O0[a] + mid / g.sq;
+        blo[a] -= mid;
+        bhi[a] -= mid;
       }
       if (R.precision == 1)
         write_frame<double>(R, c, s0, cn, zt, g, O);
@@ -1235,9 +1280,11 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <int FD>
+// Floats per staged source record: x, y, z, labels (and |x|^2 for the
+// expanded gradient pass), rounded up to whole 16-byte reads.
+template <int FD, bool EXP = false>
 struct RecStride {
-  static constexpr int value = (3 + FD + 3) / 4 * 4;
+  static constexpr int value = (3 + FD + (EXP ? 1 : 0) + 3) / 4 * 4;
 };
 
 __device__ __forceinline__ unsigned long long wave_or(unsigned long long v) {
@@ -1283,7 +1330,8 @@ template <typename CT, int FD, bool CUT, typename Op>
 __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const ClusInfo& ci, int c, int k,
                                                      long long lo_s, long long hi_s, CT rc2, Op& op, cptr<CT> xr,
                                                      int xs, CT* recs) {
-  constexpr int RS = RecStride<FD>::value;
+  constexpr int RS = RecStride<FD, Op::kExpanded>::value;
+  constexpr int NX = 3 + FD + (Op::kExpanded ? 1 : 0);  // floats read per record
   constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
   static_assert(NR % kWave == 0 && NR >= kWave, "a staging round holds at least one batch");
   const int l = lane_id();
@@ -1366,18 +1414,18 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const C
       const int b1 = min(b0 + kBlock, count);
       int i = b0;
       for (; i + U <= b1; i += U) {
-        CT r4[U][3 + FD];
+        CT r4[U][NX];
 #pragma unroll
         for (int u = 0; u < U; u++)
 #pragma unroll
-          for (int q = 0; q < 3 + FD; q++) r4[u][q] = recs[(i + u) * RS + q];
+          for (int q = 0; q < NX; q++) r4[u][q] = recs[(i + u) * RS + q];
 #pragma unroll
         for (int u = 0; u < U; u++) op.pair(r4[u]);
       }
       for (; i < b1; i++) {
-        CT r1[3 + FD];
+        CT r1[NX];
 #pragma unroll
-        for (int q = 0; q < 3 + FD; q++) r1[q] = recs[i * RS + q];
+        for (int q = 0; q < NX; q++) r1[q] = recs[i * RS + q];
         op.pair(r1);
       }
       op.fold();
@@ -1417,6 +1465,7 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const C
       CT* dst = recs + (count + __popcll(km & ((1ull << l) - 1ull))) * RS;
 #pragma unroll
       for (int q = 0; q < 3 + FD; q++) dst[q] = rec[q];
+      if constexpr (Op::kExpanded) dst[3 + FD] = rec[0] * rec[0] + rec[1] * rec[1] + rec[2] * rec[2];
     }
     count += __popcll(km);
     if (count > NR - kWave || (last && count > 0)) flush();
@@ -1504,6 +1553,7 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
     lever(lv);
     op.setup(R.state->xi, lv, 1.0 / isq, valid);
   } else {
+    op.expand();
     op.acc.init();
     op.within = 0;
   }
@@ -1555,6 +1605,12 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
 
     double W, Dx, Dy, Dz;
     op.acc.result(W, Dx, Dy, Dz);
+    if (Op::kExpanded && !overflow) {
+      // S = sum w x  ->  D = sum w (z - x) = z W - S
+      Dx = (double)zx * W - Dx;
+      Dy = (double)zy * W - Dy;
+      Dz = (double)zz * W - Dz;
+    }
     if (!valid) W = Dx = Dy = Dz = 0.0;
     Dx *= isq;
     Dy *= isq;
@@ -1566,11 +1622,13 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
     const double oy = lv[2] * Dx - lv[0] * Dz;
     const double oz = lv[0] * Dy - lv[1] * Dx;
 
+    // (wave-uniform values are read outside the lane-dependent branch)
+    const int s0 = uniform(ci.s0);
+    const double ell_c = R.stage_ell[uniform(ci.stage)];
     if (R.mode == kModeEvalTargets && R.per_target && valid) {
-      const double ell = R.stage_ell[uniform(ci.stage)];
-      const double il2 = 1.0 / (ell * ell);
+      const double il2 = 1.0 / (ell_c * ell_c);
       const double a2 = R.state->a2;
-      double* o = R.per_target + (size_t)R.zorig[uniform(ci.s0) + l] * 7;
+      double* o = R.per_target + (size_t)R.zorig[s0 + l] * 7;
       o[0] = R.s2f * W;
       o[1] = R.s2f * ox * il2 / a2;
       o[2] = R.s2f * oy * il2 / a2;
@@ -1601,9 +1659,9 @@ template <typename CT, int FD, bool CUT, bool QUART>
 __global__ __launch_bounds__(kPairBlockWaves* kWave) void k_pairs(const ReqStatic* __restrict__ reqs,
                                                                   const int* __restrict__ clus_end, int nreq,
                                                                   QueueRef Q) {
-  constexpr int RS = RecStride<FD>::value;
+  constexpr int RS = RecStride<FD, std::is_same<CT, float>::value && !QUART>::value;
   constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
-  __shared__ CT recs_all[kPairBlockWaves][NR * RS];
+  __shared__ __align__(16) CT recs_all[kPairBlockWaves][NR * RS];
   __shared__ unsigned int next;
   CT* recs = recs_all[threadIdx.x >> 6];
   const unsigned int nitems = (unsigned)uniform((int)min(Q.q->nitems, Q.cap));
