@@ -624,13 +624,17 @@ __device__ __forceinline__ void one_pair(const CT* __restrict__ r, CT zx, CT zy,
 // The gradient pass's per-lane state: the lane's target (frame
 // coordinates, labels), the cutoff and the accumulators.
 //
-// FP32 staged sources (kExpanded) carry |x|^2 after the labels, and the pair
-// uses r^2 = |x|^2 + |z|^2 - 2 x.z (one add and three fma instead of three
-// subtractions, a product and two fma) and accumulates S = sum w x; the
-// item's D = sum w (z - x) is z W - S.  Frame coordinates are relative to the
-// cluster's centre, so |x|^2 and |z|^2 stay within a few tens (scaled units)
-// and the expansion costs a few ulp of r^2.  pair_cell (the overflow path,
-// cell-local coordinates) keeps the difference form and accumulates D.
+// FP32 (kExpanded) has two forms of the pair, chosen per cluster:
+//  * expanded (ex): r^2 = |x|^2 + |z|^2 - 2 x.z with |x|^2 staged beside the
+//    source (one add and three fma instead of three subtractions, a product
+//    and two fma), accumulating S = sum w x; the item's D = sum w (z - x) is
+//    z W - S.  The expansion loses about eps (|x|^2 + |z|^2) of r^2, so it is
+//    taken only when the cluster's box lies within kExpandHalf scaled units of
+//    its centre (the frame origin): then |x|^2 + |z|^2 stays below ~100.
+//  * difference: d = z - x, r^2 = d.d, accumulating D directly (clusters that
+//    span more, e.g. long chains of targets at a small length-scale).
+constexpr float kExpandHalf = 3.0f;
+
 template <typename CT, int FD, bool CUT>
 struct GradOp {
   static constexpr bool kExpanded = std::is_same<CT, float>::value;
@@ -638,17 +642,20 @@ struct GradOp {
   CT mj[FD];
   CT rc2;
   CT m0, m1, m2, z2;  // -2 z, |z|^2 (expanded form)
+  bool ex;            // the expanded form (wave-uniform)
   Acc<CT> acc;
   unsigned long long within;
-  __device__ __forceinline__ void expand() {
+  __device__ __forceinline__ void expand(bool ok) {
+    ex = kExpanded && ok;
     m0 = (CT)-2 * zx;
     m1 = (CT)-2 * zy;
     m2 = (CT)-2 * zz;
     z2 = zx * zx + zy * zy + zz * zz;
   }
-  __device__ __forceinline__ void pair(const CT* r) {
-    if constexpr (kExpanded) {
-      const CT r2 = fmaf(r[0], m0, fmaf(r[1], m1, fmaf(r[2], m2, r[3 + FD] + z2)));
+  template <bool E>
+  __device__ __forceinline__ void pair_t(const CT* r) {
+    if constexpr (E) {
+      const CT r2 = fma(r[0], m0, fma(r[1], m1, fma(r[2], m2, r[3 + FD] + z2)));
       const CT e = kexp2(-r2);
       CT c = r[3] * mj[0];
 #pragma unroll
@@ -667,7 +674,10 @@ struct GradOp {
       one_pair<CT, FD, CUT>(r, zx, zy, zz, mj, rc2, acc, within);
     }
   }
-  __device__ __forceinline__ void pair_cell(const CT* r) { one_pair<CT, FD, CUT>(r, zx, zy, zz, mj, rc2, acc, within); }
+  __device__ __forceinline__ void pair(const CT* r) {
+    if (ex) pair_t<true>(r);
+    else pair_t<false>(r);
+  }
   __device__ __forceinline__ void fold() { acc.fold(); }
 };
 
@@ -723,28 +733,44 @@ struct Acc4<double> {
 //      = eps + beta delta + g2^2/2 - beta^4/12.
 template <typename CT, int FD, bool CUT>
 struct QuartOp {
-  static constexpr bool kExpanded = false;
+  // Expanded form, as in the gradient pass: with dk = z - x,
+  // <dk, p> = <z, p> - <x, p>, so each coefficient is one fma chain on the
+  // source position with q = -p and the lane's constant k = c + <z, p>, and
+  // r^2 = |x|^2 + |z|^2 - 2 x.z; no difference vector is formed.
+  static constexpr bool kExpanded = true;
   CT zx, zy, zz;
   CT mj[FD];
   CT rc2;
-  CT p[4][3];
-  CT c2, c3, c4;
+  CT q[4][3];         // expanded: -p_k; difference form: p_k
+  CT k1, k2, k3, k4;  // expanded: c_k + <z, p_k>; difference form: c_k (c_1 = 0)
+  CT m0, m1, m2, z2;  // -2 z, |z|^2
+  bool ex;            // the expanded form (wave-uniform; as for the gradient pass)
   Acc4<CT> acc;
-  __device__ __forceinline__ void pair(const CT* r) {
-    const CT dx = zx - r[0];
-    const CT dy = zy - r[1];
-    const CT dz = zz - r[2];
-    const CT r2 = dx * dx + dy * dy + dz * dz;
+  template <bool E>
+  __device__ __forceinline__ void pair_t(const CT* r) {
+    // pos: the source (expanded) or d = z - x (difference form)
+    CT pos[3], r2;
+    if constexpr (E) {
+      pos[0] = r[0];
+      pos[1] = r[1];
+      pos[2] = r[2];
+      r2 = fma(r[0], m0, fma(r[1], m1, fma(r[2], m2, r[3 + FD] + z2)));
+    } else {
+      pos[0] = zx - r[0];
+      pos[1] = zy - r[1];
+      pos[2] = zz - r[2];
+      r2 = pos[0] * pos[0] + pos[1] * pos[1] + pos[2] * pos[2];
+    }
     const CT e = kexp2(-r2);
     CT c = r[3] * mj[0];
 #pragma unroll
     for (int f = 1; f < FD; f++) c += r[3 + f] * mj[f];
     CT w = c * e;
     if (CUT) w = (r2 <= rc2) ? w : (CT)0;
-    const CT be = dx * p[0][0] + dy * p[0][1] + dz * p[0][2];
-    const CT ga = c2 + dx * p[1][0] + dy * p[1][1] + dz * p[1][2];
-    const CT de = c3 + dx * p[2][0] + dy * p[2][1] + dz * p[2][2];
-    const CT ep = c4 + dx * p[3][0] + dy * p[3][1] + dz * p[3][2];
+    const CT be = fma(pos[0], q[0][0], fma(pos[1], q[0][1], fma(pos[2], q[0][2], k1)));
+    const CT ga = fma(pos[0], q[1][0], fma(pos[1], q[1][1], fma(pos[2], q[1][2], k2)));
+    const CT de = fma(pos[0], q[2][0], fma(pos[1], q[2][1], fma(pos[2], q[2][2], k3)));
+    const CT ep = fma(pos[0], q[3][0], fma(pos[1], q[3][1], fma(pos[2], q[3][2], k4)));
     const CT b2 = be * be;
     const CT g2 = b2 * (CT)0.5 + ga;
     const CT g3 = be * (b2 * (CT)(1.0 / 6.0) + ga) + de;
@@ -754,58 +780,73 @@ struct QuartOp {
     acc.a[2] += w * g3;
     acc.a[3] += w * g4;
   }
-  __device__ __forceinline__ void pair_cell(const CT* r) { pair(r); }
+  __device__ __forceinline__ void pair(const CT* r) {
+    if (ex) pair_t<true>(r);
+    else pair_t<false>(r);
+  }
   __device__ __forceinline__ void fold() { acc.fold(); }
   // per-target vectors from the direction (w, v) and the target's position
-  // zt (m), in FP64; lanes past the cluster get zero (their pairs have w = 0
-  // and finite g)
-  __device__ void setup(const double* __restrict__ xi, const double (&zt)[3], double s, bool valid) {
+  // zt (m), in FP64, and the lane's frame position (zx, zy, zz, scaled);
+  // lanes past the cluster get zero (their pairs have w = 0 and finite g)
+  __device__ void setup(const double* __restrict__ xi, const double (&zt)[3], double s, bool valid, bool ok) {
+    ex = ok;
     const double w0 = xi[0], w1 = xi[1], w2 = xi[2];
     double u[4][3];
     u[0][0] = w1 * zt[2] - w2 * zt[1] + xi[3];
     u[0][1] = w2 * zt[0] - w0 * zt[2] + xi[4];
     u[0][2] = w0 * zt[1] - w1 * zt[0] + xi[5];
-    for (int q = 1; q < 4; q++) {
-      u[q][0] = w1 * u[q - 1][2] - w2 * u[q - 1][1];
-      u[q][1] = w2 * u[q - 1][0] - w0 * u[q - 1][2];
-      u[q][2] = w0 * u[q - 1][1] - w1 * u[q - 1][0];
+    for (int n = 1; n < 4; n++) {
+      u[n][0] = w1 * u[n - 1][2] - w2 * u[n - 1][1];
+      u[n][1] = w2 * u[n - 1][0] - w0 * u[n - 1][2];
+      u[n][2] = w0 * u[n - 1][1] - w1 * u[n - 1][0];
     }
-    for (int q = 0; q < 4; q++)
-      for (int a = 0; a < 3; a++) u[q][a] = valid ? u[q][a] * s : 0.0;
+    for (int n = 0; n < 4; n++)
+      for (int a = 0; a < 3; a++) u[n][a] = valid ? u[n][a] * s : 0.0;
     const double ln2 = 0.69314718055994530942;
     const double f[4] = {2.0 * ln2, -ln2, ln2 / 3.0, -ln2 / 12.0};
-    for (int q = 0; q < 4; q++)
-      for (int a = 0; a < 3; a++) p[q][a] = (CT)(f[q] * u[q][a]);
+    double pk[4][3];
+    for (int n = 0; n < 4; n++)
+      for (int a = 0; a < 3; a++) pk[n][a] = f[n] * u[n][a];
     auto dot = [&](int i, int j) { return u[i][0] * u[j][0] + u[i][1] * u[j][1] + u[i][2] * u[j][2]; };
-    c2 = (CT)(-ln2 * dot(0, 0));
-    c3 = (CT)(ln2 * dot(0, 1));
-    c4 = (CT)(-ln2 * (0.25 * dot(1, 1) + dot(0, 2) / 3.0));
+    const double cc[4] = {0.0, -ln2 * dot(0, 0), ln2 * dot(0, 1), -ln2 * (0.25 * dot(1, 1) + dot(0, 2) / 3.0)};
+    const double z[3] = {(double)zx, (double)zy, (double)zz};
+    double kk[4];
+    for (int n = 0; n < 4; n++) {
+      kk[n] = ex ? cc[n] + z[0] * pk[n][0] + z[1] * pk[n][1] + z[2] * pk[n][2] : cc[n];
+      for (int a = 0; a < 3; a++) q[n][a] = (CT)(ex ? -pk[n][a] : pk[n][a]);
+    }
+    k1 = (CT)kk[0];
+    k2 = (CT)kk[1];
+    k3 = (CT)kk[2];
+    k4 = (CT)kk[3];
+    m0 = (CT)-2 * zx;
+    m1 = (CT)-2 * zy;
+    m2 = (CT)-2 * zz;
+    z2 = zx * zx + zy * zy + zz * zz;
     acc.init();
   }
 };
 
-// All sources of one cell segment [a, b) against the lane's target.
+// All sources of one cell segment [a, b) of cell (cx, cy, cz) against the
+// lane's target, the records moved into the cluster frame as the staging
+// does (FP64 offset, one rounding).  The overflow path, when a cluster's
+// cell list does not fit.
 template <typename CT, int FD, typename Op>
-__device__ __forceinline__ void cell_segment(cptr<CT> xr, int xs, int a, int b, Op& op) {
+__device__ __forceinline__ void cell_segment(cptr<CT> xr, int xs, int a, int b, int cx, int cy, int cz,
+                                             const ClusInfo& ci, Op& op) {
   constexpr int NR = 3 + FD;
-  constexpr int U = 4;
+  constexpr int NX = NR + (Op::kExpanded ? 1 : 0);
+  const double off[3] = {ci.base[0] + cx * ci.hs, ci.base[1] + cy * ci.hs, ci.base[2] + cz * ci.hs};
   for (int b0 = a; b0 < b; b0 += kBlock) {
     const int b1 = min(b0 + kBlock, b);
-    int i = b0;
-    for (; i + U <= b1; i += U) {
-      CT rec[U][NR];
-#pragma unroll
-      for (int u = 0; u < U; u++)
-#pragma unroll
-        for (int q = 0; q < NR; q++) rec[u][q] = xr[(size_t)(i + u) * xs + q];
-#pragma unroll
-      for (int u = 0; u < U; u++) op.pair_cell(rec[u]);
-    }
-    for (; i < b1; i++) {
-      CT rec[NR];
+    for (int i = b0; i < b1; i++) {
+      CT rec[NX];
 #pragma unroll
       for (int q = 0; q < NR; q++) rec[q] = xr[(size_t)i * xs + q];
-      op.pair_cell(rec);
+#pragma unroll
+      for (int q = 0; q < 3; q++) rec[q] = (CT)((double)rec[q] + off[q]);
+      if constexpr (Op::kExpanded) rec[NR] = rec[0] * rec[0] + rec[1] * rec[1] + rec[2] * rec[2];
+      op.pair(rec);
     }
     op.fold();
   }
@@ -1147,15 +1188,9 @@ __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ r
 
 template <typename CT, int FD, typename Op>
 __device__ __forceinline__ void run_cell(const GridInfo& g, cptr<CT> xr, int xs, int key, int a, int b,
-                                         const double (&zt)[3], bool valid, Op& op) {
+                                         const ClusInfo& ci, Op& op) {
   const int cx = key % g.nx, cy = (key / g.nx) % g.ny, cz = key / (g.nx * g.ny);
-  // lanes past the end of the cluster sit far outside every cell: their
-  // pairs fail the cutoff test and their kernel values underflow to 0
-  const CT far = (CT)1e30;
-  op.zx = valid ? (CT)((zt[0] - (g.ox + cx * g.h)) * g.sq) : far;
-  op.zy = valid ? (CT)((zt[1] - (g.oy + cy * g.h)) * g.sq) : far;
-  op.zz = valid ? (CT)((zt[2] - (g.oz + cz * g.h)) * g.sq) : far;
-  cell_segment<CT, FD, Op>(xr, xs, a, b, op);
+  cell_segment<CT, FD, Op>(xr, xs, a, b, cx, cy, cz, ci, op);
 }
 
 // F, omega, v from the request's summed terms.
@@ -1407,8 +1442,10 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const C
 
   long long paired = 0;
   int count = 0;  // staged survivors
-  auto flush = [&]() {
-    wave_lds_sync();
+  // the pairing of a full staging area, one copy of the loop per form of
+  // the pair (the form is fixed per item)
+  auto pair_all = [&](auto form) {
+    constexpr bool E = decltype(form)::value;
     constexpr int U = 4;
     for (int b0 = 0; b0 < count; b0 += kBlock) {
       const int b1 = min(b0 + kBlock, count);
@@ -1420,16 +1457,23 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const C
 #pragma unroll
           for (int q = 0; q < NX; q++) r4[u][q] = recs[(i + u) * RS + q];
 #pragma unroll
-        for (int u = 0; u < U; u++) op.pair(r4[u]);
+        for (int u = 0; u < U; u++) op.template pair_t<E>(r4[u]);
       }
       for (; i < b1; i++) {
         CT r1[NX];
 #pragma unroll
         for (int q = 0; q < NX; q++) r1[q] = recs[i * RS + q];
-        op.pair(r1);
+        op.template pair_t<E>(r1);
       }
       op.fold();
     }
+  };
+  auto flush = [&]() {
+    wave_lds_sync();
+    if (Op::kExpanded && op.ex)
+      pair_all(std::integral_constant<bool, Op::kExpanded>());
+    else
+      pair_all(std::false_type());
     paired += count;
     count = 0;
     wave_lds_sync();
@@ -1535,6 +1579,11 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
   const int xs = uniform(R.xs);
   const double isq = ci.isq;
   const bool overflow = uniform(ci.overflow) != 0;
+  // the expanded pair form keeps its precision while the cluster's box stays
+  // within kExpandHalf scaled units of the frame origin (its centre)
+  bool expand_ok = true;
+#pragma unroll
+  for (int a = 0; a < 3; a++) expand_ok = expand_ok && fmaxf(-ci.blo[a], ci.bhi[a]) <= kExpandHalf;
 
   // the target position z~_j (m): the torque's lever, the quartic vectors'
   // base point (FP64 from the pose when the list overflowed)
@@ -1551,9 +1600,9 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
   if constexpr (QUART) {
     double lv[3];
     lever(lv);
-    op.setup(R.state->xi, lv, 1.0 / isq, valid);
+    op.setup(R.state->xi, lv, 1.0 / isq, valid, expand_ok);
   } else {
-    op.expand();
+    op.expand(expand_ok);
     op.acc.init();
     op.within = 0;
   }
@@ -1582,7 +1631,7 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
         const long long cbeg = base + lane_value(incl - cnt, src);
         const int a = cfirst + (int)(lo_s > cbeg ? lo_s - cbeg : 0);
         const int b = cfirst + (int)((hi_s - cbeg) < ccnt ? (hi_s - cbeg) : ccnt);
-        run_cell<CT, FD, Op>(g, xr, xs, ckey, a, b, zt, valid, op);
+        run_cell<CT, FD, Op>(g, xr, xs, ckey, a, b, ci, op);
         span += b - a;
       }
       base += lane_value(incl, kWave - 1);
@@ -1605,7 +1654,7 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
 
     double W, Dx, Dy, Dz;
     op.acc.result(W, Dx, Dy, Dz);
-    if (Op::kExpanded && !overflow) {
+    if (op.ex) {
       // S = sum w x  ->  D = sum w (z - x) = z W - S
       Dx = (double)zx * W - Dx;
       Dy = (double)zy * W - Dy;
@@ -1656,10 +1705,10 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
 // depend on which wavefront takes an item.  Every wavefront reaches the exit:
 // the counter grows by one per take and the share is finite.
 template <typename CT, int FD, bool CUT, bool QUART>
-__global__ __launch_bounds__(kPairBlockWaves* kWave) void k_pairs(const ReqStatic* __restrict__ reqs,
+__global__ __launch_bounds__(kPairBlockWaves* kWave, (sizeof(CT) == 4 ? 4 : 2)) void k_pairs(const ReqStatic* __restrict__ reqs,
                                                                   const int* __restrict__ clus_end, int nreq,
                                                                   QueueRef Q) {
-  constexpr int RS = RecStride<FD, std::is_same<CT, float>::value && !QUART>::value;
+  constexpr int RS = RecStride<FD, std::is_same<CT, float>::value || QUART>::value;
   constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
   __shared__ __align__(16) CT recs_all[kPairBlockWaves][NR * RS];
   __shared__ unsigned int next;

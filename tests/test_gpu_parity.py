@@ -214,3 +214,29 @@ def test_device_inputs_same_as_host(ctx, rgbd_small):
     b = ctx.register(torch.from_numpy(p.src_xyz).to(dev), torch.from_numpy(p.src_feat).to(dev),
                      torch.from_numpy(p.tgt_xyz).to(dev), torch.from_numpy(p.tgt_feat).to(dev), prm)
     assert np.array_equal(a["T"], b["T"])
+
+
+def _overflow_case():
+    # 64 targets on a 3 m line (one cluster) over a dense slab of sources:
+    # the cluster's reachable cells (~2,600 at ell = 0.02) exceed the 512-entry
+    # cell list, so the pair kernel enumerates the candidate box itself
+    rng = np.random.default_rng(77)
+    n = 20000
+    x = np.stack([rng.uniform(0, 3.0, n), rng.uniform(-0.06, 0.06, n), rng.uniform(-0.06, 0.06, n)], 1)
+    z = np.stack([np.linspace(0.0, 3.0, 64), np.zeros(64), np.zeros(64)], 1)
+    lx = rng.uniform(0, 1, (n, 5))
+    lz = rng.uniform(0, 1, (64, 5))
+    T = synth.random_motion(rng, 0.5, 0.005)
+    return (x.astype(np.float32), lx.astype(np.float32), z.astype(np.float32), lz.astype(np.float32), T)
+
+
+def test_cell_list_overflow_path(ctx):
+    x, lx, z, lz, T = _overflow_case()
+    for ell in (0.02, 0.04):
+        g = ctx.eval(x, lx, z, lz, T, Params(stage_ell=(ell,), cutoff_mult=3.0, a2=1.0))
+        ref = oracle.eval(x, lx, z, lz, T, ell=ell, kappa=3.0, a2=1.0)
+        check(g, ref, what=f"overflow ell {ell}")
+        # the per-target path (one work item per cluster) sums in another
+        # order: the same bar against the oracle
+        per = ctx.eval_targets(x, lx, z, lz, T, Params(stage_ell=(ell,), cutoff_mult=3.0, a2=1.0))
+        check(per.sum(axis=0), ref, what=f"overflow targets ell {ell}")

@@ -193,3 +193,12 @@ def test_quartic_rule_batched_equals_sync():
         assert b["rc"] == 0 and b["iters"] == 12
         assert np.array_equal(s["T"], b["T"]) and s["F"] == b["F"]
     assert not np.array_equal(sync[0]["T"], sync[1]["T"])
+
+
+def test_coefficients_cell_list_overflow(ctx):
+    from test_gpu_parity import _overflow_case
+    x, lx, z, lz, T = _overflow_case()
+    w, v = np.array([0.5, -1.0, 0.3]), np.array([0.02, 0.01, -0.03])
+    c = ctx.quartic(x, lx, z, lz, T, w, v, Params(stage_ell=(0.02,), cutoff_mult=3.0, a2=1.0))
+    ref, absref = oracle.quartic(x, lx, z, lz, T, w, v, ell=0.02, kappa=3.0)
+    check_coef(c, ref, absref, 2e-5, what="overflow")
