@@ -77,6 +77,64 @@ def gen_batch(nreq):
         return list(ex.map(_gen_request, synth.batched_sizes(nreq)))
 
 
+def _gen_pool_pair(seed):
+    from paper_1904_02266_amd import synth
+    p = synth.rgbd_pair(300000, 300000, seed=seed, select="random")
+    rng = np.random.default_rng(seed + 17)
+    a, b = rng.permutation(len(p.src_xyz)), rng.permutation(len(p.tgt_xyz))
+    return p.src_xyz[a], p.src_feat[a], p.tgt_xyz[b], p.tgt_feat[b]
+
+
+def gen_serving_pool(npairs):
+    """Frame pairs the serving requests are cut from (random pixel subsets of
+    300k points; a request of n points takes the first n).  Drawn in worker
+    processes before this process touches the GPU."""
+    if npairs <= 0:
+        return []
+    with ProcessPoolExecutor(max_workers=max(1, min(16, npairs))) as ex:
+        return list(ex.map(_gen_pool_pair, [5100 + k for k in range(npairs)]))
+
+
+def serving(pool, rates=(50, 200, 1000), window_s=2.0):
+    """Poisson arrivals at each rate over window_s seconds, cloud sizes
+    lognormal (median 20k, shape 1.0, clamped to 1000..300000) cut from the
+    pool, RGB-D parameters with tol 1e-5 and at most 200 iterations; each
+    request is submitted at its arrival time and its latency is submission to
+    completion (the library's wall clock)."""
+    import torch
+    from paper_1904_02266_amd import Context, params_rgbd, synth
+    dev = torch.device("cuda:0")
+    dpool = [[torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in c] for c in pool]
+    torch.cuda.synchronize()
+    prm = params_rgbd(tol=1e-5, max_iters=200)
+    out = []
+    for rate in rates:
+        stream = synth.serving_stream(rate, window_s=window_s)
+        ctx = Context(0, max_slots=4096)
+        t0 = time.perf_counter()
+        subs = []
+        for arr, seed, ns, nt in stream:
+            c = dpool[seed % len(dpool)]
+            now = time.perf_counter() - t0
+            if arr > now:
+                time.sleep(arr - now)
+            ts = time.perf_counter() - t0
+            tk, keep = ctx.submit(c[0][:ns], c[1][:ns], c[2][:nt], c[3][:nt], prm)
+            subs.append((tk, keep, ts))
+        res = [(ctx.poll(tk), ts) for tk, _, ts in subs]
+        ctx.close()
+        ok = [r for r, _ in res if r["rc"] == 0]
+        lat = np.array([r["wall_ms"] for r in ok])
+        end = max(ts + r["wall_ms"] / 1e3 for r, ts in res)
+        out.append({"rate": rate, "requests": len(res), "completed": len(ok),
+                    "throughput_per_s": len(ok) / end, "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                                                                     "p99": float(np.percentile(lat, 99))},
+                    "mean_iters": float(np.mean([r["iters"] for r in ok])),
+                    "converged": float(np.mean([r["converged"] for r in ok]))})
+    return {"window_s": window_s, "sizes": "lognormal median 20k, shape 1.0, clamped 1000..300000",
+            "params": "RGB-D schedule, tol 1e-5, cap 200 iterations", "rates": out}
+
+
 def batched(clouds, repeats=2):
     """The registrations of `clouds` (the RGB-D generator, per-request seeds
     4000 + k, cloud sizes uniform in 5000..60000, 100 iterations each)
@@ -127,6 +185,8 @@ def main():
                     help="timed registrations with the quartic step rule (0: skip)")
     ap.add_argument("--odometry-frames", type=int, default=8,
                     help="frames of the synthetic odometry sequence (0: skip)")
+    ap.add_argument("--serving-window", type=float, default=2.0,
+                    help="seconds of Poisson arrivals per serving rate (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the measurement, copy a MIB-MiB device buffer once (reference dispatch "
                          "of known size for hardware-counter runs)")
@@ -136,6 +196,7 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     batch_clouds = gen_batch(args.batch)
+    serve_pool = gen_serving_pool(6 if args.serving_window > 0 else 0)
     odo_frames = None
     if args.odometry_frames > 1:
         from paper_1904_02266_amd import synth as _synth
@@ -255,6 +316,8 @@ def main():
 
     batch = batched(batch_clouds) if batch_clouds else None
 
+    serve = serving(serve_pool, window_s=args.serving_window) if serve_pool else None
+
     odo = None
     if odo_frames:
         from paper_1904_02266_amd import odometry, params_table1
@@ -305,6 +368,7 @@ def main():
         "quartic_rule": quart,
         "odometry": odo,
         "batched": batch,
+        "serving": serve,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
