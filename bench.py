@@ -98,17 +98,19 @@ def gen_serving_pool(npairs):
 def serving(pool, rates=(50, 200, 1000), window_s=2.0):
     """Poisson arrivals at each rate over window_s seconds, cloud sizes
     lognormal (median 20k, shape 1.0, clamped to 1000..300000) cut from the
-    pool, RGB-D parameters with tol 1e-5 and at most 200 iterations; each
-    request is submitted at its arrival time and its latency is submission to
-    completion (the library's wall clock)."""
+    pool, RGB-D parameters with tol 1e-5 and at most 200 iterations (and, at
+    the two lower rates, the Table 1 parameter set); each request is
+    submitted at its arrival time and its latency is submission to completion
+    (the library's wall clock)."""
     import torch
-    from paper_1904_02266_amd import Context, params_rgbd, synth
+    from paper_1904_02266_amd import Context, params_rgbd, params_table1, synth
     dev = torch.device("cuda:0")
     dpool = [[torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in c] for c in pool]
     torch.cuda.synchronize()
-    prm = params_rgbd(tol=1e-5, max_iters=200)
+    runs = [("rgbd", params_rgbd(tol=1e-5, max_iters=200), r) for r in rates]
+    runs += [("table1", params_table1(), r) for r in rates[:2]]
     out = []
-    for rate in rates:
+    for pname, prm, rate in runs:
         stream = synth.serving_stream(rate, window_s=window_s)
         ctx = Context(0, max_slots=4096)
         t0 = time.perf_counter()
@@ -126,13 +128,15 @@ def serving(pool, rates=(50, 200, 1000), window_s=2.0):
         ok = [r for r, _ in res if r["rc"] == 0]
         lat = np.array([r["wall_ms"] for r in ok])
         end = max(ts + r["wall_ms"] / 1e3 for r, ts in res)
-        out.append({"rate": rate, "requests": len(res), "completed": len(ok),
+        out.append({"params": pname, "rate": rate, "requests": len(res), "completed": len(ok),
                     "throughput_per_s": len(ok) / end, "latency_ms": {"p50": float(np.percentile(lat, 50)),
                                                                      "p99": float(np.percentile(lat, 99))},
                     "mean_iters": float(np.mean([r["iters"] for r in ok])),
                     "converged": float(np.mean([r["converged"] for r in ok]))})
     return {"window_s": window_s, "sizes": "lognormal median 20k, shape 1.0, clamped 1000..300000",
-            "params": "RGB-D schedule, tol 1e-5, cap 200 iterations", "rates": out}
+            "params": {"rgbd": "RGB-D schedule, fixed step, tol 1e-5, cap 200 iterations",
+                       "table1": "Table 1 set: quartic step, value floor 1e-3, thresholds 1e-5 / 5e-5, cap 200"},
+            "rates": out}
 
 
 def batched(clouds, repeats=2):
@@ -180,7 +184,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-oracle", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--n", type=int, default=30000)
-    ap.add_argument("--batch", type=int, default=64, help="requests in the batched run (0: skip)")
+    ap.add_argument("--batch", type=int, default=256, help="requests in the batched run (0: skip)")
     ap.add_argument("--quartic-steps", type=int, default=3,
                     help="timed registrations with the quartic step rule (0: skip)")
     ap.add_argument("--odometry-frames", type=int, default=8,
