@@ -60,8 +60,18 @@ struct CellEntry {
 
 // Per target cluster, rebuilt every iteration by the prepare kernel: the
 // frame in which the pair kernel works on the cluster, and its candidates.
+// Candidate cell box of a target cluster and its bounding sphere (cells
+// lo .. lo + r - 1 per axis; a cell counts only if it is within reach of the
+// sphere of centre cc).
+struct CandBox {
+  int lo0, lo1, lo2, rx, ry, rz, ncand;
+  int pad;
+  double cc[3];
+  double reach2;
+};
+
 struct ClusInfo {
-  double O[3];        // origin: the first target's transformed position (m)
+  double O[3];        // origin: the centre of the targets' bounding box (m)
   double base[3];     // position of source cell (0,0,0) relative to O, scaled units
   double hs;          // cell edge, scaled units
   double isq;         // 1 / (scale): scaled units -> m
@@ -75,6 +85,7 @@ struct ClusInfo {
   int chunk;          // candidate sources per work item (the last one may hold fewer)
   int s0, cn;         // first sorted target and target count
   int stage;
+  CandBox box;        // the candidate box the list was built from (the overflow path enumerates it again)
 };
 
 // Work list of one iteration launch: the prepare kernel appends items, each

@@ -942,32 +942,29 @@ __device__ __forceinline__ void load_targets(const ReqStatic& R, const double* _
   for (int a = 0; a < 3; a++) zt[a] = T[4 * a] * z0 + T[4 * a + 1] * z1 + T[4 * a + 2] * z2 + T[4 * a + 3];
 }
 
-// Candidate cell box of the cluster and its bounding sphere.
-struct CandBox {
-  int lo0, lo1, lo2, rx, ry, rz, ncand;
-  double cc[3];
-  double reach2;
-};
-
-__device__ __forceinline__ CandBox cand_box(const GridInfo& g, const double (&zt)[3], bool valid) {
+// Candidate cell box of the cluster and its bounding sphere, from the
+// cluster frame: box [O + blo / sq, O + bhi / sq] (the origin O is the box
+// centre) and sphere radius rho = max |z~ - O|.
+__device__ __forceinline__ CandBox cand_box_frame(const GridInfo& g, const double (&O)[3], const double (&blo)[3],
+                                                  const double (&bhi)[3], double rho) {
   CandBox B;
   int lo[3], hi[3];
-  B.cc[0] = B.cc[1] = B.cc[2] = 0.0;
+  B.pad = 0;
+  B.cc[0] = O[0];
+  B.cc[1] = O[1];
+  B.cc[2] = O[2];
   B.reach2 = INFINITY;
   if (g.cutoff) {
     const double o[3] = {g.ox, g.oy, g.oz};
     const int dim[3] = {g.nx, g.ny, g.nz};
     for (int a = 0; a < 3; a++) {
-      const double bmin = wave_min(valid ? zt[a] : INFINITY);
-      const double bmax = wave_max(valid ? zt[a] : -INFINITY);
-      B.cc[a] = 0.5 * (bmin + bmax);
+      const double bmin = O[a] + blo[a] / g.sq;
+      const double bmax = O[a] + bhi[a] / g.sq;
       const double fl = floor((bmin - g.reach - o[a]) / g.h);
       const double fh = floor((bmax + g.reach - o[a]) / g.h);
       lo[a] = (int)fmin(fmax(fl, 0.0), (double)dim[a]);
       hi[a] = (int)fmax(fmin(fh, (double)(dim[a] - 1)), -1.0);
     }
-    const double d0 = zt[0] - B.cc[0], d1 = zt[1] - B.cc[1], d2 = zt[2] - B.cc[2];
-    const double rho = sqrt(wave_max(valid ? d0 * d0 + d1 * d1 + d2 * d2 : 0.0));
     B.reach2 = (rho + g.reach) * (rho + g.reach);
   } else {
     lo[0] = lo[1] = lo[2] = 0;
@@ -1012,12 +1009,12 @@ __device__ __forceinline__ void cand_cell(const GridInfo& g, const CandBox& B, c
 //  * The compacted list of reachable non-empty source cells in box order, the
 //    candidate count, and the cut into work items of at least kChunkMin
 //    sources (at most kChunksMax per cluster) with the list entry that holds
-//    each item's first candidate.  The cells of a round (up to 8 per lane,
+//    each item's first candidate.  The cells of a round (up to 16 per lane,
 //    lane-major, so that the list keeps box order) are looked up together.
 //  * The items are appended to the launch's work list, one atomic per
 //    workgroup; their order there varies from run to run and results do not
 //    depend on it (every item has its own output row).
-constexpr int kPrepCells = 8;  // candidate cells per lane and round
+constexpr int kPrepCells = 16;  // candidate cells per lane and round
 template <typename CT>
 __device__ __forceinline__ void write_frame(const ReqStatic& R, int c, int s0, int cn, const double (&zt)[3],
                                             const GridInfo& g, const double (&O)[3]) {
@@ -1078,7 +1075,9 @@ __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ r
 
       // candidate cells, rounds of 64 x kPrepCells in box order (cell
       // t = round base + q * 64 + lane; slots past the box are skipped)
-      const CandBox B = cand_box(g, zt, valid);
+      double rho2 = 0.0;
+      for (int a = 0; a < 3; a++) rho2 += valid ? (zt[a] - O[a]) * (zt[a] - O[a]) : 0.0;
+      const CandBox B = cand_box_frame(g, O, blo, bhi, sqrt(wave_max(rho2)));
       CellEntry* list = R.cells + (size_t)c * kCellCap;
       int* centry = R.centry + (size_t)c * kChunksMax;
       constexpr int PR = kWave * kPrepCells;
@@ -1166,6 +1165,7 @@ __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ r
       ci->s0 = s0;
       ci->cn = cn;
       ci->stage = stage;
+      ci->box = B;
     }
   }
   if (l == 0) wcount[w] = nchunks;
@@ -1610,11 +1610,11 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
   if (!overflow) {
     if (lo_s < hi_s) span = pairs_from_list<CT, FD, CUT, Op>(R, ci, c, k, lo_s, hi_s, rc2, op, xr, xs, recs);
   } else {
-    // the list overflowed: enumerate the candidate box again in the same
-    // order, from the FP64 target positions
+    // the list overflowed: enumerate the candidate box the prepare kernel
+    // counted again, in the same order
     const GridInfo g = R.grid[uniform(ci.stage)];
     const int* __restrict__ cs = uniform_ptr(R.cstart[uniform(ci.stage)]);
-    const CandBox B = cand_box(g, zt, valid);
+    const CandBox B = ci.box;
     long long base = 0;
     for (int c0 = 0; c0 < B.ncand && base < hi_s; c0 += kWave) {
       int key, first, cnt;
