@@ -470,9 +470,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const ScanArgs* __rest
 
 // ---------------------------------------------------------------------------
 // target clusters, one clustering per length-scale stage: runs of at most 64
-// consecutive Morton-ordered targets, cut wherever two consecutive targets are
-// farther apart than D = max(2.5 Morton bucket edges, 2 x the stage's cutoff
-// radius), so that no cluster straddles a large jump of the Morton curve.
+// consecutive Morton-ordered targets, cut (with a cutoff) wherever two
+// consecutive targets are farther apart than D = max(2.5 Morton bucket
+// edges, 2 x the stage's cutoff radius), so that no cluster straddles a large
+// jump of the Morton curve.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_cl_flags(const float* __restrict__ zrec, int zs, int m,
                                                   const double* __restrict__ zbox, double kappa,
@@ -483,11 +484,15 @@ __global__ __launch_bounds__(256) void k_cl_flags(const float* __restrict__ zrec
   // with a cutoff, a gap up to twice the cutoff radius stays inside a cluster:
   // fuller clusters (fewer idle lanes) cost fewer candidate slots than the
   // larger boxes add, while the cutoff is large against the Morton buckets
+  // Without a cutoff every source pairs with every target: no gap cuts at
+  // all (runs of 64 in Morton order), or a sparse cloud would fall apart into
+  // clusters of a few targets and leave most lanes idle.
   const double D = fmax(2.5 * e / (double)(1 << kZBits), 2.0 * kappa * stage_ell[stage]);
   const double D2 = isfinite(D) ? D * D : 0.0;
+  const bool gaps = kappa > 0.0;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
-    int f = 1;
-    if (p > 0) {
+    int f = p == 0 ? 1 : 0;
+    if (p > 0 && gaps) {
       const float* a = zrec + (size_t)p * zs;
       const float* b = zrec + (size_t)(p - 1) * zs;
       const double dx = (double)a[0] - b[0], dy = (double)a[1] - b[1], dz = (double)a[2] - b[2];
