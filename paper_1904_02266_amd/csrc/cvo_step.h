@@ -63,8 +63,14 @@ __host__ __device__ inline bool quartic_argmax(const double A[5], double* t_out)
   for (int i = 0; i + 1 < nb; i++) {
     double lo = bp[i], hi = bp[i + 1];
     if (!(dP(lo) > 0.0 && dP(hi) <= 0.0)) continue;
-    // P' > 0 at lo, <= 0 at hi, monotone in between: one crossing
+    // P' > 0 at lo, <= 0 at hi, monotone in between: one crossing.  Start
+    // from the quadratic model's maximiser -A1 / (2 A2) when it falls inside
+    // (the usual case: few Newton steps), else from the middle.
     double t = 0.5 * (lo + hi);
+    if (c[1] < 0.0) {
+      const double tq = -c[0] / c[1];
+      if (tq > lo && tq < hi) t = tq;
+    }
     for (int it = 0; it < 100; it++) {
       const double f = dP(t);
       if (f > 0.0) lo = t;
