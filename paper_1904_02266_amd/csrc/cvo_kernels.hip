@@ -1006,7 +1006,7 @@ __device__ __forceinline__ void cand_cell(const GridInfo& g, const CandBox& B, c
 }
 
 // Kernel A: per target cluster (one wavefront each).
-//  * The cluster frame: origin O (the first target, FP64), the targets
+//  * The cluster frame: origin O (the centre of the targets' box, FP64), the targets
 //    relative to O in scaled units (one rounding to the pair type) with their
 //    labels, their bounding box, and the source-grid offsets in the same
 //    frame, so that a work item needs no FP64 transform and no dependent
