@@ -199,3 +199,32 @@ def test_poll_unknown_ticket_and_pending():
         assert e.value.code == CVO_EINVAL
     finally:
         ctx.close()
+
+
+def test_batched_mixed_kernel_variants_equal_sync():
+    """Requests of different kernel variants (precision, label channels,
+    cutoff, step rule, value floor) submitted together run in separate
+    launch groups and each equals its synchronous run bit for bit."""
+    rng = np.random.default_rng(91)
+    cases = []
+    for k, (prec, fd, kappa, rule, floor) in enumerate([("fp32", 5, 3.0, "fixed", 0.0), ("fp64", 5, 3.0, "fixed", 0.0),
+                                                        ("fp32", 3, 3.0, "quartic", 0.0), ("fp32", 5, 0.0, "fixed", 0.0),
+                                                        ("fp32", 5, 0.0, "quartic", 1e-3), ("fp64", 2, 3.0, "quartic", 0.0)]):
+        q = synth.rgbd_pair(2500 + 300 * k, 2200 + 200 * k, seed=8100 + k)
+        sf = q.src_feat[:, :fd].copy()
+        tf = q.tgt_feat[:, :fd].copy()
+        prm = params_rgbd(max_iters=8, stage_iters=(2, 2, 2), precision=prec, step_rule=rule,
+                          cutoff_mult=kappa, kernel_floor=floor)
+        cases.append((q, sf, tf, prm))
+    ctx = Context(0, max_slots=8)
+    try:
+        sync = [ctx.register(q.src_xyz, sf, q.tgt_xyz, tf, prm) for q, sf, tf, prm in cases]
+        tks = [ctx.submit(q.src_xyz, sf, q.tgt_xyz, tf, prm)[0] for q, sf, tf, prm in cases]
+        bat = [ctx.poll(t) for t in tks]
+    finally:
+        ctx.close()
+    for s, b in zip(sync, bat):
+        assert b["rc"] == 0 and b["iters"] == 8
+        assert np.array_equal(s["T"], b["T"]) and s["F"] == b["F"]
+    # the variants differ from one another
+    assert len({float(s["F"]) for s in sync}) == len(sync)
