@@ -112,11 +112,23 @@ def dense_bruteforce(cloud, repeats=2):
         ks = ctx.kernel_stats(reset=True)
         if best is None or ks["ms"] < best["ms"]:
             best = ks
+    # the all-FP64 path on the same evaluation, and the two results' agreement
+    prm64 = Params(stage_ell=(0.05,), cutoff_mult=0.0, max_iters=1, precision="fp64")
+    ctx.kernel_stats(reset=True)
+    ctx.set_profiling(True)
+    o64 = ctx.register(*t, prm64)
+    ctx.set_profiling(False)
+    k64 = ctx.kernel_stats(reset=True)
     ctx.close()
+    g32 = np.array([out["F"], *out["omega"], *out["v"]])
+    g64 = np.array([o64["F"], *o64["omega"], *o64["v"]])
     ach = FLOPS_PER_PAIR * best["pairs"] / (best["ms"] * 1e-3) / 1e12
     return {"pairs": best["pairs"], "pair_kernel_ms": best["ms"], "achieved_tflops": ach,
             "frac": ach / PEAK_TFLOPS, "pair_evals_per_s": best["pairs"] / (best["ms"] * 1e-3),
-            "kernel": "k_pairs<float,5,false,false>", "F": out["F"]}
+            "kernel": "k_pairs<float,5,false,false>", "F": out["F"],
+            "fp64_path": {"pair_kernel_ms": k64["ms"], "speedup_of_mixed": k64["ms"] / best["ms"],
+                          "max_abs_diff_over_abs": float(np.max(np.abs(g32 - g64) / np.maximum(np.abs(g64), 1e-300))),
+                          "F_rel_diff": float(abs(g32[0] - g64[0]) / g64[0])}}
 
 
 def planes_c1(steps=10):
@@ -162,7 +174,7 @@ def serving(pool, rates=(50, 200, 1000), window_s=2.0):
     dev = torch.device("cuda:0")
     dpool = [[torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in c] for c in pool]
     torch.cuda.synchronize()
-    runs = [("rgbd", params_rgbd(tol=1e-5, max_iters=200), r) for r in rates]
+    runs = [("rgbd", params_rgbd(grad_tol=1e-5, max_iters=200), r) for r in rates]
     runs += [("table1", params_table1(), r) for r in rates[:2]]
     out = []
     for pname, prm, rate in runs:
@@ -189,12 +201,23 @@ def serving(pool, rates=(50, 200, 1000), window_s=2.0):
                     "mean_iters": float(np.mean([r["iters"] for r in ok])),
                     "converged": float(np.mean([r["converged"] for r in ok]))})
     return {"window_s": window_s, "sizes": "lognormal median 20k, shape 1.0, clamped 1000..300000",
-            "params": {"rgbd": "RGB-D schedule, fixed step, tol 1e-5, cap 200 iterations",
+            "params": {"rgbd": "RGB-D schedule, fixed step, stop at |(omega, v)| < 1e-5, cap 200 iterations",
                        "table1": "Table 1 set: quartic step, value floor 1e-3, thresholds 1e-5 / 5e-5, cap 200"},
             "rates": out}
 
 
-def batched(clouds, repeats=2):
+def batched_both(clouds):
+    """The batched run in the mixed-precision path and in the all-FP64 path
+    (every pair term in FP64) on the same requests."""
+    out = batched(clouds)
+    f64 = batched(clouds, repeats=1, precision="fp64")
+    out["fp64_path"] = {"regs_per_s": f64["regs_per_s"], "pair_evals_per_s": f64["pair_evals_per_s"],
+                        "wall_s": f64["wall_s"], "latency_ms": f64["latency_ms"],
+                        "speedup_of_mixed": out["regs_per_s"] / f64["regs_per_s"]}
+    return out
+
+
+def batched(clouds, repeats=2, precision="fp32"):
     """The registrations of `clouds` (the RGB-D generator, per-request seeds
     4000 + k, cloud sizes uniform in 5000..60000, 100 iterations each)
     submitted at once to the continuous-batching scheduler; inputs already on
@@ -206,7 +229,7 @@ def batched(clouds, repeats=2):
     dclouds = [[torch.from_numpy(a).to(dev) for a in c] for c in clouds]
     torch.cuda.synchronize()
     ctx = Context(0, max_slots=max(nreq, 1))
-    prm = params_rgbd()
+    prm = params_rgbd(precision=precision)
 
     def run():
         t0 = time.perf_counter()
@@ -378,7 +401,23 @@ def main():
                  "pose_error": {"rot_deg": float(np.degrees(np.arccos(np.clip((np.trace(Eq) - 1) / 2, -1, 1)))),
                                 "trans_m": float(np.linalg.norm(oq["T"][:3, 3] - Eq @ pair.T_true[:3, 3]))}}
 
-    batch = batched(batch_clouds) if batch_clouds else None
+    batch = batched_both(batch_clouds) if batch_clouds else None
+
+    # the same single registration with every pair term in FP64
+    prm64 = params_rgbd(precision="fp64")
+    ctx.register(sx, sf, tx, tf, prm64)
+    torch.cuda.synchronize()
+    f0 = time.perf_counter()
+    n64 = max(1, args.steps // 4)
+    for _ in range(n64):
+        o64 = ctx.register(sx, sf, tx, tf, prm64)
+    torch.cuda.synchronize()
+    f_el = (time.perf_counter() - f0) / n64
+    fp64_path = {"ms_per_registration": f_el * 1e3, "pair_evals_per_s": o64["pairs_within"] / f_el,
+                 "speedup_of_mixed": f_el * 1e3 / (elapsed * 1e3 / args.steps),
+                 "pose_diff_vs_mixed": {"rot_deg": float(np.degrees(np.arccos(np.clip(
+                     (np.trace(o64["T"][:3, :3] @ out["T"][:3, :3].T) - 1) / 2, -1, 1)))),
+                     "trans_m": float(np.linalg.norm(o64["T"][:3, 3] - out["T"][:3, 3]))}}
 
     serve = serving(serve_pool, window_s=args.serving_window) if serve_pool else None
     dense = dense_bruteforce(dense_cloud) if dense_cloud is not None else None
@@ -431,6 +470,7 @@ def main():
         "pairs_examined_per_registration": examined / args.steps,
         "pose_error": {"rot_deg": rot_err_deg, "trans_m": trans_err},
         "parity": parity,
+        "fp64_path": fp64_path,
         "quartic_rule": quart,
         "odometry": odo,
         "batched": batch,

@@ -1702,9 +1702,9 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
 }
 
 // Kernel B: persistent workgroups, as many as are resident at once (two per
-// compute unit).  Workgroup b takes the b-th equal share of the launch's work
-// items; its wavefronts take the items of the share one at a time from a
-// counter in LDS, so the compute unit stays busy until its share is done and
+// compute unit).  Workgroup b takes an equal share of the launch's work items
+// (see below); its wavefronts take the items of the share one at a time from
+// a counter in LDS, so the compute unit stays busy until its share is done and
 // no device-wide atomic is needed (one same-address device atomic per item
 // costs more than the items' arithmetic at this granularity).  Results do not
 // depend on which wavefront takes an item.  Every wavefront reaches the exit:
@@ -1720,9 +1720,19 @@ __global__ __launch_bounds__(kPairBlockWaves* kWave, (sizeof(CT) == 4 ? 4 : 2)) 
   CT* recs = recs_all[threadIdx.x >> 6];
   const unsigned int nitems = (unsigned)uniform((int)min(Q.q->nitems, Q.cap));
   const unsigned long long G = gridDim.x;
-  const unsigned int lo = (unsigned)((unsigned long long)nitems * blockIdx.x / G);
-  const unsigned int hi = (unsigned)((unsigned long long)nitems * (blockIdx.x + 1) / G);
-  if (threadIdx.x == 0) next = lo;
+  // Shares: the workgroups of one XCD (the hardware places workgroup b on
+  // XCD b mod 8) take a contiguous range of the list, so a cluster's items
+  // (adjacent in the list) share that XCD's L2; inside the range the XCD's
+  // workgroups take every cx-th item, so each mixes items of many clusters
+  // and the shares' costs even out.
+  const unsigned int b = blockIdx.x, x = b % 8u, rk = b / 8u;
+  unsigned long long before = 0;
+  for (unsigned int y = 0; y < x; y++) before += (G - y + 7u) / 8u;
+  const unsigned int cx = (unsigned)((G - x + 7u) / 8u);
+  const unsigned int lo = (unsigned)((unsigned long long)nitems * before / G);
+  const unsigned int hi = (unsigned)((unsigned long long)nitems * (before + cx) / G);
+  const unsigned int cnt = rk < hi - lo ? (hi - lo - rk + cx - 1u) / cx : 0u;
+  if (threadIdx.x == 0) next = 0u;
   __syncthreads();
   // No branch on the lane index may sit in this loop: the compiler may thread
   // the loop's back edge on such a branch, which splits the wavefront so that
@@ -1731,9 +1741,9 @@ __global__ __launch_bounds__(kPairBlockWaves* kWave, (sizeof(CT) == 4 ? 4 : 2)) 
   // and the ticket is lane 0's result.
   for (;;) {
     const unsigned int mine = atomicAdd(&next, lane_id() == 0 ? 1u : 0u);
-    const unsigned int it = (unsigned)uniform((int)mine);
-    if (it >= hi) break;
-    const unsigned int item = uniform((int)Q.items[it]);
+    const unsigned int t = (unsigned)uniform((int)mine);
+    if (t >= cnt) break;
+    const unsigned int item = uniform((int)Q.items[lo + rk + t * cx]);
     process_item<CT, FD, CUT, QUART>(reqs, clus_end, nreq, (int)(item >> kItemShift),
                               (int)(item & ((1u << kItemShift) - 1u)), recs);
   }
