@@ -131,6 +131,31 @@ def dense_bruteforce(cloud, repeats=2):
                           "F_rel_diff": float(abs(g32[0] - g64[0]) / g64[0])}}
 
 
+def frontend_vga(frame, k=30000, steps=20):
+    """The device front end on one synthetic 640x480 RGB-D frame already in
+    HBM (30,000 points kept): ms per frame and the algorithmic bytes (depth
+    and colour read, points and labels written) per second."""
+    import torch
+    from paper_1904_02266_amd import Context
+    dev = torch.device("cuda:0")
+    d = torch.from_numpy(frame.depth).to(dev)
+    c = torch.from_numpy(frame.rgb).to(dev)
+    ctx = Context(0)
+    ctx.frontend(d, c, k, frame.fx, frame.fy, frame.cx, frame.cy, frame.dmin, frame.dmax)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        xyz, feat = ctx.frontend(d, c, k, frame.fx, frame.fy, frame.cx, frame.cy, frame.dmin, frame.dmax)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    ctx.close()
+    P = frame.depth.size
+    algo = 16 * P + 32 * xyz.shape[0]
+    return {"ms_per_frame": el * 1e3, "pixels": P, "points": int(xyz.shape[0]),
+            "algorithmic_bytes": algo, "achieved_gb_per_s": algo / el / 1e9,
+            "note": "synchronous call (host reads the selected count back); 14 short kernels per frame"}
+
+
 def planes_c1(steps=10):
     """The 2,000-point three-plane registration (all pairs, 50 steps):
     launch-bound, reported as ms per registration."""
@@ -421,6 +446,7 @@ def main():
 
     serve = serving(serve_pool, window_s=args.serving_window) if serve_pool else None
     dense = dense_bruteforce(dense_cloud) if dense_cloud is not None else None
+    fe = frontend_vga(odo_frames[0]) if odo_frames else None
     c1 = planes_c1() if not args.no_dense else None
 
     odo = None
@@ -476,6 +502,7 @@ def main():
         "batched": batch,
         "serving": serve,
         "dense_300k_bruteforce": dense,
+        "frontend_vga": fe,
         "planes_2k": c1,
     }
     print(json.dumps(line), flush=True)
