@@ -19,7 +19,7 @@ constexpr int kChunksMax = 64;      // work items per target cluster, at most
 constexpr int kItemShift = 6;       // work item = launch-wide cluster index << kItemShift | chunk
 static_assert((1 << kItemShift) >= kChunksMax, "chunk index fits the item encoding");
 constexpr int kMaxLaunchClusters = 1 << (32 - kItemShift);
-constexpr int kPairBlockWaves = 8;  // wavefronts per pair-kernel workgroup (two workgroups per CU)
+constexpr int kPairBlockWaves = 16;  // wavefronts per FP32 pair-kernel workgroup (one workgroup per CU; FP64: 8)
 constexpr int kCellCap = 512;       // cell-list entries per cluster; beyond: box enumeration
 constexpr int kMaxDim = 2047;       // cells per grid axis (packed coordinates use 11 bits)
 constexpr int kStage32 = 128;       // sources staged in LDS per round and wave (FP32 path)

@@ -1709,13 +1709,20 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
 // costs more than the items' arithmetic at this granularity).  Results do not
 // depend on which wavefront takes an item.  Every wavefront reaches the exit:
 // the counter grows by one per take and the share is finite.
+template <typename CT>
+struct PairWaves {
+  // one 16-wave workgroup per CU for FP32 (4 waves per SIMD at <= 128 VGPRs);
+  // the FP64 instances need more registers: two waves per SIMD, 8-wave groups
+  static constexpr int value = sizeof(CT) == 4 ? kPairBlockWaves : kPairBlockWaves / 2;
+};
+
 template <typename CT, int FD, bool CUT, bool QUART>
-__global__ __launch_bounds__(kPairBlockWaves* kWave, (sizeof(CT) == 4 ? 4 : 2)) void k_pairs(const ReqStatic* __restrict__ reqs,
+__global__ __launch_bounds__((PairWaves<CT>::value * kWave), (sizeof(CT) == 4 ? 4 : 2)) void k_pairs(const ReqStatic* __restrict__ reqs,
                                                                   const int* __restrict__ clus_end, int nreq,
                                                                   QueueRef Q) {
   constexpr int RS = RecStride<FD, std::is_same<CT, float>::value || QUART>::value;
   constexpr int NR = (sizeof(CT) == 4) ? kStage32 : kStage64;
-  __shared__ __align__(16) CT recs_all[kPairBlockWaves][NR * RS];
+  __shared__ __align__(16) CT recs_all[PairWaves<CT>::value][NR * RS];
   __shared__ unsigned int next;
   CT* recs = recs_all[threadIdx.x >> 6];
   const unsigned int nitems = (unsigned)uniform((int)min(Q.q->nitems, Q.cap));
@@ -2146,11 +2153,11 @@ hipError_t launch_ingest(const IngestArgs& a, hipStream_t s) {
 // Persistent grid of the pair kernel: as many workgroups as are resident at
 // once (occupancy of this instance times the compute units), capped by the
 // largest item count the launch can have.
-static int resident_blocks(const void* kernel) {
+static int resident_blocks(const void* kernel, int block_threads) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kPairBlockWaves * kWave, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block_threads, 0) != hipSuccess)
     return -1;
   return (per_cu < 1 ? 1 : per_cu) * (cus < 1 ? 1 : cus);
 }
@@ -2161,13 +2168,13 @@ static hipError_t launch_pairs3(const ReqStatic* reqs, const int* clus_end, int 
   static std::atomic<int> resident_cache{0};  // per instance; every device of a process is the same part
   int resident = resident_cache.load(std::memory_order_relaxed);
   if (resident <= 0) {
-    resident = resident_blocks((const void*)k_pairs<CT, FD, CUT, QUART>);
+    resident = resident_blocks((const void*)k_pairs<CT, FD, CUT, QUART>, PairWaves<CT>::value * kWave);
     if (resident <= 0) return hipErrorInvalidValue;
     resident_cache.store(resident, std::memory_order_relaxed);
   }
   const long long most = (long long)total * kChunksMax;
   const int blocks = (int)(most < resident ? most : resident);
-  hipLaunchKernelGGL((k_pairs<CT, FD, CUT, QUART>), dim3(blocks), dim3(kPairBlockWaves * kWave), 0, s, reqs,
+  hipLaunchKernelGGL((k_pairs<CT, FD, CUT, QUART>), dim3(blocks), dim3(PairWaves<CT>::value * kWave), 0, s, reqs,
                      clus_end, nreq, Q);
   return hipGetLastError();
 }
