@@ -240,3 +240,20 @@ def test_cell_list_overflow_path(ctx):
         # order: the same bar against the oracle
         per = ctx.eval_targets(x, lx, z, lz, T, Params(stage_ell=(ell,), cutoff_mult=3.0, a2=1.0))
         check(per.sum(axis=0), ref, what=f"overflow targets ell {ell}")
+
+
+def test_far_from_origin(ctx):
+    # clouds 2 km from the origin: the FP64 frames keep the FP32 pair terms
+    # as accurate as near the origin (absolute FP32 coordinates there would
+    # carry ~1e-4 m of rounding)
+    p = synth.rgbd_pair(4000, 3500, seed=43)
+    off = np.array([1500.0, -800.0, 1200.0], dtype=np.float32)
+    sx = (p.src_xyz + off).astype(np.float32)
+    tx = (p.tgt_xyz + off).astype(np.float32)
+    T = p.T_true.copy()
+    T[:3, 3] += off.astype(np.float64) - T[:3, :3] @ off.astype(np.float64)  # the same motion about the offset
+    for kappa in (3.0, 0.0):
+        prm = Params(stage_ell=(0.1,), cutoff_mult=kappa, a2=4.0)
+        g = ctx.eval(sx, p.src_feat, tx, p.tgt_feat, T, prm)
+        ref = oracle.eval(sx, p.src_feat, tx, p.tgt_feat, T, ell=0.1, kappa=kappa, a2=4.0)
+        check(g, ref, what=f"far kappa {kappa}")
