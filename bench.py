@@ -34,7 +34,7 @@ FLOPS_PER_PAIR = 26          # d:3, r^2:5, exponent scale:1, label product (5 ch
 # quartic pass: d:3, r^2:5, scale:1, labels:9, weight:1, beta:5, gamma/delta/eps:18, beta^2:1,
 # g2:2, g3:4, g4:8, four sums:8
 QUARTIC_FLOPS_PER_PAIR = 65
-PEAK_TFLOPS = 78.6           # FP32 VALU issue peak without packed FP32
+PEAK_TFLOPS = 78.6           # FP32 VALU issue peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
 METRIC = "pair-evals/s per registration + batched regs/s, p50/p99 latency @1e-5 rel"
 KERNEL_SRC = os.path.join(ROOT, "paper_1904_02266_amd", "csrc", "cvo_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_rgbd30k_traffic.md")

@@ -80,7 +80,7 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
-                           "(run __graft_entry__.build() or python -m paper_1904_02266_amd.build)")
+                           "(build it with: python -m paper_1904_02266_amd.build)")
     # One HIP runtime per process: torch ships its own libamdhip64.so.7.  Loading
     # torch first makes the library bind to that already-loaded runtime (same
     # soname), so device pointers and streams are shared with torch.
