@@ -207,6 +207,17 @@ int cvo_submit(cvo_ctx* ctx, const cvo_cloud* src, const cvo_cloud* tgt, const c
  * with T_out and res filled, and the ticket is released. */
 int cvo_poll(cvo_ctx* ctx, uint64_t ticket, int32_t wait_us, double T_out[16], cvo_result* res);
 
+/* Serving counters of the batched path (cvo_submit / cvo_poll). */
+typedef struct {
+  int64_t pending;          /* submitted, not yet admitted */
+  int64_t active;           /* admitted and iterating */
+  int64_t completed;        /* finished since cvo_create (any status) */
+  int64_t failed;           /* of those, finished with a negative status */
+  uint64_t hbm_in_use;      /* device bytes held by admitted requests */
+  uint64_t hbm_budget;      /* the admission budget (bytes) */
+} cvo_serving_counters;
+int cvo_serving_stats(cvo_ctx* ctx, cvo_serving_counters* out);
+
 /* Copy the per-iteration trace of the last cvo_register call (ticket 0) into
  * buf[iters][26]: F, omega[3], v[3], tau, ell, pairs within the cutoff, then
  * the pose T (row-major 4x4) after that iteration's step.  Returns the number

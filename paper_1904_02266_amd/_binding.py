@@ -49,6 +49,11 @@ class cvo_params(ctypes.Structure):
                 ("grad_tol", ctypes.c_double), ("kernel_floor", ctypes.c_double)]
 
 
+class cvo_serving_counters(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_int64), ("active", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("hbm_in_use", ctypes.c_uint64), ("hbm_budget", ctypes.c_uint64)]
+
+
 class cvo_rgbd_frame(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("depth", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
@@ -107,13 +112,14 @@ def load():
     L.cvo_quartic.argtypes = [vp, P(cvo_cloud), P(cvo_cloud), P(cvo_params), P(dbl), P(dbl), P(dbl), P(dbl)]
     L.cvo_quartic_step.argtypes = [P(dbl), P(dbl)]
     L.cvo_frontend.argtypes = [vp, P(cvo_rgbd_frame), i32, vp, vp, P(i32)]
+    L.cvo_serving_stats.argtypes = [vp, P(cvo_serving_counters)]
     L.cvo_strerror.argtypes = [ctypes.c_int]
     L.cvo_strerror.restype = ctypes.c_char_p
     L.cvo_last_error.argtypes = [vp]
     L.cvo_last_error.restype = ctypes.c_char_p
     for name in ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
                  "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
-                 "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend"):
+                 "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend", "cvo_serving_stats"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -121,8 +127,8 @@ def load():
 
 EXPORTED = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
             "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
-            "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend", "cvo_strerror",
-            "cvo_last_error")
+            "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend", "cvo_serving_stats",
+            "cvo_strerror", "cvo_last_error")
 
 
 class CvoError(RuntimeError):
@@ -401,6 +407,13 @@ class Context:
         self._check(self.L.cvo_submit(self.h, ctypes.byref(s.c), ctypes.byref(t.c), ctypes.byref(p), Tp,
                                       ctypes.byref(tk)), "cvo_submit")
         return tk.value, (s, t)
+
+    def serving_stats(self):
+        """Counters of the batched path: pending, active, completed, failed,
+        hbm_in_use, hbm_budget."""
+        st = cvo_serving_counters()
+        self._check(self.L.cvo_serving_stats(self.h, ctypes.byref(st)), "cvo_serving_stats")
+        return {f: getattr(st, f) for f, _ in cvo_serving_counters._fields_}
 
     def poll(self, ticket, wait_us=-1):
         Tout = np.zeros(16)

@@ -275,6 +275,9 @@ struct cvo_ctx {
   bool sched_started = false;
   hipStream_t serve_stream = nullptr;
   size_t max_pending = 65536;
+  // serving counters (under q_mu)
+  int64_t st_active = 0, st_completed = 0, st_failed = 0;
+  uint64_t st_hbm_in_use = 0;
 };
 
 static int fail(cvo_ctx* c, hipError_t e, const char* what) {
@@ -725,6 +728,8 @@ namespace {
 
 void complete(cvo_ctx* c, Request* q, int status) {
   std::lock_guard<std::mutex> g(c->q_mu);
+  c->st_completed++;
+  if (status != CVO_OK) c->st_failed++;
   q->status = status;
   q->res.status = status;
   q->res.wall_ms = std::chrono::duration<double, std::milli>(Clock::now() - q->t_submit).count();
@@ -790,6 +795,8 @@ void scheduler(cvo_ctx* c) {
         const size_t fp = footprint(*q);
         if (c->budget && fp > c->budget) {
           c->pending.pop_front();
+          c->st_completed++;
+          c->st_failed++;
           q->status = CVO_ENOMEM;
           q->res.status = CVO_ENOMEM;
           c->done_cv.notify_all();
@@ -801,6 +808,8 @@ void scheduler(cvo_ctx* c) {
         in_use += fp;
         admit.push_back(q);
       }
+      c->st_active = (int64_t)(active.size() + admit.size());
+      c->st_hbm_in_use = in_use;
     }
     for (Request* q : admit) {
       const int rc = admit_one(c, q, s, h_stage);
@@ -810,6 +819,11 @@ void scheduler(cvo_ctx* c) {
         continue;
       }
       active.push_back(q);
+    }
+    {
+      std::lock_guard<std::mutex> g(c->q_mu);
+      c->st_active = (int64_t)active.size();
+      c->st_hbm_in_use = in_use;
     }
     if (active.empty()) continue;
 
@@ -887,6 +901,11 @@ void scheduler(cvo_ctx* c) {
       }
     }
     active.swap(still);
+    {
+      std::lock_guard<std::mutex> g(c->q_mu);
+      c->st_active = (int64_t)active.size();
+      c->st_hbm_in_use = in_use;
+    }
   }
   if (d_reqs) (void)hipFree(d_reqs);
   if (d_end) (void)hipFree(d_end);
@@ -1200,6 +1219,18 @@ int cvo_submit(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo
   }
   c->q_cv.notify_all();
   *ticket = q->ticket;
+  return CVO_OK;
+}
+
+int cvo_serving_stats(cvo_ctx* c, cvo_serving_counters* out) {
+  if (!c || !out) return CVO_EINVAL;
+  std::lock_guard<std::mutex> g(c->q_mu);
+  out->pending = (int64_t)c->pending.size();
+  out->active = c->st_active;
+  out->completed = c->st_completed;
+  out->failed = c->st_failed;
+  out->hbm_in_use = c->st_hbm_in_use;
+  out->hbm_budget = c->budget;
   return CVO_OK;
 }
 

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1904_02266_amd import (CVO_ENOMEM, CVO_ENOTFOUND, CVO_EINVAL, Context, CvoError, Params,
+from paper_1904_02266_amd import (CVO_ENOMEM, CVO_ENOOVERLAP, CVO_ENOTFOUND, CVO_EINVAL, Context, CvoError, Params,
                                   params_planes, params_rgbd, synth)
 
 pytestmark = pytest.mark.gpu
@@ -228,3 +228,27 @@ def test_batched_mixed_kernel_variants_equal_sync():
         assert np.array_equal(s["T"], b["T"]) and s["F"] == b["F"]
     # the variants differ from one another
     assert len({float(s["F"]) for s in sync}) == len(sync)
+
+
+def test_serving_counters():
+    prm = params_rgbd(max_iters=6, stage_iters=(2, 2, 2))
+    reqs = _small_requests(300, 5)
+    ctx = Context(0, max_slots=8)
+    try:
+        s0 = ctx.serving_stats()
+        assert s0["completed"] == 0 and s0["active"] == 0 and s0["pending"] == 0
+        tks = [ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)[0] for q in reqs]
+        bad = ctx.submit(reqs[0].src_xyz, reqs[0].src_feat, reqs[0].tgt_xyz + np.float32(50.0), reqs[0].tgt_feat,
+                         prm)[0]
+        outs = [ctx.poll(t) for t in tks]
+        assert ctx.poll(bad)["rc"] == CVO_ENOOVERLAP
+        import time
+        t0 = time.time()
+        while ctx.serving_stats()["active"] and time.time() - t0 < 10:
+            time.sleep(0.01)
+        s1 = ctx.serving_stats()
+    finally:
+        ctx.close()
+    assert all(o["rc"] == 0 for o in outs)
+    assert s1["completed"] == 6 and s1["failed"] == 1
+    assert s1["active"] == 0 and s1["pending"] == 0 and s1["hbm_in_use"] == 0
