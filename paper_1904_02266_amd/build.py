@@ -35,7 +35,8 @@ def build(verbose=False) -> str:
         subprocess.check_call(cmd, stderr=subprocess.DEVNULL if not verbose else None)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread",
+           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     subprocess.check_call(cmd, stderr=subprocess.DEVNULL if not verbose else None)
     os.replace(tmp, LIB)
     for o in objs:

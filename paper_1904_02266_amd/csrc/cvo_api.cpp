@@ -23,6 +23,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/cvo.h"
 #include "cvo_internal.h"
 #include "cvo_step.h"
@@ -649,6 +651,13 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
   }
   int launched = 0;
   const int chunk = (q.tol > 0.0 || q.grad_tol > 0.0) ? 16 : q.max_iters;
+  // roctx ranges (visible with rocprofv3 --marker-trace): the iteration
+  // chunks of a synchronous call
+  struct RangeGuard {
+    ~RangeGuard() { roctxRangePop(); }
+  };
+  roctxRangePushA(q.mode == kModeRegister ? "cvo_register" : "cvo_eval");
+  RangeGuard range_guard;
   for (int k = 0; k < q.max_iters;) {
     const int kend = std::min(q.max_iters, k + chunk);
     for (; k < kend; k++) {
@@ -871,6 +880,7 @@ void scheduler(cvo_ctx* c) {
                   queue.reset(s) == hipSuccess &&
                   hipMemcpyAsync(d_reqs, h_reqs, sizeof(ReqStatic) * nreq, hipMemcpyHostToDevice, s) == hipSuccess &&
                   hipMemcpyAsync(d_end, h_end, sizeof(int) * nreq, hipMemcpyHostToDevice, s) == hipSuccess;
+    roctxRangePushA("cvo_batch_iterations");
     for (int it = 0; it < chunk && dev_ok; it++) {
       for (const G& g : gl) {
         if (launch_iteration_rule(g.rule, g.precision, g.fd, g.cut != 0, d_reqs + g.first, d_end + g.first, g.count,
@@ -882,6 +892,7 @@ void scheduler(cvo_ctx* c) {
       if (hipMemcpyAsync(h_states + k, order[k]->state, sizeof(ReqState), hipMemcpyDeviceToHost, s) != hipSuccess)
         dev_ok = false;
     if (dev_ok && hipStreamSynchronize(s) != hipSuccess) dev_ok = false;
+    roctxRangePop();
     std::vector<Request*> still;
     for (int k = 0; k < nreq; k++) {
       Request* q = order[k];
