@@ -111,6 +111,13 @@ typedef struct {
                                pairs with sigma^2 exp(-r^2/(2 ell^2)) < kernel_floor are dropped,
                                i.e. the cutoff r <= ell sqrt(2 ln(sigma^2 / kernel_floor)); needs
                                cutoff_mult = 0 and sigma^2 > kernel_floor.  0: cutoff_mult applies */
+  int32_t dof_mask;         /* the subgroup of SE(3) the registration runs on: bit q set = the flow moves
+                               along generator q (bits 0-2: rotation about x, y, z; 3-5: translation
+                               along x, y, z); the step uses the gradient's components in the mask
+                               (its orthogonal projection under the metric a^2, b^2).  0 or 0x3F: SE(3);
+                               0x1C: planar motion SE(2) (rotation about z, translation in x, y);
+                               0x07: SO(3); 0x38: translations.  The trace and result report the full
+                               gradient. */
 } cvo_params;
 
 /* One organised RGB-D frame (the input of the front end, Sec. VII-B). */

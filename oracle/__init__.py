@@ -56,8 +56,8 @@ def _load():
         L.cvo_oracle_mean_sqnorm.restype = c_double
         L.cvo_oracle_register.argtypes = [c_int, f32p, f32p, c_int, f32p, f32p, c_int,
                                           c_double, c_double, c_double, c_double, c_double, c_double,
-                                          c_int, i32p, f64p, c_int, c_double, c_double, c_int, f64p, c_int,
-                                          f64p, f64p, i32p, i32p]
+                                          c_int, i32p, f64p, c_int, c_double, c_double, c_int, c_int, f64p,
+                                          c_int, f64p, f64p, i32p, i32p]
         L.cvo_oracle_register.restype = c_int
         L.cvo_oracle_quartic.argtypes = [c_int, f32p, f32p, c_int, f32p, f32p, c_int,
                                          c_double, c_double, c_double, c_double, f64p, f64p, f64p, c_int,
@@ -192,7 +192,7 @@ STEP_RULES = {"fixed": 0, "quartic": 1}
 
 def register(src_xyz, src_feat, tgt_xyz, tgt_feat, *, sigma=0.1, feat_scale=0.2, a2=None, b2=1.0,
              eta=1.0, kappa=0.0, stage_iters=(), stage_ell=(0.1,), max_iters=50, tol=0.0, grad_tol=0.0,
-             step_rule="fixed", T0=None, nthreads=None):
+             step_rule="fixed", dof_mask=0, T0=None, nthreads=None):
     """Run the registration iteration; returns dict(T, iters, converged, trace[iters,26], rc).
     step_rule "fixed": tau = eta ell^2 / F; "quartic": the maximiser of the
     fourth-order model (eq. fourth), falling back to the fixed rule when the
@@ -216,7 +216,7 @@ def register(src_xyz, src_feat, tgt_xyz, tgt_feat, *, sigma=0.1, feat_scale=0.2,
                                z.shape[0], _ptr(z, ctypes.c_float), _ptr(lz, ctypes.c_float), fd,
                                sigma, feat_scale, -1.0 if a2 is None else a2, b2, eta, kappa, ns,
                                _ptr(si, ctypes.c_int), _ptr(se, ctypes.c_double), max_iters, tol, grad_tol,
-                               STEP_RULES[step_rule], _ptr(T0, ctypes.c_double), nthreads or default_threads(),
+                               STEP_RULES[step_rule], dof_mask, _ptr(T0, ctypes.c_double), nthreads or default_threads(),
                                _ptr(Tout, ctypes.c_double), _ptr(trace, ctypes.c_double),
                                _ptr(it, ctypes.c_int), _ptr(cv, ctypes.c_int))
     return dict(T=Tout.reshape(4, 4), iters=int(it[0]), converged=bool(cv[0]),

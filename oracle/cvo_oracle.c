@@ -441,11 +441,13 @@ int cvo_oracle_quartic_step(const double A[5], double* t_out) {
  *   ell   = schedule length-scale of the stage containing k
  *   (F, omega, v) at the current h
  *   F <= 1e-300 -> no overlap (error)
+ *   xi    = (omega, v) with the components outside dof_mask set to zero (the
+ *           flow on the subgroup of SE(3) the mask selects; 0 = all six)
  *   tau = eta ell^2 / F (step_rule 0), or (step_rule 1) the maximiser of the
- *         quartic model when it has one on t > 0, else eta ell^2 / F;
- *   h <- h exp(tau (omega^, v))
- *   stop when the last stage is reached and |tau (omega, v)|_2 < tol (the
- *   transformation threshold of Table 1) or |(omega, v)|_2 < grad_tol (the
+ *         quartic model along xi when it has one on t > 0, else eta ell^2 / F;
+ *   h <- h exp(tau xi)
+ *   stop when the last stage is reached and |tau xi|_2 < tol (the
+ *   transformation threshold of Table 1) or |xi|_2 < grad_tol (the
  *   gradient-norm threshold); a zero threshold is off.
  * Stage s spans stage_iters[s] iterations; the last stage runs to max_iters.
  * T0 and T_out use the library convention T = h^-1.
@@ -455,11 +457,13 @@ int cvo_oracle_quartic_step(const double A[5], double* t_out) {
 int cvo_oracle_register(int n, const float* x, const float* lx, int m, const float* z, const float* lz,
                         int fd, double sigma, double feat_scale, double a2, double b2, double eta,
                         double kappa, int n_stages, const int* stage_iters, const double* stage_ell,
-                        int max_iters, double tol, double grad_tol, int step_rule, const double T0[16],
-                        int nthreads,
+                        int max_iters, double tol, double grad_tol, int step_rule, int dof_mask,
+                        const double T0[16], int nthreads,
                         double T_out[16], double* trace, int* iters_out, int* converged_out) {
     if (n_stages < 1 || !stage_ell || max_iters < 1 || !(eta > 0.0)) return OR_EINVAL;
     if (!(tol >= 0.0) || !(grad_tol >= 0.0)) return OR_EINVAL;
+    if (dof_mask < 0 || dof_mask > 63) return OR_EINVAL;
+    if (dof_mask == 0) dof_mask = 63;
     for (int s = 0; s < n_stages; s++) {
         if (!(stage_ell[s] > 0.0)) return OR_EINVAL;
         if (s < n_stages - 1 && (!stage_iters || stage_iters[s] < 1)) return OR_EINVAL;
@@ -481,21 +485,26 @@ int cvo_oracle_register(int n, const float* x, const float* lx, int m, const flo
                                NULL, nthreads, g, ga, cnt, NULL);
         if (rc != OR_OK) break;
         if (!(g[0] > 1e-300)) { rc = OR_ENOOVERLAP; break; }
+        /* the flow on the subgroup dof_mask selects (bits 0-2 omega, 3-5 v):
+           the gradient of F restricted to it is the metric-orthogonal
+           projection of the full gradient, here the masked components */
+        double xi[6];
+        for (int q = 0; q < 6; q++) xi[q] = ((dof_mask >> q) & 1) ? g[1 + q] : 0.0;
         double tau = eta * ell * ell / g[0];
         if (step_rule == 1) {
-            /* quartic model along xi = (omega, v) at the current pose */
+            /* quartic model along xi at the current pose */
             double Tcur[16], A[5], Aa[5], tq;
             rigid_inverse(h, Tcur);
-            rc = cvo_oracle_quartic(n, x, lx, m, z, lz, fd, sigma, feat_scale, ell, kappa, Tcur, g + 1, g + 4,
+            rc = cvo_oracle_quartic(n, x, lx, m, z, lz, fd, sigma, feat_scale, ell, kappa, Tcur, xi, xi + 3,
                                     nthreads, A, Aa);
             if (rc != OR_OK) break;
             if (cvo_oracle_quartic_step(A, &tq)) tau = tq;
         }
-        newstep(h, g + 1, g + 4, tau);
+        newstep(h, xi, xi + 3, tau);
         double sq = 0.0, gq = 0.0;
-        for (int q = 1; q < 7; q++) {
-            sq += (tau * g[q]) * (tau * g[q]);
-            gq += g[q] * g[q];
+        for (int q = 0; q < 6; q++) {
+            sq += (tau * xi[q]) * (tau * xi[q]);
+            gq += xi[q] * xi[q];
         }
         if (trace) {
             double* tr = trace + 26 * (size_t)k;

@@ -29,6 +29,8 @@ CVO_FP64 = 1
 CVO_STEP_FIXED = 0
 CVO_STEP_QUARTIC = 1
 STEP_RULES = {"fixed": CVO_STEP_FIXED, "quartic": CVO_STEP_QUARTIC}
+# subgroups of SE(3) for Params.dof_mask (bits: rotation x, y, z, translation x, y, z)
+DOF_SE3, DOF_SE2, DOF_SO3, DOF_R3 = 0x3F, 0x1C, 0x07, 0x38
 TRACE_COLS = 26
 
 
@@ -46,7 +48,7 @@ class cvo_params(ctypes.Structure):
                 ("stage_ell", ctypes.POINTER(ctypes.c_double)),
                 ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("trace", ctypes.c_int32), ("step_rule", ctypes.c_int32),
-                ("grad_tol", ctypes.c_double), ("kernel_floor", ctypes.c_double)]
+                ("grad_tol", ctypes.c_double), ("kernel_floor", ctypes.c_double), ("dof_mask", ctypes.c_int32)]
 
 
 class cvo_serving_counters(ctypes.Structure):
@@ -156,6 +158,7 @@ class Params:
     step_rule: str = "fixed"
     grad_tol: float = 0.0
     kernel_floor: float = 0.0
+    dof_mask: int = 0
 
     def to_c(self):
         ns = len(self.stage_ell)
@@ -165,7 +168,7 @@ class Params:
                        ctypes.cast(si, ctypes.POINTER(ctypes.c_int32)),
                        ctypes.cast(se, ctypes.POINTER(ctypes.c_double)), self.max_iters, self.tol,
                        CVO_FP64 if self.precision == "fp64" else CVO_FP32_KAHAN, 1 if self.trace else 0,
-                       STEP_RULES[self.step_rule], self.grad_tol, self.kernel_floor)
+                       STEP_RULES[self.step_rule], self.grad_tol, self.kernel_floor, self.dof_mask)
         return p, (si, se)
 
 

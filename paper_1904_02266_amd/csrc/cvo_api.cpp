@@ -47,6 +47,7 @@ struct Request {
   int mode = kModeRegister;
   int n = 0, m = 0, fd = 0, n_stages = 1, max_iters = 1, precision = 0, trace_on = 0;
   int step_rule = kStepFixed;
+  int dof_mask = 0x3F;
   double xi0[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // direction of the coefficient evaluation
   double sigma = 0.1, sf = 0.2, a2 = -1.0, b2 = 1.0, eta = 1.0, kappa = 0.0, tol = 0.0, grad_tol = 0.0;
   int stage_iters[kMaxStages] = {0};
@@ -322,6 +323,7 @@ static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
   if (p->precision != CVO_FP32_KAHAN && p->precision != CVO_FP64) return CVO_EINVAL;
   if (p->step_rule != CVO_STEP_FIXED && p->step_rule != CVO_STEP_QUARTIC) return CVO_EINVAL;
   if (!(p->grad_tol >= 0.0) || !(p->kernel_floor >= 0.0) || !std::isfinite(p->kernel_floor)) return CVO_EINVAL;
+  if (p->dof_mask < 0 || p->dof_mask > 0x3F) return CVO_EINVAL;
   // value sparsification (Table 1): sigma^2 exp(-r^2 / (2 ell^2)) >= floor
   // keeps exactly r <= ell sqrt(2 ln(sigma^2 / floor))
   if (p->kernel_floor > 0.0 && (p->cutoff_mult > 0.0 || !(p->sigma * p->sigma > p->kernel_floor)))
@@ -341,6 +343,7 @@ static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
   q.precision = p->precision;
   q.trace_on = (mode == kModeRegister) ? (p->trace ? 1 : 0) : 0;
   q.step_rule = (mode == kModeRegister) ? p->step_rule : (mode == kModeQuartic ? kStepQuartic : kStepFixed);
+  q.dof_mask = p->dof_mask == 0 ? 0x3F : p->dof_mask;
   q.sigma = p->sigma;
   q.sf = p->feat_scale;
   q.a2 = p->a2;
@@ -522,6 +525,7 @@ static int finish_setup(cvo_ctx* c, Request& q, const Layout& L, const LayoutB& 
   st.mode = q.mode;
   st.precision = q.precision;
   st.step_rule = q.step_rule;
+  st.dof_mask = q.dof_mask;
   int end = 0;
   for (int k = 0; k < kMaxStages; k++) {
     if (k < S - 1) {

@@ -124,7 +124,8 @@ struct ReqStatic {
   double* per_target;                // [m][7] or null (per-target terms, eval-targets mode)
   int m, n, fd, zs, xs, nclus;        // nclus: the largest cluster count over the stages
   int n_stages, max_iters, mode, precision;
-  int step_rule, pad_rule;
+  int step_rule;
+  int dof_mask;                      // generators the flow moves along: bits 0-2 omega, 3-5 v
   int stage_end[kMaxStages];         // iteration index where stage s ends; last = INT_MAX
   double stage_ell[kMaxStages];
   double s2f;                        // sigma^2 * s_f

@@ -1221,8 +1221,15 @@ __device__ void take_step(const ReqStatic& R, ReqState* __restrict__ S, double t
   const double ell = R.stage_ell[stage];
   const double* g = S->g;
   S->tau = tau;
-  const double w[3] = {-tau * g[1], -tau * g[2], -tau * g[3]};
-  const double u[3] = {-tau * g[4], -tau * g[5], -tau * g[6]};
+  // the flow on the subgroup the mask selects: the gradient's components
+  // outside it are dropped (an orthogonal projection under the diagonal
+  // metric a^2, b^2)
+  double w[3], u[3], gm[6];
+  for (int q = 0; q < 6; q++) gm[q] = ((R.dof_mask >> q) & 1) ? g[1 + q] : 0.0;
+  for (int a = 0; a < 3; a++) {
+    w[a] = -tau * gm[a];
+    u[a] = -tau * gm[3 + a];
+  }
   double T[12];
   for (int q = 0; q < 12; q++) T[q] = S->T[q];
   left_compose_exp(T, w, u);
@@ -1243,7 +1250,7 @@ __device__ void take_step(const ReqStatic& R, ReqState* __restrict__ S, double t
   double sq = 0.0, gq = 0.0;
   for (int a = 0; a < 3; a++) {
     sq += w[a] * w[a] + u[a] * u[a];
-    gq += g[1 + a] * g[1 + a] + g[4 + a] * g[4 + a];
+    gq += gm[a] * gm[a] + gm[3 + a] * gm[3 + a];
   }
   const int kn = k + 1;
   S->iter = kn;
@@ -1301,7 +1308,7 @@ __device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S, con
     return;
   }
   if (phase == kPhaseGradient) {
-    for (int q = 0; q < 6; q++) S->xi[q] = g[1 + q];
+    for (int q = 0; q < 6; q++) S->xi[q] = ((R.dof_mask >> q) & 1) ? g[1 + q] : 0.0;
     S->last_pairs = (unsigned long long)acc[7];
     return;
   }

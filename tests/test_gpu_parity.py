@@ -257,3 +257,31 @@ def test_far_from_origin(ctx):
         g = ctx.eval(sx, p.src_feat, tx, p.tgt_feat, T, prm)
         ref = oracle.eval(sx, p.src_feat, tx, p.tgt_feat, T, ell=0.1, kappa=kappa, a2=4.0)
         check(g, ref, what=f"far kappa {kappa}")
+
+
+@pytest.mark.parametrize("mask", [0x1C, 0x07, 0x38])
+def test_subgroup_registration_matches_oracle(ctx, mask):
+    """Registration on a subgroup of SE(3) (planar motion, rotations,
+    translations): the GPU trajectory follows the oracle's and stays in the
+    subgroup."""
+    p = synth.planes_pair(1500, seed=5)
+    prm = Params(stage_ell=(0.1,), max_iters=30, trace=True, dof_mask=mask)
+    out = ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, prm)
+    tr = ctx.trace()
+    ref = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, stage_ell=(0.1,), max_iters=30,
+                          dof_mask=mask)
+    E = out["T"][:3, :3] @ ref["T"][:3, :3].T
+    assert np.arccos(np.clip((np.trace(E) - 1) / 2, -1, 1)) < 1e-4
+    assert np.linalg.norm(out["T"][:3, 3] - E @ ref["T"][:3, 3]) < 1e-4
+    T = out["T"]
+    if mask == 0x1C:
+        assert np.all(np.abs(T[2, :2]) < 1e-12) and np.all(np.abs(T[:2, 2]) < 1e-12) and abs(T[2, 3]) < 1e-12
+    if mask == 0x07:
+        assert np.all(np.abs(T[:3, 3]) < 1e-12)
+    if mask == 0x38:
+        assert np.all(np.abs(T[:3, :3] - np.eye(3)) < 1e-12)
+    a2 = oracle.mean_sqnorm(p.src_xyz)
+    for k in (0, 5, 29):
+        Tk = np.eye(4) if k == 0 else tr[k - 1, 10:26].reshape(4, 4)
+        check(tr[k, :7], oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, Tk, ell=0.1, a2=a2),
+              what=f"mask {mask:#x} iter {k}")

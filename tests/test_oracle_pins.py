@@ -444,3 +444,53 @@ def test_gradient_norm_threshold_stops():
     k = int(np.argmax(gn < thr * 1.0000001))
     assert r["converged"] and r["iters"] == k + 1
     np.testing.assert_array_equal(r["trace"], base["trace"][: k + 1])
+
+
+# --------------------------------------------------------------------------
+# Registration on subgroups of SE(3) (the problem is posed for a Lie group
+# acting on the space, Sec. III; a subgroup's flow uses the gradient's
+# metric-orthogonal projection onto its subalgebra)
+def _motion_pair(R, t, n=900, seed=31):
+    p = synth.planes_pair(n, seed=seed, theta_max_deg=0.0, t_max=0.0)
+    M = np.eye(4)
+    M[:3, :3] = R
+    M[:3, 3] = t
+    rng = np.random.default_rng(seed + 1)
+    tgt = (p.src_xyz.astype(np.float64) @ R.T + t + rng.normal(0, 0.002, p.src_xyz.shape)).astype(np.float32)
+    return p.src_xyz, p.src_feat, tgt, p.src_feat, np.linalg.inv(M)
+
+
+def _rz(deg):
+    a = math.radians(deg)
+    return np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1.0]])
+
+
+@pytest.mark.parametrize("mask,R,t", [
+    (0x1C, _rz(4.0), np.array([0.04, -0.03, 0.0])),                               # SE(2): rotation about z, xy
+    (0x07, synth.rotation_axis_angle([1, 2, 3], math.radians(4.0)), np.zeros(3)),  # SO(3)
+    (0x38, np.eye(3), np.array([0.03, -0.02, 0.04])),                             # translations
+])
+def test_subgroup_flow_stays_in_subgroup_and_recovers(mask, R, t):
+    x, lx, z, lz, T_true = _motion_pair(R, t)
+    r = oracle.register(x, lx, z, lz, stage_ell=(0.15,), max_iters=60, dof_mask=mask, a2=7.0)
+    T = r["T"]
+    for tr in r["trace"]:
+        Tk = tr[10:26].reshape(4, 4)
+        if mask == 0x1C:
+            assert np.all(np.abs(Tk[2, :2]) < 1e-14) and np.all(np.abs(Tk[:2, 2]) < 1e-14)
+            assert abs(Tk[2, 3]) < 1e-14 and abs(Tk[2, 2] - 1.0) < 1e-14
+        if mask == 0x07:
+            assert np.all(np.abs(Tk[:3, 3]) < 1e-14)
+        if mask == 0x38:
+            assert np.all(np.abs(Tk[:3, :3] - np.eye(3)) < 1e-14)
+    assert rot_angle_deg(T, T_true) < 0.1 and trans_err(T, T_true) < 0.005
+    F = r["trace"][:, 0]
+    assert np.all(np.diff(F) > -1e-9 * F[1:])
+
+
+def test_subgroup_mask_zero_is_full_group():
+    p = small_pair(seed=29)
+    a = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, stage_ell=(0.15,), max_iters=10, a2=7.0)
+    b = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, stage_ell=(0.15,), max_iters=10, a2=7.0,
+                        dof_mask=0x3F)
+    np.testing.assert_array_equal(a["T"], b["T"])
