@@ -50,6 +50,8 @@ def _load():
         L.cvo_oracle_eval.restype = c_int
         L.cvo_oracle_eval_h.argtypes = L.cvo_oracle_eval.argtypes
         L.cvo_oracle_eval_h.restype = c_int
+        L.cvo_oracle_eval_grid.argtypes = L.cvo_oracle_eval.argtypes
+        L.cvo_oracle_eval_grid.restype = c_int
         L.cvo_oracle_expmap.argtypes = [f64p, f64p, f64p, f64p]
         L.cvo_oracle_expmap.restype = None
         L.cvo_oracle_mean_sqnorm.argtypes = [c_int, f32p]
@@ -57,7 +59,7 @@ def _load():
         L.cvo_oracle_register.argtypes = [c_int, f32p, f32p, c_int, f32p, f32p, c_int,
                                           c_double, c_double, c_double, c_double, c_double, c_double,
                                           c_int, i32p, f64p, c_int, c_double, c_double, c_int, c_int, f64p,
-                                          c_int, f64p, f64p, i32p, i32p]
+                                          c_int, f64p, f64p, i32p, i32p, c_int, f64p]
         L.cvo_oracle_register.restype = c_int
         L.cvo_oracle_quartic.argtypes = [c_int, f32p, f32p, c_int, f32p, f32p, c_int,
                                          c_double, c_double, c_double, c_double, f64p, f64p, f64p, c_int,
@@ -95,12 +97,17 @@ def mean_sqnorm(x):
 
 
 def eval(src_xyz, src_feat, tgt_xyz, tgt_feat, T, *, sigma=0.1, feat_scale=0.2, ell=0.1,
-         kappa=0.0, a2=None, b2=1.0, sel=None, nthreads=None, per_target=False, paper_pose=False):
+         kappa=0.0, a2=None, b2=1.0, sel=None, nthreads=None, per_target=False, paper_pose=False,
+         grid=False):
     """F, omega, v at pose T (library convention: T acts on target points).
 
     Returns dict(g=[F, w0, w1, w2, v0, v1, v2], abs=[same with |terms|],
     within=int, examined=int, per_target=[nsel,7] or None).
     With paper_pose=True, T is read as the paper's h (= library T^-1).
+    grid=True (needs kappa > 0) enumerates the cutoff pairs through the
+    oracle's own uniform source grid instead of testing every pair: the same
+    pair set (pinned against the brute force), for clouds too large for it;
+    `examined` then counts the grid's candidates.
     """
     L = _load()
     x = _f32(src_xyz, 3)
@@ -125,7 +132,9 @@ def eval(src_xyz, src_feat, tgt_xyz, tgt_feat, T, *, sigma=0.1, feat_scale=0.2, 
     pt = None
     if per_target:
         pt = np.zeros((nsel if sel is not None else z.shape[0], 7))
-    fn = L.cvo_oracle_eval_h if paper_pose else L.cvo_oracle_eval
+    if grid and paper_pose:
+        raise ValueError("grid enumeration takes the library pose")
+    fn = L.cvo_oracle_eval_grid if grid else (L.cvo_oracle_eval_h if paper_pose else L.cvo_oracle_eval)
     rc = fn(x.shape[0], _ptr(x, ctypes.c_float), _ptr(lx, ctypes.c_float),
             z.shape[0], _ptr(z, ctypes.c_float), _ptr(lz, ctypes.c_float), fd,
             sigma, feat_scale, ell, kappa, a2, b2, _ptr(T, ctypes.c_double), nsel, selp, nth,
@@ -192,11 +201,13 @@ STEP_RULES = {"fixed": 0, "quartic": 1}
 
 def register(src_xyz, src_feat, tgt_xyz, tgt_feat, *, sigma=0.1, feat_scale=0.2, a2=None, b2=1.0,
              eta=1.0, kappa=0.0, stage_iters=(), stage_ell=(0.1,), max_iters=50, tol=0.0, grad_tol=0.0,
-             step_rule="fixed", dof_mask=0, T0=None, nthreads=None):
-    """Run the registration iteration; returns dict(T, iters, converged, trace[iters,26], rc).
+             step_rule="fixed", dof_mask=0, T0=None, nthreads=None, grid=False):
+    """Run the registration iteration; returns dict(T, iters, converged,
+    trace[iters,26], abs[iters,7] (sums of |terms| per iteration), rc).
     step_rule "fixed": tau = eta ell^2 / F; "quartic": the maximiser of the
     fourth-order model (eq. fourth), falling back to the fixed rule when the
-    model has no maximum on t > 0."""
+    model has no maximum on t > 0.  grid=True (kappa > 0) evaluates through
+    the oracle's grid enumeration (same pair set as the brute force)."""
     L = _load()
     x = _f32(src_xyz, 3)
     fd = np.asarray(src_feat).shape[1]
@@ -210,6 +221,7 @@ def register(src_xyz, src_feat, tgt_xyz, tgt_feat, *, sigma=0.1, feat_scale=0.2,
     T0 = np.ascontiguousarray(T0).reshape(16)
     Tout = np.zeros(16)
     trace = np.zeros((max_iters, TRACE_COLS))
+    abs_trace = np.zeros((max_iters, 7))
     it = np.zeros(1, dtype=np.int32)
     cv = np.zeros(1, dtype=np.int32)
     rc = L.cvo_oracle_register(x.shape[0], _ptr(x, ctypes.c_float), _ptr(lx, ctypes.c_float),
@@ -218,6 +230,7 @@ def register(src_xyz, src_feat, tgt_xyz, tgt_feat, *, sigma=0.1, feat_scale=0.2,
                                _ptr(si, ctypes.c_int), _ptr(se, ctypes.c_double), max_iters, tol, grad_tol,
                                STEP_RULES[step_rule], dof_mask, _ptr(T0, ctypes.c_double), nthreads or default_threads(),
                                _ptr(Tout, ctypes.c_double), _ptr(trace, ctypes.c_double),
-                               _ptr(it, ctypes.c_int), _ptr(cv, ctypes.c_int))
+                               _ptr(it, ctypes.c_int), _ptr(cv, ctypes.c_int), 1 if grid else 0,
+                               _ptr(abs_trace, ctypes.c_double))
     return dict(T=Tout.reshape(4, 4), iters=int(it[0]), converged=bool(cv[0]),
-                trace=trace[: int(it[0])], rc=rc)
+                trace=trace[: int(it[0])], abs=abs_trace[: int(it[0])], rc=rc)

@@ -10,6 +10,9 @@
  * Everything is FP64.  Point coordinates and labels arrive as FP32 and are
  * promoted exactly.  Every pair (i, j) is enumerated (brute force); with a
  * cutoff kappa > 0 a pair contributes only if |x_i - z~_j|^2 <= (kappa*ell)^2.
+ * For large clouds cvo_oracle_eval_grid enumerates the same cutoff pairs
+ * through a uniform source grid (the oracle's own, pinned against the brute
+ * force: identical pair set, sums equal to rounding).
  *
  * Notation (paper, Sections III-IV and VI):
  *   X = {x_i}, labels l_i;  Z = {z_j}, labels m_j.
@@ -44,19 +47,6 @@
 #define OR_EINVAL (-1)
 #define OR_ENOOVERLAP (-4)
 
-typedef struct {
-    int n, m, fd;
-    const float *x, *lx, *z, *lz;
-    double sigma, sf, ell, kappa, a2, b2;
-    double Rt[9], tt[3]; /* z~ = Rt z + tt  (Rt = R_h^T, tt = -R_h^T t_h) */
-    int j0, j1;
-    /* per-target outputs (optional) */
-    const int *sel;
-    double *per_target; /* [nsel][7] */
-    /* results */
-    double sum[7], abs_sum[7];
-    long long within, examined;
-} job_t;
 
 static void pose_to_inverse_action(const double h[16], double Rt[9], double tt[3]) {
     /* h = [R t; 0 1]; h^-1 z = R^T z - R^T t */
@@ -69,38 +59,100 @@ static void pose_to_inverse_action(const double h[16], double Rt[9], double tt[3
     }
 }
 
-/* Terms of the double sum for one target point j, over all sources i. */
-static void target_terms(const job_t* J, int j, double s7[7], double a7[7], long long* within) {
-    const double zx = J->z[3 * j], zy = J->z[3 * j + 1], zz = J->z[3 * j + 2];
-    double zt[3];
-    for (int r = 0; r < 3; r++)
-        zt[r] = J->Rt[3 * r] * zx + J->Rt[3 * r + 1] * zy + J->Rt[3 * r + 2] * zz + J->tt[r];
+/* Source grid of the enumeration mode (see cvo_oracle_eval_grid): uniform
+ * cubic cells of edge h over the source bounding box; the sources of cell k
+ * are idx[start[k] .. start[k+1]), in increasing source index. */
+typedef struct {
+    double o[3], h;
+    int dim[3];
+    int* start;
+    int* idx;
+} sgrid_t;
+
+typedef struct {
+    int n, m, fd;
+    const float *x, *lx, *z, *lz;
+    double sigma, sf, ell, kappa, a2, b2;
+    double Rt[9], tt[3]; /* z~ = Rt z + tt  (Rt = R_h^T, tt = -R_h^T t_h) */
+    int j0, j1;
+    const sgrid_t* grid; /* NULL: every source is a candidate of every target */
+    /* per-target outputs (optional) */
+    const int *sel;
+    double *per_target; /* [nsel][7] */
+    /* results */
+    double sum[7], abs_sum[7];
+    long long within, examined;
+} job_t;
+
+/* One pair (i, j): adds its terms to s7 and |terms| to a7 if it is inside the
+ * cutoff; returns 1 then, 0 otherwise. */
+static int pair_terms(const job_t* J, int i, int j, const double zt[3], double s7[7], double a7[7]) {
     const double inv2l2 = 1.0 / (2.0 * J->ell * J->ell);
     const double rc2 = (J->kappa > 0.0) ? (J->kappa * J->ell) * (J->kappa * J->ell) : INFINITY;
     const double s2 = J->sigma * J->sigma;
     const double cw = 1.0 / (J->a2 * J->ell * J->ell);
     const double cv = 1.0 / (J->b2 * J->ell * J->ell);
+    const double x0 = J->x[3 * i], x1 = J->x[3 * i + 1], x2 = J->x[3 * i + 2];
+    const double d0 = zt[0] - x0, d1 = zt[1] - x1, d2 = zt[2] - x2;
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    if (!(r2 <= rc2)) return 0;
+    double lm = 0.0;
+    for (int f = 0; f < J->fd; f++) lm += (double)J->lx[J->fd * i + f] * (double)J->lz[J->fd * j + f];
+    const double cij = J->sf * lm;
+    const double kij = s2 * exp(-r2 * inv2l2);
+    const double w = cij * kij;
+    /* x_i cross z~_j */
+    const double c0 = x1 * zt[2] - x2 * zt[1];
+    const double c1 = x2 * zt[0] - x0 * zt[2];
+    const double c2 = x0 * zt[1] - x1 * zt[0];
+    const double t[7] = {w, cw * w * c0, cw * w * c1, cw * w * c2, cv * w * d0, cv * w * d1, cv * w * d2};
+    for (int q = 0; q < 7; q++) { s7[q] += t[q]; a7[q] += fabs(t[q]); }
+    return 1;
+}
+
+/* cell coordinate of u along one axis, or a value outside [0, dim) */
+static long grid_coord(const sgrid_t* G, int a, double u) {
+    const double c = floor((u - G->o[a]) / G->h);
+    if (!(c > -2.0)) return -2;
+    if (!(c < (double)G->dim[a] + 1.0)) return (long)G->dim[a] + 1;
+    return (long)c;
+}
+
+/* Terms of the double sum for one target point j, over all sources i (or,
+ * with a grid, over the sources of the 27 cells around z~_j: every source
+ * within the cutoff lies there, see cvo_oracle_eval_grid).  *examined counts
+ * the candidates tested. */
+static void target_terms(const job_t* J, int j, double s7[7], double a7[7], long long* within,
+                         long long* examined) {
+    const double zx = J->z[3 * j], zy = J->z[3 * j + 1], zz = J->z[3 * j + 2];
+    double zt[3];
+    for (int r = 0; r < 3; r++)
+        zt[r] = J->Rt[3 * r] * zx + J->Rt[3 * r + 1] * zy + J->Rt[3 * r + 2] * zz + J->tt[r];
     for (int q = 0; q < 7; q++) { s7[q] = 0.0; a7[q] = 0.0; }
-    long long cnt = 0;
-    for (int i = 0; i < J->n; i++) {
-        const double x0 = J->x[3 * i], x1 = J->x[3 * i + 1], x2 = J->x[3 * i + 2];
-        const double d0 = zt[0] - x0, d1 = zt[1] - x1, d2 = zt[2] - x2;
-        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-        if (!(r2 <= rc2)) continue;
-        cnt++;
-        double lm = 0.0;
-        for (int f = 0; f < J->fd; f++) lm += (double)J->lx[J->fd * i + f] * (double)J->lz[J->fd * j + f];
-        const double cij = J->sf * lm;
-        const double kij = s2 * exp(-r2 * inv2l2);
-        const double w = cij * kij;
-        /* x_i cross z~_j */
-        const double c0 = x1 * zt[2] - x2 * zt[1];
-        const double c1 = x2 * zt[0] - x0 * zt[2];
-        const double c2 = x0 * zt[1] - x1 * zt[0];
-        const double t[7] = {w, cw * w * c0, cw * w * c1, cw * w * c2, cv * w * d0, cv * w * d1, cv * w * d2};
-        for (int q = 0; q < 7; q++) { s7[q] += t[q]; a7[q] += fabs(t[q]); }
+    long long cnt = 0, ex = 0;
+    const sgrid_t* G = J->grid;
+    if (!G) {
+        for (int i = 0; i < J->n; i++) cnt += pair_terms(J, i, j, zt, s7, a7);
+        ex = J->n;
+    } else {
+        long lo[3], hi[3];
+        for (int a = 0; a < 3; a++) {
+            const long c = grid_coord(G, a, zt[a]);
+            lo[a] = c - 1 < 0 ? 0 : c - 1;
+            hi[a] = c + 1 > G->dim[a] - 1 ? G->dim[a] - 1 : c + 1;
+        }
+        for (long cz = lo[2]; cz <= hi[2]; cz++)
+            for (long cy = lo[1]; cy <= hi[1]; cy++)
+                for (long cx = lo[0]; cx <= hi[0]; cx++) {
+                    const long k = (cz * G->dim[1] + cy) * G->dim[0] + cx;
+                    for (int p = G->start[k]; p < G->start[k + 1]; p++) {
+                        cnt += pair_terms(J, G->idx[p], j, zt, s7, a7);
+                        ex++;
+                    }
+                }
     }
     *within = cnt;
+    *examined = ex;
 }
 
 static void* run_job(void* arg) {
@@ -110,11 +162,11 @@ static void* run_job(void* arg) {
     for (int jj = J->j0; jj < J->j1; jj++) {
         const int j = J->sel ? J->sel[jj] : jj;
         double s7[7], a7[7];
-        long long w;
-        target_terms(J, j, s7, a7, &w);
+        long long w, ex;
+        target_terms(J, j, s7, a7, &w, &ex);
         for (int q = 0; q < 7; q++) { J->sum[q] += s7[q]; J->abs_sum[q] += a7[q]; }
         J->within += w;
-        J->examined += J->n;
+        J->examined += ex;
         if (J->per_target)
             for (int q = 0; q < 7; q++) J->per_target[7 * jj + q] = s7[q];
     }
@@ -147,12 +199,83 @@ double cvo_oracle_mean_sqnorm(int n, const float* x) {
  * (optional) receives each target's own terms.  nthreads >= 1 splits the
  * targets into contiguous blocks whose partials are added in block order.
  */
-int cvo_oracle_eval_h(int n, const float* x, const float* lx, int m, const float* z, const float* lz,
-                      int fd, double sigma, double feat_scale, double ell, double kappa, double a2,
-                      double b2, const double h[16], int nsel, const int* sel, int nthreads,
-                      double out[7], double absout[7], long long counts[2], double* per_target) {
+/*
+ * Grid enumeration of the same cutoff sum.  Cells are cubes of edge
+ * e >= kappa ell (1 + 1e-7) over the sources' bounding box, cell coordinate
+ * floor((x_a - o_a) / e) per axis.  A pair within the cutoff has
+ * |x_a - z~_a| <= kappa ell < e on every axis, so the two cell coordinates
+ * differ by at most one (with at most 2^20 cells per axis the rounding of the
+ * divisions stays below 1e-9, far inside the 1e-7 margin): the 27 cells
+ * around z~_j hold every source the brute-force enumeration would accept,
+ * and each candidate meets the same per-pair test.  The edge grows when the
+ * table would exceed 2^26 cells or 2^20 per axis.  Returns 0 on success
+ * (free with free_grid).
+ */
+static int build_grid(int n, const float* x, double edge, sgrid_t* G) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = 0; i < n; i++)
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmin(lo[a], (double)x[3 * i + a]);
+            hi[a] = fmax(hi[a], (double)x[3 * i + a]);
+        }
+    for (;;) {
+        double cells = 1.0, most = 0.0;
+        for (int a = 0; a < 3; a++) {
+            const double d = floor((hi[a] - lo[a]) / edge) + 1.0;
+            cells *= d;
+            most = fmax(most, d);
+        }
+        if (cells <= 67108864.0 && most <= 1048576.0) break;
+        edge *= 1.5;
+    }
+    G->h = edge;
+    long ncell = 1;
+    for (int a = 0; a < 3; a++) {
+        G->o[a] = lo[a];
+        G->dim[a] = (int)floor((hi[a] - lo[a]) / edge) + 1;
+        ncell *= G->dim[a];
+    }
+    G->start = (int*)calloc((size_t)ncell + 1, sizeof(int));
+    G->idx = (int*)malloc((size_t)n * sizeof(int));
+    long* key = (long*)malloc((size_t)n * sizeof(long));
+    int* cur = (int*)malloc((size_t)ncell * sizeof(int));
+    if (!G->start || !G->idx || !key || !cur) {
+        free(G->start); free(G->idx); free(key); free(cur);
+        return -1;
+    }
+    for (int i = 0; i < n; i++) {
+        long c[3];
+        for (int a = 0; a < 3; a++) {
+            c[a] = grid_coord(G, a, (double)x[3 * i + a]);
+            if (c[a] < 0) c[a] = 0;
+            if (c[a] > G->dim[a] - 1) c[a] = G->dim[a] - 1;
+        }
+        key[i] = (c[2] * G->dim[1] + c[1]) * G->dim[0] + c[0];
+        G->start[key[i] + 1]++;
+    }
+    for (long k = 0; k < ncell; k++) G->start[k + 1] += G->start[k];
+    for (long k = 0; k < ncell; k++) cur[k] = G->start[k];
+    for (int i = 0; i < n; i++) G->idx[cur[key[i]]++] = i;
+    free(key);
+    free(cur);
+    return 0;
+}
+
+static void free_grid(sgrid_t* G) {
+    free(G->start);
+    free(G->idx);
+}
+
+static int eval_h_impl(int n, const float* x, const float* lx, int m, const float* z, const float* lz,
+                       int fd, double sigma, double feat_scale, double ell, double kappa, double a2,
+                       double b2, const double h[16], int nsel, const int* sel, int nthreads,
+                       double out[7], double absout[7], long long counts[2], double* per_target,
+                       int use_grid) {
     if (!check_cloud(n, fd, x, lx) || !check_cloud(m, fd, z, lz)) return OR_EINVAL;
     if (!(ell > 0.0) || !(a2 > 0.0) || !(b2 > 0.0) || kappa < 0.0) return OR_EINVAL;
+    if (use_grid && !(kappa > 0.0)) return OR_EINVAL;
+    sgrid_t grid;
+    if (use_grid && build_grid(n, x, kappa * ell * (1.0 + 1e-7), &grid) != 0) return OR_EINVAL;
     const int nt_total = sel ? nsel : m;
     if (sel)
         for (int k = 0; k < nsel; k++) if (sel[k] < 0 || sel[k] >= m) return OR_EINVAL;
@@ -160,9 +283,14 @@ int cvo_oracle_eval_h(int n, const float* x, const float* lx, int m, const float
     if (nthreads > nt_total) nthreads = nt_total > 0 ? nt_total : 1;
     job_t* jobs = (job_t*)calloc((size_t)nthreads, sizeof(job_t));
     pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
-    if (!jobs || !th) { free(jobs); free(th); return OR_EINVAL; }
+    if (!jobs || !th) {
+        free(jobs); free(th);
+        if (use_grid) free_grid(&grid);
+        return OR_EINVAL;
+    }
     for (int k = 0; k < nthreads; k++) {
         job_t* J = &jobs[k];
+        J->grid = use_grid ? &grid : NULL;
         J->n = n; J->m = m; J->fd = fd; J->x = x; J->lx = lx; J->z = z; J->lz = lz;
         J->sigma = sigma; J->sf = feat_scale; J->ell = ell; J->kappa = kappa; J->a2 = a2; J->b2 = b2;
         pose_to_inverse_action(h, J->Rt, J->tt);
@@ -180,7 +308,16 @@ int cvo_oracle_eval_h(int n, const float* x, const float* lx, int m, const float
         counts[0] += jobs[k].within; counts[1] += jobs[k].examined;
     }
     free(jobs); free(th);
+    if (use_grid) free_grid(&grid);
     return OR_OK;
+}
+
+int cvo_oracle_eval_h(int n, const float* x, const float* lx, int m, const float* z, const float* lz,
+                      int fd, double sigma, double feat_scale, double ell, double kappa, double a2,
+                      double b2, const double h[16], int nsel, const int* sel, int nthreads,
+                      double out[7], double absout[7], long long counts[2], double* per_target) {
+    return eval_h_impl(n, x, lx, m, z, lz, fd, sigma, feat_scale, ell, kappa, a2, b2, h, nsel, sel, nthreads,
+                       out, absout, counts, per_target, 0);
 }
 
 /* Closed-form SE(3) exponential (eq. step) of the twist t*(w^, u), t = 1:
@@ -261,6 +398,21 @@ int cvo_oracle_eval(int n, const float* x, const float* lx, int m, const float* 
     rigid_inverse(T, h);
     return cvo_oracle_eval_h(n, x, lx, m, z, lz, fd, sigma, feat_scale, ell, kappa, a2, b2, h, nsel,
                              sel, nthreads, out, absout, counts, per_target);
+}
+
+/* The cutoff sum of cvo_oracle_eval (kappa > 0 required) with the candidates
+ * of each target taken from a uniform source grid (build_grid) instead of all
+ * sources: the same pair set and the same per-pair arithmetic; only the order
+ * of the sources inside a target's sum differs.  counts[1] is the number of
+ * candidates tested. */
+int cvo_oracle_eval_grid(int n, const float* x, const float* lx, int m, const float* z, const float* lz,
+                         int fd, double sigma, double feat_scale, double ell, double kappa, double a2,
+                         double b2, const double T[16], int nsel, const int* sel, int nthreads,
+                         double out[7], double absout[7], long long counts[2], double* per_target) {
+    double h[16];
+    rigid_inverse(T, h);
+    return eval_h_impl(n, x, lx, m, z, lz, fd, sigma, feat_scale, ell, kappa, a2, b2, h, nsel, sel, nthreads,
+                       out, absout, counts, per_target, 1);
 }
 
 /*
@@ -452,14 +604,18 @@ int cvo_oracle_quartic_step(const double A[5], double* t_out) {
  * Stage s spans stage_iters[s] iterations; the last stage runs to max_iters.
  * T0 and T_out use the library convention T = h^-1.
  * trace (optional) receives per iteration 26 doubles:
- *   F, omega[3], v[3], tau, ell, within-pairs, then T (16, row-major) after the step.
+ *   F, omega[3], v[3], tau, ell, within-pairs, then T (16, row-major) after the step;
+ * abs_trace (optional) per iteration the 7 sums of |terms| of F, omega, v.
+ * use_grid != 0 (with kappa > 0) takes each evaluation's pairs from the grid
+ * enumeration (cvo_oracle_eval_grid: the same pair set).
  */
 int cvo_oracle_register(int n, const float* x, const float* lx, int m, const float* z, const float* lz,
                         int fd, double sigma, double feat_scale, double a2, double b2, double eta,
                         double kappa, int n_stages, const int* stage_iters, const double* stage_ell,
                         int max_iters, double tol, double grad_tol, int step_rule, int dof_mask,
                         const double T0[16], int nthreads,
-                        double T_out[16], double* trace, int* iters_out, int* converged_out) {
+                        double T_out[16], double* trace, int* iters_out, int* converged_out,
+                        int use_grid, double* abs_trace) {
     if (n_stages < 1 || !stage_ell || max_iters < 1 || !(eta > 0.0)) return OR_EINVAL;
     if (!(tol >= 0.0) || !(grad_tol >= 0.0)) return OR_EINVAL;
     if (dof_mask < 0 || dof_mask > 63) return OR_EINVAL;
@@ -481,8 +637,8 @@ int cvo_oracle_register(int n, const float* x, const float* lx, int m, const flo
         const double ell = stage_ell[stage];
         double g[7], ga[7];
         long long cnt[2];
-        rc = cvo_oracle_eval_h(n, x, lx, m, z, lz, fd, sigma, feat_scale, ell, kappa, a2, b2, h, 0,
-                               NULL, nthreads, g, ga, cnt, NULL);
+        rc = eval_h_impl(n, x, lx, m, z, lz, fd, sigma, feat_scale, ell, kappa, a2, b2, h, 0, NULL, nthreads,
+                         g, ga, cnt, NULL, use_grid && kappa > 0.0);
         if (rc != OR_OK) break;
         if (!(g[0] > 1e-300)) { rc = OR_ENOOVERLAP; break; }
         /* the flow on the subgroup dof_mask selects (bits 0-2 omega, 3-5 v):
@@ -512,6 +668,8 @@ int cvo_oracle_register(int n, const float* x, const float* lx, int m, const flo
             tr[7] = tau; tr[8] = ell; tr[9] = (double)cnt[0];
             rigid_inverse(h, tr + 10);
         }
+        if (abs_trace)
+            for (int q = 0; q < 7; q++) abs_trace[7 * (size_t)k + q] = ga[q];
         if (stage == n_stages - 1 && (sqrt(sq) < tol || sqrt(gq) < grad_tol)) { conv = 1; k++; break; }
     }
     rigid_inverse(h, T_out);

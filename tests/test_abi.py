@@ -54,8 +54,9 @@ def _P(A, t):
 
 
 def test_quartic_step_host_rule_matches_oracle():
-    # The library's step rule for the quartic model (bracketed Newton on P')
-    # against the oracle's (closed-form roots of the cubic P'), on random
+    # The library's step rule for the quartic model (Newton's method on P'
+    # inside the brackets cut at the roots of P'') against the oracle's
+    # (plain bisection of P' inside the same kind of brackets), on random
     # coefficient sets of mixed signs and scales, A1 >= 0 as along a gradient.
     import oracle
     from paper_1904_02266_amd import quartic_step

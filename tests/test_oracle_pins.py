@@ -494,3 +494,105 @@ def test_subgroup_mask_zero_is_full_group():
     b = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, stage_ell=(0.15,), max_iters=10, a2=7.0,
                         dof_mask=0x3F)
     np.testing.assert_array_equal(a["T"], b["T"])
+
+
+# --------------------------------------------------------------------------
+# the oracle's grid enumeration (for clouds too large for the brute force)
+# and its selected-target mode (per-target rows)
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def rgbd_small():
+    return synth.rgbd_pair(5000, 5000, seed=2)
+
+
+@pytest.mark.parametrize("ell", [0.2, 0.05])
+def test_grid_enumeration_is_the_brute_force_pair_set(rgbd_small, ell):
+    """The grid's candidates contain every pair inside the cutoff: the pair
+    count equals the brute force exactly, per target and in total, and the
+    sums agree to the rounding of a different summation order."""
+    p = rgbd_small
+    rng = np.random.default_rng(17)
+    for T in (np.eye(4), p.T_true, synth.random_motion(rng, 20.0, 0.3)):
+        b = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=ell, kappa=3.0, per_target=True)
+        g = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=ell, kappa=3.0, per_target=True,
+                        grid=True)
+        assert b["within"] == g["within"] > 0
+        assert g["examined"] < b["examined"] / 2          # the grid prunes
+        assert abs(g["g"][0] - b["g"][0]) <= 1e-13 * b["g"][0]
+        assert (np.abs(g["g"][1:] - b["g"][1:]) <= 1e-13 * b["abs"][1:]).all()
+        assert (np.abs(g["abs"] - b["abs"]) <= 1e-13 * b["abs"]).all()
+        # per target: the same pairs (a zero row stays zero)
+        pb, pg = b["per_target"], g["per_target"]
+        assert ((pb[:, 0] == 0) == (pg[:, 0] == 0)).all()
+        scale = np.abs(pb).max(axis=1, keepdims=True)
+        assert (np.abs(pg - pb) <= 1e-13 * scale).all()
+
+
+def test_grid_enumeration_boundary_pairs():
+    """Pairs exactly at the cutoff radius along a cell axis, and targets far
+    outside the sources' box, are handled as by the brute force."""
+    rng = np.random.default_rng(3)
+    ell, kappa = 0.0625, 2.0           # cutoff 0.125 (exact in binary)
+    x = np.round(rng.uniform(-1, 1, size=(400, 3)) * 64) / 64     # multiples of 1/64
+    z = np.concatenate([x[:200] + np.array([0.125, 0.0, 0.0]),     # exactly at the cutoff
+                        x[200:300] + np.array([0.0, -0.125, 0.0]),
+                        x[300:] + np.array([25.0, 0.0, 0.0])])     # out of reach
+    l = rng.uniform(0, 1, size=(400, 5))
+    b = oracle.eval(x, l, z, l, np.eye(4), ell=ell, kappa=kappa, a2=1.0)
+    g = oracle.eval(x, l, z, l, np.eye(4), ell=ell, kappa=kappa, a2=1.0, grid=True)
+    assert b["within"] == g["within"] >= 300
+    assert abs(g["g"][0] - b["g"][0]) <= 1e-13 * b["g"][0]
+    # one source point only: a single-cell grid
+    one = oracle.eval(x[:1], l[:1], z, l, np.eye(4), ell=ell, kappa=kappa, a2=1.0, grid=True)
+    ref = oracle.eval(x[:1], l[:1], z, l, np.eye(4), ell=ell, kappa=kappa, a2=1.0)
+    assert one["within"] == ref["within"] and one["g"][0] == ref["g"][0]
+
+
+def test_grid_registration_equals_brute_force_registration():
+    p = synth.rgbd_pair(2500, 2500, seed=2)
+    kw = dict(kappa=3.0, stage_iters=(3, 3), stage_ell=(0.2, 0.1, 0.05), max_iters=9)
+    a = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, **kw)
+    b = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, grid=True, **kw)
+    assert a["iters"] == b["iters"] == 9
+    np.testing.assert_array_equal(a["trace"][:, 9], b["trace"][:, 9])      # pair counts
+    np.testing.assert_allclose(b["trace"][:, 0], a["trace"][:, 0], rtol=1e-13)
+    np.testing.assert_allclose(b["T"], a["T"], atol=1e-12)
+    assert (b["abs"] > 0).all()
+
+
+def test_selected_target_rows_sum_to_the_objective():
+    """Per-target rows over a permuted selection of every target sum to the
+    full F, omega, v; rows follow the selection order."""
+    p = small_pair(300, seed=14)
+    T = synth.random_motion(np.random.default_rng(6), 6.0, 0.06)
+    full = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=0.2, kappa=3.0)
+    sel = np.random.default_rng(1).permutation(p.tgt_xyz.shape[0]).astype(np.int32)
+    part = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=0.2, kappa=3.0, sel=sel,
+                       per_target=True, nthreads=3)
+    rows = part["per_target"]
+    assert abs(rows[:, 0].sum() - full["g"][0]) <= 1e-13 * full["g"][0]
+    assert (np.abs(rows[:, 1:].sum(axis=0) - full["g"][1:]) <= 1e-13 * full["abs"][1:]).all()
+    assert part["within"] == full["within"]
+    # a subset: its rows are the subset's own total
+    sub = sel[:37]
+    ps = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=0.2, kappa=3.0, sel=sub,
+                     per_target=True)
+    np.testing.assert_array_equal(ps["per_target"], rows[:37])
+    assert abs(ps["g"][0] - rows[:37, 0].sum()) <= 1e-13 * ps["g"][0]
+
+
+def test_selected_target_row_is_the_single_target_objective():
+    """Row k of the selected-target mode equals the objective of the target
+    cloud {z_sel[k]} alone (the same sum over sources), for the brute force
+    and the grid enumeration."""
+    p = small_pair(300, seed=15)
+    T = synth.random_motion(np.random.default_rng(8), 6.0, 0.06)
+    a2 = oracle.mean_sqnorm(p.src_xyz)
+    sel = np.array([5, 0, 299, 123, 5], dtype=np.int32)
+    for grid in (False, True):
+        rows = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=0.2, kappa=3.0, a2=a2, sel=sel,
+                           per_target=True, grid=grid)["per_target"]
+        for k, j in enumerate(sel):
+            one = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz[j:j + 1], p.tgt_feat[j:j + 1], T, ell=0.2,
+                              kappa=3.0, a2=a2, grid=grid)
+            np.testing.assert_array_equal(rows[k], one["g"])
