@@ -1,20 +1,23 @@
 #!/usr/bin/env python3
-"""Benchmark: pair evaluations per second of one RGB-D-frame registration on MI355X.
+"""Benchmark: pair evaluations per second of one dense RGB-D-frame registration on MI355X.
 
-Workload (one step = one full registration, inputs resident in HBM):
-  two synthetic 640x480 RGB-D frames of a piecewise-planar room, 30,000
-  semi-dense (highest intensity gradient) points per frame with 5 label
-  channels, ground-truth motion <= 5 deg / 0.05 m; kernel cutoff 3 ell with the
-  voxel-grid neighbour search; 100 gradient-flow iterations with ell annealed
-  geometrically 0.2 -> 0.05 m over 4 stages.
+Headline workload (one step = one full registration, inputs resident in HBM):
+  two synthetic 640x480 RGB-D frames of a piecewise-planar room, a seeded
+  random subset of 300,000 valid pixels per frame (the dense frame), 5 label
+  channels, ground-truth motion <= 5 deg / 0.05 m; kernel cutoff 3 ell with
+  the voxel-grid neighbour search; 100 gradient-flow iterations with ell
+  annealed geometrically 0.2 -> 0.05 m over 4 stages; FP32 pair terms,
+  compensated FP32 partials, FP64 reduction, step and pose.
 value = pairs inside the cutoff evaluated over the timed registrations / wall time.
 
-Also reported: the iteration kernel against the FP32 ALU roofline (event-timed
-on the launch stream), per-registration latency p50/p99, the same registration
-with the paper's quartic step rule (second pair pass per iteration), a batched
-run through the continuous-batching scheduler (regs/s, per-request latency),
-and the FP64 CPU oracle on a bounded teacher-forced sample (which doubles as a
-parity check).
+Also reported: the pair kernel against the FP32 vector roofline (event-timed
+on the launch stream), per-registration latency p50/p99, the all-FP64 path
+on the same registration, teacher-forced parity and the CPU oracle timed on
+a bounded sample of the same registration (its own trajectory's poses), the
+30k semi-dense RGB-D pair (fixed, conjugate-direction and quartic step
+rules, and all pairs without the cutoff), a batched run through the
+continuous-batching scheduler (regs/s, per-request latency), Poisson
+serving at 200-2000 requests/s, and the remaining workloads.
 """
 import argparse
 import hashlib
@@ -34,13 +37,18 @@ FLOPS_PER_PAIR = 26          # d:3, r^2:5, exponent scale:1, label product (5 ch
 # quartic pass: d:3, r^2:5, scale:1, labels:9, weight:1, beta:5, gamma/delta/eps:18, beta^2:1,
 # g2:2, g3:4, g4:8, four sums:8
 QUARTIC_FLOPS_PER_PAIR = 65
-PEAK_TFLOPS = 78.6           # FP32 VALU issue peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+PEAK_TFLOPS = 157.3          # MI355X published FP32 vector peak (counts packed FP32, two FMAs per lane per cycle)
+# the FP32 issue ceiling without packed FP32 (which this library's kernels do
+# not use): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+PEAK_UNPACKED_TFLOPS = 78.6
 METRIC = "pair-evals/s per registration + batched regs/s, p50/p99 latency @1e-5 rel"
 KERNEL_SRC = os.path.join(ROOT, "paper_1904_02266_amd", "csrc", "cvo_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_rgbd30k_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_dense300k_traffic.md")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "dense300k_trajectory.json")
+SAMPLE_ITERS = (0, 25, 50, 99)   # one iteration of each length-scale stage (oracle sample, parity)
 
 
-def measured_traffic():
+def measured_traffic(path=TRAFFIC_FILE):
     """HBM bytes per pair-kernel launch from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None when
     the kernel source has changed since the counters were taken."""
@@ -48,7 +56,7 @@ def measured_traffic():
         with open(KERNEL_SRC, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
         fields = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             for line in f:
                 if ":" in line and line.startswith("- "):
                     key, val = line[2:].split(":", 1)
@@ -88,7 +96,7 @@ def _gen_pool_pair(seed):
 def _gen_dense(seed):
     from paper_1904_02266_amd import synth
     p = synth.rgbd_pair(300000, 300000, seed=seed, select="random")
-    return p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat
+    return (p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat), p.T_true
 
 
 def dense_bruteforce(cloud, repeats=2):
@@ -187,20 +195,22 @@ def gen_serving_pool(npairs):
         return list(ex.map(_gen_pool_pair, [5100 + k for k in range(npairs)]))
 
 
-def serving(pool, rates=(50, 200, 1000), window_s=2.0):
+def serving(pool, rates=(200, 500, 1000, 2000), window_s=10.0, table1_rates=(200,)):
     """Poisson arrivals at each rate over window_s seconds, cloud sizes
     lognormal (median 20k, shape 1.0, clamped to 1000..300000) cut from the
-    pool, RGB-D parameters with tol 1e-5 and at most 200 iterations (and, at
-    the two lower rates, the Table 1 parameter set); each request is
-    submitted at its arrival time and its latency is submission to completion
-    (the library's wall clock)."""
+    pool, RGB-D schedule with the conjugate-direction quartic step, stop once
+    the last stage's applied twist |tau d| < 1e-5, at most 200 iterations
+    (and the Table 1 parameter set at table1_rates); each request is submitted
+    at its arrival time and its latency is submission to completion (the
+    library's wall clock).  The saturation point is the highest offered rate
+    that completes at >= 95% of the offered rate."""
     import torch
     from paper_1904_02266_amd import Context, params_rgbd, params_table1, synth
     dev = torch.device("cuda:0")
     dpool = [[torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in c] for c in pool]
     torch.cuda.synchronize()
-    runs = [("rgbd", params_rgbd(grad_tol=1e-5, max_iters=200), r) for r in rates]
-    runs += [("table1", params_table1(), r) for r in rates[:2]]
+    runs = [("rgbd", params_rgbd(step_rule="conjugate", tol=1e-5, max_iters=200), r) for r in rates]
+    runs += [("table1", params_table1(), r) for r in table1_rates]
     out = []
     for pname, prm, rate in runs:
         stream = synth.serving_stream(rate, window_s=window_s)
@@ -216,18 +226,28 @@ def serving(pool, rates=(50, 200, 1000), window_s=2.0):
             tk, keep = ctx.submit(c[0][:ns], c[1][:ns], c[2][:nt], c[3][:nt], prm)
             subs.append((tk, keep, ts))
         res = [(ctx.poll(tk), ts) for tk, _, ts in subs]
+        st = ctx.serving_stats()
         ctx.close()
         ok = [r for r, _ in res if r["rc"] == 0]
         lat = np.array([r["wall_ms"] for r in ok])
         end = max(ts + r["wall_ms"] / 1e3 for r, ts in res)
         out.append({"params": pname, "rate": rate, "requests": len(res), "completed": len(ok),
-                    "throughput_per_s": len(ok) / end, "latency_ms": {"p50": float(np.percentile(lat, 50)),
-                                                                     "p99": float(np.percentile(lat, 99))},
+                    "throughput_per_s": len(ok) / end, "span_s": end,
+                    "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
                     "mean_iters": float(np.mean([r["iters"] for r in ok])),
-                    "converged": float(np.mean([r["converged"] for r in ok]))})
+                    "converged": float(np.mean([r["converged"] for r in ok])),
+                    "hbm_peak_gb": st["hbm_peak"] / 1e9})
+    sat = None
+    for r in out:
+        if r["params"] == "rgbd" and r["throughput_per_s"] >= 0.95 * r["rate"]:
+            sat = r["rate"] if sat is None else max(sat, r["rate"])
+    top = max((r["throughput_per_s"] for r in out if r["params"] == "rgbd"), default=None)
     return {"window_s": window_s, "sizes": "lognormal median 20k, shape 1.0, clamped 1000..300000",
-            "params": {"rgbd": "RGB-D schedule, fixed step, stop at |(omega, v)| < 1e-5, cap 200 iterations",
+            "params": {"rgbd": "RGB-D schedule, conjugate-direction quartic step, stop at |tau d| < 1e-5 in the "
+                               "last stage, cap 200 iterations",
                        "table1": "Table 1 set: quartic step, value floor 1e-3, thresholds 1e-5 / 5e-5, cap 200"},
+            "saturation": {"highest_rate_served_per_s": sat, "max_throughput_per_s": top,
+                           "criterion": "completed/s >= 0.95 x offered"},
             "rates": out}
 
 
@@ -280,21 +300,187 @@ def batched(clouds, repeats=2, precision="fp32"):
             "note": "all requests submitted at once; latency = submission to completion"}
 
 
+def rot_err_deg(T, T_true):
+    E = T[:3, :3] @ T_true[:3, :3].T
+    return float(np.degrees(np.arccos(np.clip((np.trace(E) - 1) / 2, -1, 1))))
+
+
+def trans_err_m(T, T_true):
+    E = T[:3, :3] @ T_true[:3, :3].T
+    return float(np.linalg.norm(T[:3, 3] - E @ T_true[:3, 3]))
+
+
+def time_registrations(ctx, t, prm, steps, warmup):
+    """Wall time of `steps` registrations after `warmup` untimed ones, then the
+    same registrations with HIP events around every launch (pair kernel
+    average).  Inputs are device tensors."""
+    import torch
+    for _ in range(warmup):
+        ctx.register(*t, prm)
+    torch.cuda.synchronize()
+    lat, pairs, examined = [], 0, 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        out = ctx.register(*t, prm)
+        lat.append((time.perf_counter() - s0) * 1e3)
+        pairs += out["pairs_within"]
+        examined += out["pairs_examined"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.kernel_stats(reset=True)
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    te0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.register(*t, prm)
+    torch.cuda.synchronize()
+    elapsed_ev = time.perf_counter() - te0
+    ctx.set_profiling(False)
+    ks = ctx.kernel_stats(reset=True)
+    return {"out": out, "elapsed": elapsed, "lat": lat, "pairs": pairs, "examined": examined, "ks": ks,
+            "elapsed_ev": elapsed_ev}
+
+
+def roofline_of(ks, traffic):
+    achieved = FLOPS_PER_PAIR * ks["pairs"] / (ks["ms"] * 1e-3) / 1e12 if ks["ms"] > 0 else 0.0
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS, "traffic": traffic,
+            "kernel": "k_pairs<float,5,true,false>", "kernel_ms_avg": ks["ms"] / max(1, ks["launches"]),
+            "launches": ks["launches"], "flops_per_pair": FLOPS_PER_PAIR,
+            "pairs_per_launch": ks["pairs"] / max(1, ks["launches"]),
+            "peak_unpacked": PEAK_UNPACKED_TFLOPS, "frac_of_unpacked": achieved / PEAK_UNPACKED_TFLOPS,
+            "peak_note": "peak = published FP32 vector rate (packed FP32); peak_unpacked = the issue ceiling "
+                         "without packed FP32 (256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz), which the "
+                         "kernels do not use",
+            "prepare_kernel_ms_avg": ks["prepare_ms"] / max(1, ks["launches"])}
+
+
+def oracle_sample(pair, golden, ctx, t, iters=SAMPLE_ITERS):
+    """The FP64 oracle (grid enumeration, all host threads) at the oracle
+    trajectory's poses of `iters`: the CPU baseline's timing, and the GPU's
+    F, omega, v at the same poses against it (teacher-forced parity).  Also a
+    one-thread rate and the brute-force enumeration's rate, each on a sample
+    of targets."""
+    import oracle
+    from paper_1904_02266_amd import Params
+    tr = np.array(golden["trace"])
+    a2 = golden["a2"]
+    nth = oracle.default_threads()
+    t_cpu, p_cpu, worst = 0.0, 0, 0.0
+    for k in iters:
+        Tk = np.eye(4) if k == 0 else tr[k - 1, 10:26].reshape(4, 4)
+        ell = tr[k, 8]
+        c0 = time.perf_counter()
+        r = oracle.eval(pair.src_xyz, pair.src_feat, pair.tgt_xyz, pair.tgt_feat, Tk, ell=ell, kappa=3.0, a2=a2,
+                        nthreads=nth, grid=True)
+        t_cpu += time.perf_counter() - c0
+        p_cpu += r["within"]
+        g = ctx.eval(*t, Tk, Params(stage_ell=(ell,), cutoff_mult=3.0, a2=a2))
+        err = max([abs(g[0] - r["g"][0]) / r["g"][0]] + [abs(g[q] - r["g"][q]) / r["abs"][q] for q in range(1, 7)])
+        worst = max(worst, err)
+    # one thread, every 16th target at the last iteration's pose
+    k = iters[-1]
+    Tk = tr[k - 1, 10:26].reshape(4, 4)
+    sel = np.arange(0, pair.tgt_xyz.shape[0], 16, dtype=np.int32)
+    c0 = time.perf_counter()
+    r1 = oracle.eval(pair.src_xyz, pair.src_feat, pair.tgt_xyz, pair.tgt_feat, Tk, ell=tr[k, 8], kappa=3.0, a2=a2,
+                     nthreads=1, grid=True, sel=sel)
+    t1 = time.perf_counter() - c0
+    # brute force (every pair tested), all threads, every 256th target
+    selb = np.arange(0, pair.tgt_xyz.shape[0], 256, dtype=np.int32)
+    c0 = time.perf_counter()
+    rb = oracle.eval(pair.src_xyz, pair.src_feat, pair.tgt_xyz, pair.tgt_feat, Tk, ell=tr[k, 8], kappa=3.0, a2=a2,
+                     nthreads=nth, sel=selb)
+    tb = time.perf_counter() - c0
+    cpu = {"value": p_cpu / t_cpu, "unit": "pair-evals/s", "cores": nth, "kind": "oracle",
+           "sample": f"{len(iters)} of the 100 FP64 evaluations of the registration (oracle grid enumeration of "
+                     f"the cutoff pairs) at the oracle trajectory's poses of iterations {list(iters)}, "
+                     f"{p_cpu:.3g} pairs in {t_cpu:.1f} s",
+           "nproc": os.cpu_count(),
+           "one_core": {"value": r1["within"] / t1, "unit": "pair-evals/s", "cores": 1,
+                        "sample": f"iteration {k}, every 16th target ({sel.size}), {t1:.1f} s"},
+           "brute_force": {"value": rb["within"] / tb, "examined_per_s": rb["examined"] / tb, "unit": "pair-evals/s",
+                           "cores": nth, "sample": f"iteration {k}, every 256th target ({selb.size}), every pair "
+                                                   f"tested, {tb:.1f} s"}}
+    parity = {"max_rel_err": worst, "criterion": "F rel; omega,v abs / oracle sum|terms| (teacher-forced at the "
+                                                 "oracle's poses)", "iters": list(iters)}
+    return cpu, parity
+
+
+def rgbd30k(ctx, pair, steps, quartic_steps):
+    """The 30k semi-dense RGB-D pair: fixed-step registration (kernel and
+    pose error), the same registration over all pairs (no cutoff), and the
+    conjugate-direction and quartic step rules (pose error, iterations)."""
+    import torch
+    from paper_1904_02266_amd import params_rgbd
+    dev = torch.device("cuda:0")
+    t = [torch.from_numpy(a).to(dev) for a in (pair.src_xyz, pair.src_feat, pair.tgt_xyz, pair.tgt_feat)]
+    torch.cuda.synchronize()
+    r = time_registrations(ctx, t, params_rgbd(), steps, 2)
+    out = r["out"]
+    res = {"workload": "640x480 synthetic RGB-D frame pair, 30,000 semi-dense points (highest intensity gradient) "
+                       "per frame, cutoff 3 ell, ell 0.2->0.05 m over 4x25 iterations",
+           "ms_per_registration": r["elapsed"] * 1e3 / steps,
+           "pair_evals_per_s": r["pairs"] / r["elapsed"],
+           "pairs_per_registration": r["pairs"] / steps, "pairs_examined_per_registration": r["examined"] / steps,
+           "roofline": roofline_of(r["ks"], measured_traffic(os.path.join(ROOT, "profiles",
+                                                                          "k_pairs_rgbd30k_traffic.md"))),
+           "pose_error_fixed": {"rot_deg": rot_err_deg(out["T"], pair.T_true),
+                                "trans_m": trans_err_m(out["T"], pair.T_true)}}
+    # all pairs, no cutoff (the pruning's reference)
+    rb = time_registrations(ctx, t, params_rgbd(cutoff_mult=0.0), max(2, steps // 4), 1)
+    res["bruteforce_no_cutoff"] = {"ms_per_registration": rb["elapsed"] * 1e3 / max(2, steps // 4),
+                                   "pairs_per_registration": rb["pairs"] / max(2, steps // 4),
+                                   "pair_evals_per_s": rb["pairs"] / rb["elapsed"],
+                                   "speedup_of_cutoff": rb["elapsed"] / max(2, steps // 4) /
+                                   (r["elapsed"] / steps)}
+    for rule in ("conjugate", "quartic"):
+        if quartic_steps <= 0:
+            break
+        prm = params_rgbd(step_rule=rule)
+        ctx.register(*t, prm)
+        torch.cuda.synchronize()
+        q0 = time.perf_counter()
+        for _ in range(quartic_steps):
+            oq = ctx.register(*t, prm)
+        torch.cuda.synchronize()
+        q_el = (time.perf_counter() - q0) / quartic_steps
+        ctx.kernel_stats(reset=True)
+        ctx.set_profiling(True)
+        ctx.register(*t, prm)
+        ctx.set_profiling(False)
+        kq = ctx.kernel_stats(reset=True)
+        q_ach = QUARTIC_FLOPS_PER_PAIR * kq["pairs"] / (kq["quartic_ms"] * 1e-3) / 1e12 if kq["quartic_ms"] else 0
+        conv = ctx.register(*t, params_rgbd(step_rule=rule, tol=1e-5, max_iters=200))
+        res[rule + "_rule"] = {
+            "ms_per_registration": q_el * 1e3, "iterations": 100,
+            "pose_error": {"rot_deg": rot_err_deg(oq["T"], pair.T_true), "trans_m": trans_err_m(oq["T"], pair.T_true)},
+            "quartic_kernel_ms_avg": kq["quartic_ms"] / max(1, kq["launches"]),
+            "quartic_pass_roofline": {"achieved": q_ach, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+                                      "frac": q_ach / PEAK_TFLOPS, "flops_per_pair": QUARTIC_FLOPS_PER_PAIR,
+                                      "kernel": "k_pairs<float,5,true,true>"},
+            "with_tol_1e-5": {"iters": conv["iters"], "converged": bool(conv["converged"]),
+                              "rot_deg": rot_err_deg(conv["T"], pair.T_true),
+                              "trans_m": trans_err_m(conv["T"], pair.T_true)}}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-oracle", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--n", type=int, default=30000)
     ap.add_argument("--batch", type=int, default=256, help="requests in the batched run (0: skip)")
     ap.add_argument("--quartic-steps", type=int, default=3,
-                    help="timed registrations with the quartic step rule (0: skip)")
+                    help="timed 30k registrations with the conjugate and quartic step rules (0: skip)")
     ap.add_argument("--odometry-frames", type=int, default=8,
                     help="frames of the synthetic odometry sequence (0: skip)")
-    ap.add_argument("--serving-window", type=float, default=2.0,
+    ap.add_argument("--serving-window", type=float, default=10.0,
                     help="seconds of Poisson arrivals per serving rate (0: skip)")
-    ap.add_argument("--no-dense", action="store_true", help="skip the dense-300k brute-force evaluation")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline registration, its roofline and the CPU baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the measurement, copy a MIB-MiB device buffer once (reference dispatch "
                          "of known size for hardware-counter runs)")
@@ -303,172 +489,82 @@ def main():
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    batch_clouds = gen_batch(args.batch)
-    serve_pool = gen_serving_pool(6 if args.serving_window > 0 else 0)
-    dense_cloud = None
-    if not args.no_dense:
-        with ProcessPoolExecutor(max_workers=1) as ex:
-            dense_cloud = ex.submit(_gen_dense, 3).result()
+    extra = not args.no_extra
+    batch_clouds = gen_batch(args.batch if extra else 0)
+    serve_pool = gen_serving_pool(6 if (args.serving_window > 0 and extra) else 0)
+    with ProcessPoolExecutor(max_workers=1) as ex:
+        dense_cloud, G = ex.submit(_gen_dense, 3).result()
     odo_frames = None
-    if args.odometry_frames > 1:
+    if args.odometry_frames > 1 and extra:
         from paper_1904_02266_amd import synth as _synth
         odo_frames = _synth.rgbd_sequence(args.odometry_frames, seed=9)
+    with open(GOLDEN) as f:
+        golden = json.load(f)
 
     import torch
     from paper_1904_02266_amd import Context, params_rgbd, synth
 
     dev = torch.device("cuda:0")
-    pair = synth.rgbd_pair(args.n, args.n, seed=2)
-    sx = torch.from_numpy(pair.src_xyz).to(dev)
-    sf = torch.from_numpy(pair.src_feat).to(dev)
-    tx = torch.from_numpy(pair.tgt_xyz).to(dev)
-    tf = torch.from_numpy(pair.tgt_feat).to(dev)
+    pair = synth.CloudPair(*dense_cloud, T_true=G)
+    t = [torch.from_numpy(a).to(dev) for a in dense_cloud]
     torch.cuda.synchronize()
     ctx = Context(0)
     prm = params_rgbd()
 
-    for _ in range(args.warmup):
-        ctx.register(sx, sf, tx, tf, prm)
-    torch.cuda.synchronize()
+    # headline: the dense registration, timed region = the registrations alone
+    r = time_registrations(ctx, t, prm, args.steps, args.warmup)
+    out, elapsed, lat, ks = r["out"], r["elapsed"], r["lat"], r["ks"]
 
-    # timed region: the registrations alone
-    lat = []
-    pairs = 0
-    examined = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        out = ctx.register(sx, sf, tx, tf, prm)
-        lat.append((time.perf_counter() - s0) * 1e3)
-        pairs += out["pairs_within"]
-        examined += out["pairs_examined"]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    # the same registrations again with HIP events around every kernel launch
-    # (on the launch stream): average duration of the pair kernel
-    ctx.kernel_stats(reset=True)
-    ctx.set_profiling(True)
-    torch.cuda.synchronize()
-    te0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.register(sx, sf, tx, tf, prm)
-    torch.cuda.synchronize()
-    elapsed_ev = time.perf_counter() - te0
-    ctx.set_profiling(False)
-    ks = ctx.kernel_stats(reset=True)
-
-    kern_ms_avg = ks["ms"] / max(1, ks["launches"])
-    achieved = FLOPS_PER_PAIR * ks["pairs"] / (ks["ms"] * 1e-3) / 1e12 if ks["ms"] > 0 else 0.0
-    E = out["T"][:3, :3] @ pair.T_true[:3, :3].T
-    rot_err_deg = float(np.degrees(np.arccos(np.clip((np.trace(E) - 1) / 2, -1, 1))))
-    trans_err = float(np.linalg.norm(out["T"][:3, 3] - E @ pair.T_true[:3, 3]))
-
-    # teacher-forced oracle sample: CPU baseline timing and parity at one
-    # iteration of each length-scale stage plus the last one
-    cpu = None
-    parity = None
+    cpu = parity = None
     if not args.no_oracle:
-        import oracle
-        prm_t = params_rgbd(trace=True)
-        ctx.register(sx, sf, tx, tf, prm_t)
-        tr = ctx.trace()
-        a2 = oracle.mean_sqnorm(pair.src_xyz)
-        nth = oracle.default_threads()
-        its = list(range(100))
-        t_cpu = 0.0
-        p_cpu = 0
-        worst = 0.0
-        for k in its:
-            Tk = np.eye(4) if k == 0 else tr[k - 1, 10:26].reshape(4, 4)
-            c0 = time.perf_counter()
-            r = oracle.eval(pair.src_xyz, pair.src_feat, pair.tgt_xyz, pair.tgt_feat, Tk, ell=tr[k, 8],
-                            kappa=3.0, a2=a2, nthreads=nth)
-            t_cpu += time.perf_counter() - c0
-            p_cpu += r["within"]
-            g = tr[k, :7]
-            err = max([abs(g[0] - r["g"][0]) / r["g"][0]] +
-                      [abs(g[q] - r["g"][q]) / r["abs"][q] for q in range(1, 7)])
-            worst = max(worst, err)
-        cpu = {"value": p_cpu / t_cpu, "unit": "pair-evals/s", "cores": nth, "kind": "oracle",
-               "sample": f"{len(its)} FP64 oracle evaluations (brute-force enumeration with the cutoff test) "
-                         f"at the GPU trajectory's poses of iterations {its}, {t_cpu:.1f} s"}
-        parity = {"max_rel_err": worst, "criterion": "F rel; omega,v abs/sum|terms|", "iters": its}
+        cpu, parity = oracle_sample(pair, golden, ctx, t)
 
-    quart = None
-    if args.quartic_steps > 0:
-        prm_q = params_rgbd(step_rule="quartic")
-        ctx.register(sx, sf, tx, tf, prm_q)  # warm-up
-        torch.cuda.synchronize()
-        qp = 0
-        q0 = time.perf_counter()
-        for _ in range(args.quartic_steps):
-            oq = ctx.register(sx, sf, tx, tf, prm_q)
-            qp += oq["pairs_within"]
-        torch.cuda.synchronize()
-        q_el = time.perf_counter() - q0
-        ctx.kernel_stats(reset=True)
-        ctx.set_profiling(True)
-        ctx.register(sx, sf, tx, tf, prm_q)
-        ctx.set_profiling(False)
-        kq = ctx.kernel_stats(reset=True)
-        Eq = oq["T"][:3, :3] @ pair.T_true[:3, :3].T
-        q_ach = QUARTIC_FLOPS_PER_PAIR * kq["pairs"] / (kq["quartic_ms"] * 1e-3) / 1e12 if kq["quartic_ms"] > 0 else 0
-        quart = {"ms_per_registration": q_el * 1e3 / args.quartic_steps,
-                 "pair_evals_per_s": qp / q_el,
-                 "note": "pair-evals count the gradient pass; the quartic pass visits the same pairs again",
-                 "quartic_kernel_ms_avg": kq["quartic_ms"] / max(1, kq["launches"]),
-                 "gradient_kernel_ms_avg": kq["ms"] / max(1, kq["launches"]),
-                 "roofline": {"bound": "alu", "achieved": q_ach, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                              "frac": q_ach / PEAK_TFLOPS, "flops_per_pair": QUARTIC_FLOPS_PER_PAIR,
-                              "kernel": "k_pairs<float,5,true,true>"},
-                 "pose_error": {"rot_deg": float(np.degrees(np.arccos(np.clip((np.trace(Eq) - 1) / 2, -1, 1)))),
-                                "trans_m": float(np.linalg.norm(oq["T"][:3, 3] - Eq @ pair.T_true[:3, 3]))}}
-
-    batch = batched_both(batch_clouds) if batch_clouds else None
-
-    # the same single registration with every pair term in FP64
+    # the same registration with every pair term in FP64
     prm64 = params_rgbd(precision="fp64")
-    ctx.register(sx, sf, tx, tf, prm64)
+    ctx.register(*t, prm64)
     torch.cuda.synchronize()
     f0 = time.perf_counter()
-    n64 = max(1, args.steps // 4)
+    n64 = 2
     for _ in range(n64):
-        o64 = ctx.register(sx, sf, tx, tf, prm64)
+        o64 = ctx.register(*t, prm64)
     torch.cuda.synchronize()
     f_el = (time.perf_counter() - f0) / n64
     fp64_path = {"ms_per_registration": f_el * 1e3, "pair_evals_per_s": o64["pairs_within"] / f_el,
-                 "speedup_of_mixed": f_el * 1e3 / (elapsed * 1e3 / args.steps),
-                 "pose_diff_vs_mixed": {"rot_deg": float(np.degrees(np.arccos(np.clip(
-                     (np.trace(o64["T"][:3, :3] @ out["T"][:3, :3].T) - 1) / 2, -1, 1)))),
-                     "trans_m": float(np.linalg.norm(o64["T"][:3, 3] - out["T"][:3, 3]))}}
+                 "speedup_of_mixed": f_el / (elapsed / args.steps),
+                 "pose_diff_vs_mixed": {"rot_deg": rot_err_deg(o64["T"], out["T"]),
+                                        "trans_m": float(np.linalg.norm(o64["T"][:3, 3] - out["T"][:3, 3]))}}
+    To = np.array(golden["trace"])[99, 10:26].reshape(4, 4)
+    vs_oracle = {"rot_deg": rot_err_deg(out["T"], To), "trans_m": float(np.linalg.norm(out["T"][:3, 3] - To[:3, 3])),
+                 "fp64_rot_deg": rot_err_deg(o64["T"], To),
+                 "fp64_trans_m": float(np.linalg.norm(o64["T"][:3, 3] - To[:3, 3]))}
 
-    serve = serving(serve_pool, window_s=args.serving_window) if serve_pool else None
-    dense = dense_bruteforce(dense_cloud) if dense_cloud is not None else None
-    fe = frontend_vga(odo_frames[0]) if odo_frames else None
-    c1 = planes_c1() if not args.no_dense else None
-
-    odo = None
-    if odo_frames:
-        from paper_1904_02266_amd import odometry, params_table1
-        odometry.run_on_device(ctx, odo_frames[:2], params_table1())  # warm-up
-        torch.cuda.synchronize()
-        o0 = time.perf_counter()
-        res = odometry.run_on_device(ctx, odo_frames, params_table1())
-        torch.cuda.synchronize()
-        o_el = time.perf_counter() - o0
-        odo = {"frames": len(odo_frames), "frames_per_s": (len(odo_frames) - 1) / o_el,
-               "ms_per_frame": o_el * 1e3 / (len(odo_frames) - 1),
-               "params": "Table 1 (quartic step, value floor 1e-3, ell 0.15/0.10/0.06/0.03, thresholds 1e-5/5e-5)",
-               "per_frame": "device front end of the new frame (30,000 points) + registration; frames uploaded "
-                            "from host memory each step (the images' PCIe copy is inside the timing)",
-               "iterations": res.iterations, "relative_error_cdf": res.cdf(),
-               "sequence": "synthetic, 640x480, 1 deg / 2 cm per frame, 1% depth noise, seed 9"}
+    c2 = batch = serve = dense = fe = c1 = odo = None
+    if extra:
+        c2 = rgbd30k(ctx, synth.rgbd_pair(30000, 30000, seed=2), max(4, args.steps), args.quartic_steps)
+        batch = batched_both(batch_clouds) if batch_clouds else None
+        serve = serving(serve_pool, window_s=args.serving_window) if serve_pool else None
+        dense = dense_bruteforce(dense_cloud)
+        fe = frontend_vga(odo_frames[0]) if odo_frames else None
+        c1 = planes_c1()
+        if odo_frames:
+            from paper_1904_02266_amd import odometry, params_table1
+            odometry.run_on_device(ctx, odo_frames[:2], params_table1())  # warm-up
+            torch.cuda.synchronize()
+            o0 = time.perf_counter()
+            res = odometry.run_on_device(ctx, odo_frames, params_table1())
+            torch.cuda.synchronize()
+            o_el = time.perf_counter() - o0
+            odo = {"frames": len(odo_frames), "frames_per_s": (len(odo_frames) - 1) / o_el,
+                   "ms_per_frame": o_el * 1e3 / (len(odo_frames) - 1),
+                   "params": "Table 1 (quartic step, value floor 1e-3, ell 0.15/0.10/0.06/0.03, thresholds 1e-5/5e-5)",
+                   "per_frame": "device front end of the new frame (30,000 points) + registration; frames uploaded "
+                                "from host memory each step (the images' PCIe copy is inside the timing)",
+                   "iterations": res.iterations, "relative_error_cdf": res.cdf(),
+                   "sequence": "synthetic, 640x480, 1 deg / 2 cm per frame, 1% depth noise, seed 9"}
 
     line = {
         "metric": METRIC,
-        "value": pairs / elapsed,
+        "value": r["pairs"] / elapsed,
         "unit": "pair-evals/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -479,39 +575,37 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"rgbd-{args.n // 1000}k: 640x480 synthetic RGB-D frame pair, {args.n} "
-                               "semi-dense points per frame, 5 label channels, cutoff 3 ell with voxel grid, "
-                               "ell 0.2->0.05 m over 4x25 iterations",
-                   "points_src": int(pair.src_xyz.shape[0]), "points_tgt": int(pair.tgt_xyz.shape[0]),
+        "config": {"workload": "dense-300k: 640x480 synthetic RGB-D frame pair, a seeded random subset of 300,000 "
+                               "valid pixels per frame, 5 label channels, cutoff 3 ell with voxel grid, "
+                               "ell 0.2->0.05 m over 4x25 iterations, fixed step",
+                   "points_src": int(dense_cloud[0].shape[0]), "points_tgt": int(dense_cloud[2].shape[0]),
                    "iterations": 100, "precision": "fp32 pair terms, kahan fp32 partials, fp64 reduce+step"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS, "traffic": measured_traffic(),
-                     "kernel": "k_pairs<float,5,true,false>", "kernel_ms_avg": kern_ms_avg,
-                     "launches": ks["launches"], "flops_per_pair": FLOPS_PER_PAIR,
-                     "prepare_kernel_ms_avg": ks["prepare_ms"] / max(1, ks["launches"]),
-                     "instrumented_ms_per_step": elapsed_ev * 1e3 / args.steps},
+        "roofline": roofline_of(ks, measured_traffic()),
         "cpu_baseline": cpu,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "pairs_per_registration": pairs / args.steps,
-        "pairs_examined_per_registration": examined / args.steps,
-        "pose_error": {"rot_deg": rot_err_deg, "trans_m": trans_err},
+        "pairs_per_registration": r["pairs"] / args.steps,
+        "pairs_examined_per_registration": r["examined"] / args.steps,
+        "within_cutoff_fraction_of_examined": r["pairs"] / max(1, r["examined"]),
+        "instrumented_ms_per_step": r["elapsed_ev"] * 1e3 / args.steps,
+        "pose_error": {"rot_deg": rot_err_deg(out["T"], G), "trans_m": trans_err_m(out["T"], G)},
+        "final_pose_vs_oracle": vs_oracle,
         "parity": parity,
         "fp64_path": fp64_path,
-        "quartic_rule": quart,
-        "odometry": odo,
+        "rgbd_30k": c2,
         "batched": batch,
         "serving": serve,
-        "dense_300k_bruteforce": dense,
+        "dense_300k_bruteforce_eval": dense,
         "frontend_vga": fe,
         "planes_2k": c1,
+        "odometry": odo,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
     if args.copy_calibration > 0:
         a = torch.ones(args.copy_calibration * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
+        bb = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)
+        bb.copy_(a)
         torch.cuda.synchronize()
 
 

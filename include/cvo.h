@@ -36,6 +36,17 @@
  *       exponent's exact Taylor coefficients (alpha .. eps of the moving
  *       target exp(-t Xi) z~; the printed gamma, delta, eps omit the
  *       exponential's factorials and signs) and the paper's g^1..g^4.
+ *     CVO_STEP_CONJUGATE  the paper's line search of CVO_STEP_QUARTIC taken
+ *       along conjugate directions instead of the gradient itself (a project
+ *       rule): d = g + beta d_prev with the Polak-Ribiere
+ *       beta = max(0, <g, g - g_prev> / <g_prev, g_prev>), inner products in
+ *       the metric a^2 omega.eta + b^2 v.u (Sec. IV-B), g the gradient in the
+ *       subgroup dof_mask selects; d restarts from g at the first iteration
+ *       of every length-scale stage, every 6 steps and whenever
+ *       <g, d> <= 0.  The pose moves by Exp(-tau d); the trace and result
+ *       still report the gradient.  The gradient flow's fixed step contracts
+ *       the slowest direction of the RGB-D workloads by ~1% per iteration;
+ *       conjugate directions reach |tau d| < 1e-5 within a stage.
  *   - With cutoff_mult = kappa > 0 a pair contributes only if
  *     |x_i - z~_j| <= kappa * ell (the paper sparsifies small kernel values,
  *     Section VII-B; here in distance form); kappa = 0 sums all pairs.
@@ -44,9 +55,13 @@
  *   - Host inputs (on_device = 0) are copied before the call returns (or
  *     before cvo_submit returns).
  *   - Device inputs (on_device = 1) must be device pointers on the context's
- *     device.  They are read on the context's stream and borrowed until the
- *     call returns (cvo_eval, cvo_register) or until cvo_poll reports a
- *     terminal status for the ticket (cvo_submit).
+ *     device.  cvo_eval / cvo_register read them on the context's stream (see
+ *     cvo_set_stream), ordered after the work already queued there; they are
+ *     borrowed until the call returns.  cvo_submit reads them later on the
+ *     scheduler's own stream, with no ordering against any caller stream: the
+ *     data must be complete when cvo_submit is called (synchronize the stream
+ *     that wrote them first), and stay valid and unmodified until cvo_poll
+ *     reports a terminal status for the ticket.
  *   - All outputs go to caller buffers; the context owns all device state.
  *   - cvo_eval / cvo_register serialise on the context.  cvo_submit and
  *     cvo_poll are thread-safe.
@@ -77,7 +92,7 @@ enum {
 };
 
 enum { CVO_FP32_KAHAN = 0, CVO_FP64 = 1 };
-enum { CVO_STEP_FIXED = 0, CVO_STEP_QUARTIC = 1 };
+enum { CVO_STEP_FIXED = 0, CVO_STEP_QUARTIC = 1, CVO_STEP_CONJUGATE = 2 };
 
 /* One labelled point cloud (Section III-A: points x_i with labels l(x_i) in R^feat_dim). */
 typedef struct {
@@ -100,11 +115,13 @@ typedef struct {
   const int32_t* stage_iters; /* [n_stages-1] iterations spent in each stage but the last (>= 1) */
   const double* stage_ell;  /* [n_stages] length-scale of each stage (> 0) */
   int32_t max_iters;        /* iteration cap, >= 1 */
-  double tol;               /* stop once the last stage is reached and |tau (omega, v)|_2 < tol */
+  double tol;               /* stop once the last stage is reached and the applied twist
+                               |tau d|_2 < tol (d = (omega, v), or the conjugate direction) */
   int32_t precision;        /* CVO_FP32_KAHAN (FP32 pair terms, Kahan FP32 partials, FP64
                                reduction and step) or CVO_FP64 (every pair term in FP64) */
   int32_t trace;            /* 1: keep the per-iteration trace (cvo_trace) */
-  int32_t step_rule;        /* CVO_STEP_FIXED or CVO_STEP_QUARTIC (see the step length above) */
+  int32_t step_rule;        /* CVO_STEP_FIXED, CVO_STEP_QUARTIC or CVO_STEP_CONJUGATE (see the step
+                               length above) */
   double grad_tol;          /* also stop once the last stage is reached and |(omega, v)|_2 < grad_tol
                                (Table 1's gradient-norm threshold; 0: off) */
   double kernel_floor;      /* > 0: sparsify by kernel value as in the TUM experiment (Table 1):
@@ -141,6 +158,7 @@ typedef struct {
   double wall_ms;           /* host time from call (or submission) to completion */
   uint64_t pairs_within;    /* pairs inside the cutoff, summed over iterations */
   uint64_t pairs_examined;  /* candidate pairs tested, summed over iterations */
+  uint64_t device_bytes;    /* device memory the request held (set-up and iteration buffers) */
 } cvo_result;
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device
@@ -222,13 +240,27 @@ typedef struct {
   int64_t failed;           /* of those, finished with a negative status */
   uint64_t hbm_in_use;      /* device bytes held by admitted requests */
   uint64_t hbm_budget;      /* the admission budget (bytes) */
+  uint64_t hbm_peak;        /* the largest hbm_in_use since cvo_create */
 } cvo_serving_counters;
 int cvo_serving_stats(cvo_ctx* ctx, cvo_serving_counters* out);
 
-/* Copy the per-iteration trace of the last cvo_register call (ticket 0) into
- * buf[iters][26]: F, omega[3], v[3], tau, ell, pairs within the cutoff, then
- * the pose T (row-major 4x4) after that iteration's step.  Returns the number
- * of rows written (<= cap) or a negative code. */
+/* Bound the submission queue (requests submitted and not yet admitted):
+ * cvo_submit returns CVO_EBUSY while max_pending requests wait.  Default
+ * 65536; 0 refuses every submission.  Admission itself is bounded by the
+ * context's slots and its device-memory budget: a request is charged its set-up
+ * buffers exactly and its iteration buffers by estimate until its ingest has
+ * counted its target clusters, then exactly; one that no longer fits beside
+ * the running requests returns to the head of the queue. */
+int cvo_set_queue_limit(cvo_ctx* ctx, int64_t max_pending);
+
+/* Copy a per-iteration trace into buf[iters][26]: F, omega[3], v[3], tau,
+ * ell, pairs within the cutoff, then the pose T (row-major 4x4) after that
+ * iteration's step (with params->trace = 1).  ticket 0: the last cvo_register
+ * call.  A batched ticket: its trace once the request has finished, before
+ * and after cvo_poll (the traces of the 1024 most recently polled tickets are
+ * kept); CVO_PENDING while it runs.  Returns the number of rows written
+ * (<= cap), CVO_PENDING, or a negative code (CVO_ENOTFOUND: unknown ticket,
+ * or a ticket polled long ago). */
 int cvo_trace(cvo_ctx* ctx, uint64_t ticket, double* buf, int32_t cap);
 
 /* Event timing of the kernels of each iteration (the per-cluster

@@ -196,7 +196,7 @@ def quartic_step(coef):
 
 
 TRACE_COLS = 26
-STEP_RULES = {"fixed": 0, "quartic": 1}
+STEP_RULES = {"fixed": 0, "quartic": 1, "conjugate": 2}
 
 
 def register(src_xyz, src_feat, tgt_xyz, tgt_feat, *, sigma=0.1, feat_scale=0.2, a2=None, b2=1.0,
@@ -206,8 +206,11 @@ def register(src_xyz, src_feat, tgt_xyz, tgt_feat, *, sigma=0.1, feat_scale=0.2,
     trace[iters,26], abs[iters,7] (sums of |terms| per iteration), rc).
     step_rule "fixed": tau = eta ell^2 / F; "quartic": the maximiser of the
     fourth-order model (eq. fourth), falling back to the fixed rule when the
-    model has no maximum on t > 0.  grid=True (kappa > 0) evaluates through
-    the oracle's grid enumeration (same pair set as the brute force)."""
+    model has no maximum on t > 0; "conjugate": the same line search along
+    Polak-Ribiere conjugate directions (restarts at each stage, every 6
+    steps, and on a non-ascent direction).  grid=True (kappa > 0) evaluates
+    through the oracle's grid enumeration (same pair set as the brute
+    force)."""
     L = _load()
     x = _f32(src_xyz, 3)
     fd = np.asarray(src_feat).shape[1]

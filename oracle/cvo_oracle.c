@@ -595,10 +595,19 @@ int cvo_oracle_quartic_step(const double A[5], double* t_out) {
  *   F <= 1e-300 -> no overlap (error)
  *   xi    = (omega, v) with the components outside dof_mask set to zero (the
  *           flow on the subgroup of SE(3) the mask selects; 0 = all six)
- *   tau = eta ell^2 / F (step_rule 0), or (step_rule 1) the maximiser of the
- *         quartic model along xi when it has one on t > 0, else eta ell^2 / F;
- *   h <- h exp(tau xi)
- *   stop when the last stage is reached and |tau xi|_2 < tol (the
+ *   d     = the search direction: xi itself (step rules 0 and 1), or
+ *           (step_rule 2, conjugate directions, a project rule) xi + beta d'
+ *           with d' the previous iteration's direction and the
+ *           Polak-Ribiere beta = max(0, <xi, xi - xi'>_M / <xi', xi'>_M),
+ *           xi' the previous iteration's xi and <p, q>_M =
+ *           a^2 p_w.q_w + b^2 p_v.q_v the metric of Sec. IV-B; d = xi instead
+ *           at the first iteration of each stage, after 6 directions since
+ *           the last such restart, and whenever <xi, d>_M <= 0
+ *   tau = eta ell^2 / F (step_rule 0), or (step_rules 1, 2) the maximiser of
+ *         the quartic model along d when it has one on t > 0, else
+ *         eta ell^2 / F;
+ *   h <- h exp(tau d)
+ *   stop when the last stage is reached and |tau d|_2 < tol (the
  *   transformation threshold of Table 1) or |xi|_2 < grad_tol (the
  *   gradient-norm threshold); a zero threshold is off.
  * Stage s spans stage_iters[s] iterations; the last stage runs to max_iters.
@@ -629,6 +638,10 @@ int cvo_oracle_register(int n, const float* x, const float* lx, int m, const flo
     double h[16];
     rigid_inverse(T0, h);
     int stage = 0, stage_start = 0, k = 0, conv = 0, rc = OR_OK;
+    /* conjugate directions: the previous xi and d, directions since the
+       last restart, and the stage they belong to */
+    double xi_prev[6] = {0, 0, 0, 0, 0, 0}, d_prev[6] = {0, 0, 0, 0, 0, 0};
+    int since_restart = 0, d_stage = -1;
     for (k = 0; k < max_iters; k++) {
         while (stage < n_stages - 1 && k - stage_start >= stage_iters[stage]) {
             stage_start += stage_iters[stage];
@@ -646,20 +659,47 @@ int cvo_oracle_register(int n, const float* x, const float* lx, int m, const flo
            projection of the full gradient, here the masked components */
         double xi[6];
         for (int q = 0; q < 6; q++) xi[q] = ((dof_mask >> q) & 1) ? g[1 + q] : 0.0;
+        double d[6];
+        for (int q = 0; q < 6; q++) d[q] = xi[q];
+        if (step_rule == 2) {
+            int restart = since_restart == 0 || since_restart >= 6 || d_stage != stage;
+            if (!restart) {
+                double num = 0.0, den = 0.0;
+                for (int q = 0; q < 6; q++) {
+                    const double wq = q < 3 ? a2 : b2;
+                    num += wq * xi[q] * (xi[q] - xi_prev[q]);
+                    den += wq * xi_prev[q] * xi_prev[q];
+                }
+                const double beta = (den > 0.0 && num > 0.0) ? num / den : 0.0;
+                double slope = 0.0;
+                for (int q = 0; q < 6; q++) {
+                    d[q] = xi[q] + beta * d_prev[q];
+                    slope += (q < 3 ? a2 : b2) * xi[q] * d[q];
+                }
+                if (!(slope > 0.0)) restart = 1;
+            }
+            if (restart) {
+                for (int q = 0; q < 6; q++) d[q] = xi[q];
+                since_restart = 0;
+            }
+            since_restart++;
+            d_stage = stage;
+            for (int q = 0; q < 6; q++) { xi_prev[q] = xi[q]; d_prev[q] = d[q]; }
+        }
         double tau = eta * ell * ell / g[0];
-        if (step_rule == 1) {
-            /* quartic model along xi at the current pose */
+        if (step_rule == 1 || step_rule == 2) {
+            /* quartic model along d at the current pose */
             double Tcur[16], A[5], Aa[5], tq;
             rigid_inverse(h, Tcur);
-            rc = cvo_oracle_quartic(n, x, lx, m, z, lz, fd, sigma, feat_scale, ell, kappa, Tcur, xi, xi + 3,
+            rc = cvo_oracle_quartic(n, x, lx, m, z, lz, fd, sigma, feat_scale, ell, kappa, Tcur, d, d + 3,
                                     nthreads, A, Aa);
             if (rc != OR_OK) break;
             if (cvo_oracle_quartic_step(A, &tq)) tau = tq;
         }
-        newstep(h, xi, xi + 3, tau);
+        newstep(h, d, d + 3, tau);
         double sq = 0.0, gq = 0.0;
         for (int q = 0; q < 6; q++) {
-            sq += (tau * xi[q]) * (tau * xi[q]);
+            sq += (tau * d[q]) * (tau * d[q]);
             gq += xi[q] * xi[q];
         }
         if (trace) {

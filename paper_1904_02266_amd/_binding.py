@@ -28,7 +28,8 @@ CVO_FP32_KAHAN = 0
 CVO_FP64 = 1
 CVO_STEP_FIXED = 0
 CVO_STEP_QUARTIC = 1
-STEP_RULES = {"fixed": CVO_STEP_FIXED, "quartic": CVO_STEP_QUARTIC}
+CVO_STEP_CONJUGATE = 2
+STEP_RULES = {"fixed": CVO_STEP_FIXED, "quartic": CVO_STEP_QUARTIC, "conjugate": CVO_STEP_CONJUGATE}
 # subgroups of SE(3) for Params.dof_mask (bits: rotation x, y, z, translation x, y, z)
 DOF_SE3, DOF_SE2, DOF_SO3, DOF_R3 = 0x3F, 0x1C, 0x07, 0x38
 TRACE_COLS = 26
@@ -53,7 +54,8 @@ class cvo_params(ctypes.Structure):
 
 class cvo_serving_counters(ctypes.Structure):
     _fields_ = [("pending", ctypes.c_int64), ("active", ctypes.c_int64), ("completed", ctypes.c_int64),
-                ("failed", ctypes.c_int64), ("hbm_in_use", ctypes.c_uint64), ("hbm_budget", ctypes.c_uint64)]
+                ("failed", ctypes.c_int64), ("hbm_in_use", ctypes.c_uint64), ("hbm_budget", ctypes.c_uint64),
+                ("hbm_peak", ctypes.c_uint64)]
 
 
 class cvo_rgbd_frame(ctypes.Structure):
@@ -68,13 +70,14 @@ class cvo_result(ctypes.Structure):
                 ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("F", ctypes.c_double), ("omega", ctypes.c_double * 3), ("v", ctypes.c_double * 3),
                 ("gpu_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
-                ("pairs_within", ctypes.c_uint64), ("pairs_examined", ctypes.c_uint64)]
+                ("pairs_within", ctypes.c_uint64), ("pairs_examined", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64)]
 
     def as_dict(self):
         return dict(status=self.status, iters=self.iters, converged=bool(self.converged), F=self.F,
                     omega=np.array(self.omega[:]), v=np.array(self.v[:]), gpu_ms=self.gpu_ms,
                     wall_ms=self.wall_ms, pairs_within=int(self.pairs_within),
-                    pairs_examined=int(self.pairs_examined))
+                    pairs_examined=int(self.pairs_examined), device_bytes=int(self.device_bytes))
 
 
 _lib = None
@@ -115,13 +118,15 @@ def load():
     L.cvo_quartic_step.argtypes = [P(dbl), P(dbl)]
     L.cvo_frontend.argtypes = [vp, P(cvo_rgbd_frame), i32, vp, vp, P(i32)]
     L.cvo_serving_stats.argtypes = [vp, P(cvo_serving_counters)]
+    L.cvo_set_queue_limit.argtypes = [vp, ctypes.c_int64]
     L.cvo_strerror.argtypes = [ctypes.c_int]
     L.cvo_strerror.restype = ctypes.c_char_p
     L.cvo_last_error.argtypes = [vp]
     L.cvo_last_error.restype = ctypes.c_char_p
     for name in ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
                  "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
-                 "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend", "cvo_serving_stats"):
+                 "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend", "cvo_serving_stats",
+                 "cvo_set_queue_limit"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -130,7 +135,7 @@ def load():
 EXPORTED = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
             "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
             "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend", "cvo_serving_stats",
-            "cvo_strerror", "cvo_last_error")
+            "cvo_set_queue_limit", "cvo_strerror", "cvo_last_error")
 
 
 class CvoError(RuntimeError):
@@ -394,16 +399,28 @@ class Context:
         out["T"] = Tout.reshape(4, 4)
         return out
 
-    def trace(self, cap=100000):
+    def trace(self, cap=100000, ticket=0):
+        """The per-iteration trace of the last register call (ticket 0) or of a
+        finished batched ticket; None while that ticket is still running."""
         buf = np.zeros((cap, TRACE_COLS))
-        rows = self._check(self.L.cvo_trace(self.h, 0, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cap),
-                           "cvo_trace")
+        rows = self._check(self.L.cvo_trace(self.h, ticket, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            cap), "cvo_trace")
+        if rows == CVO_PENDING and ticket != 0:
+            return None
         return buf[:rows]
+
+    def set_queue_limit(self, max_pending):
+        self._check(self.L.cvo_set_queue_limit(self.h, int(max_pending)), "cvo_set_queue_limit")
 
     def submit(self, src_xyz, src_feat, tgt_xyz, tgt_feat, params: Params, T0=None):
         """Returns (ticket, keepalive); keep `keepalive` until the ticket is polled
-        when passing device tensors (they are borrowed)."""
+        when passing device tensors (they are borrowed).  Device tensors are read
+        later on the scheduler's stream: torch's current stream is synchronized
+        first, so conversions queued on it (dtype, contiguity) are complete."""
         s, t = _Cloud(src_xyz, src_feat), _Cloud(tgt_xyz, tgt_feat)
+        if s.on_device or t.on_device:
+            import torch
+            torch.cuda.current_stream(self.device).synchronize()
         p, keep = params.to_c()
         Ta, Tp = _pose(np.eye(4) if T0 is None else T0)
         tk = ctypes.c_uint64()

@@ -58,6 +58,7 @@ struct Request {
   const float *sx = nullptr, *sfeat = nullptr, *tx = nullptr, *tfeat = nullptr;
   std::vector<float> hsx, hsf, htx, htf;  // host copies (submit with host inputs)
   int nclus = 0;   // target clusters (read back after ingest)
+  size_t need_bytes = 0;  // exact device bytes once known (a request sent back to the queue)
   // device arenas: set-up data (A) and per-cluster iteration buffers (B)
   char* arena = nullptr;
   size_t arena_bytes = 0;
@@ -179,11 +180,16 @@ LayoutB plan_b(const Request& q, int nclus) {
   return L;
 }
 
-// conservative device-memory estimate of a request before its cluster count is known
+// Device memory of a request for admission.  Arena A is exact; arena B
+// depends on the number of target clusters, known only after the ingest, and
+// is estimated from ~2 clusters per 64 targets (spatially coherent clouds).
+// Once the ingest has run, the scheduler charges the exact size (need_bytes)
+// and sends a request whose exact size does not fit back to the queue.
 size_t footprint(const Request& q) {
+  if (q.need_bytes) return q.need_bytes;
   const Layout L = plan(q);
-  const int nclus_max = (q.m + kWave - 1) / kWave * 2 + 64;
-  return L.total + plan_b(q, std::min(nclus_max, q.m)).total;
+  const int nclus_est = (q.m + kWave - 1) / kWave * 2 + 64;
+  return L.total + plan_b(q, std::min(nclus_est, q.m)).total;
 }
 
 }  // namespace
@@ -280,7 +286,10 @@ struct cvo_ctx {
   size_t max_pending = 65536;
   // serving counters (under q_mu)
   int64_t st_active = 0, st_completed = 0, st_failed = 0;
-  uint64_t st_hbm_in_use = 0;
+  uint64_t st_hbm_in_use = 0, st_hbm_peak = 0;
+  // traces of polled batched tickets, newest last (cvo_trace after cvo_poll)
+  std::unordered_map<uint64_t, std::vector<double>> kept_traces;
+  std::deque<uint64_t> kept_order;
 };
 
 static int fail(cvo_ctx* c, hipError_t e, const char* what) {
@@ -321,7 +330,8 @@ static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
   if (p->n_stages > 1 && !p->stage_iters) return CVO_EINVAL;
   if (p->max_iters < 1 || !(p->tol >= 0.0)) return CVO_EINVAL;
   if (p->precision != CVO_FP32_KAHAN && p->precision != CVO_FP64) return CVO_EINVAL;
-  if (p->step_rule != CVO_STEP_FIXED && p->step_rule != CVO_STEP_QUARTIC) return CVO_EINVAL;
+  if (p->step_rule != CVO_STEP_FIXED && p->step_rule != CVO_STEP_QUARTIC && p->step_rule != CVO_STEP_CONJUGATE)
+    return CVO_EINVAL;
   if (!(p->grad_tol >= 0.0) || !(p->kernel_floor >= 0.0) || !std::isfinite(p->kernel_floor)) return CVO_EINVAL;
   if (p->dof_mask < 0 || p->dof_mask > 0x3F) return CVO_EINVAL;
   // value sparsification (Table 1): sigma^2 exp(-r^2 / (2 ell^2)) >= floor
@@ -672,7 +682,7 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
         HIPCHK(c, hipEventRecord(ev[1], s));
         HIPCHK(c, launch_pair_kernel(q.precision, q.fd, cut, c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR, s));
         HIPCHK(c, hipEventRecord(ev[2], s));
-        if (q.step_rule == kStepQuartic) {
+        if (q.step_rule != kStepFixed) {
           HIPCHK(c, launch_step(c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR, s, kPhaseGradient, false));
           HIPCHK(c, hipEventRecord(ev[3], s));
           HIPCHK(c, launch_quartic_pairs(q.precision, q.fd, cut, c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR,
@@ -703,6 +713,7 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
   HIPCHK(c, hipStreamSynchronize(s));
   fill_result(q, *hs);
   q.status = hs->status;
+  q.res.device_bytes = L.total + LB.total;
   if (q.trace_on) {
     const int rows = std::min(hs->iter, q.max_iters);
     q.trace.resize((size_t)rows * kTraceCols);
@@ -719,7 +730,7 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
       float e1 = 0.f, e2 = 0.f, e3 = 0.f;
       HIPCHK(c, hipEventElapsedTime(&e1, ev[0], ev[1]));
       HIPCHK(c, hipEventElapsedTime(&e2, ev[1], ev[2]));
-      if (q.step_rule == kStepQuartic) HIPCHK(c, hipEventElapsedTime(&e3, ev[3], ev[4]));
+      if (q.step_rule != kStepFixed) HIPCHK(c, hipEventElapsedTime(&e3, ev[3], ev[4]));
       prep += e1;
       tot += e2;
       quart += e3;
@@ -758,9 +769,10 @@ void release(Request* q, uint64_t& in_use) {
   q->arena_bytes = 0;
 }
 
-// Admit one request: allocate, ingest, read back its cluster count, allocate
-// the iteration buffers.  Returns CVO_OK or an error code for the request.
-int admit_one(cvo_ctx* c, Request* q, hipStream_t s, void* h_stage) {
+// Admit one request, first half: allocate arena A, ingest, read back the
+// cluster count.  *exact receives the request's exact device bytes (arenas A
+// and B).  Returns CVO_OK or an error code for the request.
+int admit_ingest(cvo_ctx* c, Request* q, hipStream_t s, void* h_stage, size_t* exact) {
   const Layout L = plan(*q);
   if (hipMalloc(&q->arena, L.total) != hipSuccess) {
     q->arena = nullptr;
@@ -774,11 +786,20 @@ int admit_one(cvo_ctx* c, Request* q, hipStream_t s, void* h_stage) {
     return CVO_EDEVICE;
   if (hs->done) return hs->status ? hs->status : CVO_EINVAL;
   q->nclus = hs->nclus;
+  *exact = L.total + plan_b(*q, q->nclus).total;
+  return CVO_OK;
+}
+
+// Second half: allocate the iteration buffers (arena B) and fill the
+// request's device constants.
+int admit_finish(cvo_ctx* c, Request* q, hipStream_t s) {
+  const Layout L = plan(*q);
   const LayoutB LB = plan_b(*q, q->nclus);
   if (hipMalloc(&q->arena_b, LB.total) != hipSuccess) {
     q->arena_b = nullptr;
     return CVO_ENOMEM;
   }
+  q->res.device_bytes = L.total + LB.total;
   return finish_setup(c, *q, L, LB, s);
 }
 
@@ -823,9 +844,29 @@ void scheduler(cvo_ctx* c) {
       }
       c->st_active = (int64_t)(active.size() + admit.size());
       c->st_hbm_in_use = in_use;
+      c->st_hbm_peak = std::max(c->st_hbm_peak, (uint64_t)in_use);
     }
+    std::vector<Request*> requeue;
     for (Request* q : admit) {
-      const int rc = admit_one(c, q, s, h_stage);
+      size_t exact = 0;
+      int rc = admit_ingest(c, q, s, h_stage, &exact);
+      if (rc == CVO_OK) {
+        // charge the exact size; a request that no longer fits beside the
+        // running ones waits in the queue with its exact size (its ingest is
+        // redone on admission), one that cannot fit at all fails
+        in_use = in_use - q->arena_bytes + exact;
+        q->arena_bytes = exact;
+        q->need_bytes = exact;
+        if (c->budget && exact > c->budget) {
+          rc = CVO_ENOMEM;
+        } else if (c->budget && in_use > c->budget && !(active.empty() && q == admit.front())) {
+          release(q, in_use);
+          requeue.push_back(q);
+          continue;
+        } else {
+          rc = admit_finish(c, q, s);
+        }
+      }
       if (rc != CVO_OK) {
         release(q, in_use);
         complete(c, q, rc);
@@ -835,8 +876,10 @@ void scheduler(cvo_ctx* c) {
     }
     {
       std::lock_guard<std::mutex> g(c->q_mu);
+      for (auto it = requeue.rbegin(); it != requeue.rend(); ++it) c->pending.push_front(*it);
       c->st_active = (int64_t)active.size();
       c->st_hbm_in_use = in_use;
+      c->st_hbm_peak = std::max(c->st_hbm_peak, (uint64_t)in_use);
     }
     if (active.empty()) continue;
 
@@ -1246,6 +1289,14 @@ int cvo_serving_stats(cvo_ctx* c, cvo_serving_counters* out) {
   out->failed = c->st_failed;
   out->hbm_in_use = c->st_hbm_in_use;
   out->hbm_budget = c->budget;
+  out->hbm_peak = c->st_hbm_peak;
+  return CVO_OK;
+}
+
+int cvo_set_queue_limit(cvo_ctx* c, int64_t max_pending) {
+  if (!c || max_pending < 0) return CVO_EINVAL;
+  std::lock_guard<std::mutex> g(c->q_mu);
+  c->max_pending = (size_t)max_pending;
   return CVO_OK;
 }
 
@@ -1266,20 +1317,45 @@ int cvo_poll(cvo_ctx* c, uint64_t ticket, int32_t wait_us, double T_out[16], cvo
   if (T_out) memcpy(T_out, q->T_out, sizeof(q->T_out));
   if (res) *res = q->res;
   const int st = q->status;
+  if (q->trace_on) {
+    constexpr size_t kKeptTraces = 1024;
+    c->kept_traces[ticket] = std::move(q->trace);
+    c->kept_order.push_back(ticket);
+    while (c->kept_order.size() > kKeptTraces) {
+      c->kept_traces.erase(c->kept_order.front());
+      c->kept_order.pop_front();
+    }
+  }
   c->tickets.erase(it);
   delete q;
   return st;
 }
 
+static int copy_trace(const std::vector<double>& tr, double* buf, int32_t cap) {
+  const int rows = (int)(tr.size() / kTraceCols);
+  const int w = std::min(rows, (int)cap);
+  if (w > 0) memcpy(buf, tr.data(), (size_t)w * kTraceCols * 8);
+  return w;
+}
+
 int cvo_trace(cvo_ctx* c, uint64_t ticket, double* buf, int32_t cap) {
   if (!c || cap < 0 || (cap > 0 && !buf)) return CVO_EINVAL;
-  if (ticket != 0) return CVO_ENOTFOUND;
-  std::lock_guard<std::mutex> g(c->call_mu);
-  if (!c->have_last) return CVO_ENOTFOUND;
-  const int rows = (int)(c->last_register.trace.size() / kTraceCols);
-  const int w = std::min(rows, cap);
-  if (w > 0) memcpy(buf, c->last_register.trace.data(), (size_t)w * kTraceCols * 8);
-  return w;
+  if (ticket == 0) {
+    std::lock_guard<std::mutex> g(c->call_mu);
+    if (!c->have_last) return CVO_ENOTFOUND;
+    return copy_trace(c->last_register.trace, buf, cap);
+  }
+  // a batched ticket: the scheduler writes the trace before it publishes the
+  // terminal status under q_mu
+  std::lock_guard<std::mutex> g(c->q_mu);
+  auto it = c->tickets.find(ticket);
+  if (it != c->tickets.end()) {
+    if (it->second->status == CVO_PENDING) return CVO_PENDING;
+    return copy_trace(it->second->trace, buf, cap);
+  }
+  auto kt = c->kept_traces.find(ticket);
+  if (kt == c->kept_traces.end()) return CVO_ENOTFOUND;
+  return copy_trace(kt->second, buf, cap);
 }
 
 const char* cvo_strerror(int code) {

@@ -29,9 +29,12 @@ constexpr int kScanBlock = 1024;    // multi-block scan: threads per block
 constexpr int kScanTile = kScanPerThread * kScanBlock;
 
 enum Mode : int { kModeRegister = 0, kModeEval = 1, kModeEvalTargets = 2, kModeQuartic = 3 };
-// Step rules: tau = eta ell^2 / F, or the maximiser of the fourth-order model
-// of G(t) = F(h exp(t xi)) along the gradient (second pair pass).
-enum StepRule : int { kStepFixed = 0, kStepQuartic = 1 };
+// Step rules: tau = eta ell^2 / F along the gradient; the maximiser of the
+// fourth-order model of G(t) = F(h exp(t d)) (second pair pass) along the
+// gradient d = grad F, or along conjugate directions d (Polak-Ribiere with
+// restarts, the inner products in the metric a^2, b^2).
+enum StepRule : int { kStepFixed = 0, kStepQuartic = 1, kStepConjugate = 2 };
+constexpr int kCgRestart = 6;  // conjugate directions restart from the gradient every 6 steps (dim se(3))
 // Phases of the step kernel: the whole step (fixed rule); the gradient only
 // (first pass of the quartic rule, or of a coefficient evaluation); the
 // quartic step from the second pass's sums.
@@ -137,7 +140,8 @@ struct ReqStatic {
 struct ReqState {
   double T[12];                      // rows 0..2 of the pose acting on target points
   double g[7];                       // F, omega, v at the last evaluated pose
-  double xi[6];                      // direction (omega, v) of the second (quartic) pass
+  double xi[6];                      // direction (omega, v) of the second (quartic) pass and of the step
+  double gprev[6];                   // the previous iteration's gradient (in the mask), conjugate rule
   double A[5];                       // F and the model coefficients A1..A4 of the last quartic pass
   unsigned long long last_pairs;     // pairs within the cutoff of the last gradient pass
   double a2;                         // rotational metric weight (device-computed default)
@@ -145,6 +149,8 @@ struct ReqState {
   unsigned long long pairs_within, pairs_examined;
   int iter, stage, done, status, converged;
   unsigned int reserved;
+  int cg_n;                          // conjugate rule: steps since the last restart (0: restart now)
+  int cg_stage;                      // conjugate rule: stage of the direction in xi
   int bad_input;                     // set by the finiteness check
   int nclus;                         // target clusters, the largest over the stages (device-computed at ingest)
   int nclus_s[kMaxStages];           // target clusters of each stage

@@ -1213,22 +1213,30 @@ __device__ void gradient_from_sums(const ReqStatic& R, ReqState* __restrict__ S,
   S->pairs_examined += (unsigned long long)acc[8];
 }
 
-// The exponential-map step h <- h exp(tau xi), xi = (omega, v) = S->g
-// (T <- Exp(-tau xi) T), the trace row, the stopping test and the stage
-// schedule.
-__device__ void take_step(const ReqStatic& R, ReqState* __restrict__ S, double tau, double pairs) {
+// The gradient's components in the subgroup the mask selects (the others
+// dropped: an orthogonal projection under the diagonal metric a^2, b^2).
+__device__ __forceinline__ void masked_gradient(const ReqStatic& R, const double* g, double (&gm)[6]) {
+  for (int q = 0; q < 6; q++) gm[q] = ((R.dof_mask >> q) & 1) ? g[1 + q] : 0.0;
+}
+
+// <p, q> in the metric: a^2 p_w . q_w + b^2 p_v . q_v
+__device__ __forceinline__ double metric_dot(const ReqStatic& R, const ReqState* S, const double* p, const double* q) {
+  return S->a2 * (p[0] * q[0] + p[1] * q[1] + p[2] * q[2]) + R.b2 * (p[3] * q[3] + p[4] * q[4] + p[5] * q[5]);
+}
+
+// The exponential-map step h <- h exp(tau d) along direction d = (omega, v)
+// (the gradient, or a conjugate direction; T <- Exp(-tau d) T), the trace
+// row, the stopping test and the stage schedule.
+__device__ void take_step(const ReqStatic& R, ReqState* __restrict__ S, double tau, double pairs, const double (&d)[6]) {
   const int stage = S->stage;
   const double ell = R.stage_ell[stage];
   const double* g = S->g;
   S->tau = tau;
-  // the flow on the subgroup the mask selects: the gradient's components
-  // outside it are dropped (an orthogonal projection under the diagonal
-  // metric a^2, b^2)
   double w[3], u[3], gm[6];
-  for (int q = 0; q < 6; q++) gm[q] = ((R.dof_mask >> q) & 1) ? g[1 + q] : 0.0;
+  masked_gradient(R, g, gm);
   for (int a = 0; a < 3; a++) {
-    w[a] = -tau * gm[a];
-    u[a] = -tau * gm[3 + a];
+    w[a] = -tau * d[a];
+    u[a] = -tau * d[3 + a];
   }
   double T[12];
   for (int q = 0; q < 12; q++) T[q] = S->T[q];
@@ -1270,6 +1278,12 @@ __device__ void take_step(const ReqStatic& R, ReqState* __restrict__ S, double t
 //  kPhaseQuartic   the quartic model's coefficients from the second pass's
 //                  sums, then the step at its maximiser (tau = eta ell^2 / F
 //                  when the model has no maximum on t > 0).
+// The direction of the second pass (S->xi) is the gradient in the mask
+// (quartic rule) or the conjugate direction
+//   d = g + beta d_prev,  beta = max(0, <g, g - g_prev> / <g_prev, g_prev>)
+// (Polak-Ribiere, inner products in the metric), restarted from d = g at the
+// first iteration of every length-scale stage, every kCgRestart steps, and
+// whenever d is not an ascent direction (<g, d> <= 0).
 __device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S, const double (&acc)[kSlot], int phase) {
   if (phase == kPhaseQuartic) {
     S->A[0] = S->g[0];
@@ -1278,19 +1292,20 @@ __device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S, con
       S->done = 1;
       return;
     }
-    // Along the gradient, A1 = G'(0) = <grad F, xi> = a^2 |omega|^2 + b^2 |v|^2
-    // over the same pairs.  Taken from this identity in FP64: near
-    // convergence the terms of the summed A1 cancel to a small remainder
-    // that the FP32 pair terms resolve only to their rounding, and the step
-    // is about -A1 / (2 A2).
-    const double* xi = S->xi;
-    S->A[1] = S->a2 * (xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]) +
-              R.b2 * (xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
+    // Along d, A1 = G'(0) = <grad F, d> = a^2 omega . d_w + b^2 v . d_v over
+    // the same pairs.  Taken from this identity in FP64: near convergence
+    // the terms of the summed A1 cancel to a small remainder that the FP32
+    // pair terms resolve only to their rounding, and the step is about
+    // -A1 / (2 A2).
+    double d[6], gm[6];
+    for (int q = 0; q < 6; q++) d[q] = S->xi[q];
+    masked_gradient(R, S->g, gm);
+    S->A[1] = metric_dot(R, S, gm, d);
     const double ell = R.stage_ell[S->stage];
     double tau = R.eta * ell * ell / S->g[0];
     double t;
     if (quartic_argmax(S->A, &t)) tau = t;
-    take_step(R, S, tau, (double)S->last_pairs);
+    take_step(R, S, tau, (double)S->last_pairs, d);
     return;
   }
   double g[7];
@@ -1307,13 +1322,37 @@ __device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S, con
     S->done = 1;
     return;
   }
+  double gm[6];
+  masked_gradient(R, g, gm);
   if (phase == kPhaseGradient) {
-    for (int q = 0; q < 6; q++) S->xi[q] = ((R.dof_mask >> q) & 1) ? g[1 + q] : 0.0;
+    double d[6];
+    for (int q = 0; q < 6; q++) d[q] = gm[q];
+    if (R.step_rule == kStepConjugate) {
+      const int stage = S->stage;
+      bool fresh = S->cg_n <= 0 || S->cg_n >= kCgRestart || S->cg_stage != stage;
+      if (!fresh) {
+        double diff[6];
+        for (int q = 0; q < 6; q++) diff[q] = gm[q] - S->gprev[q];
+        const double den = metric_dot(R, S, S->gprev, S->gprev);
+        double beta = den > 0.0 ? metric_dot(R, S, gm, diff) / den : 0.0;
+        beta = beta > 0.0 ? beta : 0.0;
+        for (int q = 0; q < 6; q++) d[q] = gm[q] + beta * S->xi[q];
+        if (!(metric_dot(R, S, gm, d) > 0.0)) fresh = true;
+      }
+      if (fresh) {
+        for (int q = 0; q < 6; q++) d[q] = gm[q];
+        S->cg_n = 0;
+      }
+      S->cg_n += 1;
+      S->cg_stage = stage;
+      for (int q = 0; q < 6; q++) S->gprev[q] = gm[q];
+    }
+    for (int q = 0; q < 6; q++) S->xi[q] = d[q];
     S->last_pairs = (unsigned long long)acc[7];
     return;
   }
   const double ell = R.stage_ell[S->stage];
-  take_step(R, S, R.eta * ell * ell / g[0], acc[7]);
+  take_step(R, S, R.eta * ell * ell / g[0], acc[7], gm);
 }
 
 // Wave-local LDS ordering between the lanes of one wavefront.  The LDS
@@ -1851,6 +1890,9 @@ __global__ void k_init_state(ReqState* __restrict__ S, const double* __restrict_
   for (int q = 0; q < 12; q++) S->T[q] = T0[q];
   for (int q = 0; q < 7; q++) S->g[q] = 0.0;
   for (int q = 0; q < 6; q++) S->xi[q] = xi0 ? xi0[q] : 0.0;
+  for (int q = 0; q < 6; q++) S->gprev[q] = 0.0;
+  S->cg_n = 0;
+  S->cg_stage = 0;
   for (int q = 0; q < 5; q++) S->A[q] = 0.0;
   S->last_pairs = 0ull;
   S->a2 = a2_param;
@@ -2260,7 +2302,7 @@ hipError_t launch_iteration_rule(int step_rule, int precision, int fd, bool cuto
   if (e != hipSuccess) return e;
   e = launch_pair_kernel(precision, fd, cutoff, reqs, clus_end, nreq, total_clusters, Q, s);
   if (e != hipSuccess) return e;
-  if (step_rule != kStepQuartic) return launch_step(reqs, clus_end, nreq, total_clusters, Q, s);
+  if (step_rule == kStepFixed) return launch_step(reqs, clus_end, nreq, total_clusters, Q, s);
   e = launch_step(reqs, clus_end, nreq, total_clusters, Q, s, kPhaseGradient, false);
   if (e != hipSuccess) return e;
   e = launch_quartic_pairs(precision, fd, cutoff, reqs, clus_end, nreq, total_clusters, Q, s);

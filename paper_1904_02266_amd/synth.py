@@ -247,13 +247,13 @@ def _select(valid, gmag, n, rng, mode):
 
 
 def rgbd_pair(n_src=30000, n_tgt=None, seed=2, theta_max_deg=5.0, t_max=0.05,
-              select="gradient"):
+              select="gradient", depth_noise=0.01):
     """Two synthetic RGB-D frames of one seeded room.
 
     The source camera is at the world origin, the target camera at a seeded
     pose G (theta <= theta_max, |t| <= t_max); each frame has its own depth
-    noise and its own point selection.  T_true = G maps target-frame points
-    onto source-frame points.
+    noise (relative standard deviation depth_noise) and its own point
+    selection.  T_true = G maps target-frame points onto source-frame points.
     """
     if n_tgt is None:
         n_tgt = n_src
@@ -262,7 +262,7 @@ def rgbd_pair(n_src=30000, n_tgt=None, seed=2, theta_max_deg=5.0, t_max=0.05,
     G = random_motion(rng, theta_max_deg, t_max)
     out = []
     for pose, n in ((np.eye(4), n_src), (G, n_tgt)):
-        cam, _, valid, feat, gmag = render(room, pose, rng)
+        cam, _, valid, feat, gmag = render(room, pose, rng, depth_noise=depth_noise)
         sel = _select(valid, gmag, n, rng, select)
         out.append((cam[sel].astype(np.float32), feat[sel].astype(np.float32)))
     (sx, sf), (tx, tf) = out

@@ -1,0 +1,120 @@
+"""The dense 300k frame pair: the registration the benchmark times, against
+the FP64 oracle's own trajectory.
+
+Workload: synth.rgbd_pair(300000, 300000, seed=3, select="random") (a seeded
+random subset of 300,000 valid pixels of each synthetic 640x480 RGB-D frame),
+cutoff 3 ell, ell annealed 0.2 -> 0.05 m over 4 x 25 iterations, the fixed
+step, T0 = I.  The oracle's registration (every pair inside the cutoff,
+enumerated through its grid, FP64 throughout) is stored in
+tests/golden/dense300k_trajectory.json by make_dense300k.py, so no oracle
+input comes from the GPU.
+
+* Teacher-forced (reading C15): the GPU evaluates F, omega, v (eq. scalar,
+  eq. 3_gradient) at the oracle's pose of iterations 0, 1, 5, 10, 25, 50, 99
+  with that iteration's ell.  FP32-Kahan path: |F - F_ref| <= 1e-5 F_ref and
+  |g_k - g_ref,k| <= 1e-5 A_k with A_k the oracle's sum of |terms| (reading
+  C12); all-FP64 path: 1e-10 on the same scales.  Pair counts: FP32 and FP64
+  decisions may differ for pairs within ~1e-7 of the cutoff (reading C13).
+* Trajectory: the GPU registrations (FP32-Kahan and FP64) run their own 100
+  iterations; every iteration's F stays within 1e-5 of the oracle's and the
+  final pose within 1e-4 rad / 1e-4 m (FP64: 1e-7).
+"""
+import hashlib
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1904_02266_amd import Context, Params, params_rgbd, synth
+
+pytestmark = pytest.mark.gpu
+
+FIX = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dense300k_trajectory.json")
+CHECK_ITERS = (0, 1, 5, 10, 25, 50, 99)
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(FIX) as f:
+        doc = json.load(f)
+    doc["trace"] = np.array(doc["trace"])
+    doc["abs"] = np.array(doc["abs"])
+    return doc
+
+
+@pytest.fixture(scope="module")
+def pair_dev():
+    import torch
+    p = synth.rgbd_pair(300000, 300000, seed=3, select="random")
+    h = hashlib.sha256()
+    for a in (p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat):
+        h.update(np.ascontiguousarray(a).tobytes())
+    dev = torch.device("cuda:0")
+    t = [torch.from_numpy(a).to(dev) for a in (p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat)]
+    torch.cuda.synchronize()
+    return p, t, h.hexdigest()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def pose_before(trace, k):
+    return np.eye(4) if k == 0 else trace[k - 1, 10:26].reshape(4, 4)
+
+
+def angle(A, B):
+    E = A[:3, :3] @ B[:3, :3].T
+    s = np.linalg.norm([E[2, 1] - E[1, 2], E[0, 2] - E[2, 0], E[1, 0] - E[0, 1]]) / 2
+    return math.atan2(s, (np.trace(E) - 1) / 2)
+
+
+def test_inputs_match_the_fixture(golden, pair_dev):
+    # the generator is seeded; a different digest would mean the inputs moved
+    # by more than the rounding the tolerances below absorb
+    p, _, digest = pair_dev
+    if digest != golden["input_sha256"]:
+        pytest.skip("generator output differs in its last bits on this host (BLAS / libm); the parity "
+                    "tests below still apply their tolerances")
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp32", 1e-5), ("fp64", 1e-10)])
+def test_teacher_forced_against_oracle_trajectory(ctx, golden, pair_dev, precision, rtol):
+    p, t, _ = pair_dev
+    tr, A = golden["trace"], golden["abs"]
+    for k in CHECK_ITERS:
+        ell = tr[k, 8]
+        prm = Params(stage_ell=(ell,), cutoff_mult=3.0, max_iters=1, a2=golden["a2"], precision=precision,
+                     trace=True)
+        out = ctx.register(*t, prm, T0=pose_before(tr, k))
+        g = ctx.trace()[0]
+        ref = tr[k]
+        assert abs(g[0] - ref[0]) <= rtol * ref[0], (precision, k, "F", g[0], ref[0])
+        for q in range(1, 7):
+            assert abs(g[q] - ref[q]) <= rtol * A[k, q], (precision, k, q, g[q], ref[q], (g[q] - ref[q]) / A[k, q])
+        # pair count: boundary flips only (reading C13)
+        assert abs(g[9] - ref[9]) <= 1e-7 * ref[9] + 100, (precision, k, g[9], ref[9])
+        assert out["iters"] == 1
+
+
+@pytest.mark.parametrize("precision,pose_tol", [("fp32", 1e-4), ("fp64", 1e-7)])
+def test_registration_follows_oracle_trajectory(ctx, golden, pair_dev, precision, pose_tol):
+    p, t, _ = pair_dev
+    tr = golden["trace"]
+    out = ctx.register(*t, params_rgbd(trace=True, a2=golden["a2"], precision=precision))
+    g = ctx.trace()
+    assert out["iters"] == 100 and g.shape[0] == 100
+    relF = np.abs(g[:, 0] - tr[:, 0]) / tr[:, 0]
+    assert relF.max() <= 1e-5, (precision, relF.max(), int(relF.argmax()))
+    np.testing.assert_allclose(g[:, 8], tr[:, 8], rtol=0, atol=0)   # the same ell schedule
+    Tg, To = out["T"], tr[99, 10:26].reshape(4, 4)
+    assert angle(Tg, To) <= pose_tol, (precision, angle(Tg, To))
+    assert np.linalg.norm(Tg[:3, 3] - To[:3, 3]) <= pose_tol
+    # the pose stays a rigid motion
+    R = Tg[:3, :3]
+    assert np.abs(R.T @ R - np.eye(3)).max() < 1e-12

@@ -177,15 +177,12 @@ def test_register_quartic_rgbd_schedule_teacher_forced(ctx):
 
 
 def test_quartic_rule_batched_equals_sync():
-    reqs = [synth.rgbd_pair(3000 + 900 * k, 2800 + 700 * k, seed=7100 + k) for k in range(4)]
-    pq = params_rgbd(max_iters=12, stage_iters=(3, 3, 3), step_rule="quartic")
-    pf = params_rgbd(max_iters=12, stage_iters=(3, 3, 3))
+    reqs = [synth.rgbd_pair(3000 + 900 * k, 2800 + 700 * k, seed=7100 + k) for k in range(6)]
+    rules = [params_rgbd(max_iters=12, stage_iters=(3, 3, 3), step_rule=r) for r in ("quartic", "fixed", "conjugate")]
     ctx = Context(0, max_slots=8)
     try:
-        sync = [ctx.register(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, pq if k % 2 == 0 else pf)
-                for k, q in enumerate(reqs)]
-        tks = [ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, pq if k % 2 == 0 else pf)[0]
-               for k, q in enumerate(reqs)]
+        sync = [ctx.register(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, rules[k % 3]) for k, q in enumerate(reqs)]
+        tks = [ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, rules[k % 3])[0] for k, q in enumerate(reqs)]
         bat = [ctx.poll(t) for t in tks]
     finally:
         ctx.close()
@@ -193,6 +190,60 @@ def test_quartic_rule_batched_equals_sync():
         assert b["rc"] == 0 and b["iters"] == 12
         assert np.array_equal(s["T"], b["T"]) and s["F"] == b["F"]
     assert not np.array_equal(sync[0]["T"], sync[1]["T"])
+
+
+# --------------------------------------------------------------------------
+# conjugate directions (the quartic line search along Polak-Ribiere
+# directions): the GPU's trajectory against the oracle's under the same rule
+# --------------------------------------------------------------------------
+def _angle_deg(A, B):
+    E = A[:3, :3] @ B[:3, :3].T
+    return float(np.degrees(np.arccos(np.clip((np.trace(E) - 1) / 2, -1, 1))))
+
+
+def test_register_conjugate_planes_follows_oracle(ctx):
+    p = synth.planes_pair(2000, seed=1)
+    prm = params_planes(trace=True, step_rule="conjugate", max_iters=30)
+    out = ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, prm)
+    tr = ctx.trace()
+    ref = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, stage_ell=(0.1,), max_iters=30,
+                          step_rule="conjugate")
+    rt = ref["trace"]
+    assert out["rc"] == 0 and tr.shape[0] == 30 and rt.shape[0] == 30
+    # the gradient and step of the same iteration (the trajectories agree to
+    # FP32 rounding while the gradient is resolved: the first 10 steps)
+    np.testing.assert_allclose(tr[:10, 0], rt[:10, 0], rtol=1e-5)
+    np.testing.assert_allclose(tr[:10, 7], rt[:10, 7], rtol=1e-3)
+    assert _angle_deg(out["T"], ref["T"]) < 1e-4 * 180 / np.pi
+    assert np.linalg.norm(out["T"][:3, 3] - ref["T"][:3, 3]) < 1e-4
+    assert _angle_deg(out["T"], p.T_true) < 0.05
+
+
+def test_register_conjugate_rgbd_schedule_follows_oracle(ctx):
+    p = synth.rgbd_pair(4000, 4000, seed=41)
+    prm = params_rgbd(max_iters=24, stage_iters=(6, 6, 6), trace=True, step_rule="conjugate")
+    out = ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, prm)
+    tr = ctx.trace()
+    ref = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, kappa=3.0, stage_iters=(6, 6, 6),
+                          stage_ell=prm.stage_ell, max_iters=24, step_rule="conjugate")
+    assert out["rc"] == 0 and tr.shape[0] == 24
+    np.testing.assert_allclose(tr[:, 0], ref["trace"][:, 0], rtol=1e-5)
+    assert _angle_deg(out["T"], ref["T"]) < 1e-3
+    assert np.linalg.norm(out["T"][:3, 3] - ref["T"][:3, 3]) < 1e-4
+
+
+def test_register_conjugate_converges_with_tolerance(ctx):
+    """With tol the conjugate rule stops in the last stage once the applied
+    twist is below it; the oracle stops at the same iteration."""
+    p = synth.rgbd_pair(5000, 5000, seed=43, select="random")
+    prm = params_rgbd(max_iters=200, step_rule="conjugate", tol=1e-5)
+    out = ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, prm)
+    ref = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, kappa=3.0, stage_iters=(25, 25, 25),
+                          stage_ell=prm.stage_ell, max_iters=200, step_rule="conjugate", tol=1e-5)
+    assert out["rc"] == 0 and out["converged"] and ref["converged"]
+    assert 75 < out["iters"] < 200
+    assert abs(out["iters"] - ref["iters"]) <= 3, (out["iters"], ref["iters"])
+    assert _angle_deg(out["T"], ref["T"]) < 1e-3
 
 
 def test_coefficients_cell_list_overflow(ctx):

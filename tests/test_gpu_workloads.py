@@ -252,3 +252,165 @@ def test_serving_counters():
     assert all(o["rc"] == 0 for o in outs)
     assert s1["completed"] == 6 and s1["failed"] == 1
     assert s1["active"] == 0 and s1["pending"] == 0 and s1["hbm_in_use"] == 0
+
+
+def test_queue_limit_busy():
+    """A bounded submission queue: with no room every submission is refused
+    with CVO_EBUSY and nothing is queued; with room again it is accepted."""
+    from paper_1904_02266_amd import CVO_EBUSY
+    q = synth.planes_pair(500, seed=3)
+    prm = params_planes(max_iters=5)
+    ctx = Context(0, max_slots=2)
+    try:
+        ctx.set_queue_limit(0)
+        with pytest.raises(CvoError) as e:
+            ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)
+        assert e.value.code == CVO_EBUSY
+        assert ctx.serving_stats()["pending"] == 0
+        ctx.set_queue_limit(16)
+        tk, _ = ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)
+        assert ctx.poll(tk)["rc"] == 0
+    finally:
+        ctx.close()
+
+
+def test_batched_ticket_traces():
+    """Each batched ticket keeps its own per-iteration trace: readable once
+    the request has finished, before and after the poll, and equal to the
+    synchronous run's trace."""
+    reqs = _small_requests(400, 3)
+    prm = params_rgbd(max_iters=9, stage_iters=(3, 3, 3), trace=True)
+    ctx = Context(0, max_slots=4)
+    try:
+        sync = []
+        for q in reqs:
+            ctx.register(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)
+            sync.append(ctx.trace())
+        tks = [ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)[0] for q in reqs]
+        # the last ticket: wait for it, then read its trace before polling it
+        import time
+        t0 = time.time()
+        tr_last = None
+        while tr_last is None and time.time() - t0 < 30:
+            tr_last = ctx.trace(ticket=tks[-1])
+            time.sleep(0.002)
+        outs = [ctx.poll(t) for t in tks]
+        after = [ctx.trace(ticket=t) for t in tks]
+        with pytest.raises(CvoError) as e:
+            ctx.trace(ticket=987654321)
+        assert e.value.code == CVO_ENOTFOUND
+    finally:
+        ctx.close()
+    assert all(o["rc"] == 0 for o in outs)
+    np.testing.assert_array_equal(tr_last, sync[-1])
+    for s, a in zip(sync, after):
+        assert a.shape == (9, 26)
+        np.testing.assert_array_equal(a, s)
+
+
+def test_admission_charges_exact_bytes_for_scattered_targets():
+    """Targets far apart from one another fall into many small clusters, so
+    their iteration buffers outgrow the admission estimate; the scheduler
+    charges the exact size once the ingest has counted them, so the
+    memory in use never falls below what the requests hold."""
+    rng = np.random.default_rng(5)
+    m = 4000
+    z = (rng.uniform(-1, 1, size=(m, 3)) * 40.0).astype(np.float32)          # sparse: ~5 m apart
+    x = (z + rng.normal(0, 0.01, size=z.shape)).astype(np.float32)
+    l = rng.uniform(0, 1, size=(m, 5)).astype(np.float32)
+    prm = Params(stage_ell=(0.1,), cutoff_mult=3.0, max_iters=20)
+    dense = synth.rgbd_pair(4000, 4000, seed=6300)
+    ctx = Context(0, max_slots=4)
+    try:
+        tk1, _ = ctx.submit(x, l, z, l, prm)
+        tk2, _ = ctx.submit(dense.src_xyz, dense.src_feat, dense.tgt_xyz, dense.tgt_feat, prm)
+        o1, o2 = ctx.poll(tk1), ctx.poll(tk2)
+        st = ctx.serving_stats()
+    finally:
+        ctx.close()
+    assert o1["rc"] == 0 and o2["rc"] == 0
+    assert o1["device_bytes"] > o2["device_bytes"]      # many clusters
+    assert st["hbm_peak"] >= o1["device_bytes"]
+    assert st["hbm_in_use"] == 0
+
+
+def test_exact_size_that_does_not_fit_waits_then_runs():
+    """With a budget that holds one scattered request but not two, the
+    second waits in the queue (its exact size known) and runs after the
+    first; both results equal their synchronous runs."""
+    rng = np.random.default_rng(6)
+    m = 3000
+    reqs = []
+    for k in range(2):
+        z = (rng.uniform(-1, 1, size=(m, 3)) * 40.0).astype(np.float32)
+        x = (z + rng.normal(0, 0.01, size=z.shape)).astype(np.float32)
+        l = rng.uniform(0, 1, size=(m, 5)).astype(np.float32)
+        reqs.append((x, l, z, l))
+    prm = Params(stage_ell=(0.1,), cutoff_mult=3.0, max_iters=10)
+    probe = Context(0)
+    try:
+        sync = [probe.register(*r, prm) for r in reqs]
+    finally:
+        probe.close()
+    one = max(s["device_bytes"] for s in sync)
+    ctx = Context(0, hbm_budget=int(one * 1.5), max_slots=4)
+    try:
+        tks = [ctx.submit(*r, prm)[0] for r in reqs]
+        outs = [ctx.poll(t) for t in tks]
+        st = ctx.serving_stats()
+    finally:
+        ctx.close()
+    for s, o in zip(sync, outs):
+        assert o["rc"] == 0 and np.array_equal(s["T"], o["T"])
+    assert st["hbm_peak"] <= int(one * 1.5)
+
+
+def test_serving_alone_equals_mix_under_poisson_traffic():
+    """16 requests of the serving workload (lognormal sizes cut from random
+    pixel subsets of 300k frames, conjugate rule, stop at |tau d| < 1e-5,
+    cap 200) give bit-identical results when run alone and when submitted at
+    Poisson arrival times (rate 1000/s) among other requests."""
+    import time
+    import torch
+    dev = torch.device("cuda:0")
+    pool = []
+    for k in range(2):
+        p = synth.rgbd_pair(300000, 300000, seed=5100 + k, select="random")
+        r = np.random.default_rng(5117 + k)
+        a, b = r.permutation(len(p.src_xyz)), r.permutation(len(p.tgt_xyz))
+        pool.append([torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+                     for v in (p.src_xyz[a], p.src_feat[a], p.tgt_xyz[b], p.tgt_feat[b])])
+    torch.cuda.synchronize()
+    stream = synth.serving_stream(1000, window_s=0.25, seed=55, nmax=60000)
+    assert len(stream) > 150
+    prm = params_rgbd(max_iters=200, step_rule="conjugate", tol=1e-5)
+    chosen = set(range(0, len(stream), max(1, len(stream) // 16))[:16])
+
+    def cut(seed, ns, nt):
+        c = pool[seed % 2]
+        return c[0][:ns], c[1][:ns], c[2][:nt], c[3][:nt]
+
+    ctx = Context(0, max_slots=256)
+    try:
+        alone = {}
+        for i in sorted(chosen):
+            _, seed, ns, nt = stream[i]
+            tk, keep = ctx.submit(*cut(seed, ns, nt), prm)
+            alone[i] = ctx.poll(tk)
+        t0 = time.perf_counter()
+        subs = []
+        for i, (arr, seed, ns, nt) in enumerate(stream):
+            now = time.perf_counter() - t0
+            if arr > now:
+                time.sleep(arr - now)
+            subs.append((i, ctx.submit(*cut(seed, ns, nt), prm)))
+        mixed = {i: ctx.poll(tk) for i, (tk, keep) in subs}
+        peak_active = ctx.serving_stats()
+    finally:
+        ctx.close()
+    for i in chosen:
+        a, m = alone[i], mixed[i]
+        assert a["rc"] == 0 and m["rc"] == 0, (i, a["rc"], m["rc"])
+        assert a["iters"] == m["iters"] and a["converged"] == m["converged"]
+        assert np.array_equal(a["T"], m["T"]) and a["F"] == m["F"], i
+    assert sum(m["converged"] for m in mixed.values()) >= 0.9 * len(mixed)

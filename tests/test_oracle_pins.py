@@ -596,3 +596,76 @@ def test_selected_target_row_is_the_single_target_objective():
             one = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz[j:j + 1], p.tgt_feat[j:j + 1], T, ell=0.2,
                               kappa=3.0, a2=a2, grid=grid)
             np.testing.assert_array_equal(rows[k], one["g"])
+
+
+# --------------------------------------------------------------------------
+# conjugate directions with the quartic line search (step_rule "conjugate")
+# --------------------------------------------------------------------------
+def _exact_copy(n=300, seed=5):
+    """Z = M X exactly (the same points and labels moved by M): by the
+    Section V theorem the maximum of F (no cutoff) is at T = M^-1."""
+    p = synth.planes_pair(n, seed=seed, noise=0.0, theta_max_deg=8.0, t_max=0.08)
+    M = synth.invert_rigid(p.T_true)
+    z = (p.src_xyz.astype(np.float64) @ M[:3, :3].T + M[:3, 3]).astype(np.float32)
+    return p.src_xyz, p.src_feat, z, p.src_feat, synth.invert_rigid(M)
+
+
+def test_conjugate_rule_recovers_exact_motion_fast():
+    x, lx, z, lz, Tstar = _exact_copy()
+    its = {}
+    for rule in ("quartic", "conjugate"):
+        r = oracle.register(x, lx, z, lz, stage_ell=(0.3,), max_iters=200, tol=1e-10, step_rule=rule, a2=7.0)
+        assert r["rc"] == 0 and r["converged"]
+        assert rot_angle_deg(r["T"], Tstar) < 1e-5 and trans_err(r["T"], Tstar) < 1e-7
+        its[rule] = r["iters"]
+    # conjugate directions need far fewer line searches than the gradient
+    assert its["conjugate"] <= 20 and its["conjugate"] * 2 <= its["quartic"], its
+
+
+def _step_twist(T0, T1):
+    """(w, u) with T1 = Exp(w, u) T0 (library convention), via the matrix logarithm."""
+    L = np.real(scipy.linalg.logm(T1 @ np.linalg.inv(T0)))
+    return np.array([L[2, 1], L[0, 2], L[1, 0], *L[:3, 3]])
+
+
+def test_conjugate_rule_restarts_and_conjugate_steps():
+    """The first step of each stage moves along the gradient itself
+    (Exp(-tau g)); later steps do not (the direction carries the previous
+    one); the first step equals the quartic rule's."""
+    x, lx, z, lz, _ = _exact_copy(240, seed=9)
+    kw = dict(stage_iters=(5,), stage_ell=(0.3, 0.2), max_iters=10, a2=7.0)
+    c = oracle.register(x, lx, z, lz, step_rule="conjugate", **kw)
+    q = oracle.register(x, lx, z, lz, step_rule="quartic", max_iters=1, stage_ell=(0.3,), a2=7.0)
+    np.testing.assert_allclose(c["trace"][0, 10:26], q["trace"][0, 10:26], rtol=0, atol=1e-15)
+    tr = c["trace"]
+    off = []
+    for k in range(10):
+        T0 = np.eye(4) if k == 0 else tr[k - 1, 10:26].reshape(4, 4)
+        step = _step_twist(T0, tr[k, 10:26].reshape(4, 4))
+        along_g = -tr[k, 7] * tr[k, 1:7]
+        rel = np.linalg.norm(step - along_g) / np.linalg.norm(along_g)
+        if k in (0, 5):
+            assert rel < 1e-7, (k, rel)
+        else:
+            off.append(rel)
+    assert max(off) > 1e-2, off
+
+
+def test_conjugate_rule_recovers_rgbd_motion():
+    """On the RGB-D generator (random pixel selection, no depth noise) the
+    annealed registration with conjugate directions recovers the generating
+    motion far better than the fixed step's 100 iterations, and every
+    length-scale stage ends converged (applied twist |tau d| small)."""
+    p = synth.rgbd_pair(6000, 6000, seed=2, select="random", depth_noise=0.0)
+    ells = [0.2 * 0.25 ** (s / 3.0) for s in range(4)]
+    kw = dict(kappa=3.0, stage_iters=(25, 25, 25), stage_ell=ells, max_iters=100)
+    c = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, step_rule="conjugate", **kw)
+    f = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, step_rule="fixed", **kw)
+    ec = rot_angle_deg(c["T"], p.T_true), trans_err(c["T"], p.T_true)
+    ef = rot_angle_deg(f["T"], p.T_true), trans_err(f["T"], p.T_true)
+    assert ec[0] < 0.2 and ec[1] < 0.008, (ec, ef)
+    assert ec[0] < 0.6 * ef[0], (ec, ef)
+    tr = c["trace"]
+    for end in (24, 49, 74, 99):
+        T0, T1 = tr[end - 1, 10:26].reshape(4, 4), tr[end, 10:26].reshape(4, 4)
+        assert np.linalg.norm(_step_twist(T0, T1)) < 1e-4, end
