@@ -47,7 +47,8 @@ struct GridInfo {
   double sq;          // coordinate scale sqrt(log2(e) / (2 ell^2)): exp2(-|sq d|^2) = exp(-|d|^2/(2 ell^2))
   double ell;
   double reach;       // candidate-cell search radius (m); 0 for brute force
-  float rc2s;         // cutoff radius squared in scaled units; +inf for brute force
+  double rc2s;        // cutoff radius squared in scaled units; +inf for brute force (each pair
+                      // type rounds it once: FP64 keeps the cutoff exact to FP64)
   int nx, ny, nz, ncell;
   int cutoff;         // 1: grid culling and per-pair cutoff test
   int pad;

@@ -246,7 +246,7 @@ __global__ void k_grid_setup(const double* __restrict__ xbox, int n_stages, cons
   g.sq = sqrt(LOG2E / (2.0 * ell * ell));
   if (g.cutoff) {
     // kappa^2 ell^2 * log2(e)/(2 ell^2)
-    g.rc2s = (float)(kappa * kappa * LOG2E * 0.5);
+    g.rc2s = kappa * kappa * LOG2E * 0.5;
     // candidate cells must contain every source the FP32 test can accept
     g.reach = kappa * ell * (1.0 + 1e-5) + 1e-7;
   } else {
