@@ -178,6 +178,21 @@ int cvo_set_stream(cvo_ctx* ctx, void* hip_stream);
 int cvo_eval(cvo_ctx* ctx, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* params,
              const double T[16], double* F, double omega[3], double v[3]);
 
+/* cvo_eval for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation and kernels, with every device buffer taken from a 64 MiB array
+ * that the library holds per device for the life of the process (no
+ * hipMalloc, hipFree or pinned host allocation during the call; the context
+ * must exist beforehand).  Limits: at most 65,536 points per cloud, and the
+ * request's set-up and per-cluster buffers must fit the array (spatially
+ * coherent 30k-point clouds need about 25 MiB); otherwise CVO_ENOMEM with the
+ * reason in cvo_last_error.  Calls on one device share the array: the library
+ * serialises them within the process (calls that overlap on one GPU would
+ * race), and each call overwrites what the previous one left.  Inputs and
+ * outputs as for cvo_eval. */
+int cvo_eval_static(cvo_ctx* ctx, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* params,
+                    const double T[16], double* F, double omega[3], double v[3]);
+
 /* The fourth-order model of the line G(t) = F(h exp(t xi)) at pose T along
  * xi = (omega, v) (Sec. VI-B, eq. fourth; h = T^-1), ell = params->stage_ell[0]:
  * coef = F, A1, A2, A3, A4 with G(t) = coef . (1, t, t^2, t^3, t^4) + O(t^5),

@@ -105,6 +105,7 @@ def load():
     L.cvo_destroy.argtypes = [vp]
     L.cvo_set_stream.argtypes = [vp, vp]
     L.cvo_eval.argtypes = [vp, P(cvo_cloud), P(cvo_cloud), P(cvo_params), P(dbl), P(dbl), P(dbl), P(dbl)]
+    L.cvo_eval_static.argtypes = [vp, P(cvo_cloud), P(cvo_cloud), P(cvo_params), P(dbl), P(dbl), P(dbl), P(dbl)]
     L.cvo_eval_targets.argtypes = [vp, P(cvo_cloud), P(cvo_cloud), P(cvo_params), P(dbl), i32,
                                    P(i32), P(dbl)]
     L.cvo_register.argtypes = [vp, P(cvo_cloud), P(cvo_cloud), P(cvo_params), P(dbl), P(dbl),
@@ -126,7 +127,7 @@ def load():
     for name in ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
                  "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
                  "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend", "cvo_serving_stats",
-                 "cvo_set_queue_limit"):
+                 "cvo_set_queue_limit", "cvo_eval_static"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -135,7 +136,7 @@ def load():
 EXPORTED = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
             "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
             "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend", "cvo_serving_stats",
-            "cvo_set_queue_limit", "cvo_strerror", "cvo_last_error")
+            "cvo_set_queue_limit", "cvo_eval_static", "cvo_strerror", "cvo_last_error")
 
 
 class CvoError(RuntimeError):
@@ -314,6 +315,20 @@ class Context:
         v = (ctypes.c_double * 3)()
         self._check(self.L.cvo_eval(self.h, ctypes.byref(s.c), ctypes.byref(t.c), ctypes.byref(p), Tp,
                                     ctypes.byref(F), w, v), "cvo_eval")
+        return np.array([F.value, *w[:], *v[:]])
+
+    def eval_static(self, src_xyz, src_feat, tgt_xyz, tgt_feat, T, params: Params):
+        """eval() through cvo_eval_static: no allocation inside the library call
+        (the device buffers come from the library's per-device static array)."""
+        s, t = _Cloud(src_xyz, src_feat), _Cloud(tgt_xyz, tgt_feat)
+        self._sync_stream([s, t])
+        p, keep = params.to_c()
+        Ta, Tp = _pose(T)
+        F = ctypes.c_double()
+        w = (ctypes.c_double * 3)()
+        v = (ctypes.c_double * 3)()
+        self._check(self.L.cvo_eval_static(self.h, ctypes.byref(s.c), ctypes.byref(t.c), ctypes.byref(p), Tp,
+                                           ctypes.byref(F), w, v), "cvo_eval_static")
         return np.array([F.value, *w[:], *v[:]])
 
     def frontend(self, depth, rgb, k, fx, fy, cx, cy, dmin=0.5, dmax=5.0):

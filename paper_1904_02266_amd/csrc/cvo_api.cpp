@@ -308,6 +308,30 @@ static int fail(cvo_ctx* c, hipError_t e, const char* what) {
   } while (0)
 
 // ---------------------------------------------------------------------------
+// the allocation-free evaluation's device array: its address per device
+// (looked up once, by cvo_create with that device current), and a lock per
+// device that serialises the calls sharing it
+// ---------------------------------------------------------------------------
+constexpr int kMaxDevices = 64;
+constexpr int kStaticMaxPoints = 65536;  // points per cloud of cvo_eval_static
+static std::mutex g_static_mu;
+static void* g_static_ptr[kMaxDevices] = {};
+static std::mutex g_static_call_mu[kMaxDevices];
+static char g_static_host[kMaxDevices][64 * 1024];  // host staging of the set-up structures
+
+static hipError_t init_static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_static_mu);
+  if (g_static_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = static_scratch_address(&p);
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_static_ptr[device] = p;
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
 // validation and request construction
 // ---------------------------------------------------------------------------
 static bool finite_host(const float* p, size_t cnt) {
@@ -997,6 +1021,12 @@ int cvo_create(int device, uint64_t hbm_budget_bytes, int max_slots, cvo_ctx** o
     return CVO_EDEVICE;
   }
   c->stream = c->own_stream;
+  if (init_static_scratch(device) != hipSuccess) {
+    (void)hipStreamDestroy(c->own_stream);
+    (void)hipStreamDestroy(c->serve_stream);
+    delete c;
+    return CVO_EDEVICE;
+  }
   if (hbm_budget_bytes == 0) {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess) hbm_budget_bytes = (uint64_t)(0.8 * (double)fr);
@@ -1084,6 +1114,71 @@ int cvo_eval(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
   return CVO_OK;
 }
 
+// cvo_eval without allocation: every device buffer of the evaluation (the
+// request's set-up and iteration arenas, its constants, the work list) is
+// carved out of the device's static array; host structures are staged through
+// a static host buffer.  The same kernels as cvo_eval, on the context's stream.
+static int run_eval_static(cvo_ctx* c, Request& q) {
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  char* base = (char*)g_static_ptr[c->device];
+  if (!base) return CVO_EDEVICE;
+  char* host = g_static_host[c->device];
+  // layout: [ReqStatic | clus_end | WorkQueue] [arena A] [arena B] [work items]
+  const size_t off_reqs = 0;
+  const size_t off_end = align_up(sizeof(ReqStatic), 256);
+  const size_t off_wq = off_end + 256;
+  const size_t off_a = off_wq + 256;
+  const Layout L = plan(q);
+  const size_t off_b = align_up(off_a + L.total, 256);
+  if (off_b > kStaticScratchBytes) {
+    c->last_error = "cvo_eval_static: inputs exceed the static device array";
+    return CVO_ENOMEM;
+  }
+  q.arena = base + off_a;
+  q.arena_bytes = L.total;
+  int rc = enqueue_ingest(c, q, L, s, host);
+  if (rc) return rc;
+  ReqState* hs = (ReqState*)(host + 32768);
+  HIPCHK(c, hipMemcpyAsync(hs, q.state, sizeof(ReqState), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  q.nclus = hs->nclus;
+  if (hs->done) {
+    fill_result(q, *hs);
+    q.status = hs->status;
+    return CVO_OK;
+  }
+  const LayoutB LB = plan_b(q, q.nclus);
+  const size_t off_items = align_up(off_b + LB.total, 256);
+  const unsigned long long cap = (unsigned long long)std::max(q.nclus, 1) * kChunksMax;
+  if (off_items + cap * sizeof(unsigned int) > kStaticScratchBytes) {
+    c->last_error = "cvo_eval_static: the target clusters' buffers exceed the static device array";
+    return CVO_ENOMEM;
+  }
+  q.arena_b = base + off_b;
+  q.arena_b_bytes = LB.total;
+  rc = finish_setup(c, q, L, LB, s);
+  if (rc) return rc;
+  ReqStatic* hst = (ReqStatic*)(host + 16384);
+  int* hend = (int*)(host + 16384 + sizeof(ReqStatic) + 64);
+  *hst = q.st;
+  *hend = q.nclus;
+  ReqStatic* d_reqs = (ReqStatic*)(base + off_reqs);
+  int* d_end = (int*)(base + off_end);
+  const QueueRef QR{(WorkQueue*)(base + off_wq), (unsigned int*)(base + off_items), (unsigned int)cap};
+  HIPCHK(c, hipMemcpyAsync(d_reqs, hst, sizeof(ReqStatic), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(d_end, hend, sizeof(int), hipMemcpyHostToDevice, s));
+  // the work list starts empty (the array keeps the previous call's contents)
+  HIPCHK(c, launch_zero(QR.q, sizeof(WorkQueue), s));
+  HIPCHK(c, launch_iteration_rule(kStepFixed, q.precision, q.fd, q.kappa > 0.0, d_reqs, d_end, 1, q.nclus, QR, s));
+  HIPCHK(c, hipMemcpyAsync(hs, q.state, sizeof(ReqState), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  fill_result(q, *hs);
+  q.status = hs->status;
+  q.res.device_bytes = off_items + cap * sizeof(unsigned int);
+  return CVO_OK;
+}
+
 int cvo_quartic(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* p, const double T[16],
                 const double omega[3], const double v[3], double coef[5]) {
   if (!c || !omega || !v || !coef) return CVO_EINVAL;
@@ -1101,6 +1196,30 @@ int cvo_quartic(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cv
   if (rc) return rc;
   if (q.status) return q.status;
   for (int i = 0; i < 5; i++) coef[i] = q.coef[i];
+  return CVO_OK;
+}
+
+int cvo_eval_static(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* p, const double T[16],
+                    double* F, double omega[3], double v[3]) {
+  if (!c) return CVO_EINVAL;
+  Request q;
+  int rc = build_request(src, tgt, p, T, kModeEval, q);
+  if (rc) return rc;
+  if (q.n > kStaticMaxPoints || q.m > kStaticMaxPoints) {
+    c->last_error = "cvo_eval_static: more than 65,536 points in a cloud";
+    return CVO_ENOMEM;
+  }
+  if (c->device < 0 || c->device >= kMaxDevices) return CVO_EDEVICE;
+  std::lock_guard<std::mutex> g(c->call_mu);
+  std::lock_guard<std::mutex> gd(g_static_call_mu[c->device]);
+  rc = run_eval_static(c, q);
+  if (rc) return rc;
+  if (q.status) return q.status;
+  if (F) *F = q.res.F;
+  for (int a = 0; a < 3; a++) {
+    if (omega) omega[a] = q.res.omega[a];
+    if (v) v[a] = q.res.v[a];
+  }
   return CVO_OK;
 }
 

@@ -240,6 +240,10 @@ struct FrontendArgs {
 };
 hipError_t launch_frontend(const FrontendArgs& a, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// The allocation-free evaluation's device array (cvo_eval_static): its size,
+// and its device address on the current device.
+constexpr size_t kStaticScratchBytes = 64ull << 20;
+hipError_t static_scratch_address(void** ptr);
 // One gradient-flow iteration (or one evaluation) for a batch of requests that
 // share precision, label dimension and cutoff mode.  clus_end[r] is the
 // cumulative cluster count of requests 0..r.

@@ -2134,6 +2134,14 @@ static inline int blocks_for(long long work, int bs, int cap) {
   return (int)b;
 }
 
+// Device memory of the allocation-free evaluation (cvo_eval_static): one
+// file-scope array per device, alive until the process ends.  Host code never
+// passes the array's name to a kernel (in host code it is a stand-in, not a
+// device address); it asks for the device address once per device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch_address(void** ptr) { return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch)); }
+
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t words = bytes / 4;
   if (words == 0) return hipSuccess;
