@@ -48,6 +48,11 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "dense300k_trajectory.json")
 SAMPLE_ITERS = (0, 25, 50, 99)   # one iteration of each length-scale stage (oracle sample, parity)
 
 
+def progress(msg):
+    """One line per finished leg on stderr (the JSON line stays alone on stdout)."""
+    print(f"bench: {msg} ({time.strftime('%H:%M:%S')})", file=sys.stderr, flush=True)
+
+
 def measured_traffic(path=TRAFFIC_FILE):
     """HBM bytes per pair-kernel launch from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None when
@@ -231,6 +236,7 @@ def serving(pool, rates=(200, 500, 1000, 2000), window_s=10.0, table1_rates=(200
         ok = [r for r, _ in res if r["rc"] == 0]
         lat = np.array([r["wall_ms"] for r in ok])
         end = max(ts + r["wall_ms"] / 1e3 for r, ts in res)
+        progress(f"serving {pname} at {rate}/s: {len(ok)} of {len(res)} in {end:.1f} s")
         out.append({"params": pname, "rate": rate, "requests": len(res), "completed": len(ok),
                     "throughput_per_s": len(ok) / end, "span_s": end,
                     "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
@@ -491,6 +497,7 @@ def main():
         sys.exit(2)
     extra = not args.no_extra
     batch_clouds = gen_batch(args.batch if extra else 0)
+    progress(f"batched inputs drawn ({len(batch_clouds)})")
     serve_pool = gen_serving_pool(6 if (args.serving_window > 0 and extra) else 0)
     with ProcessPoolExecutor(max_workers=1) as ex:
         dense_cloud, G = ex.submit(_gen_dense, 3).result()
@@ -512,12 +519,15 @@ def main():
     prm = params_rgbd()
 
     # headline: the dense registration, timed region = the registrations alone
+    progress("inputs ready")
     r = time_registrations(ctx, t, prm, args.steps, args.warmup)
     out, elapsed, lat, ks = r["out"], r["elapsed"], r["lat"], r["ks"]
+    progress(f"headline: {elapsed * 1e3 / args.steps:.1f} ms per registration")
 
     cpu = parity = None
     if not args.no_oracle:
         cpu, parity = oracle_sample(pair, golden, ctx, t)
+        progress(f"oracle sample: {cpu['value']:.3g} pair-evals/s on {cpu['cores']} threads")
 
     # the same registration with every pair term in FP64
     prm64 = params_rgbd(precision="fp64")
@@ -540,10 +550,14 @@ def main():
 
     c2 = batch = serve = dense = fe = c1 = odo = None
     if extra:
+        progress("fp64 path done")
         c2 = rgbd30k(ctx, synth.rgbd_pair(30000, 30000, seed=2), max(4, args.steps), args.quartic_steps)
+        progress("rgbd 30k done")
         batch = batched_both(batch_clouds) if batch_clouds else None
+        progress("batched done")
         serve = serving(serve_pool, window_s=args.serving_window) if serve_pool else None
         dense = dense_bruteforce(dense_cloud)
+        progress("dense brute force done")
         fe = frontend_vga(odo_frames[0]) if odo_frames else None
         c1 = planes_c1()
         if odo_frames:
