@@ -135,6 +135,13 @@ typedef struct {
                                0x1C: planar motion SE(2) (rotation about z, translation in x, y);
                                0x07: SO(3); 0x38: translations.  The trace and result report the full
                                gradient. */
+  int32_t work_item_min;    /* work items: a target cluster's candidate sources are cut into items of at
+                               least this many sources (8 .. 2^20); 0: the context's tuning table */
+  int32_t work_items_max;   /* ... and at most this many items per cluster (1 .. 256); 0: the table.
+                               The sizing changes only how the pair terms are grouped into compensated
+                               FP32 partials and FP64 sums (results agree to that rounding); it depends
+                               on the request alone, so a request gives the same result alone and in a
+                               batch. */
 } cvo_params;
 
 /* One organised RGB-D frame (the input of the front end, Sec. VII-B). */
@@ -278,6 +285,15 @@ int cvo_set_queue_limit(cvo_ctx* ctx, int64_t max_pending);
  * or a ticket polled long ago). */
 int cvo_trace(cvo_ctx* ctx, uint64_t ticket, double* buf, int32_t cap);
 
+/* Launch mode of cvo_register's iteration loop: 0 (default) launches each
+ * iteration's kernels on the stream; 1 captures a chunk of iterations (the
+ * whole registration, or 16 iterations when a stopping tolerance is set) as a
+ * HIP graph once per launch layout and replays it per chunk (the kernels read
+ * the request's state on the device and return at once after it has
+ * stopped).  Graphs need a stream other than the legacy null stream; with
+ * profiling on, or on the null stream, iterations are launched directly. */
+int cvo_set_graphs(cvo_ctx* ctx, int32_t enable);
+
 /* Event timing of the kernels of each iteration (the per-cluster
  * candidate-list kernel, the pair kernel and, with the quartic rule, the pair
  * kernel's second pass): when enabled, every iteration of cvo_register
@@ -288,6 +304,18 @@ int cvo_set_profiling(cvo_ctx* ctx, int32_t enable);
  * quartic pass, and the pairs within the cutoff evaluated (gradient pass). */
 int cvo_kernel_stats(cvo_ctx* ctx, int32_t reset, int64_t* iterations, double* pair_ms, double* prepare_ms,
                      double* quartic_ms, uint64_t* pairs);
+
+/* The work-item sizing the context gives a request of n sources, m targets,
+ * with (cutoff = 1) or without a cutoff when its parameters leave it at 0:
+ * the first class of the tuning table that matches, else 256 sources per item
+ * and 64 items per cluster.  The table is read by cvo_create from the file
+ * named by the CVO_TUNING_FILE environment variable, else from tuning.json
+ * one directory above the library file: {"classes": [{"cutoff": 0|1,
+ * "max_points": N, "work_item_min": N, "work_items_max": N}, ...]} (classes
+ * in order; a request matches the first of its kind with max(n, m) <=
+ * max_points).  *table_classes receives the classes loaded (0: none). */
+int cvo_tuning(cvo_ctx* ctx, int32_t n, int32_t m, int32_t cutoff, int32_t* work_item_min, int32_t* work_items_max,
+               int32_t* table_classes);
 
 /* Static text for a return code; cvo_last_error gives the last HIP message. */
 const char* cvo_strerror(int code);

@@ -49,7 +49,8 @@ class cvo_params(ctypes.Structure):
                 ("stage_ell", ctypes.POINTER(ctypes.c_double)),
                 ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("trace", ctypes.c_int32), ("step_rule", ctypes.c_int32),
-                ("grad_tol", ctypes.c_double), ("kernel_floor", ctypes.c_double), ("dof_mask", ctypes.c_int32)]
+                ("grad_tol", ctypes.c_double), ("kernel_floor", ctypes.c_double), ("dof_mask", ctypes.c_int32),
+                ("work_item_min", ctypes.c_int32), ("work_items_max", ctypes.c_int32)]
 
 
 class cvo_serving_counters(ctypes.Structure):
@@ -120,6 +121,8 @@ def load():
     L.cvo_frontend.argtypes = [vp, P(cvo_rgbd_frame), i32, vp, vp, P(i32)]
     L.cvo_serving_stats.argtypes = [vp, P(cvo_serving_counters)]
     L.cvo_set_queue_limit.argtypes = [vp, ctypes.c_int64]
+    L.cvo_tuning.argtypes = [vp, i32, i32, i32, P(i32), P(i32), P(i32)]
+    L.cvo_set_graphs.argtypes = [vp, i32]
     L.cvo_strerror.argtypes = [ctypes.c_int]
     L.cvo_strerror.restype = ctypes.c_char_p
     L.cvo_last_error.argtypes = [vp]
@@ -127,7 +130,7 @@ def load():
     for name in ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
                  "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
                  "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend", "cvo_serving_stats",
-                 "cvo_set_queue_limit", "cvo_eval_static"):
+                 "cvo_set_queue_limit", "cvo_eval_static", "cvo_tuning", "cvo_set_graphs"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -136,7 +139,8 @@ def load():
 EXPORTED = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
             "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
             "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend", "cvo_serving_stats",
-            "cvo_set_queue_limit", "cvo_eval_static", "cvo_strerror", "cvo_last_error")
+            "cvo_set_queue_limit", "cvo_eval_static", "cvo_tuning", "cvo_set_graphs", "cvo_strerror",
+            "cvo_last_error")
 
 
 class CvoError(RuntimeError):
@@ -165,6 +169,8 @@ class Params:
     grad_tol: float = 0.0
     kernel_floor: float = 0.0
     dof_mask: int = 0
+    work_item_min: int = 0       # 0: the context's tuning table
+    work_items_max: int = 0
 
     def to_c(self):
         ns = len(self.stage_ell)
@@ -174,7 +180,8 @@ class Params:
                        ctypes.cast(si, ctypes.POINTER(ctypes.c_int32)),
                        ctypes.cast(se, ctypes.POINTER(ctypes.c_double)), self.max_iters, self.tol,
                        CVO_FP64 if self.precision == "fp64" else CVO_FP32_KAHAN, 1 if self.trace else 0,
-                       STEP_RULES[self.step_rule], self.grad_tol, self.kernel_floor, self.dof_mask)
+                       STEP_RULES[self.step_rule], self.grad_tol, self.kernel_floor, self.dof_mask,
+                       self.work_item_min, self.work_items_max)
         return p, (si, se)
 
 
@@ -284,11 +291,22 @@ class Context:
         return rc
 
     def _sync_stream(self, clouds):
+        """Device inputs: run on torch's current stream, ordered after the work
+        queued there.  torch's legacy default stream cannot carry that order
+        (the library then uses its own non-blocking stream), so it is
+        synchronized first."""
         if any(c.on_device for c in clouds):
             import torch
-            self.L.cvo_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+            cur = torch.cuda.current_stream(self.device)
+            if cur.cuda_stream == 0:
+                cur.synchronize()
+            self.L.cvo_set_stream(self.h, ctypes.c_void_p(cur.cuda_stream))
         else:
             self.L.cvo_set_stream(self.h, None)
+
+    def set_graphs(self, on=True):
+        """Replay cvo_register's iteration chunks as HIP graphs (see cvo_set_graphs)."""
+        self._check(self.L.cvo_set_graphs(self.h, 1 if on else 0), "set_graphs")
 
     def set_profiling(self, on=True):
         self._check(self.L.cvo_set_profiling(self.h, 1 if on else 0), "set_profiling")
@@ -423,6 +441,14 @@ class Context:
         if rows == CVO_PENDING and ticket != 0:
             return None
         return buf[:rows]
+
+    def tuning(self, n, m, cutoff=True):
+        """(work_item_min, work_items_max, classes in the loaded table) for a request
+        of n sources and m targets."""
+        a, b_, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.L.cvo_tuning(self.h, n, m, 1 if cutoff else 0, ctypes.byref(a), ctypes.byref(b_),
+                                      ctypes.byref(t)), "cvo_tuning")
+        return a.value, b_.value, t.value
 
     def set_queue_limit(self, max_pending):
         self._check(self.L.cvo_set_queue_limit(self.h, int(max_pending)), "cvo_set_queue_limit")

@@ -23,6 +23,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include <dlfcn.h>
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "../../include/cvo.h"
@@ -48,6 +49,7 @@ struct Request {
   int n = 0, m = 0, fd = 0, n_stages = 1, max_iters = 1, precision = 0, trace_on = 0;
   int step_rule = kStepFixed;
   int dof_mask = 0x3F;
+  int chunk_min = kChunkMinDefault, chunks_max = kChunksMaxDefault;  // work-item sizing
   double xi0[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // direction of the coefficient evaluation
   double sigma = 0.1, sf = 0.2, a2 = -1.0, b2 = 1.0, eta = 1.0, kappa = 0.0, tol = 0.0, grad_tol = 0.0;
   int stage_iters[kMaxStages] = {0};
@@ -170,9 +172,9 @@ LayoutB plan_b(const Request& q, int nclus) {
   const size_t nc = (size_t)nclus;
   L.off_cinfo = take(sizeof(ClusInfo) * nc);
   L.off_cells = take(sizeof(CellEntry) * nc * kCellCap);
-  L.off_centry = take(sizeof(int) * nc * kChunksMax);
+  L.off_centry = take(sizeof(int) * nc * (size_t)q.chunks_max);
   L.off_tblk = take((q.precision == CVO_FP64 ? 8 : 4) * nc * (3 + (size_t)q.fd) * kWave);
-  L.off_sslots = take(8 * nc * kChunksMax * kSlot);
+  L.off_sslots = take(8 * nc * (size_t)q.chunks_max * kSlot);
   L.off_csum = take(8 * nc * kSlot);
   L.off_trace = q.trace_on ? take((size_t)q.max_iters * kTraceCols * 8) : 0;
   L.off_pt = (q.mode == kModeEvalTargets) ? take((size_t)q.m * 7 * 8) : 0;
@@ -202,13 +204,14 @@ struct DevQueue {
   unsigned int* items = nullptr;
   unsigned int cap = 0;
   QueueRef ref() const { return QueueRef{q, items, cap}; }
-  // capacity for a launch over total_clusters clusters; false if out of memory
-  bool ensure(int total_clusters) {
+  // capacity for a launch of max_items work items (the sum over its
+  // requests of clusters x chunks_max); false if out of memory
+  bool ensure(unsigned long long max_items) {
     if (!q && hipMalloc(&q, sizeof(WorkQueue)) != hipSuccess) {
       q = nullptr;
       return false;
     }
-    const unsigned long long need = (unsigned long long)std::max(total_clusters, 1) * kChunksMax;
+    const unsigned long long need = std::max(max_items, 1ull);
     if (need > 0xffffffffull) return false;
     if (need <= cap) return true;
     const unsigned long long want = std::min<unsigned long long>(std::max<unsigned long long>(need, 2ull * cap), 0xffffffffull);
@@ -262,6 +265,22 @@ struct cvo_ctx {
   Request last_register;
   bool have_last = false;
 
+  // iteration chunks replayed as HIP graphs (synchronous path)
+  bool graphs = false;
+  struct GraphKey {
+    int nclus = -1, precision = -1, fd = -1, cut = -1, rule = -1, iters = -1;
+    const void* items = nullptr;
+    unsigned int cap = 0;
+    hipStream_t stream = nullptr;
+    bool operator==(const GraphKey& o) const {
+      return nclus == o.nclus && precision == o.precision && fd == o.fd && cut == o.cut && rule == o.rule &&
+             iters == o.iters && items == o.items && cap == o.cap && stream == o.stream;
+    }
+  };
+  GraphKey graph_key;
+  hipGraphExec_t graph_exec = nullptr;
+  int64_t graph_captures = 0, graph_launches = 0;
+
   // profiling
   bool profile = false;
   std::vector<hipEvent_t> ev_pool;
@@ -271,6 +290,15 @@ struct cvo_ctx {
   double prof_quart_ms = 0.0;    // pair kernel, quartic pass
   uint64_t prof_pairs = 0;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
+
+  // work-item sizing per size class (tuning table, loaded by cvo_create)
+  struct TuneClass {
+    int cutoff;      // 1: requests with a cutoff, 0: brute force
+    int max_points;  // the class holds requests with max(n, m) <= max_points
+    int chunk_min, chunks_max;
+  };
+  std::vector<TuneClass> tuning;
+  std::string tuning_path;
 
   // serving
   std::mutex q_mu;
@@ -332,6 +360,106 @@ static hipError_t init_static_scratch(int device) {
 }
 
 // ---------------------------------------------------------------------------
+// tuning table: {"classes": [{"cutoff": 0|1, "max_points": N, "work_item_min": N,
+// "work_items_max": N}, ...], ...}.  Only the integer fields of the objects of
+// the "classes" array are read; other fields are ignored.
+// ---------------------------------------------------------------------------
+static bool parse_tuning(const std::string& text, std::vector<cvo_ctx::TuneClass>& out) {
+  const size_t arr = text.find("\"classes\"");
+  if (arr == std::string::npos) return false;
+  size_t p = text.find('[', arr);
+  if (p == std::string::npos) return false;
+  out.clear();
+  // walk the array: each object at depth 1 is a class (nested objects and
+  // quoted strings are skipped over)
+  int depth = 0;
+  size_t ob = std::string::npos;
+  for (size_t k = p + 1; k < text.size(); k++) {
+    const char ch = text[k];
+    if (ch == '"') {
+      for (k++; k < text.size() && text[k] != '"'; k++)
+        if (text[k] == '\\') k++;
+      continue;
+    }
+    if (ch == '{' && depth++ == 0) ob = k;
+    if (ch == '}' && --depth == 0) {
+      const std::string obj = text.substr(ob, k - ob + 1);
+      auto field = [&](const char* key, long long* v) {
+        const std::string kq = std::string("\"") + key + "\"";
+        const size_t at = obj.find(kq);
+        if (at == std::string::npos) return false;
+        const size_t colon = obj.find(':', at + kq.size());
+        if (colon == std::string::npos) return false;
+        char* e = nullptr;
+        const long long x = strtoll(obj.c_str() + colon + 1, &e, 10);
+        if (e == obj.c_str() + colon + 1) return false;
+        *v = x;
+        return true;
+      };
+      long long cut, mp, cmin, cmax;
+      if (!field("cutoff", &cut) || !field("max_points", &mp) || !field("work_item_min", &cmin) ||
+          !field("work_items_max", &cmax))
+        return false;
+      if (cmin < kChunkMinLo || cmin > (1 << 20) || cmax < 1 || cmax > kChunksCap || mp < 1) return false;
+      out.push_back(cvo_ctx::TuneClass{cut ? 1 : 0, (int)std::min<long long>(mp, INT32_MAX), (int)cmin, (int)cmax});
+    }
+    if (depth < 0 || (ch == ']' && depth == 0)) break;
+  }
+  return !out.empty() && depth == 0;
+}
+
+// The table next to the library (<package>/tuning.json, one level above
+// lib/libcvo.so), or the file named by CVO_TUNING_FILE; none: the defaults.
+static void load_tuning(cvo_ctx* c) {
+  std::string path;
+  if (const char* env = getenv("CVO_TUNING_FILE")) {
+    path = env;
+  } else {
+    Dl_info info;
+    if (dladdr((const void*)&load_tuning, &info) && info.dli_fname) {
+      std::string lib = info.dli_fname;
+      const size_t s1 = lib.rfind('/');
+      const std::string dir = s1 == std::string::npos ? std::string(".") : lib.substr(0, s1);
+      path = dir + "/../tuning.json";
+    }
+  }
+  if (path.empty()) return;
+  FILE* f = fopen(path.c_str(), "rb");
+  if (!f) return;
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof buf, f)) > 0 && text.size() < (1u << 20)) text.append(buf, got);
+  fclose(f);
+  std::vector<cvo_ctx::TuneClass> t;
+  if (parse_tuning(text, t)) {
+    c->tuning = t;
+    c->tuning_path = path;
+  }
+}
+
+// Work-item sizing of a request: the parameters' explicit values, else the
+// first table class of the request's kind (cutoff or not) that holds
+// max(n, m) points, else the defaults.  It depends only on the request
+// itself, so a request runs the same work items alone and in a batch.
+static void tune_request(const cvo_ctx* c, const cvo_params* p, Request& q) {
+  int cmin = kChunkMinDefault, cmax = kChunksMaxDefault;
+  const int pts = std::max(q.n, q.m);
+  const int cut = q.kappa > 0.0 ? 1 : 0;
+  for (const auto& t : c->tuning) {
+    if (t.cutoff == cut && pts <= t.max_points) {
+      cmin = t.chunk_min;
+      cmax = t.chunks_max;
+      break;
+    }
+  }
+  if (p->work_item_min > 0) cmin = p->work_item_min;
+  if (p->work_items_max > 0) cmax = p->work_items_max;
+  q.chunk_min = cmin;
+  q.chunks_max = cmax;
+}
+
+// ---------------------------------------------------------------------------
 // validation and request construction
 // ---------------------------------------------------------------------------
 static bool finite_host(const float* p, size_t cnt) {
@@ -340,8 +468,8 @@ static bool finite_host(const float* p, size_t cnt) {
   return true;
 }
 
-static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* p, const double* T0,
-                         int mode, Request& q) {
+static int build_request(const cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* p,
+                         const double* T0, int mode, Request& q) {
   if (!src || !tgt || !p || !T0) return CVO_EINVAL;
   if (src->n <= 0 || tgt->n <= 0) return CVO_EINVAL;
   if (src->n > kMaxPoints || tgt->n > kMaxPoints) return CVO_EINVAL;
@@ -358,6 +486,9 @@ static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
     return CVO_EINVAL;
   if (!(p->grad_tol >= 0.0) || !(p->kernel_floor >= 0.0) || !std::isfinite(p->kernel_floor)) return CVO_EINVAL;
   if (p->dof_mask < 0 || p->dof_mask > 0x3F) return CVO_EINVAL;
+  if (p->work_item_min < 0 || (p->work_item_min > 0 && (p->work_item_min < kChunkMinLo || p->work_item_min > (1 << 20))))
+    return CVO_EINVAL;
+  if (p->work_items_max < 0 || p->work_items_max > kChunksCap) return CVO_EINVAL;
   // value sparsification (Table 1): sigma^2 exp(-r^2 / (2 ell^2)) >= floor
   // keeps exactly r <= ell sqrt(2 ln(sigma^2 / floor))
   if (p->kernel_floor > 0.0 && (p->cutoff_mult > 0.0 || !(p->sigma * p->sigma > p->kernel_floor)))
@@ -402,6 +533,7 @@ static int build_request(const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
   q.sfeat = src->feat;
   q.tx = tgt->xyz;
   q.tfeat = tgt->feat;
+  tune_request(c, p, q);
   return CVO_OK;
 }
 
@@ -560,6 +692,8 @@ static int finish_setup(cvo_ctx* c, Request& q, const Layout& L, const LayoutB& 
   st.precision = q.precision;
   st.step_rule = q.step_rule;
   st.dof_mask = q.dof_mask;
+  st.chunk_min = q.chunk_min;
+  st.chunks_max = q.chunks_max;
   int end = 0;
   for (int k = 0; k < kMaxStages; k++) {
     if (k < S - 1) {
@@ -626,6 +760,51 @@ static int grow(cvo_ctx* c, char** buf, size_t* have, size_t need, hipStream_t s
   return CVO_OK;
 }
 
+// The executable graph of `iters` consecutive iterations of the synchronous
+// request (its launches captured from the stream once, replayed per chunk):
+// the kernels read the request's state on the device, so one graph serves
+// every chunk, and an exited request's kernels return at once.  Captured
+// again when the launch layout changes.
+static int chunk_graph(cvo_ctx* c, const Request& q, const QueueRef& QR, bool cut, int iters, hipStream_t s,
+                       hipGraphExec_t* out) {
+  cvo_ctx::GraphKey key;
+  key.nclus = q.nclus;
+  key.precision = q.precision;
+  key.fd = q.fd;
+  key.cut = cut ? 1 : 0;
+  key.rule = q.step_rule;
+  key.iters = iters;
+  key.items = QR.items;
+  key.cap = QR.cap;
+  key.stream = s;
+  if (c->graph_exec && c->graph_key == key) {
+    *out = c->graph_exec;
+    return CVO_OK;
+  }
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  c->graph_exec = nullptr;
+  HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < iters && e == hipSuccess; i++)
+    e = launch_iteration_rule(q.step_rule, q.precision, q.fd, cut, c->d_reqs_sync, c->d_clus_end_sync, 1, q.nclus, QR,
+                              s);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(c, e != hipSuccess ? e : e2, "iteration graph capture");
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(c, e, "hipGraphInstantiate");
+  c->graph_exec = ex;
+  c->graph_key = key;
+  c->graph_captures++;
+  *out = ex;
+  return CVO_OK;
+}
+
 // Synchronous single-request run (eval, eval-targets, register).
 static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out) {
   HIPCHK(c, hipSetDevice(c->device));
@@ -674,7 +853,7 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
   HIPCHK(c, hipMemcpyAsync(c->d_reqs_sync, hst, sizeof(ReqStatic), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->d_clus_end_sync, hend, sizeof(int), hipMemcpyHostToDevice, s));
 
-  if (!c->queue_sync.ensure(q.nclus)) return CVO_ENOMEM;
+  if (!c->queue_sync.ensure((unsigned long long)q.nclus * q.chunks_max)) return CVO_ENOMEM;
   HIPCHK(c, c->queue_sync.reset(s));
   const QueueRef QR = c->queue_sync.ref();
   const bool cut = q.kappa > 0.0;
@@ -696,8 +875,19 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
   };
   roctxRangePushA(q.mode == kModeRegister ? "cvo_register" : "cvo_eval");
   RangeGuard range_guard;
+  // graph replay needs a capturable stream (not the legacy null stream)
+  const bool use_graph = c->graphs && !prof && q.mode == kModeRegister && s != nullptr;
   for (int k = 0; k < q.max_iters;) {
     const int kend = std::min(q.max_iters, k + chunk);
+    if (use_graph && kend - k == chunk) {
+      hipGraphExec_t ex = nullptr;
+      const int grc = chunk_graph(c, q, QR, cut, chunk, s, &ex);
+      if (grc) return grc;
+      HIPCHK(c, hipGraphLaunch(ex, s));
+      c->graph_launches++;
+      launched += chunk;
+      k = kend;
+    }
     for (; k < kend; k++) {
       if (prof) {
         hipEvent_t* ev = &c->ev_pool[kEv * k];
@@ -927,17 +1117,19 @@ void scheduler(cvo_ctx* c) {
     }
     struct G {
       int precision, fd, cut, rule, first, count, clusters;
+      unsigned long long items;  // work items at most: sum of clusters x chunks_max
     };
     std::vector<G> gl;
     int pos = 0;
     std::vector<Request*> order;
     for (auto& kv : groups) {
       G g{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first), pos,
-          (int)kv.second.size(), 0};
+          (int)kv.second.size(), 0, 0ull};
       int cl = 0;
       for (Request* q : kv.second) {
         h_reqs[pos] = q->st;
         cl += q->nclus;
+        g.items += (unsigned long long)q->nclus * q->chunks_max;
         h_end[pos] = cl;
         order.push_back(q);
         pos++;
@@ -945,9 +1137,9 @@ void scheduler(cvo_ctx* c) {
       g.clusters = cl;
       gl.push_back(g);
     }
-    int most_clusters = 1;
-    for (const G& g : gl) most_clusters = std::max(most_clusters, g.clusters);
-    bool dev_ok = d_reqs && d_end && h_reqs && h_end && h_states && queue.ensure(most_clusters) &&
+    unsigned long long most_items = 1;
+    for (const G& g : gl) most_items = std::max(most_items, g.items);
+    bool dev_ok = d_reqs && d_end && h_reqs && h_end && h_states && queue.ensure(most_items) &&
                   queue.reset(s) == hipSuccess &&
                   hipMemcpyAsync(d_reqs, h_reqs, sizeof(ReqStatic) * nreq, hipMemcpyHostToDevice, s) == hipSuccess &&
                   hipMemcpyAsync(d_end, h_end, sizeof(int) * nreq, hipMemcpyHostToDevice, s) == hipSuccess;
@@ -1032,6 +1224,7 @@ int cvo_create(int device, uint64_t hbm_budget_bytes, int max_slots, cvo_ctx** o
     if (hipMemGetInfo(&fr, &tot) == hipSuccess) hbm_budget_bytes = (uint64_t)(0.8 * (double)fr);
   }
   c->budget = hbm_budget_bytes;
+  load_tuning(c);
   *out = c;
   return CVO_OK;
 }
@@ -1053,6 +1246,7 @@ int cvo_destroy(cvo_ctx* c) {
   if (c->sync_arena_b) (void)hipFree(c->sync_arena_b);
   if (c->fe_arena) (void)hipFree(c->fe_arena);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->ev_a) (void)hipEventDestroy(c->ev_a);
   if (c->ev_b) (void)hipEventDestroy(c->ev_b);
@@ -1067,6 +1261,13 @@ int cvo_set_stream(cvo_ctx* c, void* stream) {
   if (!c) return CVO_EINVAL;
   std::lock_guard<std::mutex> g(c->call_mu);
   c->stream = stream ? (hipStream_t)stream : c->own_stream;
+  return CVO_OK;
+}
+
+int cvo_set_graphs(cvo_ctx* c, int32_t enable) {
+  if (!c) return CVO_EINVAL;
+  std::lock_guard<std::mutex> g(c->call_mu);
+  c->graphs = enable != 0;
   return CVO_OK;
 }
 
@@ -1100,7 +1301,7 @@ int cvo_eval(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_p
              double* F, double omega[3], double v[3]) {
   if (!c) return CVO_EINVAL;
   Request q;
-  int rc = build_request(src, tgt, p, T, kModeEval, q);
+  int rc = build_request(c, src, tgt, p, T, kModeEval, q);
   if (rc) return rc;
   std::lock_guard<std::mutex> g(c->call_mu);
   rc = run_sync(c, q, nullptr);
@@ -1150,7 +1351,7 @@ static int run_eval_static(cvo_ctx* c, Request& q) {
   }
   const LayoutB LB = plan_b(q, q.nclus);
   const size_t off_items = align_up(off_b + LB.total, 256);
-  const unsigned long long cap = (unsigned long long)std::max(q.nclus, 1) * kChunksMax;
+  const unsigned long long cap = (unsigned long long)std::max(q.nclus, 1) * q.chunks_max;
   if (off_items + cap * sizeof(unsigned int) > kStaticScratchBytes) {
     c->last_error = "cvo_eval_static: the target clusters' buffers exceed the static device array";
     return CVO_ENOMEM;
@@ -1185,7 +1386,7 @@ int cvo_quartic(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cv
   for (int a = 0; a < 3; a++)
     if (!std::isfinite(omega[a]) || !std::isfinite(v[a])) return CVO_EINVAL;
   Request q;
-  int rc = build_request(src, tgt, p, T, kModeQuartic, q);
+  int rc = build_request(c, src, tgt, p, T, kModeQuartic, q);
   if (rc) return rc;
   for (int a = 0; a < 3; a++) {
     q.xi0[a] = omega[a];
@@ -1203,7 +1404,7 @@ int cvo_eval_static(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, cons
                     double* F, double omega[3], double v[3]) {
   if (!c) return CVO_EINVAL;
   Request q;
-  int rc = build_request(src, tgt, p, T, kModeEval, q);
+  int rc = build_request(c, src, tgt, p, T, kModeEval, q);
   if (rc) return rc;
   if (q.n > kStaticMaxPoints || q.m > kStaticMaxPoints) {
     c->last_error = "cvo_eval_static: more than 65,536 points in a cloud";
@@ -1326,7 +1527,7 @@ int cvo_eval_targets(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, con
                      const double T[16], int32_t nsel, const int32_t* sel, double* out) {
   if (!c || !out || nsel < 0 || (nsel > 0 && !sel)) return CVO_EINVAL;
   Request q;
-  int rc = build_request(src, tgt, p, T, kModeEvalTargets, q);
+  int rc = build_request(c, src, tgt, p, T, kModeEvalTargets, q);
   if (rc) return rc;
   for (int k = 0; k < nsel; k++)
     if (sel[k] < 0 || sel[k] >= q.m) return CVO_EINVAL;
@@ -1347,7 +1548,7 @@ int cvo_register(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const c
                  double T_out[16], cvo_result* res) {
   if (!c) return CVO_EINVAL;
   Request q;
-  int rc = build_request(src, tgt, p, T0, kModeRegister, q);
+  int rc = build_request(c, src, tgt, p, T0, kModeRegister, q);
   if (rc) return rc;
   std::lock_guard<std::mutex> g(c->call_mu);
   rc = run_sync(c, q, nullptr);
@@ -1364,7 +1565,7 @@ int cvo_submit(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo
   if (!c || !ticket) return CVO_EINVAL;
   Request* q = new (std::nothrow) Request();
   if (!q) return CVO_ENOMEM;
-  int rc = build_request(src, tgt, p, T0, kModeRegister, *q);
+  int rc = build_request(c, src, tgt, p, T0, kModeRegister, *q);
   if (rc) {
     delete q;
     return rc;
@@ -1475,6 +1676,21 @@ int cvo_trace(cvo_ctx* c, uint64_t ticket, double* buf, int32_t cap) {
   auto kt = c->kept_traces.find(ticket);
   if (kt == c->kept_traces.end()) return CVO_ENOTFOUND;
   return copy_trace(kt->second, buf, cap);
+}
+
+int cvo_tuning(cvo_ctx* c, int32_t n, int32_t m, int32_t cutoff, int32_t* work_item_min, int32_t* work_items_max,
+               int32_t* table_classes) {
+  if (!c || n < 1 || m < 1) return CVO_EINVAL;
+  cvo_params p{};
+  Request q;
+  q.n = n;
+  q.m = m;
+  q.kappa = cutoff ? 1.0 : 0.0;
+  tune_request(c, &p, q);
+  if (work_item_min) *work_item_min = q.chunk_min;
+  if (work_items_max) *work_items_max = q.chunks_max;
+  if (table_classes) *table_classes = (int32_t)c->tuning.size();
+  return CVO_OK;
 }
 
 const char* cvo_strerror(int code) {

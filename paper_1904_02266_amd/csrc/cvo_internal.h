@@ -14,10 +14,15 @@ constexpr int kSlot = 9;            // doubles per partial: W, omega[3], D[3], p
 constexpr int kTraceCols = 26;      // F, omega[3], v[3], tau, ell, pairs, T[16] after the step
 constexpr int kZBits = 6;           // Morton bits per axis for the target spatial order
 constexpr int kZBuckets = 1 << (3 * kZBits);
-constexpr int kChunkMin = 256;      // candidate sources per work item (chunk), at least
-constexpr int kChunksMax = 64;      // work items per target cluster, at most
-constexpr int kItemShift = 6;       // work item = launch-wide cluster index << kItemShift | chunk
-static_assert((1 << kItemShift) >= kChunksMax, "chunk index fits the item encoding");
+// Work items: a target cluster's candidate sources are cut into chunks of at
+// least chunk_min sources and at most chunks_max chunks (per request, from the
+// tuning table or the parameters; these are the defaults and the limits).
+constexpr int kChunkMinDefault = 256;  // candidate sources per work item, at least
+constexpr int kChunksMaxDefault = 64;  // work items per target cluster, at most
+constexpr int kChunkMinLo = 8;
+constexpr int kChunksCap = 256;     // the largest chunks_max
+constexpr int kItemShift = 8;       // work item = launch-wide cluster index << kItemShift | chunk
+static_assert((1 << kItemShift) >= kChunksCap, "chunk index fits the item encoding");
 constexpr int kMaxLaunchClusters = 1 << (32 - kItemShift);
 constexpr int kPairBlockWaves = 16;  // wavefronts per FP32 pair-kernel workgroup (one workgroup per CU; FP64: 8)
 constexpr int kCellCap = 512;       // cell-list entries per cluster; beyond: box enumeration
@@ -85,7 +90,7 @@ struct ClusInfo {
   int total;          // candidate sources of the cluster
   int ncells;         // list entries (may exceed kCellCap: then overflow)
   int overflow;       // 1: the pair kernel enumerates the candidate box itself
-  int nchunks;        // work items of the cluster (1..kChunksMax)
+  int nchunks;        // work items of the cluster (1..chunks_max)
   int chunk;          // candidate sources per work item (the last one may hold fewer)
   int s0, cn;         // first sorted target and target count
   int stage;
@@ -102,7 +107,7 @@ struct WorkQueue {
 struct QueueRef {
   WorkQueue* q;
   unsigned int* items;  // [cap]
-  unsigned int cap;     // >= total clusters * kChunksMax
+  unsigned int cap;     // >= sum over the launch's requests of clusters * chunks_max
 };
 
 struct ReqState;
@@ -119,10 +124,10 @@ struct ReqStatic {
   const GridInfo* grid;              // [n_stages]
   ClusInfo* cinfo;                   // [nclus]
   CellEntry* cells;                  // [nclus][kCellCap]
-  int* centry;                       // [nclus][kChunksMax] list entry holding each chunk's first candidate
+  int* centry;                       // [nclus][chunks_max] list entry holding each chunk's first candidate
   void* tblk;                        // [nclus][3 + fd][kWave] targets in the cluster frame (scaled, relative
                                      // to O; far away for lanes past the cluster) and labels, pair type
-  double* sslots;                    // [nclus][kChunksMax][kSlot] work-item partials
+  double* sslots;                    // [nclus][chunks_max][kSlot] work-item partials
   double* csum;                      // [nclus][kSlot] per-cluster sums of the partials
   double* trace;                     // [max_iters][kTraceCols] or null
   double* per_target;                // [m][7] or null (per-target terms, eval-targets mode)
@@ -130,6 +135,8 @@ struct ReqStatic {
   int n_stages, max_iters, mode, precision;
   int step_rule;
   int dof_mask;                      // generators the flow moves along: bits 0-2 omega, 3-5 v
+  int chunk_min;                     // work items: candidate sources per item at least
+  int chunks_max;                    // work items per target cluster at most (<= kChunksCap)
   int stage_end[kMaxStages];         // iteration index where stage s ends; last = INT_MAX
   double stage_ell[kMaxStages];
   double s2f;                        // sigma^2 * s_f

@@ -1012,8 +1012,8 @@ __device__ __forceinline__ void cand_cell(const GridInfo& g, const CandBox& B, c
 //    frame, so that a work item needs no FP64 transform and no dependent
 //    look-ups before its first pair.
 //  * The compacted list of reachable non-empty source cells in box order, the
-//    candidate count, and the cut into work items of at least kChunkMin
-//    sources (at most kChunksMax per cluster) with the list entry that holds
+//    candidate count, and the cut into work items of at least chunk_min
+//    sources (at most chunks_max per cluster) with the list entry that holds
 //    each item's first candidate.  The cells of a round (up to 16 per lane,
 //    lane-major, so that the list keeps box order) are looked up together.
 //  * The items are appended to the launch's work list, one atomic per
@@ -1084,7 +1084,7 @@ __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ r
       for (int a = 0; a < 3; a++) rho2 += valid ? (zt[a] - O[a]) * (zt[a] - O[a]) : 0.0;
       const CandBox B = cand_box_frame(g, O, blo, bhi, sqrt(wave_max(rho2)));
       CellEntry* list = R.cells + (size_t)c * kCellCap;
-      int* centry = R.centry + (size_t)c * kChunksMax;
+      int* centry = R.centry + (size_t)c * R.chunks_max;
       constexpr int PR = kWave * kPrepCells;
       const int rounds = (B.ncand + PR - 1) / PR;
       int ccnt[kPrepCells], cfirst[kPrepCells], cpack[kPrepCells];
@@ -1114,8 +1114,8 @@ __global__ __launch_bounds__(256) void k_prepare(const ReqStatic* __restrict__ r
         chunk = total > 0 ? total : 1;
         nchunks = 1;
       } else {
-        chunk = (int)(((long long)total + kChunksMax - 1) / kChunksMax);
-        chunk = chunk < kChunkMin ? kChunkMin : chunk;
+        chunk = (int)(((long long)total + R.chunks_max - 1) / R.chunks_max);
+        chunk = chunk < R.chunk_min ? R.chunk_min : chunk;
         nchunks = (int)(((long long)total + chunk - 1) / chunk);
         nchunks = nchunks < 1 ? 1 : nchunks;
       }
@@ -1436,7 +1436,7 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const C
 
   // entry window: lane k holds entry we0 + k (the entry holding the item's
   // first candidate was found by the prepare kernel)
-  int we0 = uniform(R.centry[(size_t)c * kChunksMax + k]);
+  int we0 = uniform(R.centry[(size_t)c * R.chunks_max + k]);
   int navail = 0;
   long long win_end = 0;
   CellEntry me;
@@ -1688,7 +1688,7 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
       base += lane_value(incl, kWave - 1);
     }
   }
-  double* row = R.sslots + ((size_t)c * kChunksMax + k) * kSlot;
+  double* row = R.sslots + ((size_t)c * R.chunks_max + k) * kSlot;
   if constexpr (QUART) {
     double a4[4];
     op.acc.result(a4);
@@ -1817,14 +1817,26 @@ __global__ __launch_bounds__(256) void k_reduce(const ReqStatic* __restrict__ re
   if (uniform(R.state->done)) return;
   const int c = lc - (r > 0 ? clus_end[r - 1] : 0);
   const int l = lane_id();
-  // clusters past the current stage's count hold no items: a zero row
+  // clusters past the current stage's count hold no items: a zero row.
+  // Lane l holds chunks l, l + 64, l + 128, l + 192 (those that exist),
+  // added in that order.
   const int nch = c < uniform(R.state->nclus_s[uniform(R.state->stage)]) ? uniform(R.cinfo[c].nchunks) : 0;
-  const double* row = R.sslots + ((size_t)c * kChunksMax + (l < nch ? l : 0)) * kSlot;
+  const double* rows = R.sslots + (size_t)c * R.chunks_max * kSlot;
   double v[kSlot];
 #pragma unroll
-  for (int q = 0; q < kSlot; q++) v[q] = row[q];
+  for (int q = 0; q < kSlot; q++) v[q] = 0.0;
+  for (int b = 0; b < kChunksCap; b += kWave) {
+    if (b >= nch) break;  // wave-uniform
+    const bool has = b + l < nch;
+    const double* row = rows + (size_t)(has ? b + l : 0) * kSlot;
 #pragma unroll
-  for (int q = 0; q < kSlot; q++) v[q] = wave_sum(l < nch ? v[q] : 0.0);
+    for (int q = 0; q < kSlot; q++) {
+      const double x = row[q];
+      v[q] += has ? x : 0.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kSlot; q++) v[q] = wave_sum(v[q]);
   // every lane holds the sums; all store them (same address, same value)
   double* out = R.csum + (size_t)c * kSlot;
 #pragma unroll
@@ -2229,7 +2241,7 @@ static hipError_t launch_pairs3(const ReqStatic* reqs, const int* clus_end, int 
     if (resident <= 0) return hipErrorInvalidValue;
     resident_cache.store(resident, std::memory_order_relaxed);
   }
-  const long long most = (long long)total * kChunksMax;
+  const long long most = (long long)Q.cap;
   const int blocks = (int)(most < resident ? most : resident);
   hipLaunchKernelGGL((k_pairs<CT, FD, CUT, QUART>), dim3(blocks), dim3(PairWaves<CT>::value * kWave), 0, s, reqs,
                      clus_end, nreq, Q);
@@ -2263,7 +2275,7 @@ static hipError_t launch_pairs_fd(int fd, bool cut, bool quart, const ReqStatic*
 
 static bool queue_fits(int total_clusters, const QueueRef& Q) {
   return Q.q && Q.items && total_clusters >= 1 && total_clusters < kMaxLaunchClusters &&
-         (unsigned long long)total_clusters * kChunksMax <= Q.cap;
+         (unsigned long long)total_clusters <= Q.cap;
 }
 
 hipError_t launch_prepare(const ReqStatic* reqs, const int* clus_end, int nreq, int total_clusters, const QueueRef& Q,

@@ -119,6 +119,16 @@ def test_kernel_floor_equals_distance_cutoff(ctx):
     g = ctx.eval(s.src_xyz, s.src_feat, s.tgt_xyz, s.tgt_feat, s.T_true, Params(stage_ell=(0.1,), kernel_floor=floor))
     F, w, v = npo.evaluate(s.src_xyz, s.src_feat, s.tgt_xyz, s.tgt_feat, s.T_true, ell=0.1, kernel_floor=floor)
     assert abs(g[0] - F) <= 1e-5 * F
+    # omega and v too, each against the sum of its terms' magnitudes (C12)
+    wij, d, zt, _ = npo.terms(s.src_xyz, s.src_feat, s.tgt_xyz, s.tgt_feat, s.T_true, ell=0.1, kernel_floor=floor)
+    x = s.src_xyz.astype(np.float64)
+    a2 = float((x * x).sum(axis=1).mean())
+    cross = np.cross(x[:, None, :], zt[None, :, :])                     # x_i x z~_j
+    A_w = (np.abs(wij[:, :, None] * cross).sum(axis=(0, 1))) / (a2 * 0.01)
+    A_v = (np.abs(wij[:, :, None] * d).sum(axis=(0, 1))) / 0.01
+    assert (np.abs(g[1:4] - w) <= 1e-5 * A_w).all(), (g[1:4], w, A_w)
+    assert (np.abs(g[4:7] - v) <= 1e-5 * A_v).all(), (g[4:7], v, A_v)
+    assert np.count_nonzero(wij) < wij.size          # the floor drops pairs
     with pytest.raises(CvoError):
         ctx.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, p.T_true,
                  Params(stage_ell=(0.1,), kernel_floor=0.02))       # sigma^2 <= floor
