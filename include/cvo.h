@@ -30,8 +30,11 @@
  *       t > 0 that maximises the fourth-order Taylor model
  *       P(t) = F + A1 t + A2 t^2 + A3 t^3 + A4 t^4 of G(t) = F(h exp(t xi))
  *       along the gradient xi = (omega, v) (the local maximum with the
- *       largest P when there are two); when P has no maximum on t > 0 the
- *       fixed rule's tau is taken.  A second pass over the same pairs sums
+ *       largest P when there are two) within the interval where the
+ *       expansion describes G: t <= t_max = 3 ell / (|xi_w| rho + |xi_v|),
+ *       the step that moves a typical target by three length-scales (rho =
+ *       the targets' root mean square norm plus |t| of the pose); when P
+ *       has no maximum on (0, t_max] the fixed rule's tau is taken.  A second pass over the same pairs sums
  *       A_k = sigma^2 s_f sum_ij <l_i, m_j> e^alpha_ij g^k_ij with the
  *       exponent's exact Taylor coefficients (alpha .. eps of the moving
  *       target exp(-t Xi) z~; the printed gamma, delta, eps omit the
@@ -135,6 +138,9 @@ typedef struct {
                                0x1C: planar motion SE(2) (rotation about z, translation in x, y);
                                0x07: SO(3); 0x38: translations.  The trace and result report the full
                                gradient. */
+  double stage_tol;         /* > 0: a length-scale stage also ends as soon as its applied twist
+                               |tau d|_2 < stage_tol (the stage's own convergence; stage_iters then
+                               bounds each stage); 0: stages last stage_iters iterations */
   int32_t work_item_min;    /* work items: a target cluster's candidate sources are cut into items of at
                                least this many sources (8 .. 2^20); 0: the context's tuning table */
   int32_t work_items_max;   /* ... and at most this many items per cluster (1 .. 256); 0: the table.
@@ -229,6 +235,9 @@ int cvo_frontend(cvo_ctx* ctx, const cvo_rgbd_frame* frame, int32_t k, float* xy
  * of A1 t + A2 t^2 + A3 t^3 + A4 t^4 (coef[1..4]), 0 when it has no local
  * maximum on t > 0, CVO_EINVAL for null or non-finite input. */
 int cvo_quartic_step(const double coef[5], double* t);
+/* The same with the trusted interval (0, tmax] of the step kernel: only
+ * local maxima at t <= tmax count (tmax > 0, may be +inf). */
+int cvo_quartic_step_bounded(const double coef[5], double tmax, double* t);
 
 /* Per-target terms of the same double sum: for each selected original target
  * index sel[k] (0 <= sel[k] < tgt->n), out[7k..7k+6] = (F_j, omega_j, v_j),

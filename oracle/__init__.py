@@ -59,7 +59,7 @@ def _load():
         L.cvo_oracle_register.argtypes = [c_int, f32p, f32p, c_int, f32p, f32p, c_int,
                                           c_double, c_double, c_double, c_double, c_double, c_double,
                                           c_int, i32p, f64p, c_int, c_double, c_double, c_int, c_int, f64p,
-                                          c_int, f64p, f64p, i32p, i32p, c_int, f64p]
+                                          c_int, f64p, f64p, i32p, i32p, c_int, f64p, c_double]
         L.cvo_oracle_register.restype = c_int
         L.cvo_oracle_quartic.argtypes = [c_int, f32p, f32p, c_int, f32p, f32p, c_int,
                                          c_double, c_double, c_double, c_double, f64p, f64p, f64p, c_int,
@@ -67,6 +67,8 @@ def _load():
         L.cvo_oracle_quartic.restype = c_int
         L.cvo_oracle_quartic_step.argtypes = [f64p, f64p]
         L.cvo_oracle_quartic_step.restype = c_int
+        L.cvo_oracle_quartic_step_bounded.argtypes = [f64p, c_double, f64p]
+        L.cvo_oracle_quartic_step_bounded.restype = c_int
         _lib = L
     return _lib
 
@@ -185,13 +187,17 @@ def quartic(src_xyz, src_feat, tgt_xyz, tgt_feat, T, w, u, *, sigma=0.1, feat_sc
     return out, absout
 
 
-def quartic_step(coef):
+def quartic_step(coef, tmax=None):
     """t > 0 maximising P(t) = A1 t + A2 t^2 + A3 t^3 + A4 t^4 (coef[1:5]) among
-    its local maxima, or None when P has none on t > 0."""
+    its local maxima (those at t <= tmax when given), or None when P has none
+    there."""
     A = np.ascontiguousarray(coef, dtype=np.float64)
     assert A.shape == (5,)
     t = np.zeros(1)
-    ok = _load().cvo_oracle_quartic_step(_ptr(A, ctypes.c_double), _ptr(t, ctypes.c_double))
+    if tmax is None:
+        ok = _load().cvo_oracle_quartic_step(_ptr(A, ctypes.c_double), _ptr(t, ctypes.c_double))
+    else:
+        ok = _load().cvo_oracle_quartic_step_bounded(_ptr(A, ctypes.c_double), float(tmax), _ptr(t, ctypes.c_double))
     return float(t[0]) if ok else None
 
 
@@ -201,7 +207,7 @@ STEP_RULES = {"fixed": 0, "quartic": 1, "conjugate": 2}
 
 def register(src_xyz, src_feat, tgt_xyz, tgt_feat, *, sigma=0.1, feat_scale=0.2, a2=None, b2=1.0,
              eta=1.0, kappa=0.0, stage_iters=(), stage_ell=(0.1,), max_iters=50, tol=0.0, grad_tol=0.0,
-             step_rule="fixed", dof_mask=0, T0=None, nthreads=None, grid=False):
+             step_rule="fixed", dof_mask=0, T0=None, nthreads=None, grid=False, stage_tol=0.0):
     """Run the registration iteration; returns dict(T, iters, converged,
     trace[iters,26], abs[iters,7] (sums of |terms| per iteration), rc).
     step_rule "fixed": tau = eta ell^2 / F; "quartic": the maximiser of the
@@ -210,7 +216,8 @@ def register(src_xyz, src_feat, tgt_xyz, tgt_feat, *, sigma=0.1, feat_scale=0.2,
     Polak-Ribiere conjugate directions (restarts at each stage, every 6
     steps, and on a non-ascent direction).  grid=True (kappa > 0) evaluates
     through the oracle's grid enumeration (same pair set as the brute
-    force)."""
+    force).  stage_tol > 0 ends a length-scale stage early once the applied
+    twist |tau d| < stage_tol (stage_iters then bound the stages)."""
     L = _load()
     x = _f32(src_xyz, 3)
     fd = np.asarray(src_feat).shape[1]
@@ -234,6 +241,6 @@ def register(src_xyz, src_feat, tgt_xyz, tgt_feat, *, sigma=0.1, feat_scale=0.2,
                                STEP_RULES[step_rule], dof_mask, _ptr(T0, ctypes.c_double), nthreads or default_threads(),
                                _ptr(Tout, ctypes.c_double), _ptr(trace, ctypes.c_double),
                                _ptr(it, ctypes.c_int), _ptr(cv, ctypes.c_int), 1 if grid else 0,
-                               _ptr(abs_trace, ctypes.c_double))
+                               _ptr(abs_trace, ctypes.c_double), stage_tol)
     return dict(T=Tout.reshape(4, 4), iters=int(it[0]), converged=bool(cv[0]),
                 trace=trace[: int(it[0])], abs=abs_trace[: int(it[0])], rc=rc)

@@ -539,7 +539,15 @@ int cvo_oracle_quartic(int n, const float* x, const float* lx, int m, const floa
 static double poly4(const double A[5], double t) { return t * (A[1] + t * (A[2] + t * (A[3] + t * A[4]))); }
 static double dpoly3(const double c[4], double t) { return c[0] + t * (c[1] + t * (c[2] + t * c[3])); }
 
+int cvo_oracle_quartic_step_bounded(const double A[5], double tmax, double* t_out);
+
 int cvo_oracle_quartic_step(const double A[5], double* t_out) {
+    return cvo_oracle_quartic_step_bounded(A, INFINITY, t_out);
+}
+
+/* The same, counting only the local maxima at t <= tmax: the model is a
+ * Taylor expansion of G about t = 0 and is trusted only on (0, tmax]. */
+int cvo_oracle_quartic_step_bounded(const double A[5], double tmax, double* t_out) {
     const double c[4] = {A[1], 2.0 * A[2], 3.0 * A[3], 4.0 * A[4]}; /* P' coefficients */
     double big = 0.0;
     for (int i = 0; i < 4; i++) big = fmax(big, fabs(c[i]));
@@ -581,6 +589,7 @@ int cvo_oracle_quartic_step(const double A[5], double* t_out) {
             if (!(mid > lo && mid < hi)) break;
             if (dpoly3(cc, mid) > 0.0) lo = mid; else hi = mid;
         }
+        if (!(hi <= tmax)) continue;
         const double pv = poly4(A, hi);
         if (!found || pv > best_p) { found = 1; best_t = hi; best_p = pv; }
     }
@@ -604,13 +613,18 @@ int cvo_oracle_quartic_step(const double A[5], double* t_out) {
  *           at the first iteration of each stage, after 6 directions since
  *           the last such restart, and whenever <xi, d>_M <= 0
  *   tau = eta ell^2 / F (step_rule 0), or (step_rules 1, 2) the maximiser of
- *         the quartic model along d when it has one on t > 0, else
- *         eta ell^2 / F;
+ *         the quartic model along d when it has one on (0, t_max], else
+ *         eta ell^2 / F, with t_max = 3 ell / (|d_w| rho + |d_v|) the step
+ *         that moves a typical target by three length-scales (rho = the
+ *         targets' root mean square norm + |t_h|): the Taylor model describes
+ *         G only near t = 0;
  *   h <- h exp(tau d)
  *   stop when the last stage is reached and |tau d|_2 < tol (the
  *   transformation threshold of Table 1) or |xi|_2 < grad_tol (the
  *   gradient-norm threshold); a zero threshold is off.
- * Stage s spans stage_iters[s] iterations; the last stage runs to max_iters.
+ * Stage s spans stage_iters[s] iterations, or ends after the iteration whose
+ * applied twist |tau d|_2 < stage_tol (stage_tol > 0); the last stage runs
+ * to max_iters.
  * T0 and T_out use the library convention T = h^-1.
  * trace (optional) receives per iteration 26 doubles:
  *   F, omega[3], v[3], tau, ell, within-pairs, then T (16, row-major) after the step;
@@ -624,9 +638,9 @@ int cvo_oracle_register(int n, const float* x, const float* lx, int m, const flo
                         int max_iters, double tol, double grad_tol, int step_rule, int dof_mask,
                         const double T0[16], int nthreads,
                         double T_out[16], double* trace, int* iters_out, int* converged_out,
-                        int use_grid, double* abs_trace) {
+                        int use_grid, double* abs_trace, double stage_tol) {
     if (n_stages < 1 || !stage_ell || max_iters < 1 || !(eta > 0.0)) return OR_EINVAL;
-    if (!(tol >= 0.0) || !(grad_tol >= 0.0)) return OR_EINVAL;
+    if (!(tol >= 0.0) || !(grad_tol >= 0.0) || !(stage_tol >= 0.0)) return OR_EINVAL;
     if (dof_mask < 0 || dof_mask > 63) return OR_EINVAL;
     if (dof_mask == 0) dof_mask = 63;
     for (int s = 0; s < n_stages; s++) {
@@ -635,18 +649,21 @@ int cvo_oracle_register(int n, const float* x, const float* lx, int m, const flo
     }
     if (!check_cloud(n, fd, x, lx) || !check_cloud(m, fd, z, lz)) return OR_EINVAL;
     if (!(a2 > 0.0)) a2 = cvo_oracle_mean_sqnorm(n, x);
+    /* the targets' root mean square norm */
+    const double zrms = sqrt(cvo_oracle_mean_sqnorm(m, z));
     double h[16];
     rigid_inverse(T0, h);
-    int stage = 0, stage_start = 0, k = 0, conv = 0, rc = OR_OK;
+    int stage = 0, stage_start = 0, stage_done = 0, k = 0, conv = 0, rc = OR_OK;
     /* conjugate directions: the previous xi and d, directions since the
        last restart, and the stage they belong to */
     double xi_prev[6] = {0, 0, 0, 0, 0, 0}, d_prev[6] = {0, 0, 0, 0, 0, 0};
     int since_restart = 0, d_stage = -1;
     for (k = 0; k < max_iters; k++) {
-        while (stage < n_stages - 1 && k - stage_start >= stage_iters[stage]) {
-            stage_start += stage_iters[stage];
+        if (stage < n_stages - 1 && (k - stage_start >= stage_iters[stage] || stage_done)) {
+            stage_start = k;
             stage++;
         }
+        stage_done = 0;
         const double ell = stage_ell[stage];
         double g[7], ga[7];
         long long cnt[2];
@@ -688,13 +705,20 @@ int cvo_oracle_register(int n, const float* x, const float* lx, int m, const flo
         }
         double tau = eta * ell * ell / g[0];
         if (step_rule == 1 || step_rule == 2) {
-            /* quartic model along d at the current pose */
+            /* quartic model along d at the current pose, trusted while a
+               typical target moves by at most 3 ell: a target moves at
+               speed |d_w x z~ + d_v| <= |d_w| |z~| + |d_v|, and the typical
+               |z~| is bounded by rho = zrms + |t_h| */
             double Tcur[16], A[5], Aa[5], tq;
             rigid_inverse(h, Tcur);
             rc = cvo_oracle_quartic(n, x, lx, m, z, lz, fd, sigma, feat_scale, ell, kappa, Tcur, d, d + 3,
                                     nthreads, A, Aa);
             if (rc != OR_OK) break;
-            if (cvo_oracle_quartic_step(A, &tq)) tau = tq;
+            const double rho = zrms + sqrt(h[3] * h[3] + h[7] * h[7] + h[11] * h[11]);
+            const double speed = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) * rho +
+                                 sqrt(d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
+            const double tmax = speed > 0.0 ? 3.0 * ell / speed : INFINITY;
+            if (cvo_oracle_quartic_step_bounded(A, tmax, &tq)) tau = tq;
         }
         newstep(h, d, d + 3, tau);
         double sq = 0.0, gq = 0.0;
@@ -711,6 +735,8 @@ int cvo_oracle_register(int n, const float* x, const float* lx, int m, const flo
         if (abs_trace)
             for (int q = 0; q < 7; q++) abs_trace[7 * (size_t)k + q] = ga[q];
         if (stage == n_stages - 1 && (sqrt(sq) < tol || sqrt(gq) < grad_tol)) { conv = 1; k++; break; }
+        /* a stage also ends once its own applied twist is below stage_tol */
+        stage_done = sqrt(sq) < stage_tol;
     }
     rigid_inverse(h, T_out);
     if (iters_out) *iters_out = k;

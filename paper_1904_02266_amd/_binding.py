@@ -50,7 +50,8 @@ class cvo_params(ctypes.Structure):
                 ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("trace", ctypes.c_int32), ("step_rule", ctypes.c_int32),
                 ("grad_tol", ctypes.c_double), ("kernel_floor", ctypes.c_double), ("dof_mask", ctypes.c_int32),
-                ("work_item_min", ctypes.c_int32), ("work_items_max", ctypes.c_int32)]
+                ("stage_tol", ctypes.c_double), ("work_item_min", ctypes.c_int32),
+                ("work_items_max", ctypes.c_int32)]
 
 
 class cvo_serving_counters(ctypes.Structure):
@@ -118,6 +119,7 @@ def load():
     L.cvo_kernel_stats.argtypes = [vp, i32, P(ctypes.c_int64), P(dbl), P(dbl), P(dbl), P(u64)]
     L.cvo_quartic.argtypes = [vp, P(cvo_cloud), P(cvo_cloud), P(cvo_params), P(dbl), P(dbl), P(dbl), P(dbl)]
     L.cvo_quartic_step.argtypes = [P(dbl), P(dbl)]
+    L.cvo_quartic_step_bounded.argtypes = [P(dbl), dbl, P(dbl)]
     L.cvo_frontend.argtypes = [vp, P(cvo_rgbd_frame), i32, vp, vp, P(i32)]
     L.cvo_serving_stats.argtypes = [vp, P(cvo_serving_counters)]
     L.cvo_set_queue_limit.argtypes = [vp, ctypes.c_int64]
@@ -130,7 +132,8 @@ def load():
     for name in ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
                  "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
                  "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend", "cvo_serving_stats",
-                 "cvo_set_queue_limit", "cvo_eval_static", "cvo_tuning", "cvo_set_graphs"):
+                 "cvo_set_queue_limit", "cvo_eval_static", "cvo_tuning", "cvo_set_graphs",
+                 "cvo_quartic_step_bounded"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -139,8 +142,8 @@ def load():
 EXPORTED = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_eval", "cvo_eval_targets",
             "cvo_register", "cvo_submit", "cvo_poll", "cvo_trace", "cvo_set_profiling",
             "cvo_kernel_stats", "cvo_quartic", "cvo_quartic_step", "cvo_frontend", "cvo_serving_stats",
-            "cvo_set_queue_limit", "cvo_eval_static", "cvo_tuning", "cvo_set_graphs", "cvo_strerror",
-            "cvo_last_error")
+            "cvo_set_queue_limit", "cvo_eval_static", "cvo_tuning", "cvo_set_graphs",
+            "cvo_quartic_step_bounded", "cvo_strerror", "cvo_last_error")
 
 
 class CvoError(RuntimeError):
@@ -169,6 +172,7 @@ class Params:
     grad_tol: float = 0.0
     kernel_floor: float = 0.0
     dof_mask: int = 0
+    stage_tol: float = 0.0       # > 0: a stage ends early once |tau d| < stage_tol
     work_item_min: int = 0       # 0: the context's tuning table
     work_items_max: int = 0
 
@@ -181,7 +185,7 @@ class Params:
                        ctypes.cast(se, ctypes.POINTER(ctypes.c_double)), self.max_iters, self.tol,
                        CVO_FP64 if self.precision == "fp64" else CVO_FP32_KAHAN, 1 if self.trace else 0,
                        STEP_RULES[self.step_rule], self.grad_tol, self.kernel_floor, self.dof_mask,
-                       self.work_item_min, self.work_items_max)
+                       self.stage_tol, self.work_item_min, self.work_items_max)
         return p, (si, se)
 
 
@@ -249,14 +253,18 @@ def _pose(T):
     return T, T.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def quartic_step(coef):
+def quartic_step(coef, tmax=None):
     """The quartic rule's step for coefficients (F, A1..A4): the maximiser over
-    t > 0 of A1 t + ... + A4 t^4, or None when it has no local maximum there
-    (host code of the library, the rule the step kernel applies)."""
+    t > 0 (t <= tmax when given) of A1 t + ... + A4 t^4 among its local maxima,
+    or None when it has none there (host code of the library, the rule the
+    step kernel applies)."""
     L = load()
     c = (ctypes.c_double * 5)(*[float(a) for a in coef])
     t = ctypes.c_double()
-    rc = L.cvo_quartic_step(c, ctypes.byref(t))
+    if tmax is None:
+        rc = L.cvo_quartic_step(c, ctypes.byref(t))
+    else:
+        rc = L.cvo_quartic_step_bounded(c, float(tmax), ctypes.byref(t))
     if rc < 0:
         raise CvoError(rc, "cvo_quartic_step")
     return t.value if rc == 1 else None

@@ -52,6 +52,7 @@ struct Request {
   int chunk_min = kChunkMinDefault, chunks_max = kChunksMaxDefault;  // work-item sizing
   double xi0[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // direction of the coefficient evaluation
   double sigma = 0.1, sf = 0.2, a2 = -1.0, b2 = 1.0, eta = 1.0, kappa = 0.0, tol = 0.0, grad_tol = 0.0;
+  double stage_tol = 0.0;
   int stage_iters[kMaxStages] = {0};
   double stage_ell[kMaxStages] = {0.0};
   double T0[16];
@@ -489,6 +490,7 @@ static int build_request(const cvo_ctx* c, const cvo_cloud* src, const cvo_cloud
   if (p->work_item_min < 0 || (p->work_item_min > 0 && (p->work_item_min < kChunkMinLo || p->work_item_min > (1 << 20))))
     return CVO_EINVAL;
   if (p->work_items_max < 0 || p->work_items_max > kChunksCap) return CVO_EINVAL;
+  if (!(p->stage_tol >= 0.0) || !std::isfinite(p->stage_tol)) return CVO_EINVAL;
   // value sparsification (Table 1): sigma^2 exp(-r^2 / (2 ell^2)) >= floor
   // keeps exactly r <= ell sqrt(2 ln(sigma^2 / floor))
   if (p->kernel_floor > 0.0 && (p->cutoff_mult > 0.0 || !(p->sigma * p->sigma > p->kernel_floor)))
@@ -518,6 +520,7 @@ static int build_request(const cvo_ctx* c, const cvo_cloud* src, const cvo_cloud
                                    : p->cutoff_mult;
   q.tol = p->tol;
   q.grad_tol = p->grad_tol;
+  q.stage_tol = (mode == kModeRegister) ? p->stage_tol : 0.0;
   for (int s = 0; s < q.n_stages; s++) {
     q.stage_ell[s] = p->stage_ell[s];
     q.stage_iters[s] = (s < q.n_stages - 1) ? p->stage_iters[s] : INT_MAX;
@@ -694,14 +697,8 @@ static int finish_setup(cvo_ctx* c, Request& q, const Layout& L, const LayoutB& 
   st.dof_mask = q.dof_mask;
   st.chunk_min = q.chunk_min;
   st.chunks_max = q.chunks_max;
-  int end = 0;
   for (int k = 0; k < kMaxStages; k++) {
-    if (k < S - 1) {
-      end += q.stage_iters[k];
-      st.stage_end[k] = end;
-    } else {
-      st.stage_end[k] = INT_MAX;
-    }
+    st.stage_len[k] = (k < S - 1) ? q.stage_iters[k] : INT_MAX;
     st.stage_ell[k] = (k < S) ? q.stage_ell[k] : 1.0;
   }
   st.s2f = q.sigma * q.sigma * q.sf;
@@ -709,6 +706,7 @@ static int finish_setup(cvo_ctx* c, Request& q, const Layout& L, const LayoutB& 
   st.eta = q.eta;
   st.tol = q.tol;
   st.grad_tol = q.grad_tol;
+  st.stage_tol = q.stage_tol;
   q.trace_dev = st.trace;
   q.per_target_dev = st.per_target;
   return CVO_OK;
@@ -867,7 +865,7 @@ static int run_sync(cvo_ctx* c, Request& q, std::vector<double>* per_target_out)
     }
   }
   int launched = 0;
-  const int chunk = (q.tol > 0.0 || q.grad_tol > 0.0) ? 16 : q.max_iters;
+  const int chunk = (q.tol > 0.0 || q.grad_tol > 0.0 || q.stage_tol > 0.0) ? 16 : q.max_iters;
   // roctx ranges (visible with rocprofv3 --marker-trace): the iteration
   // chunks of a synchronous call
   struct RangeGuard {
@@ -1521,6 +1519,13 @@ int cvo_quartic_step(const double coef[5], double* t) {
   for (int i = 1; i < 5; i++)
     if (!std::isfinite(coef[i])) return CVO_EINVAL;
   return quartic_argmax(coef, t) ? 1 : 0;
+}
+
+int cvo_quartic_step_bounded(const double coef[5], double tmax, double* t) {
+  if (!coef || !t || !(tmax > 0.0)) return CVO_EINVAL;
+  for (int i = 1; i < 5; i++)
+    if (!std::isfinite(coef[i])) return CVO_EINVAL;
+  return quartic_argmax(coef, t, tmax) ? 1 : 0;
 }
 
 int cvo_eval_targets(cvo_ctx* c, const cvo_cloud* src, const cvo_cloud* tgt, const cvo_params* p,

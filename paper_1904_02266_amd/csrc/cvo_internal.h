@@ -40,6 +40,9 @@ enum Mode : int { kModeRegister = 0, kModeEval = 1, kModeEvalTargets = 2, kModeQ
 // restarts, the inner products in the metric a^2, b^2).
 enum StepRule : int { kStepFixed = 0, kStepQuartic = 1, kStepConjugate = 2 };
 constexpr int kCgRestart = 6;  // conjugate directions restart from the gradient every 6 steps (dim se(3))
+// The quartic model is trusted for steps that move a typical target by at
+// most this many length-scales.
+constexpr double kTrustLengths = 3.0;
 // Phases of the step kernel: the whole step (fixed rule); the gradient only
 // (first pass of the quartic rule, or of a coefficient evaluation); the
 // quartic step from the second pass's sums.
@@ -137,11 +140,12 @@ struct ReqStatic {
   int dof_mask;                      // generators the flow moves along: bits 0-2 omega, 3-5 v
   int chunk_min;                     // work items: candidate sources per item at least
   int chunks_max;                    // work items per target cluster at most (<= kChunksCap)
-  int stage_end[kMaxStages];         // iteration index where stage s ends; last = INT_MAX
+  int stage_len[kMaxStages];         // iterations of stage s at most; last = INT_MAX
   double stage_ell[kMaxStages];
   double s2f;                        // sigma^2 * s_f
   double b2, eta, tol;
   double grad_tol;                   // stop when |(omega, v)| < grad_tol in the last stage (0: off)
+  double stage_tol;                  // leave a stage early once |tau d| < stage_tol (0: off)
 };
 
 // Per-request mutable state, device-resident for the whole registration.
@@ -153,10 +157,12 @@ struct ReqState {
   double A[5];                       // F and the model coefficients A1..A4 of the last quartic pass
   unsigned long long last_pairs;     // pairs within the cutoff of the last gradient pass
   double a2;                         // rotational metric weight (device-computed default)
+  double zrad;                       // root mean square norm of the targets (m)
   double tau;
   unsigned long long pairs_within, pairs_examined;
   int iter, stage, done, status, converged;
   unsigned int reserved;
+  int stage_start;                   // iteration at which the current stage began
   int cg_n;                          // conjugate rule: steps since the last restart (0: restart now)
   int cg_stage;                      // conjugate rule: stage of the direction in xi
   int bad_input;                     // set by the finiteness check

@@ -1268,7 +1268,12 @@ __device__ void take_step(const ReqStatic& R, ReqState* __restrict__ S, double t
   } else if (kn >= R.max_iters) {
     S->done = 1;
   }
-  if (stage < R.n_stages - 1 && kn >= R.stage_end[stage]) S->stage = stage + 1;
+  // stage schedule: a stage lasts stage_len iterations, or ends early once
+  // the applied twist falls below stage_tol
+  if (stage < R.n_stages - 1 && (kn - S->stage_start >= R.stage_len[stage] || sqrt(sq) < R.stage_tol)) {
+    S->stage = stage + 1;
+    S->stage_start = kn;
+  }
 }
 
 // The step kernel's work for one request (one thread), by phase:
@@ -1303,8 +1308,18 @@ __device__ void finish_request(const ReqStatic& R, ReqState* __restrict__ S, con
     S->A[1] = metric_dot(R, S, gm, d);
     const double ell = R.stage_ell[S->stage];
     double tau = R.eta * ell * ell / S->g[0];
+    // The model is trusted while the targets move less than kTrustLengths
+    // length-scales: a target z~ moves at speed |d_w x z~ + d_v| along the
+    // line, at most |d_w| rho + |d_v| for |z~| <= rho; with rho = zrms + |t|
+    // (zrms the targets' root mean square norm) this bounds the typical
+    // target's speed.
+    const double* Tm = S->T;
+    const double rho = S->zrad + sqrt(Tm[3] * Tm[3] + Tm[7] * Tm[7] + Tm[11] * Tm[11]);
+    const double speed = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) * rho +
+                         sqrt(d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
+    const double tmax = speed > 0.0 ? kTrustLengths * ell / speed : INFINITY;
     double t;
-    if (quartic_argmax(S->A, &t)) tau = t;
+    if (quartic_argmax(S->A, &t, tmax)) tau = t;
     take_step(R, S, tau, (double)S->last_pairs, d);
     return;
   }
@@ -1905,9 +1920,11 @@ __global__ void k_init_state(ReqState* __restrict__ S, const double* __restrict_
   for (int q = 0; q < 6; q++) S->gprev[q] = 0.0;
   S->cg_n = 0;
   S->cg_stage = 0;
+  S->stage_start = 0;
   for (int q = 0; q < 5; q++) S->A[q] = 0.0;
   S->last_pairs = 0ull;
   S->a2 = a2_param;
+  S->zrad = 0.0;
   S->tau = 0.0;
   S->pairs_within = 0ull;
   S->pairs_examined = 0ull;
@@ -1931,10 +1948,11 @@ __global__ __launch_bounds__(256) void k_check_finite(const float* __restrict__ 
   if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&S->bad_input, 1);
 }
 
-__global__ void k_setup_final(ReqState* __restrict__ S, const double* __restrict__ xbox, double a2_param,
-                              int n_stages) {
+__global__ void k_setup_final(ReqState* __restrict__ S, const double* __restrict__ xbox,
+                              const double* __restrict__ zbox, double a2_param, int n_stages) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (!(a2_param > 0.0)) S->a2 = xbox[6];
+  S->zrad = sqrt(zbox[6]);  // root mean square norm of the targets
   int most = 0, least = 0x7fffffff;
   for (int st = 0; st < n_stages; st++) {
     most = max(most, S->nclus_s[st]);
@@ -2215,7 +2233,7 @@ hipError_t launch_ingest(const IngestArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_cl_table, dim3(gm), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.m, st, cstart, a.state);
     hipLaunchKernelGGL(k_cl_count, dim3(gm), dim3(B), 0, s, cstart, a.state, a.m, st, ccount);
   }
-  hipLaunchKernelGGL(k_setup_final, dim3(1), dim3(1), 0, s, a.state, a.xbox, a.a2_param, a.n_stages);
+  hipLaunchKernelGGL(k_setup_final, dim3(1), dim3(1), 0, s, a.state, a.xbox, a.zbox, a.a2_param, a.n_stages);
   return hipGetLastError();
 }
 

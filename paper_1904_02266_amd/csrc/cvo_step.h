@@ -13,9 +13,11 @@ namespace cvo {
 // a sign change of P' from + to - inside one such piece; it is found by
 // Newton's method kept inside the shrinking bracket (bisection whenever a
 // Newton step leaves it or stalls).  Among the maxima the one with the
-// largest P wins.  Returns false when P has no local maximum on t > 0 (P'
-// keeps one sign, or only touches zero).  A[0] (the value at t = 0) is unused.
-__host__ __device__ inline bool quartic_argmax(const double A[5], double* t_out) {
+// largest P wins.  Only maxima at t <= tmax count (the model is a Taylor
+// expansion, meaningful only near t = 0).  Returns false when P has no local
+// maximum on (0, tmax] (P' keeps one sign, or only touches zero, or its
+// maxima lie beyond tmax).  A[0] (the value at t = 0) is unused.
+__host__ __device__ inline bool quartic_argmax(const double A[5], double* t_out, double tmax = INFINITY) {
   const double c[4] = {A[1], 2.0 * A[2], 3.0 * A[3], 4.0 * A[4]};  // P'
   const double scale = fabs(c[0]) + fabs(c[1]) + fabs(c[2]) + fabs(c[3]);
   if (!(scale > 0.0) || !(scale < INFINITY)) return false;
@@ -85,6 +87,7 @@ __host__ __device__ inline bool quartic_argmax(const double A[5], double* t_out)
       }
       t = tn;
     }
+    if (!(t <= tmax)) continue;
     const double pv = P(t);
     if (!found || pv > best_p) {
       found = true;

@@ -96,3 +96,31 @@ def test_quartic_step_host_rule_special_cases(A, t):
         assert got is None
     else:
         assert abs(got - t) < 1e-14
+
+
+def test_quartic_step_bounded_host_rule_matches_oracle():
+    # the trusted interval (0, tmax]: only local maxima at t <= tmax count,
+    # in the library's rule and in the oracle's alike
+    import oracle
+    from paper_1904_02266_amd import quartic_step
+    rng = np.random.default_rng(11)
+    cut = 0
+    for _ in range(3000):
+        sc = 10.0 ** rng.uniform(-3, 3, size=4)
+        A = np.concatenate([[1.0], rng.normal(size=4) * sc])
+        A[1] = abs(A[1])
+        t_free = oracle.quartic_step(A)
+        tmax = 10.0 ** rng.uniform(-4, 2)
+        a, b = quartic_step(A, tmax=tmax), oracle.quartic_step(A, tmax=tmax)
+        assert (a is None) == (b is None), (A, tmax)
+        if a is not None:
+            assert a <= tmax and b <= tmax
+            if abs(a - b) > 1e-9 * b:
+                assert abs(_P(A, a) - _P(A, b)) <= 1e-12 * max(abs(_P(A, b)), 1e-300), A
+        if t_free is not None and t_free > tmax:
+            cut += 1
+    assert cut > 100
+    # P = t - t^2 has its maximum at 0.5
+    assert quartic_step([0, 1.0, -1.0, 0, 0], tmax=0.4) is None
+    assert abs(quartic_step([0, 1.0, -1.0, 0, 0], tmax=0.6) - 0.5) < 1e-14
+    assert abs(quartic_step([0, 1.0, -1.0, 0, 0], tmax=float("inf")) - 0.5) < 1e-14

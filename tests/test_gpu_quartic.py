@@ -257,3 +257,45 @@ def test_coefficients_cell_list_overflow(ctx):
     c = ctx.quartic(x, lx, z, lz, T, w, v, Params(stage_ell=(0.02,), cutoff_mult=3.0, a2=1.0))
     ref, absref = oracle.quartic(x, lx, z, lz, T, w, v, ell=0.02, kappa=3.0)
     check_coef(c, ref, absref, 2e-5, what="overflow")
+
+
+def test_register_stage_tolerance_follows_oracle(ctx):
+    """Stages that end early on their own convergence (stage_tol): the GPU's
+    schedule and stopping iteration follow the oracle's under the same rule."""
+    p = synth.rgbd_pair(5000, 5000, seed=43, select="random")
+    prm = params_rgbd(max_iters=200, step_rule="conjugate", tol=1e-5, stage_tol=1e-4, trace=True)
+    out = ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, prm)
+    tr = ctx.trace()
+    ref = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, kappa=3.0, stage_iters=(25, 25, 25),
+                          stage_ell=prm.stage_ell, max_iters=200, step_rule="conjugate", tol=1e-5, stage_tol=1e-4)
+    assert out["rc"] == 0 and out["converged"] and ref["converged"]
+    starts = lambda t: [0] + [k for k in range(1, len(t)) if t[k, 8] != t[k - 1, 8]]
+    sg, so = starts(tr), starts(ref["trace"])
+    assert len(sg) == len(so) == 4
+    assert all(abs(a - b) <= 2 for a, b in zip(sg, so)), (sg, so)
+    assert out["iters"] < 90 and abs(out["iters"] - ref["iters"]) <= 4, (out["iters"], ref["iters"])
+    assert _angle_deg(out["T"], ref["T"]) < 1e-4 * 180 / np.pi
+    assert np.linalg.norm(out["T"][:3, 3] - ref["T"][:3, 3]) < 1e-4
+
+
+def test_quartic_step_stays_in_trusted_interval(ctx):
+    """A serving request whose FP32 quartic model near convergence once had a
+    spurious maximum far out (tau ~ 1e4, the pose left the overlap): with the
+    trusted interval (no target moves farther than ell) it converges and
+    follows the oracle under the same rule."""
+    p = synth.rgbd_pair(300000, 300000, seed=5102, select="random")
+    r = np.random.default_rng(5102 + 17)
+    a, b = r.permutation(len(p.src_xyz)), r.permutation(len(p.tgt_xyz))
+    sx, sf, tx, tf = p.src_xyz[a][:5581], p.src_feat[a][:5581], p.tgt_xyz[b][:4827], p.tgt_feat[b][:4827]
+    prm = params_rgbd(max_iters=200, step_rule="conjugate", tol=1e-5, trace=True)
+    out = ctx.register(sx, sf, tx, tf, prm, check=False)
+    tr = ctx.trace()
+    ref = oracle.register(sx, sf, tx, tf, kappa=3.0, stage_iters=(25, 25, 25), stage_ell=prm.stage_ell,
+                          max_iters=200, step_rule="conjugate", tol=1e-5)
+    assert out["rc"] == 0 and out["converged"] and ref["converged"], (out["rc"], out["iters"])
+    # every step moved the targets by at most ell (the tau column against
+    # the interval's bound cannot be read back; the twist's size can)
+    assert np.all(tr[:, 7] < 1.0)
+    assert abs(out["iters"] - ref["iters"]) <= 4
+    assert _angle_deg(out["T"], ref["T"]) < 1e-4 * 180 / np.pi
+    assert np.linalg.norm(out["T"][:3, 3] - ref["T"][:3, 3]) < 1e-4

@@ -669,3 +669,45 @@ def test_conjugate_rule_recovers_rgbd_motion():
     for end in (24, 49, 74, 99):
         T0, T1 = tr[end - 1, 10:26].reshape(4, 4), tr[end, 10:26].reshape(4, 4)
         assert np.linalg.norm(_step_twist(T0, T1)) < 1e-4, end
+
+
+def test_stage_tolerance_ends_stages_early():
+    """With stage_tol a length-scale stage ends after the first iteration
+    whose applied twist is below it (or after its stage_iters); without it
+    stages last stage_iters.  The final stopping test is unchanged."""
+    p = synth.rgbd_pair(3000, 3000, seed=43, select="random")
+    ells = [0.2 * 0.25 ** (s / 3.0) for s in range(4)]
+    kw = dict(kappa=3.0, stage_iters=(25, 25, 25), stage_ell=ells, max_iters=200, step_rule="conjugate", tol=1e-5)
+    base = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, **kw)
+    fast = oracle.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, stage_tol=1e-4, **kw)
+    assert base["converged"] and fast["converged"] and fast["iters"] < base["iters"]
+    for r, st in ((base, 0.0), (fast, 1e-4)):
+        tr = r["trace"]
+        starts = [0] + [k for k in range(1, len(tr)) if tr[k, 8] != tr[k - 1, 8]]
+        assert len(starts) == 4
+        for s in range(3):
+            a, b = starts[s], starts[s + 1]
+            twists = [np.linalg.norm(_step_twist(np.eye(4) if k == 0 else tr[k - 1, 10:26].reshape(4, 4),
+                                                 tr[k, 10:26].reshape(4, 4))) for k in range(a, b)]
+            if st == 0.0:
+                assert b - a == 25
+            else:
+                # the stage ran until its first twist below stage_tol, or 25 iterations
+                below = [k for k, t in enumerate(twists) if t < st]
+                assert (below and below[0] == len(twists) - 1) or (not below and b - a == 25), (s, twists)
+    assert rot_angle_deg(fast["T"], base["T"]) < 0.05
+
+
+def test_quartic_step_trusted_interval():
+    """The quartic rule counts only maxima inside (0, tmax]: P = t - t^2 (the
+    maximum at 1/2) gives no step for tmax < 1/2; with two local maxima the
+    better one inside the interval is taken."""
+    A = [0.0, 1.0, -1.0, 0.0, 0.0]
+    assert oracle.quartic_step(A, tmax=0.49) is None
+    assert abs(oracle.quartic_step(A, tmax=0.51) - 0.5) < 1e-15
+    # P' = -(t - 1)(t - 2)(t - 4) = 8 - 14 t + 7 t^2 - t^3: local maxima of P
+    # at t = 1 (P = 37/12) and t = 4 (P = 16/3, the better one)
+    B = [0.0, 8.0, -7.0, 7.0 / 3.0, -0.25]
+    assert abs(oracle.quartic_step(B) - 4.0) < 1e-12
+    assert abs(oracle.quartic_step(B, tmax=3.0) - 1.0) < 1e-12
+    assert oracle.quartic_step(B, tmax=0.9) is None
