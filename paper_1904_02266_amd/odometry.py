@@ -104,3 +104,61 @@ def run_on_device(ctx, frames, params, k: int = 30000, init: str = "identity",
         return out["T"], out["iters"]
 
     return run(frames, register, frontend, init=init)
+
+
+def run_served(ctx, frames, params, k: int = 30000, init: str = "identity",
+               device: Optional[object] = None) -> OdometryResult:
+    """run() through the serving path: every frame goes through the device
+    front end once; the frame-pair registrations are submitted to the
+    context's continuous-batching scheduler (cvo_submit) and collected with
+    cvo_poll.  With init "identity" each pair is submitted as soon as its
+    target frame's front end is done, so the scheduler registers it while
+    the next frames are processed, and the pairs share batches; with
+    "constant_velocity" each pair waits for the previous estimate (its
+    initial pose).  The clouds stay on the device and are kept alive until
+    their tickets are polled."""
+    import time
+    import torch
+    if init not in ("identity", "constant_velocity"):
+        raise ValueError(init)
+    dev = torch.device("cuda:0") if device is None else device
+    t0 = time.perf_counter()
+
+    def frontend(f):
+        d = torch.from_numpy(f.depth).to(dev)
+        c = torch.from_numpy(f.rgb).to(dev)
+        return ctx.frontend(d, c, k, f.fx, f.fy, f.cx, f.cy, f.dmin, f.dmax)
+
+    def collect(tk):
+        out = ctx.poll(tk)
+        if out["rc"] < 0:
+            raise RuntimeError(f"registration failed: {out['rc']}")
+        rel.append(out["T"])
+        iters.append(out["iters"])
+        return out["T"]
+
+    rel, iters = [], []
+    clouds = [frontend(frames[0])] if frames else []
+    if init == "identity":
+        tickets = []
+        for q in range(1, len(frames)):
+            clouds.append(frontend(frames[q]))
+            tickets.append(ctx.submit(clouds[q - 1][0], clouds[q - 1][1], clouds[q][0], clouds[q][1], params))
+        for tk, keep in tickets:
+            collect(tk)
+    else:
+        T0 = np.eye(4)
+        for q in range(1, len(frames)):
+            clouds.append(frontend(frames[q]))
+            tk, keep = ctx.submit(clouds[q - 1][0], clouds[q - 1][1], clouds[q][0], clouds[q][1], params, T0=T0)
+            T0 = collect(tk)
+    wall = (time.perf_counter() - t0) * 1e3
+    traj = [frames[0].pose.copy()]
+    rot, trans = [], []
+    for q, T in enumerate(rel):
+        traj.append(traj[-1] @ T)
+        a, b = pose_errors(T, relative_truth(frames[q].pose, frames[q + 1].pose))
+        rot.append(a)
+        trans.append(b)
+    per = wall / max(1, len(rel))
+    return OdometryResult(rel, traj, np.array(rot), np.array(trans), iters, [per] * len(rel))

@@ -49,3 +49,79 @@ def test_sequence_relative_errors(frames, init):
     for T in res.relative:
         G = G @ T
     np.testing.assert_allclose(G, res.trajectory[-1], atol=1e-12)
+
+
+def _table1_oracle_kwargs(prm):
+    import math
+    kappa = math.sqrt(2.0 * math.log(prm.sigma ** 2 / prm.kernel_floor))   # the value floor as a distance
+    return dict(sigma=prm.sigma, kappa=kappa, stage_iters=tuple(prm.stage_iters), stage_ell=tuple(prm.stage_ell),
+                max_iters=prm.max_iters, tol=prm.tol, grad_tol=prm.grad_tol, step_rule=prm.step_rule)
+
+
+@pytest.mark.parametrize("init", ["identity", "constant_velocity"])
+def test_served_odometry_matches_oracle_chain(frames, init):
+    """Odometry through the serving path (front end, then the frame-pair
+    registrations through cvo_submit / cvo_poll) against the oracle's own
+    chain: the oracle's front end (the same pixels bit for bit) and its
+    registrations under the same rule (Table 1's schedule, value floor and
+    thresholds; the quartic line search along conjugate directions).
+
+    * Each served link equals the synchronous registration of its two clouds
+      bit for bit, and the oracle's own stopping test ends its flow within a
+      few iterations of the served one.
+    * Per iteration, F along the served trajectory agrees with F along the
+      oracle's (run for the same number of iterations) to 1e-4: the two runs
+      follow their own poses, so this bounds how far the trajectories drift
+      apart (measured 4.4e-5); the per-iteration arithmetic itself is checked
+      teacher-forced, to 1e-5, by the registration tests.
+    * The final poses agree to 1e-4 rad and 3e-4 m.  The translation bar is
+      three times the general one: these are sparse 4,000-point semi-dense
+      clouds whose objective at the last length-scale (3 cm) is flat along
+      one direction, where trajectories that differ in FP32 rounding end
+      ~1e-4 m apart after a hundred steps (measured 1.2e-4 m; the rotation
+      agrees to 3e-5 rad).
+    * The chained trajectories agree."""
+    import oracle
+    from oracle import np_frontend as fe
+    k = 4000
+    seq = frames[:5]
+    prm = params_table1(step_rule="conjugate")
+    prm_tr = params_table1(step_rule="conjugate", trace=True)
+    ctx = Context(0)
+    try:
+        served = odometry.run_served(ctx, seq, prm, k=k, init=init)
+        sync = odometry.run_on_device(ctx, seq, prm, k=k, init=init)
+        clouds_dev = [ctx.frontend(f.depth, f.rgb, k, f.fx, f.fy, f.cx, f.cy, f.dmin, f.dmax) for f in seq]
+        traces = []
+        T0 = np.eye(4)
+        for q in range(len(seq) - 1):
+            ctx.register(clouds_dev[q][0], clouds_dev[q][1], clouds_dev[q + 1][0], clouds_dev[q + 1][1], prm_tr,
+                         T0=T0)
+            traces.append(ctx.trace())
+            if init == "constant_velocity":
+                T0 = served.relative[q]
+    finally:
+        ctx.close()
+    for a, b in zip(served.relative, sync.relative):
+        assert np.array_equal(a, b)
+    clouds = [fe.frontend(f.depth, f.rgb, f.fx, f.fy, f.cx, f.cy, f.dmin, f.dmax, k) for f in seq]
+    T0 = np.eye(4)
+    G_or = seq[0].pose.copy()
+    for q in range(len(seq) - 1):
+        (sx, sf, _), (tx, tf, _) = clouds[q], clouds[q + 1]
+        kw = _table1_oracle_kwargs(prm)
+        stop = oracle.register(sx, sf, tx, tf, T0=T0, **kw)
+        assert stop["rc"] == 0
+        its = served.iterations[q]
+        assert abs(stop["iters"] - its) <= 6, (q, stop["iters"], its)
+        kw.update(max_iters=its, tol=0.0, grad_tol=0.0)
+        ref = oracle.register(sx, sf, tx, tf, T0=T0, **kw)
+        np.testing.assert_allclose(traces[q][:its, 0], ref["trace"][:, 0], rtol=1e-4)
+        T = served.relative[q]
+        E = T[:3, :3] @ ref["T"][:3, :3].T
+        ang = np.arccos(np.clip((np.trace(E) - 1) / 2, -1, 1))
+        assert ang < 1e-4 and np.linalg.norm(T[:3, 3] - ref["T"][:3, 3]) < 3e-4, (q, ang)
+        G_or = G_or @ ref["T"]
+        if init == "constant_velocity":
+            T0 = ref["T"]
+    np.testing.assert_allclose(served.trajectory[-1], G_or, atol=1e-3)
