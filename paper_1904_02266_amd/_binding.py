@@ -440,6 +440,33 @@ class Context:
         out["T"] = Tout.reshape(4, 4)
         return out
 
+    def register_planar(self, src_xy, src_feat, tgt_xy, tgt_feat, params: Params, T0=None, check=True):
+        """Registration of planar clouds on SE(2) (the n = 2 case of the
+        general-n gradient): points [n, 2] are passed as (x, y, 0) and the flow
+        runs on the subgroup of rotations about z and translations in the
+        plane (dof_mask 0x1C), whose gradient is eq. flow's for n = 2.  T0 and
+        the returned T are 3x3 (acting on target points)."""
+        import dataclasses
+
+        def lift(xy):
+            xy = np.asarray(xy, dtype=np.float32)
+            if xy.ndim != 2 or xy.shape[1] != 2:
+                raise ValueError("planar points must be [n, 2]")
+            return np.concatenate([xy, np.zeros((xy.shape[0], 1), np.float32)], axis=1)
+
+        T4 = np.eye(4)
+        if T0 is not None:
+            T0 = np.asarray(T0, dtype=np.float64)
+            T4[:2, :2] = T0[:2, :2]
+            T4[:2, 3] = T0[:2, 2]
+        out = self.register(lift(src_xy), src_feat, lift(tgt_xy), tgt_feat,
+                            dataclasses.replace(params, dof_mask=DOF_SE2), T0=T4, check=check)
+        T = np.eye(3)
+        T[:2, :2] = out["T"][:2, :2]
+        T[:2, 2] = out["T"][:2, 3]
+        out["T"] = T
+        return out
+
     def trace(self, cap=100000, ticket=0):
         """The per-iteration trace of the last register call (ticket 0) or of a
         finished batched ticket; None while that ticket is still running."""

@@ -711,3 +711,92 @@ def test_quartic_step_trusted_interval():
     assert abs(oracle.quartic_step(B) - 4.0) < 1e-12
     assert abs(oracle.quartic_step(B, tmax=3.0) - 1.0) < 1e-12
     assert oracle.quartic_step(B, tmax=0.9) is None
+
+
+# --------------------------------------------------------------------------
+# SE(n) for any n (eq. flow), NumPy oracle
+# --------------------------------------------------------------------------
+from oracle import np_sen  # noqa: E402
+
+
+def _cloud_n(n, count, seed, spread=1.0):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(0.0, spread, size=(count, n))
+    l = rng.uniform(0.0, 1.0, size=(count, 3))
+    return x, l
+
+
+def _random_h(n, rng, ang=0.2, trans=0.1):
+    A = rng.normal(size=(n, n)) * ang
+    Om = A - A.T
+    return np.asarray(np_sen.expm_series(np_sen.twist(Om, rng.normal(size=n) * trans)))
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_sen_gradient_matches_finite_differences(n):
+    """dF(h exp(eps xi))/d eps = <grad F, xi> in the metric for random twists
+    xi, n = 2..5 (the gradient of eq. flow is the metric dual of the
+    differential)."""
+    rng = np.random.default_rng(n)
+    x, lx = _cloud_n(n, 40, seed=n)
+    h = _random_h(n, rng)
+    z = (x @ h[:n, :n].T + h[:n, n] + rng.normal(0, 0.05, size=x.shape))
+    a2, b2 = 1.7, 0.6
+    F, W, v = np_sen.gradient(x, lx, z, lx, np.eye(n + 1), ell=0.5, a2=a2, b2=b2)
+    g = np_sen.ascent_twist(W, v)
+    eps = 1e-6
+    for _ in range(4):
+        A = rng.normal(size=(n, n))
+        xi = np_sen.twist(A - A.T, rng.normal(size=n))
+        fp = np_sen.objective(x, lx, z, lx, np_sen.expm_series(eps * xi), ell=0.5)
+        fm = np_sen.objective(x, lx, z, lx, np_sen.expm_series(-eps * xi), ell=0.5)
+        fd = (fp - fm) / (2 * eps)
+        pred = np_sen.metric(g, xi, a2, b2)
+        assert abs(fd - pred) <= 1e-6 * (abs(pred) + 1e-3 * F), (n, fd, pred)
+
+
+def test_sen_n3_equals_the_c_oracle():
+    """For n = 3 eq. flow's coordinates are eq. 3_gradient's: omega =
+    (w^{23}, w^{31}, w^{12}) (w^{31} = -w^{13}), v the same."""
+    p = small_pair(150, seed=22)
+    T = synth.random_motion(np.random.default_rng(3), 6.0, 0.06)
+    h = synth.invert_rigid(T)
+    r = oracle.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, ell=0.2, kappa=2.5, a2=2.0, b2=0.7)
+    F, W, v = np_sen.gradient(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, h, ell=0.2, kappa=2.5, a2=2.0, b2=0.7)
+    np.testing.assert_allclose(F, r["g"][0], rtol=1e-12)
+    np.testing.assert_allclose([W[1, 2], W[2, 0], W[0, 1]], r["g"][1:4], rtol=1e-10, atol=1e-13 * r["abs"][1:4].max())
+    np.testing.assert_allclose(v, r["g"][4:7], rtol=1e-10, atol=1e-13 * r["abs"][4:7].max())
+
+
+def test_sen_invariance_and_stationary_identity():
+    """n = 4: F(G h G^-1; GX, GZ) = F(h; X, Z) for a rigid G (Sec. V,
+    isometric action), and for Z = X the identity is stationary and beats
+    nearby poses (Sec. V theorem)."""
+    n = 4
+    rng = np.random.default_rng(40)
+    x, lx = _cloud_n(n, 60, seed=41)
+    h = _random_h(n, rng)
+    z = x @ h[:n, :n].T + h[:n, n]
+    G = _random_h(n, rng, ang=1.0, trans=1.0)
+    gx = x @ G[:n, :n].T + G[:n, n]
+    gz = z @ G[:n, :n].T + G[:n, n]
+    h1 = _random_h(n, rng, ang=0.05, trans=0.05)
+    a = np_sen.objective(x, lx, z, lx, h1, ell=0.4)
+    b = np_sen.objective(gx, lx, gz, lx, G @ h1 @ np_sen.inverse(G), ell=0.4)
+    np.testing.assert_allclose(a, b, rtol=1e-12)
+    F, W, v = np_sen.gradient(x, lx, x, lx, np.eye(n + 1), ell=0.4)
+    assert np.abs(W).max() < 1e-12 * F and np.abs(v).max() < 1e-12 * F
+    for _ in range(4):
+        assert np_sen.objective(x, lx, x, lx, _random_h(n, rng, 0.05, 0.05), ell=0.4) < F
+
+
+@pytest.mark.parametrize("n", [2, 4])
+def test_sen_registration_recovers_motion(n):
+    """The flow on SE(n) recovers a known motion of a noiseless copy."""
+    rng = np.random.default_rng(50 + n)
+    x, lx = _cloud_n(n, 150, seed=60 + n)
+    h = _random_h(n, rng, ang=0.05, trans=0.05)
+    z = x @ h[:n, :n].T + h[:n, n]          # z = h x: the paper's pose that maps X onto Z is h
+    est, tr = np_sen.register(x, lx, z, lx, ell=0.5, max_iters=150)
+    assert np.abs(est - h).max() < 1e-6, np.abs(est - h).max()
+    assert np.all(np.diff(tr[:, 0]) > -1e-9 * tr[1:, 0])
