@@ -604,7 +604,7 @@ using cptr = const __attribute__((address_space(4))) T*;
 
 template <typename CT, int FD, bool CUT>
 __device__ __forceinline__ void one_pair(const CT* __restrict__ r, CT zx, CT zy, CT zz, const CT (&mj)[FD], CT rc2,
-                                         Acc<CT>& acc, unsigned long long& within) {
+                                         Acc<CT>& acc, unsigned int& within_blk) {
   const CT dx = zx - r[0];
   const CT dy = zy - r[1];
   const CT dz = zz - r[2];
@@ -617,7 +617,7 @@ __device__ __forceinline__ void one_pair(const CT* __restrict__ r, CT zx, CT zy,
   if (CUT) {
     // branch-free cutoff: the pair count comes from the scalar unit
     const bool in = r2 <= rc2;
-    within += (unsigned long long)__popcll(__ballot(in));
+    within_blk = (unsigned)uniform((int)(within_blk + (unsigned)__popcll(__ballot(in))));
     w = in ? w : (CT)0;
   }
   acc.w += w;
@@ -649,7 +649,10 @@ struct GradOp {
   CT m0, m1, m2, z2;  // -2 z, |z|^2 (expanded form)
   bool ex;            // the expanded form (wave-uniform)
   Acc<CT> acc;
+  // pairs inside the cutoff: a wave-uniform 32-bit count since the last fold
+  // (kept in a scalar register), added to the 64-bit total at each fold
   unsigned long long within;
+  unsigned int within_blk;
   __device__ __forceinline__ void expand(bool ok) {
     ex = kExpanded && ok;
     m0 = (CT)-2 * zx;
@@ -668,7 +671,7 @@ struct GradOp {
       CT w = c * e;
       if (CUT) {
         const bool in = r2 <= rc2;
-        within += (unsigned long long)__popcll(__ballot(in));
+        within_blk = (unsigned)uniform((int)(within_blk + (unsigned)__popcll(__ballot(in))));
         w = in ? w : (CT)0;
       }
       acc.w += w;
@@ -676,14 +679,18 @@ struct GradOp {
       acc.dy += w * r[1];
       acc.dz += w * r[2];
     } else {
-      one_pair<CT, FD, CUT>(r, zx, zy, zz, mj, rc2, acc, within);
+      one_pair<CT, FD, CUT>(r, zx, zy, zz, mj, rc2, acc, within_blk);
     }
   }
   __device__ __forceinline__ void pair(const CT* r) {
     if (ex) pair_t<true>(r);
     else pair_t<false>(r);
   }
-  __device__ __forceinline__ void fold() { acc.fold(); }
+  __device__ __forceinline__ void fold() {
+    acc.fold();
+    within += within_blk;
+    within_blk = 0u;
+  }
 };
 
 // Accumulators of the quartic pass: the four coefficient sums.
@@ -1491,15 +1498,28 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const C
     // boundaries inside the batch
     const long long bk = (long long)me.end - pos;
     const int eoff = __popcll(__ballot(l < navail && bk <= 0));
-    const unsigned long long M = wave_or((l < navail && bk >= 1 && bk <= kWave - 1) ? (1ull << bk) : 0ull);
-    const unsigned long long upto = (l == kWave - 1) ? ~1ull : ((2ull << l) - 2ull);  // bits 1..l
-    int ei = eoff + __popcll(M & upto);
-    ei = ei < navail - 1 ? ei : navail - 1;
-    ei = ei < 0 ? 0 : ei;
-    const int efirst = __shfl(me.first, ei, kWave);
-    const int ecount = __shfl(me.count, ei, kWave);
-    const int eend = __shfl(me.end, ei, kWave);
-    B.cell = __shfl(me.cell, ei, kWave);
+    const bool inside = l < navail && bk >= 1 && bk <= kWave - 1;
+    int efirst, ecount, eend;
+    if (__ballot(inside) == 0ull) {
+      // no entry ends inside the batch (the common case with large cells):
+      // every lane's entry is eoff, read with scalar lane reads
+      int e = eoff < navail - 1 ? eoff : navail - 1;
+      e = e < 0 ? 0 : e;
+      efirst = lane_value(me.first, e);
+      ecount = lane_value(me.count, e);
+      eend = lane_value(me.end, e);
+      B.cell = lane_value(me.cell, e);
+    } else {
+      const unsigned long long M = wave_or(inside ? (1ull << bk) : 0ull);
+      const unsigned long long upto = (l == kWave - 1) ? ~1ull : ((2ull << l) - 2ull);  // bits 1..l
+      int ei = eoff + __popcll(M & upto);
+      ei = ei < navail - 1 ? ei : navail - 1;
+      ei = ei < 0 ? 0 : ei;
+      efirst = __shfl(me.first, ei, kWave);
+      ecount = __shfl(me.count, ei, kWave);
+      eend = __shfl(me.end, ei, kWave);
+      B.cell = __shfl(me.cell, ei, kWave);
+    }
     const int src = B.live ? efirst + (int)(p - ((long long)eend - ecount)) : 0;
     const CT* xg = xg0 + (size_t)src * xs;
 #pragma unroll
@@ -1671,6 +1691,7 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
     op.expand(expand_ok);
     op.acc.init();
     op.within = 0;
+    op.within_blk = 0u;
   }
   long long span = 0;
   if (!overflow) {
@@ -1714,7 +1735,7 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
 #pragma unroll
     for (int q = 0; q < kSlot; q++) row[q] = part[q];
   } else {
-    unsigned long long within = op.within;
+    unsigned long long within = op.within + op.within_blk;
     const unsigned long long examined = (unsigned long long)span * (unsigned long long)cn;
     if (!CUT) within = examined;
 
@@ -1790,16 +1811,23 @@ __global__ __launch_bounds__((PairWaves<CT>::value * kWave), (sizeof(CT) == 4 ? 
   const unsigned long long G = gridDim.x;
   // Shares: the workgroups of one XCD (the hardware places workgroup b on
   // XCD b mod 8) take a contiguous range of the list, so a cluster's items
-  // (adjacent in the list) share that XCD's L2; inside the range the XCD's
-  // workgroups take every cx-th item, so each mixes items of many clusters
-  // and the shares' costs even out.
+  // (adjacent in the list) share that XCD's L2.  The range is cut into blocks
+  // of cx items (cx = the XCD's workgroup count); in block t workgroup rk
+  // takes position (rk + h(t)) mod cx, h a hash of t: one item per workgroup
+  // and block, each item exactly once.  The offset moves from block to block
+  // because an item's cost depends on its position in its cluster's candidate
+  // list (the first and last chunks hold the cells at the ends of the
+  // candidate box, whose sources mostly fail the cull): with a fixed stride a
+  // workgroup would keep drawing the same positions of clusters with about
+  // cx items, and the shares' costs would not even out.
   const unsigned int b = blockIdx.x, x = b % 8u, rk = b / 8u;
   unsigned long long before = 0;
   for (unsigned int y = 0; y < x; y++) before += (G - y + 7u) / 8u;
   const unsigned int cx = (unsigned)((G - x + 7u) / 8u);
   const unsigned int lo = (unsigned)((unsigned long long)nitems * before / G);
   const unsigned int hi = (unsigned)((unsigned long long)nitems * (before + cx) / G);
-  const unsigned int cnt = rk < hi - lo ? (hi - lo - rk + cx - 1u) / cx : 0u;
+  const unsigned int nx = hi - lo;
+  const unsigned int nblk = (nx + cx - 1u) / cx;
   if (threadIdx.x == 0) next = 0u;
   __syncthreads();
   // No branch on the lane index may sit in this loop: the compiler may thread
@@ -1810,8 +1838,10 @@ __global__ __launch_bounds__((PairWaves<CT>::value * kWave), (sizeof(CT) == 4 ? 
   for (;;) {
     const unsigned int mine = atomicAdd(&next, lane_id() == 0 ? 1u : 0u);
     const unsigned int t = (unsigned)uniform((int)mine);
-    if (t >= cnt) break;
-    const unsigned int item = uniform((int)Q.items[lo + rk + t * cx]);
+    if (t >= nblk) break;
+    const unsigned int pos = t * cx + (rk + (t * 2654435761u) % cx) % cx;
+    if (pos >= nx) continue;  // the last block may be partial
+    const unsigned int item = uniform((int)Q.items[lo + pos]);
     process_item<CT, FD, CUT, QUART>(reqs, clus_end, nreq, (int)(item >> kItemShift),
                               (int)(item & ((1u << kItemShift) - 1u)), recs);
   }
