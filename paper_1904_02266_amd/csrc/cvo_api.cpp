@@ -1327,7 +1327,7 @@ static int run_eval_static(cvo_ctx* c, Request& q) {
   const size_t off_reqs = 0;
   const size_t off_end = align_up(sizeof(ReqStatic), 256);
   const size_t off_wq = off_end + 256;
-  const size_t off_a = off_wq + 256;
+  const size_t off_a = off_wq + align_up(sizeof(WorkQueue), 256);
   const Layout L = plan(q);
   const size_t off_b = align_up(off_a + L.total, 256);
   if (off_b > kStaticScratchBytes) {
