@@ -1416,7 +1416,7 @@ __device__ __forceinline__ unsigned long long wave_or(unsigned long long v) {
 // lane, with the lane's raw source record in flight.
 template <typename CT, int FD>
 struct Batch {
-  long long end;  // one past the batch's last position
+  int end;  // one past the batch's last position
   bool live;      // this lane's position is inside the batch
   int cell;       // packed cell coordinates of the lane's source
   CT raw[3 + FD];
@@ -1436,7 +1436,7 @@ struct Batch {
 // number of sources paired.
 template <typename CT, int FD, bool CUT, typename Op>
 __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const ClusInfo& ci, int c, int k,
-                                                     long long lo_s, long long hi_s, CT rc2, Op& op, cptr<CT> xr,
+                                                     int lo_s, int hi_s, CT rc2, Op& op, cptr<CT> xr,
                                                      int xs, CT* recs) {
   constexpr int RS = RecStride<FD, Op::kExpanded>::value;
   constexpr int NX = 3 + FD + (Op::kExpanded ? 1 : 0);  // floats read per record
@@ -1460,7 +1460,7 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const C
   // first candidate was found by the prepare kernel)
   int we0 = uniform(R.centry[(size_t)c * R.chunks_max + k]);
   int navail = 0;
-  long long win_end = 0;
+  int win_end = 0;  // positions are ints: a cluster's candidates number below 2^31
   CellEntry me;
   // Loads below are issued by every lane (dead lanes read a valid clamped
   // address): a load under a branch would make the compiler's wait counts
@@ -1480,23 +1480,22 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const C
     me.count = in ? ecount : 0;
     me.end = in ? eend : 0x7fffffff;
     const int last_end = lane_value(me.end, navail > 0 ? navail - 1 : 0);
-    win_end = navail > 0 ? (long long)last_end : hi_s;
+    win_end = navail > 0 ? last_end : hi_s;
   };
   // request the records of the batch starting at pos
-  auto start_batch = [&](long long pos, Batch<CT, FD>& B) {
+  auto start_batch = [&](int pos, Batch<CT, FD>& B) {
     if (pos >= win_end) {
       we0 += navail;
       load_window();
     }
-    long long bend = pos + kWave;
-    if (bend > hi_s) bend = hi_s;
+    int bend = (hi_s - pos < kWave) ? hi_s : pos + kWave;
     if (bend > win_end) bend = win_end;
     B.end = bend;
-    const long long p = pos + l;
-    B.live = p < bend;
+    B.live = l < bend - pos;
+    const int p = pos + (B.live ? l : 0);
     // entries of the window that end at or before pos, and the entry
     // boundaries inside the batch
-    const long long bk = (long long)me.end - pos;
+    const int bk = me.end - pos;  // (me.end >= 0, pos >= 0: no overflow)
     const int eoff = __popcll(__ballot(l < navail && bk <= 0));
     const bool inside = l < navail && bk >= 1 && bk <= kWave - 1;
     int efirst, ecount, eend;
@@ -1520,7 +1519,7 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const C
       eend = __shfl(me.end, ei, kWave);
       B.cell = __shfl(me.cell, ei, kWave);
     }
-    const int src = B.live ? efirst + (int)(p - ((long long)eend - ecount)) : 0;
+    const int src = B.live ? efirst + (p - (eend - ecount)) : 0;
     const CT* xg = xg0 + (size_t)src * xs;
 #pragma unroll
     for (int q = 0; q < 3 + FD; q++) B.raw[q] = xg[q];
@@ -1614,7 +1613,7 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const C
   A.cell = 0;
 #pragma unroll
   for (int q = 0; q < 3 + FD; q++) A.raw[q] = (CT)0;
-  long long pos = lo_s;
+  int pos = lo_s;
   for (;;) {
     const bool moreB = pos < hi_s;
     start_batch(pos, B);
@@ -1646,8 +1645,8 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
   const int total = uniform(ci.total);
   const int chunk = uniform(ci.chunk);
   const int cn = uniform(ci.cn);
-  const long long lo_s = (long long)k * chunk;
-  const long long hi_s = min(lo_s + chunk, (long long)total);
+  const int lo_s = k * chunk;  // k < chunks of the cluster: below total
+  const int hi_s = (total - lo_s < chunk) ? total : lo_s + chunk;
   const bool valid = l < cn;
   // targets in the cluster frame, and labels
   const CT* blk = (const CT*)R.tblk + (size_t)c * (3 + FD) * kWave;
