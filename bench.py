@@ -44,6 +44,8 @@ PEAK_UNPACKED_TFLOPS = 78.6
 METRIC = "pair-evals/s per registration + batched regs/s, p50/p99 latency @1e-5 rel"
 KERNEL_SRC = os.path.join(ROOT, "paper_1904_02266_amd", "csrc", "cvo_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_dense300k_traffic.md")
+# the legs after the headline registration, in the order they run
+LEGS = ("rgbd30k", "batched", "serving", "bruteforce", "frontend", "planes", "odometry")
 GOLDEN = os.path.join(ROOT, "tests", "golden", "dense300k_trajectory.json")
 SAMPLE_ITERS = (0, 25, 50, 99)   # one iteration of each length-scale stage (oracle sample, parity)
 
@@ -491,6 +493,9 @@ def main():
                     help="seconds of Poisson arrivals per serving rate (0: skip)")
     ap.add_argument("--no-extra", action="store_true",
                     help="only the headline registration, its roofline and the CPU baseline")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated extra legs to run after the headline (default: all of "
+                         + ", ".join(LEGS) + ")")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the measurement, copy a MIB-MiB device buffer once (reference dispatch "
                          "of known size for hardware-counter runs)")
@@ -500,13 +505,18 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     extra = not args.no_extra
-    batch_clouds = gen_batch(args.batch if extra else 0)
+    legs = set(x.strip() for x in args.legs.split(",") if x.strip()) if extra else set()
+    unknown = legs - set(LEGS)
+    if unknown:
+        print(f"bench.py: unknown legs {sorted(unknown)}; choose from {', '.join(LEGS)}", file=sys.stderr)
+        sys.exit(2)
+    batch_clouds = gen_batch(args.batch if "batched" in legs else 0)
     progress(f"batched inputs drawn ({len(batch_clouds)})")
-    serve_pool = gen_serving_pool(6 if (args.serving_window > 0 and extra) else 0)
+    serve_pool = gen_serving_pool(6 if (args.serving_window > 0 and "serving" in legs) else 0)
     with ProcessPoolExecutor(max_workers=1) as ex:
         dense_cloud, G = ex.submit(_gen_dense, 3).result()
     odo_frames = None
-    if args.odometry_frames > 1 and extra:
+    if args.odometry_frames > 1 and ("odometry" in legs or "frontend" in legs):
         from paper_1904_02266_amd import synth as _synth
         odo_frames = _synth.rgbd_sequence(args.odometry_frames, seed=9)
     with open(GOLDEN) as f:
@@ -553,32 +563,38 @@ def main():
                  "fp64_trans_m": float(np.linalg.norm(o64["T"][:3, 3] - To[:3, 3]))}
 
     c2 = batch = serve = dense = fe = c1 = odo = None
-    if extra:
-        progress("fp64 path done")
+    progress("fp64 path done")
+    if "rgbd30k" in legs:
         c2 = rgbd30k(ctx, synth.rgbd_pair(30000, 30000, seed=2), max(4, args.steps), args.quartic_steps)
         progress("rgbd 30k done")
-        batch = batched_both(batch_clouds) if batch_clouds else None
+    if batch_clouds:
+        batch = batched_both(batch_clouds)
         progress("batched done")
-        serve = serving(serve_pool, window_s=args.serving_window) if serve_pool else None
+    if serve_pool:
+        serve = serving(serve_pool, window_s=args.serving_window)
+        progress("serving done")
+    if "bruteforce" in legs:
         dense = dense_bruteforce(dense_cloud)
         progress("dense brute force done")
-        fe = frontend_vga(odo_frames[0]) if odo_frames else None
+    if "frontend" in legs and odo_frames:
+        fe = frontend_vga(odo_frames[0])
+    if "planes" in legs:
         c1 = planes_c1()
-        if odo_frames:
-            from paper_1904_02266_amd import odometry, params_table1
-            odometry.run_on_device(ctx, odo_frames[:2], params_table1())  # warm-up
-            torch.cuda.synchronize()
-            o0 = time.perf_counter()
-            res = odometry.run_on_device(ctx, odo_frames, params_table1())
-            torch.cuda.synchronize()
-            o_el = time.perf_counter() - o0
-            odo = {"frames": len(odo_frames), "frames_per_s": (len(odo_frames) - 1) / o_el,
-                   "ms_per_frame": o_el * 1e3 / (len(odo_frames) - 1),
-                   "params": "Table 1 (quartic step, value floor 1e-3, ell 0.15/0.10/0.06/0.03, thresholds 1e-5/5e-5)",
-                   "per_frame": "device front end of the new frame (30,000 points) + registration; frames uploaded "
-                                "from host memory each step (the images' PCIe copy is inside the timing)",
-                   "iterations": res.iterations, "relative_error_cdf": res.cdf(),
-                   "sequence": "synthetic, 640x480, 1 deg / 2 cm per frame, 1% depth noise, seed 9"}
+    if "odometry" in legs and odo_frames:
+        from paper_1904_02266_amd import odometry, params_table1
+        odometry.run_on_device(ctx, odo_frames[:2], params_table1())  # warm-up
+        torch.cuda.synchronize()
+        o0 = time.perf_counter()
+        res = odometry.run_on_device(ctx, odo_frames, params_table1())
+        torch.cuda.synchronize()
+        o_el = time.perf_counter() - o0
+        odo = {"frames": len(odo_frames), "frames_per_s": (len(odo_frames) - 1) / o_el,
+               "ms_per_frame": o_el * 1e3 / (len(odo_frames) - 1),
+               "params": "Table 1 (quartic step, value floor 1e-3, ell 0.15/0.10/0.06/0.03, thresholds 1e-5/5e-5)",
+               "per_frame": "device front end of the new frame (30,000 points) + registration; frames uploaded "
+                            "from host memory each step (the images' PCIe copy is inside the timing)",
+               "iterations": res.iterations, "relative_error_cdf": res.cdf(),
+               "sequence": "synthetic, 640x480, 1 deg / 2 cm per frame, 1% depth noise, seed 9"}
 
     line = {
         "metric": METRIC,
