@@ -1,11 +1,16 @@
 """Frame-to-frame odometry on a synthetic RGB-D sequence with the TUM
 parameter set of Table 1 (front end and registrations on the GPU).
 
-The frames carry 1% depth noise and independent pixel selections, which
-bounds the attainable accuracy (about 0.1-0.5 deg and 0.5-3 cm per pair on
-1 deg / 2 cm steps); the checks are that the estimates beat the no-motion
-estimate and stay within that floor, and that each link of the chain is the
-plain registration of its two frames."""
+Each registration converges to the maximum of its own pair's objective,
+which on these frames lies about 0.1-0.5 deg and 0.5-3 cm from the
+generating motion of a 1 deg / 2 cm step: the semi-dense selection and the
+depth limits are anchored to each camera, not to the scene, so the two
+frames see different parts of the room (the oracle follows the same
+trajectories).  The accuracy checks are therefore that the estimates beat
+the no-motion estimate and stay within that offset, and that each link of
+the chain is the plain registration of its two frames; whether the chain is
+the method's is checked against the oracle's own chain
+(test_served_odometry_matches_oracle_chain)."""
 import numpy as np
 import pytest
 
