@@ -87,6 +87,7 @@ struct Layout {
   size_t off_count[kMaxStages + 1], off_cursor[kMaxStages + 1], off_tmp[kMaxStages + 1], off_sums[kMaxStages + 1];
   size_t off_segs, off_scans, off_clscan_args, off_zrec, off_zorig, off_xrec[kMaxStages], off_xrecptr;
   size_t off_clflag, off_clscan, off_clfirst, off_clsums, off_clstart, off_clcount;
+  size_t cl_sums_stride;  // ints per stage in the clustering scan's tile sums
   size_t off_state;
   size_t total;
   int kcap, zs, xs, nblk_bbox;
@@ -145,16 +146,17 @@ Layout plan(const Request& q) {
   }
   L.off_segs = take(sizeof(SortSeg) * (S + 1));
   L.off_scans = take(sizeof(ScanArgs) * (S + 1));
-  L.off_clscan_args = take(sizeof(ScanArgs));
+  L.off_clscan_args = take(sizeof(ScanArgs) * S);
   L.off_zrec = take(m * L.zs * 4);
   L.off_zorig = take(m * 4);
   const size_t xb = (q.precision == CVO_FP64) ? 8 : 4;
   for (int s = 0; s < S; s++) L.off_xrec[s] = take(n * L.xs * xb);
   L.off_xrecptr = take(sizeof(void*) * kMaxStages);
-  L.off_clflag = take(4 * m);
-  L.off_clscan = take(4 * m);
-  L.off_clfirst = take(4 * m);
-  L.off_clsums = take(4 * (size_t)(scan_tiles((long long)m) + 1));
+  L.cl_sums_stride = (size_t)(scan_tiles((long long)m) + 1);
+  L.off_clflag = take(4 * m * S);
+  L.off_clscan = take(4 * m * S);
+  L.off_clfirst = take(4 * m * S);
+  L.off_clsums = take(4 * L.cl_sums_stride * S);
   L.off_clstart = take(4 * m * S);
   L.off_clcount = take(4 * m * S);
   L.off_state = take(sizeof(ReqState));
@@ -549,7 +551,7 @@ static int enqueue_ingest(cvo_ctx* c, Request& q, const Layout& L, hipStream_t s
     double ell[kMaxStages];
     SortSeg segs[kMaxStages + 1];
     ScanArgs scans[kMaxStages + 1];
-    ScanArgs clscan;
+    ScanArgs clscan[kMaxStages];
     void* xrecptr[kMaxStages];
   };
   static_assert(sizeof(Staging) < 16384, "staging area");
@@ -578,17 +580,19 @@ static int enqueue_ingest(cvo_ctx* c, Request& q, const Layout& L, hipStream_t s
     sa.len0 = 1;
     sa.sums = g.sums;
   }
-  h->clscan.data = (int*)(A + L.off_clscan);
-  h->clscan.lenp = nullptr;
-  h->clscan.len0 = q.m;
-  h->clscan.sums = (int*)(A + L.off_clsums);
+  for (int st = 0; st < S; st++) {
+    h->clscan[st].data = (int*)(A + L.off_clscan) + (size_t)st * q.m;
+    h->clscan[st].lenp = nullptr;
+    h->clscan[st].len0 = q.m;
+    h->clscan[st].sums = (int*)(A + L.off_clsums) + (size_t)st * L.cl_sums_stride;
+  }
   for (int k = 0; k < kMaxStages; k++) h->xrecptr[k] = (k < S) ? (void*)(A + L.off_xrec[k]) : nullptr;
 
   HIPCHK(c, hipMemcpyAsync(A + L.off_T0, h->T0, sizeof(h->T0), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(A + L.off_ell, h->ell, sizeof(h->ell), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(A + L.off_segs, h->segs, sizeof(SortSeg) * (S + 1), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(A + L.off_scans, h->scans, sizeof(ScanArgs) * (S + 1), hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(A + L.off_clscan_args, &h->clscan, sizeof(ScanArgs), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(A + L.off_clscan_args, h->clscan, sizeof(ScanArgs) * S, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(A + L.off_xrecptr, h->xrecptr, sizeof(h->xrecptr), hipMemcpyHostToDevice, s));
 
   const float *sx = q.sx, *sf = q.sfeat, *tx = q.tx, *tf = q.tfeat;

@@ -213,13 +213,14 @@ struct IngestArgs {
   int* tgt_perm;             // [m]
   SortSeg* segs;             // device [n_stages + 1] (target segment last)
   ScanArgs* sort_scans;      // device [n_stages + 1], over the count arrays (K + 1 entries)
-  ScanArgs* cl_scan_args;    // device [1], over cl_scan (m entries)
+  ScanArgs* cl_scan_args;    // device [n_stages], stage s over cl_scan + s m (m entries)
   int max_seg_n, max_kcap;
   float* zrec;
   int* zorig;
   void* const* xrec_dev;     // device array [n_stages] of record pointers
-  // target clustering (one per stage): scratch [m] each (cl_sums: [m/kScanTile + 1]),
-  // outputs [n_stages][m]
+  // target clustering (one per stage, all stages in each launch): scratch
+  // [n_stages][m] each (cl_sums: [n_stages][m/kScanTile + 1]), outputs
+  // [n_stages][m]
   int *cl_flag, *cl_scan, *cl_first, *cl_sums;
   int *clus_start, *clus_count;
   ReqState* state;

@@ -166,19 +166,35 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const float* __restrict__ 
   if (t < 7) part[7 * blockIdx.x + t] = sh[t][0];
 }
 
-// out: min xyz, max xyz, mean |p|^2
-__global__ void k_bbox_final(const double* __restrict__ part, int nblk, int n, double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// out: min xyz, max xyz, mean |p|^2.  One block of kBboxThreads: thread t
+// folds partials t, t + kBboxThreads, ... in order, then a fixed tree in LDS
+// (the same order on every run).
+constexpr int kBboxThreads = 256;
+__global__ __launch_bounds__(kBboxThreads) void k_bbox_final(const double* __restrict__ part, int nblk, int n,
+                                                            double* __restrict__ out) {
+  __shared__ double sh[7][kBboxThreads];
+  const int t = threadIdx.x;
   double r[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
-  for (int b = 0; b < nblk; b++) {
+  for (int b = t; b < nblk; b += kBboxThreads) {
     for (int a = 0; a < 3; a++) {
       r[a] = fmin(r[a], part[7 * b + a]);
       r[3 + a] = fmax(r[3 + a], part[7 * b + 3 + a]);
     }
     r[6] += part[7 * b + 6];
   }
-  r[6] /= (double)n;
-  for (int q = 0; q < 7; q++) out[q] = r[q];
+  for (int q = 0; q < 7; q++) sh[q][t] = r[q];
+  __syncthreads();
+  for (int o = kBboxThreads / 2; o > 0; o >>= 1) {
+    if (t < o) {
+      for (int a = 0; a < 3; a++) {
+        sh[a][t] = fmin(sh[a][t], sh[a][t + o]);
+        sh[3 + a][t] = fmax(sh[3 + a][t], sh[3 + a][t + o]);
+      }
+      sh[6][t] += sh[6][t + o];
+    }
+    __syncthreads();
+  }
+  if (t < 7) out[t] = (t == 6) ? sh[6][0] / (double)n : sh[t][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -475,10 +491,14 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const ScanArgs* __rest
 // edges, 2 x the stage's cutoff radius), so that no cluster straddles a large
 // jump of the Morton curve.
 // ---------------------------------------------------------------------------
+// (blockIdx.y = stage in all of them; scratch and outputs [stage][m])
 __global__ __launch_bounds__(256) void k_cl_flags(const float* __restrict__ zrec, int zs, int m,
                                                   const double* __restrict__ zbox, double kappa,
-                                                  const double* __restrict__ stage_ell, int stage,
-                                                  int* __restrict__ flag, int* __restrict__ scan) {
+                                                  const double* __restrict__ stage_ell,
+                                                  int* __restrict__ flag_all, int* __restrict__ scan_all) {
+  const int stage = blockIdx.y;
+  int* __restrict__ flag = flag_all + (size_t)stage * m;
+  int* __restrict__ scan = scan_all + (size_t)stage * m;
   double e = 0.0;
   for (int a = 0; a < 3; a++) e = fmax(e, zbox[3 + a] - zbox[a]);
   // with a cutoff, a gap up to twice the cutoff radius stays inside a cluster:
@@ -504,15 +524,23 @@ __global__ __launch_bounds__(256) void k_cl_flags(const float* __restrict__ zrec
 }
 
 // segment of p = (exclusive flag scan at p) + flag[p] - 1; record segment starts
-__global__ __launch_bounds__(256) void k_cl_segfirst(const int* __restrict__ flag, const int* __restrict__ scan, int m,
-                                                     int* __restrict__ first) {
+__global__ __launch_bounds__(256) void k_cl_segfirst(const int* __restrict__ flag_all, const int* __restrict__ scan_all,
+                                                     int m, int* __restrict__ first_all) {
+  const size_t so = (size_t)blockIdx.y * m;
+  const int* __restrict__ flag = flag_all + so;
+  const int* __restrict__ scan = scan_all + so;
+  int* __restrict__ first = first_all + so;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x)
     if (flag[p]) first[scan[p]] = p;
 }
 
 // cluster-start flags: a segment start, or every 64th target inside a segment
-__global__ __launch_bounds__(256) void k_cl_cflags(int* __restrict__ flag, int* __restrict__ scan,
-                                                   const int* __restrict__ first, int m) {
+__global__ __launch_bounds__(256) void k_cl_cflags(int* __restrict__ flag_all, int* __restrict__ scan_all,
+                                                   const int* __restrict__ first_all, int m) {
+  const size_t so = (size_t)blockIdx.y * m;
+  int* __restrict__ flag = flag_all + so;
+  int* __restrict__ scan = scan_all + so;
+  const int* __restrict__ first = first_all + so;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
     const int seg = scan[p] + flag[p] - 1;
     const int pos = p - first[seg];
@@ -522,17 +550,26 @@ __global__ __launch_bounds__(256) void k_cl_cflags(int* __restrict__ flag, int* 
   }
 }
 
-__global__ __launch_bounds__(256) void k_cl_table(const int* __restrict__ cflag, const int* __restrict__ cscan, int m,
-                                                  int stage, int* __restrict__ clus_start,
+__global__ __launch_bounds__(256) void k_cl_table(const int* __restrict__ cflag_all, const int* __restrict__ cscan_all,
+                                                  int m, int* __restrict__ clus_start_all,
                                                   ReqState* __restrict__ S) {
+  const int stage = blockIdx.y;
+  const size_t so = (size_t)stage * m;
+  const int* __restrict__ cflag = cflag_all + so;
+  const int* __restrict__ cscan = cscan_all + so;
+  int* __restrict__ clus_start = clus_start_all + so;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
     if (cflag[p]) clus_start[cscan[p]] = p;
     if (p == m - 1) S->nclus_s[stage] = cscan[p] + cflag[p];
   }
 }
 
-__global__ __launch_bounds__(256) void k_cl_count(const int* __restrict__ clus_start, const ReqState* __restrict__ S,
-                                                  int m, int stage, int* __restrict__ clus_count) {
+__global__ __launch_bounds__(256) void k_cl_count(const int* __restrict__ clus_start_all,
+                                                  const ReqState* __restrict__ S, int m,
+                                                  int* __restrict__ clus_count_all) {
+  const int stage = blockIdx.y;
+  const int* __restrict__ clus_start = clus_start_all + (size_t)stage * m;
+  int* __restrict__ clus_count = clus_count_all + (size_t)stage * m;
   const int nc = S->nclus_s[stage];
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x)
     clus_count[c] = ((c + 1 < nc) ? clus_start[c + 1] : m) - clus_start[c];
@@ -2225,9 +2262,9 @@ hipError_t launch_ingest(const IngestArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_check_finite, dim3(blocks_for((long long)a.fd * a.m, B, 1024)), dim3(B), 0, s, a.tfeat,
                      (long long)a.fd * a.m, a.state);
   hipLaunchKernelGGL(k_bbox_partial, dim3(a.nblk_bbox), dim3(B), 0, s, a.sx, a.n, a.xpart);
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(1), 0, s, a.xpart, a.nblk_bbox, a.n, a.xbox);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kBboxThreads), 0, s, a.xpart, a.nblk_bbox, a.n, a.xbox);
   hipLaunchKernelGGL(k_bbox_partial, dim3(a.nblk_bbox), dim3(B), 0, s, a.tx, a.m, a.zpart);
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(1), 0, s, a.zpart, a.nblk_bbox, a.m, a.zbox);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kBboxThreads), 0, s, a.zpart, a.nblk_bbox, a.m, a.zbox);
   hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(32), 0, s, a.xbox, a.n_stages, a.stage_ell, a.kappa,
                      a.cells_per_reach, a.brute_div, a.kcap, a.grid, a.ncell);
   hipLaunchKernelGGL(k_src_keys, dim3(blocks_for(a.n, B, 1024), a.n_stages), dim3(B), 0, s, a.sx, a.n, a.grid,
@@ -2248,20 +2285,17 @@ hipError_t launch_ingest(const IngestArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_src_records<float>, dim3(blocks_for(a.n, B, 1024), a.n_stages), dim3(B), 0, s, a.sx,
                        a.sfeat, a.n, a.fd, a.xs, a.grid, a.src_keys, a.src_perm, (float* const*)a.xrec_dev);
   }
-  // target clusters, one clustering per stage
+  // target clusters, one clustering per stage, every stage in each launch
   const int gm = blocks_for(a.m, B, 1024);
-  for (int st = 0; st < a.n_stages; st++) {
-    int* cstart = a.clus_start + (size_t)st * a.m;
-    int* ccount = a.clus_count + (size_t)st * a.m;
-    hipLaunchKernelGGL(k_cl_flags, dim3(gm), dim3(B), 0, s, a.zrec, a.zs, a.m, a.zbox, a.kappa, a.stage_ell, st,
-                       a.cl_flag, a.cl_scan);
-    launch_scan(a.cl_scan_args, 1, a.m, s);
-    hipLaunchKernelGGL(k_cl_segfirst, dim3(gm), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.m, a.cl_first);
-    hipLaunchKernelGGL(k_cl_cflags, dim3(gm), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.cl_first, a.m);
-    launch_scan(a.cl_scan_args, 1, a.m, s);
-    hipLaunchKernelGGL(k_cl_table, dim3(gm), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.m, st, cstart, a.state);
-    hipLaunchKernelGGL(k_cl_count, dim3(gm), dim3(B), 0, s, cstart, a.state, a.m, st, ccount);
-  }
+  const int S = a.n_stages;
+  hipLaunchKernelGGL(k_cl_flags, dim3(gm, S), dim3(B), 0, s, a.zrec, a.zs, a.m, a.zbox, a.kappa, a.stage_ell,
+                     a.cl_flag, a.cl_scan);
+  launch_scan(a.cl_scan_args, S, a.m, s);
+  hipLaunchKernelGGL(k_cl_segfirst, dim3(gm, S), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.m, a.cl_first);
+  hipLaunchKernelGGL(k_cl_cflags, dim3(gm, S), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.cl_first, a.m);
+  launch_scan(a.cl_scan_args, S, a.m, s);
+  hipLaunchKernelGGL(k_cl_table, dim3(gm, S), dim3(B), 0, s, a.cl_flag, a.cl_scan, a.m, a.clus_start, a.state);
+  hipLaunchKernelGGL(k_cl_count, dim3(gm, S), dim3(B), 0, s, a.clus_start, a.state, a.m, a.clus_count);
   hipLaunchKernelGGL(k_setup_final, dim3(1), dim3(1), 0, s, a.state, a.xbox, a.zbox, a.a2_param, a.n_stages);
   return hipGetLastError();
 }
