@@ -314,6 +314,10 @@ struct cvo_ctx {
   std::thread sched;
   bool sched_started = false;
   hipStream_t serve_stream = nullptr;
+  // stream-ordered device memory of served requests (a pool that keeps what
+  // it has allocated, so admission and release do not synchronise the
+  // device); null: plain hipMalloc / hipFree
+  hipMemPool_t pool = nullptr;
   size_t max_pending = 65536;
   // serving counters (under q_mu)
   int64_t st_active = 0, st_completed = 0, st_failed = 0;
@@ -976,33 +980,56 @@ void complete(cvo_ctx* c, Request* q, int status) {
   c->done_cv.notify_all();
 }
 
-void release(Request* q, uint64_t& in_use) {
-  if (q->arena) (void)hipFree(q->arena);
-  if (q->arena_b) (void)hipFree(q->arena_b);
+// device memory of a served request, in the order of the serving stream
+char* serve_alloc(cvo_ctx* c, size_t bytes, hipStream_t s) {
+  void* p = nullptr;
+  const hipError_t e = c->pool ? hipMallocFromPoolAsync(&p, bytes, c->pool, s) : hipMalloc(&p, bytes);
+  return e == hipSuccess ? (char*)p : nullptr;
+}
+void serve_free(cvo_ctx* c, void* p, hipStream_t s) {
+  if (!p) return;
+  if (c->pool) (void)hipFreeAsync(p, s);
+  else (void)hipFree(p);
+}
+
+// Both arenas go back after the work already enqueued on the serving stream.
+void release(cvo_ctx* c, Request* q, uint64_t& in_use, hipStream_t s) {
+  serve_free(c, q->arena, s);
+  serve_free(c, q->arena_b, s);
   q->arena = nullptr;
   q->arena_b = nullptr;
   in_use -= q->arena_bytes;
   q->arena_bytes = 0;
 }
 
-// Admit one request, first half: allocate arena A, ingest, read back the
-// cluster count.  *exact receives the request's exact device bytes (arenas A
-// and B).  Returns CVO_OK or an error code for the request.
-int admit_ingest(cvo_ctx* c, Request* q, hipStream_t s, void* h_stage, size_t* exact) {
+// Pinned host memory per request of an admission batch: the ingest's
+// staged structures, then (at kAdmitStateOff) the state read back.
+constexpr int kAdmitBatch = 32;
+constexpr size_t kAdmitStateOff = 32768;
+constexpr size_t kAdmitSlot = 49152;
+static_assert(kAdmitStateOff + sizeof(ReqState) <= kAdmitSlot, "admission slot");
+
+// Admit one request, first half: allocate arena A, enqueue the ingest and
+// the read-back of its state into the request's slot (the cluster count is
+// read after the batch's synchronisation).  Returns CVO_OK or an error code.
+int admit_enqueue(cvo_ctx* c, Request* q, hipStream_t s, char* slot) {
   const Layout L = plan(*q);
-  if (hipMalloc(&q->arena, L.total) != hipSuccess) {
-    q->arena = nullptr;
-    return CVO_ENOMEM;
-  }
-  int rc = enqueue_ingest(c, *q, L, s, h_stage);
+  q->arena = serve_alloc(c, L.total, s);
+  if (!q->arena) return CVO_ENOMEM;
+  int rc = enqueue_ingest(c, *q, L, s, slot);
   if (rc) return rc;
-  ReqState* hs = (ReqState*)((char*)h_stage + 32768);
-  if (hipMemcpyAsync(hs, q->state, sizeof(ReqState), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
+  if (hipMemcpyAsync(slot + kAdmitStateOff, q->state, sizeof(ReqState), hipMemcpyDeviceToHost, s) != hipSuccess)
     return CVO_EDEVICE;
+  return CVO_OK;
+}
+
+// After the synchronisation: the cluster count, and in *exact the request's
+// exact device bytes (arenas A and B).
+int admit_readback(Request* q, const char* slot, size_t* exact) {
+  const ReqState* hs = (const ReqState*)(slot + kAdmitStateOff);
   if (hs->done) return hs->status ? hs->status : CVO_EINVAL;
   q->nclus = hs->nclus;
-  *exact = L.total + plan_b(*q, q->nclus).total;
+  *exact = plan(*q).total + plan_b(*q, q->nclus).total;
   return CVO_OK;
 }
 
@@ -1011,10 +1038,8 @@ int admit_ingest(cvo_ctx* c, Request* q, hipStream_t s, void* h_stage, size_t* e
 int admit_finish(cvo_ctx* c, Request* q, hipStream_t s) {
   const Layout L = plan(*q);
   const LayoutB LB = plan_b(*q, q->nclus);
-  if (hipMalloc(&q->arena_b, LB.total) != hipSuccess) {
-    q->arena_b = nullptr;
-    return CVO_ENOMEM;
-  }
+  q->arena_b = serve_alloc(c, LB.total, s);
+  if (!q->arena_b) return CVO_ENOMEM;
   q->res.device_bytes = L.total + LB.total;
   return finish_setup(c, *q, L, LB, s);
 }
@@ -1030,9 +1055,10 @@ void scheduler(cvo_ctx* c) {
   ReqStatic* h_reqs = nullptr;
   int* h_end = nullptr;
   ReqState* h_states = nullptr;
+  ReqState* d_states = nullptr;  // the batch's states gathered for one read-back
   DevQueue queue;
   void* h_stage = nullptr;
-  (void)hipHostMalloc(&h_stage, 64 * 1024, hipHostMallocDefault);
+  if (hipHostMalloc(&h_stage, kAdmitSlot * kAdmitBatch, hipHostMallocDefault) != hipSuccess) h_stage = nullptr;
   const int chunk = 8;
   for (;;) {
     std::vector<Request*> admit;
@@ -1063,9 +1089,23 @@ void scheduler(cvo_ctx* c) {
       c->st_hbm_peak = std::max(c->st_hbm_peak, (uint64_t)in_use);
     }
     std::vector<Request*> requeue;
-    for (Request* q : admit) {
+    // admissions in batches: the ingests of a batch are enqueued together and
+    // the cluster counts read after one synchronisation
+    std::vector<int> enq_rc(admit.size(), CVO_OK);
+    bool synced = true;
+    for (size_t k = 0; k < admit.size(); k++) {
+      const size_t slot = k % kAdmitBatch;
+      if (slot == 0) {
+        const size_t end = std::min(admit.size(), k + kAdmitBatch);
+        for (size_t j = k; j < end; j++)
+          enq_rc[j] = h_stage ? admit_enqueue(c, admit[j], s, (char*)h_stage + (j - k) * kAdmitSlot) : CVO_ENOMEM;
+        synced = hipStreamSynchronize(s) == hipSuccess;
+      }
+      Request* q = admit[k];
       size_t exact = 0;
-      int rc = admit_ingest(c, q, s, h_stage, &exact);
+      int rc = enq_rc[k];
+      if (rc == CVO_OK)
+        rc = synced ? admit_readback(q, (const char*)h_stage + slot * kAdmitSlot, &exact) : CVO_EDEVICE;
       if (rc == CVO_OK) {
         // charge the exact size; a request that no longer fits beside the
         // running ones waits in the queue with its exact size (its ingest is
@@ -1076,7 +1116,7 @@ void scheduler(cvo_ctx* c) {
         if (c->budget && exact > c->budget) {
           rc = CVO_ENOMEM;
         } else if (c->budget && in_use > c->budget && !(active.empty() && q == admit.front())) {
-          release(q, in_use);
+          release(c, q, in_use, s);
           requeue.push_back(q);
           continue;
         } else {
@@ -1084,7 +1124,7 @@ void scheduler(cvo_ctx* c) {
         }
       }
       if (rc != CVO_OK) {
-        release(q, in_use);
+        release(c, q, in_use, s);
         complete(c, q, rc);
         continue;
       }
@@ -1107,15 +1147,24 @@ void scheduler(cvo_ctx* c) {
     if (nreq > cap_reqs) {
       if (d_reqs) (void)hipFree(d_reqs);
       if (d_end) (void)hipFree(d_end);
+      if (d_states) (void)hipFree(d_states);
       if (h_reqs) (void)hipHostFree(h_reqs);
       if (h_end) (void)hipHostFree(h_end);
       if (h_states) (void)hipHostFree(h_states);
+      d_reqs = nullptr;
+      d_end = nullptr;
+      d_states = nullptr;
+      h_reqs = nullptr;
+      h_end = nullptr;
+      h_states = nullptr;
       cap_reqs = std::max(nreq, 2 * cap_reqs);
-      (void)hipMalloc(&d_reqs, sizeof(ReqStatic) * cap_reqs);
-      (void)hipMalloc(&d_end, sizeof(int) * cap_reqs);
-      (void)hipHostMalloc(&h_reqs, sizeof(ReqStatic) * cap_reqs, hipHostMallocDefault);
-      (void)hipHostMalloc(&h_end, sizeof(int) * cap_reqs, hipHostMallocDefault);
-      (void)hipHostMalloc(&h_states, sizeof(ReqState) * cap_reqs, hipHostMallocDefault);
+      if (hipMalloc(&d_reqs, sizeof(ReqStatic) * cap_reqs) != hipSuccess) d_reqs = nullptr;
+      if (hipMalloc(&d_end, sizeof(int) * cap_reqs) != hipSuccess) d_end = nullptr;
+      if (hipMalloc(&d_states, sizeof(ReqState) * cap_reqs) != hipSuccess) d_states = nullptr;
+      if (hipHostMalloc(&h_reqs, sizeof(ReqStatic) * cap_reqs, hipHostMallocDefault) != hipSuccess) h_reqs = nullptr;
+      if (hipHostMalloc(&h_end, sizeof(int) * cap_reqs, hipHostMallocDefault) != hipSuccess) h_end = nullptr;
+      if (hipHostMalloc(&h_states, sizeof(ReqState) * cap_reqs, hipHostMallocDefault) != hipSuccess)
+        h_states = nullptr;
     }
     struct G {
       int precision, fd, cut, rule, first, count, clusters;
@@ -1141,7 +1190,7 @@ void scheduler(cvo_ctx* c) {
     }
     unsigned long long most_items = 1;
     for (const G& g : gl) most_items = std::max(most_items, g.items);
-    bool dev_ok = d_reqs && d_end && h_reqs && h_end && h_states && queue.ensure(most_items) &&
+    bool dev_ok = d_reqs && d_end && d_states && h_reqs && h_end && h_states && queue.ensure(most_items) &&
                   queue.reset(s) == hipSuccess &&
                   hipMemcpyAsync(d_reqs, h_reqs, sizeof(ReqStatic) * nreq, hipMemcpyHostToDevice, s) == hipSuccess &&
                   hipMemcpyAsync(d_end, h_end, sizeof(int) * nreq, hipMemcpyHostToDevice, s) == hipSuccess;
@@ -1153,9 +1202,10 @@ void scheduler(cvo_ctx* c) {
           dev_ok = false;
       }
     }
-    for (int k = 0; k < nreq && dev_ok; k++)
-      if (hipMemcpyAsync(h_states + k, order[k]->state, sizeof(ReqState), hipMemcpyDeviceToHost, s) != hipSuccess)
-        dev_ok = false;
+    if (dev_ok && (launch_gather_states(d_reqs, nreq, d_states, s) != hipSuccess ||
+                   hipMemcpyAsync(h_states, d_states, sizeof(ReqState) * nreq, hipMemcpyDeviceToHost, s) !=
+                       hipSuccess))
+      dev_ok = false;
     if (dev_ok && hipStreamSynchronize(s) != hipSuccess) dev_ok = false;
     roctxRangePop();
     std::vector<Request*> still;
@@ -1170,7 +1220,7 @@ void scheduler(cvo_ctx* c) {
             if (rows > 0) (void)hipMemcpy(q->trace.data(), q->trace_dev, q->trace.size() * 8, hipMemcpyDeviceToHost);
           }
         }
-        release(q, in_use);
+        release(c, q, in_use, s);
         complete(c, q, dev_ok ? h_states[k].status : CVO_EDEVICE);
       } else {
         still.push_back(q);
@@ -1183,8 +1233,10 @@ void scheduler(cvo_ctx* c) {
       c->st_hbm_in_use = in_use;
     }
   }
+  (void)hipStreamSynchronize(s);
   if (d_reqs) (void)hipFree(d_reqs);
   if (d_end) (void)hipFree(d_end);
+  if (d_states) (void)hipFree(d_states);
   if (h_reqs) (void)hipHostFree(h_reqs);
   if (h_end) (void)hipHostFree(h_end);
   if (h_states) (void)hipHostFree(h_states);
@@ -1215,9 +1267,24 @@ int cvo_create(int device, uint64_t hbm_budget_bytes, int max_slots, cvo_ctx** o
     return CVO_EDEVICE;
   }
   c->stream = c->own_stream;
+  {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = device;
+    uint64_t keep = UINT64_MAX;  // freed blocks stay in the pool for the next requests
+    if (hipMemPoolCreate(&c->pool, &props) != hipSuccess) {
+      c->pool = nullptr;
+    } else if (hipMemPoolSetAttribute(c->pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+      (void)hipMemPoolDestroy(c->pool);
+      c->pool = nullptr;
+    }
+  }
   if (init_static_scratch(device) != hipSuccess) {
     (void)hipStreamDestroy(c->own_stream);
     (void)hipStreamDestroy(c->serve_stream);
+    if (c->pool) (void)hipMemPoolDestroy(c->pool);
     delete c;
     return CVO_EDEVICE;
   }
@@ -1255,6 +1322,7 @@ int cvo_destroy(cvo_ctx* c) {
   for (auto& kv : c->tickets) delete kv.second;
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   if (c->serve_stream) (void)hipStreamDestroy(c->serve_stream);
+  if (c->pool) (void)hipMemPoolDestroy(c->pool);
   delete c;
   return CVO_OK;
 }

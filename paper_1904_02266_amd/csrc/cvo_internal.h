@@ -254,6 +254,8 @@ struct FrontendArgs {
 };
 hipError_t launch_frontend(const FrontendArgs& a, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// copies *reqs[k].state to out[k] for k < nreq (one read-back for a batch)
+hipError_t launch_gather_states(const ReqStatic* reqs, int nreq, ReqState* out, hipStream_t s);
 // The allocation-free evaluation's device array (cvo_eval_static): its size,
 // and its device address on the current device.
 constexpr size_t kStaticScratchBytes = 64ull << 20;

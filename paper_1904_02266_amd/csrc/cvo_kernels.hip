@@ -575,6 +575,20 @@ __global__ __launch_bounds__(256) void k_cl_count(const int* __restrict__ clus_s
     clus_count[c] = ((c + 1 < nc) ? clus_start[c + 1] : m) - clus_start[c];
 }
 
+// The mutable states of a launch's requests, copied next to each other so
+// that the host reads them back with one copy (request k -> out[k]).
+__global__ __launch_bounds__(256) void k_gather_states(const ReqStatic* __restrict__ reqs, int nreq,
+                                                       ReqState* __restrict__ out) {
+  static_assert(sizeof(ReqState) % 8 == 0, "states are copied as 8-byte words");
+  constexpr int W = (int)(sizeof(ReqState) / 8);
+  const long long total = (long long)nreq * W;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(i / W), w = (int)(i % W);
+    ((unsigned long long*)(out + k))[w] = ((const unsigned long long*)reqs[k].state)[w];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_zero(unsigned* __restrict__ p, size_t words) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
     p[i] = 0u;
@@ -2242,6 +2256,13 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t words = bytes / 4;
   if (words == 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero, dim3(blocks_for((long long)words, 256, 4096)), dim3(256), 0, s, (unsigned*)p, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_states(const ReqStatic* reqs, int nreq, ReqState* out, hipStream_t s) {
+  if (nreq < 1) return hipSuccess;
+  const long long words = (long long)nreq * (long long)(sizeof(ReqState) / 8);
+  hipLaunchKernelGGL(k_gather_states, dim3(blocks_for(words, 256, 1024)), dim3(256), 0, s, reqs, nreq, out);
   return hipGetLastError();
 }
 
