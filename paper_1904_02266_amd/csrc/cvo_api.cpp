@@ -84,7 +84,7 @@ struct Layout {
   size_t off_sx, off_sf, off_tx, off_tf;
   size_t off_xpart, off_zpart, off_xbox, off_zbox, off_T0, off_ell;
   size_t off_grid, off_ncell, off_skeys, off_tkeys, off_sperm, off_tperm;
-  size_t off_count[kMaxStages + 1], off_cursor[kMaxStages + 1], off_tmp[kMaxStages + 1], off_sums[kMaxStages + 1];
+  size_t off_count[kMaxStages + 1], off_radix[kMaxStages + 1], off_hist[kMaxStages + 1], off_sums[kMaxStages + 1];
   size_t off_segs, off_scans, off_clscan_args, off_zrec, off_zorig, off_xrec[kMaxStages], off_xrecptr;
   size_t off_clflag, off_clscan, off_clfirst, off_clsums, off_clstart, off_clcount;
   size_t cl_sums_stride;  // ints per stage in the clustering scan's tile sums
@@ -139,10 +139,11 @@ Layout plan(const Request& q) {
   for (int s = 0; s <= S; s++) {
     const size_t kc = (s < S) ? (size_t)L.kcap : (size_t)kZBuckets;
     const size_t nn = (s < S) ? n : m;
+    const size_t hist = (size_t)kRadixBins * ((nn + kRadixTile - 1) / kRadixTile);
     L.off_count[s] = take(4 * (kc + 1));
-    L.off_cursor[s] = take(4 * kc);
-    L.off_tmp[s] = take(4 * nn);
-    L.off_sums[s] = take(4 * (size_t)(scan_tiles((long long)kc + 1) + 1));
+    L.off_radix[s] = take(4 * 4 * nn);  // keys and indices, two of each
+    L.off_hist[s] = take(4 * hist);
+    L.off_sums[s] = take(4 * (size_t)(scan_tiles((long long)hist) + 1));
   }
   L.off_segs = take(sizeof(SortSeg) * (S + 1));
   L.off_scans = take(sizeof(ScanArgs) * (S + 1));
@@ -572,16 +573,22 @@ static int enqueue_ingest(cvo_ctx* c, Request& q, const Layout& L, hipStream_t s
     g.keys = tgt ? (const int*)(A + L.off_tkeys) : (const int*)(A + L.off_skeys) + (size_t)sidx * q.n;
     g.nkeys = ncell + sidx;
     g.count = (int*)(A + L.off_count[sidx]);
-    g.cursor = (int*)(A + L.off_cursor[sidx]);
-    g.tmp = (int*)(A + L.off_tmp[sidx]);
+    const size_t nn = (size_t)(tgt ? q.m : q.n);
+    int* rx = (int*)(A + L.off_radix[sidx]);
+    g.key_a = rx;
+    g.idx_a = rx + nn;
+    g.key_b = rx + 2 * nn;
+    g.idx_b = rx + 3 * nn;
+    g.hist = (int*)(A + L.off_hist[sidx]);
     g.perm = tgt ? (int*)(A + L.off_tperm) : (int*)(A + L.off_sperm) + (size_t)sidx * q.n;
     g.sums = (int*)(A + L.off_sums[sidx]);
     g.n = tgt ? q.m : q.n;
     g.kcap = tgt ? kZBuckets : L.kcap;
-    ScanArgs& sa = h->scans[sidx];
-    sa.data = g.count;
-    sa.lenp = g.nkeys;  // K + 1 entries
-    sa.len0 = 1;
+    g.nblocks = (int)((nn + kRadixTile - 1) / kRadixTile);
+    ScanArgs& sa = h->scans[sidx];  // over the digit counts of a radix pass
+    sa.data = g.hist;
+    sa.lenp = nullptr;
+    sa.len0 = kRadixBins * g.nblocks;
     sa.sums = g.sums;
   }
   for (int st = 0; st < S; st++) {

@@ -172,16 +172,23 @@ struct ReqState {
 
 // Descriptor of a counting sort over one key segment (one per stage for the
 // source grids, one for the target spatial order).
+// One segment of the stable key sort (an LSD radix sort over 8-bit digits,
+// tiles of kRadixTile elements per block).
+constexpr int kRadixBins = 256;
+constexpr int kRadixThreads = 256;
+constexpr int kRadixRounds = 4;
+constexpr int kRadixTile = kRadixThreads * kRadixRounds;
 struct SortSeg {
   const int* keys;   // [n]
   const int* nkeys;  // device pointer to K (keys lie in [0, K))
-  int* count;        // [Kcap+1] histogram, then exclusive scan (start table)
-  int* cursor;       // [Kcap] scatter cursors
-  int* tmp;          // [n] scatter output (arbitrary order within a key)
+  int* count;        // [Kcap+1] out: start table, count[k] = number of keys below k (k <= K)
+  int *key_a, *idx_a, *key_b, *idx_b;  // [n] each: the passes' keys and original indices
+  int* hist;         // [kRadixBins][nblocks] digit counts per block, then their exclusive scan
   int* perm;         // [n] stable order: sorted position -> original index
-  int* sums;         // [Kcap/kScanTile + 1] scan block totals
+  int* sums;         // scan tile totals of hist
   int n;
   int kcap;
+  int nblocks;       // ceil(n / kRadixTile)
 };
 
 // Exclusive in-place scan of data[0..len) with len = (lenp ? *lenp : 0) + len0.
@@ -212,7 +219,7 @@ struct IngestArgs {
   int* src_perm;             // [n_stages][n]
   int* tgt_perm;             // [m]
   SortSeg* segs;             // device [n_stages + 1] (target segment last)
-  ScanArgs* sort_scans;      // device [n_stages + 1], over the count arrays (K + 1 entries)
+  ScanArgs* sort_scans;      // device [n_stages + 1], over each segment's radix digit counts (hist)
   ScanArgs* cl_scan_args;    // device [n_stages], stage s over cl_scan + s m (m entries)
   int max_seg_n, max_kcap;
   float* zrec;

@@ -328,42 +328,107 @@ __global__ __launch_bounds__(256) void k_tgt_keys(const float* __restrict__ xyz,
 }
 
 // ---------------------------------------------------------------------------
-// 4) deterministic counting sort (blockIdx.y = segment)
-//    histogram -> exclusive scan -> scatter with cursors -> rank fix: the final
-//    position of point i inside its key is the number of points of the same
-//    key with a smaller index, so the order does not depend on atomics.
+// 4) stable key sort (blockIdx.y = segment): least-significant-digit radix
+//    sort over 8-bit digits.  Pass p: per block of kRadixTile consecutive
+//    elements (of the previous pass's order) the digit counts; their
+//    exclusive scan in digit-major order gives each (digit, block) its first
+//    output position; the scatter gives each element its rank among the
+//    equal digits of its block in element order.  Every pass is stable and
+//    the first one starts in index order, so the result is the order by key
+//    with ties by index, independent of scheduling.  The start table is found
+//    from the sorted keys by binary search.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_sort_zero(const SortSeg* __restrict__ segs) {
+__device__ __forceinline__ const int* radix_keys_in(const SortSeg& S, int pass) {
+  return pass == 0 ? S.keys : (((pass - 1) & 1) ? S.key_b : S.key_a);
+}
+
+__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const SortSeg* __restrict__ segs, int pass) {
+  static_assert(kRadixThreads == kRadixBins, "one digit per thread");
   const SortSeg S = segs[blockIdx.y];
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= S.kcap; k += gridDim.x * blockDim.x) {
-    S.count[k] = 0;
-    if (k < S.kcap) S.cursor[k] = 0;
+  const int b = blockIdx.x;
+  if (b >= S.nblocks) return;  // block-uniform
+  __shared__ int h[kRadixBins];
+  const int t = threadIdx.x;
+  h[t] = 0;
+  __syncthreads();
+  const int* __restrict__ keys = radix_keys_in(S, pass);
+  const int shift = 8 * pass;
+  for (int e = 0; e < kRadixRounds; e++) {
+    const int i = b * kRadixTile + e * kRadixThreads + t;
+    if (i < S.n) atomicAdd(&h[(keys[i] >> shift) & (kRadixBins - 1)], 1);
+  }
+  __syncthreads();
+  S.hist[(size_t)t * S.nblocks + b] = h[t];
+}
+
+__global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const SortSeg* __restrict__ segs, int pass,
+                                                                  int last) {
+  constexpr int NW = kRadixThreads / kWave;
+  const SortSeg S = segs[blockIdx.y];
+  const int b = blockIdx.x;
+  if (b >= S.nblocks) return;  // block-uniform
+  __shared__ int base[kRadixBins];     // next output position of each digit in this block
+  __shared__ int wpos[NW][kRadixBins]; // per round: the waves' counts, then their first positions
+  const int t = threadIdx.x, w = t >> 6, l = lane_id();
+  base[t] = S.hist[(size_t)t * S.nblocks + b];
+  const int* __restrict__ ksrc = radix_keys_in(S, pass);
+  const int* __restrict__ isrc = pass == 0 ? nullptr : (((pass - 1) & 1) ? S.idx_b : S.idx_a);
+  int* __restrict__ kdst = (pass & 1) ? S.key_b : S.key_a;
+  int* __restrict__ idst = last ? S.perm : ((pass & 1) ? S.idx_b : S.idx_a);
+  const int shift = 8 * pass;
+  const unsigned long long below = (1ull << l) - 1ull;  // lanes 0 .. l-1
+  for (int e = 0; e < kRadixRounds; e++) {
+#pragma unroll
+    for (int ww = 0; ww < NW; ww++) wpos[ww][t] = 0;
+    __syncthreads();
+    const int i = b * kRadixTile + e * kRadixThreads + t;
+    const bool valid = i < S.n;
+    const int key = valid ? ksrc[i] : 0;
+    const int idx = valid ? (pass == 0 ? i : isrc[i]) : 0;
+    const int d = (key >> shift) & (kRadixBins - 1);
+    // lanes of this wave with the same digit
+    unsigned long long same = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; bit++) {
+      const bool on = (d >> bit) & 1;
+      const unsigned long long bb = __ballot(on);
+      same &= on ? bb : ~bb;
+    }
+    const int rank = __popcll(same & below);
+    if (valid && rank == 0) wpos[w][d] = __popcll(same);
+    __syncthreads();
+    // digit t: the waves' first positions in wave order, and the next round's base
+    int run = base[t];
+#pragma unroll
+    for (int ww = 0; ww < NW; ww++) {
+      const int c = wpos[ww][t];
+      wpos[ww][t] = run;
+      run += c;
+    }
+    base[t] = run;
+    __syncthreads();
+    if (valid) {
+      const int pos = wpos[w][d] + rank;
+      kdst[pos] = key;
+      idst[pos] = idx;
+    }
+    __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(256) void k_sort_hist(const SortSeg* __restrict__ segs) {
+// start table: count[k] = first sorted position with key >= k, k = 0..K
+__global__ __launch_bounds__(256) void k_radix_start(const SortSeg* __restrict__ segs, int passes) {
   const SortSeg S = segs[blockIdx.y];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < S.n; i += gridDim.x * blockDim.x)
-    atomicAdd(&S.count[S.keys[i]], 1);
-}
-
-__global__ __launch_bounds__(256) void k_sort_scatter(const SortSeg* __restrict__ segs) {
-  const SortSeg S = segs[blockIdx.y];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < S.n; i += gridDim.x * blockDim.x) {
-    const int k = S.keys[i];
-    const int p = S.count[k] + atomicAdd(&S.cursor[k], 1);
-    S.tmp[p] = i;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_sort_rank(const SortSeg* __restrict__ segs) {
-  const SortSeg S = segs[blockIdx.y];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < S.n; i += gridDim.x * blockDim.x) {
-    const int k = S.keys[i];
-    const int a = S.count[k], b = S.count[k + 1];
-    int r = 0;
-    for (int q = a; q < b; q++) r += (S.tmp[q] < i) ? 1 : 0;
-    S.perm[a + r] = i;
+  const int K = *S.nkeys;
+  const int* __restrict__ sk = ((passes - 1) & 1) ? S.key_b : S.key_a;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= K; k += gridDim.x * blockDim.x) {
+    int lo = 0, hi = S.n;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (sk[mid] < k) lo = mid + 1;
+      else hi = mid;
+    }
+    S.count[k] = lo;
   }
 }
 
@@ -434,6 +499,26 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh, int& total) {
   const int r = sh[w] + incl - v;
   __syncthreads();
   return r;
+}
+
+// the whole scan in one block when it fits one tile
+__global__ __launch_bounds__(kScanBlock) void k_scan_single(const ScanArgs* __restrict__ args) {
+  const ScanArgs A = args[blockIdx.y];
+  const int len = scan_len(A);
+  const long long t0 = (long long)threadIdx.x * kScanPerThread;
+  int v[kScanPerThread];
+  int s = 0;
+  for (int k = 0; k < kScanPerThread; k++) {
+    v[k] = (t0 + k < len) ? A.data[t0 + k] : 0;
+    s += v[k];
+  }
+  __shared__ int sh[33];
+  int total;
+  int run = block_excl_scan(s, sh, total);
+  for (int k = 0; k < kScanPerThread; k++) {
+    if (t0 + k < len) A.data[t0 + k] = run;
+    run += v[k];
+  }
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_up(const ScanArgs* __restrict__ args) {
@@ -2267,6 +2352,10 @@ hipError_t launch_gather_states(const ReqStatic* reqs, int nreq, ReqState* out, 
 }
 
 static void launch_scan(const ScanArgs* args, int nseg, long long maxlen, hipStream_t s) {
+  if (maxlen <= kScanTile) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1, nseg), dim3(kScanBlock), 0, s, args);
+    return;
+  }
   const int tiles = (int)((maxlen + kScanTile - 1) / kScanTile);
   hipLaunchKernelGGL(k_scan_up, dim3(tiles, nseg), dim3(kScanBlock), 0, s, args);
   hipLaunchKernelGGL(k_scan_mid, dim3(1, nseg), dim3(kScanBlock), 0, s, args);
@@ -2292,11 +2381,19 @@ hipError_t launch_ingest(const IngestArgs& a, hipStream_t s) {
                      a.src_keys);
   hipLaunchKernelGGL(k_tgt_keys, dim3(blocks_for(a.m, B, 1024)), dim3(B), 0, s, a.tx, a.m, a.zbox, a.tgt_keys);
   const int nseg = a.n_stages + 1;
-  hipLaunchKernelGGL(k_sort_zero, dim3(blocks_for(a.max_kcap + 1LL, B, 2048), nseg), dim3(B), 0, s, a.segs);
-  hipLaunchKernelGGL(k_sort_hist, dim3(blocks_for(a.max_seg_n, B, 1024), nseg), dim3(B), 0, s, a.segs);
-  launch_scan(a.sort_scans, nseg, a.max_kcap + 1LL, s);
-  hipLaunchKernelGGL(k_sort_scatter, dim3(blocks_for(a.max_seg_n, B, 1024), nseg), dim3(B), 0, s, a.segs);
-  hipLaunchKernelGGL(k_sort_rank, dim3(blocks_for(a.max_seg_n, B, 1024), nseg), dim3(B), 0, s, a.segs);
+  // digits of the largest key range: keys lie below max_kcap
+  int bits = 1;
+  while (bits < 31 && (1LL << bits) < (long long)a.max_kcap) bits++;
+  const int passes = (bits + 7) / 8;
+  const int rblocks = (a.max_seg_n + kRadixTile - 1) / kRadixTile;
+  for (int p = 0; p < passes; p++) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(rblocks, nseg), dim3(kRadixThreads), 0, s, a.segs, p);
+    launch_scan(a.sort_scans, nseg, (long long)kRadixBins * rblocks, s);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(rblocks, nseg), dim3(kRadixThreads), 0, s, a.segs, p,
+                       p == passes - 1 ? 1 : 0);
+  }
+  hipLaunchKernelGGL(k_radix_start, dim3(blocks_for(a.max_kcap + 1LL, B, 2048), nseg), dim3(B), 0, s, a.segs,
+                     passes);
   hipLaunchKernelGGL(k_tgt_records, dim3(blocks_for(a.m, B, 1024)), dim3(B), 0, s, a.tx, a.tfeat, a.m, a.fd, a.zs,
                      a.tgt_perm, a.zrec, a.zorig);
   if (a.precision == 1) {
