@@ -17,7 +17,9 @@ a bounded sample of the same registration (its own trajectory's poses), the
 30k semi-dense RGB-D pair (fixed, conjugate-direction and quartic step
 rules, and all pairs without the cutoff), a batched run through the
 continuous-batching scheduler (regs/s, per-request latency), Poisson
-serving at 200-2000 requests/s, and the remaining workloads.
+serving at 200-2000 requests/s, and the remaining workloads.  --legs picks
+which of those legs run after the headline (default: all); --no-extra runs
+the headline and its CPU baseline only.
 """
 import argparse
 import hashlib
