@@ -171,6 +171,41 @@ def test_ragged_sizes(ctx, n, m):
             check(g, ref, what=f"{n}x{m} kappa {kappa}")
 
 
+@pytest.mark.parametrize("n,m", [(1024, 1024), (1025, 2047), (2048, 1023), (3071, 2049)])
+def test_sizes_at_sort_tile_boundaries(ctx, n, m):
+    # the set-up sorts keys in tiles of 1,024 elements: sizes at and just past
+    # tile boundaries, with a cutoff (several cells) and without
+    rng = np.random.default_rng(n * 7 + m)
+    x = rng.uniform(-0.6, 0.6, size=(n, 3)).astype(np.float32)
+    z = (x[rng.integers(0, n, size=m)] + rng.normal(0, 0.02, size=(m, 3))).astype(np.float32)
+    lx = rng.uniform(0, 1, size=(n, 5)).astype(np.float32)
+    lz = rng.uniform(0, 1, size=(m, 5)).astype(np.float32)
+    T = synth.random_motion(rng, 4.0, 0.02)
+    for kappa in (0.0, 3.0):
+        prm = Params(stage_ell=(0.05,), cutoff_mult=kappa, a2=1.0)
+        g = ctx.eval(x, lx, z, lz, T, prm)
+        ref = oracle.eval(x, lx, z, lz, T, ell=0.05, kappa=kappa, a2=1.0)
+        check(g, ref, what=f"{n}x{m} kappa {kappa}")
+
+
+def test_duplicate_points_and_single_cell(ctx):
+    # every source at one of two points (two keys with hundreds of duplicates
+    # each), then every source at the same point (a single cell)
+    rng = np.random.default_rng(91)
+    n, m = 1500, 700
+    base = np.array([[0.1, -0.2, 0.3], [0.14, -0.2, 0.31]], np.float32)
+    lx = rng.uniform(0, 1, size=(n, 5)).astype(np.float32)
+    lz = rng.uniform(0, 1, size=(m, 5)).astype(np.float32)
+    z = (base[0] + rng.normal(0, 0.05, size=(m, 3))).astype(np.float32)
+    for pts in (base[rng.integers(0, 2, size=n)], np.repeat(base[:1], n, axis=0)):
+        x = np.ascontiguousarray(pts, dtype=np.float32)
+        for kappa in (0.0, 3.0):
+            prm = Params(stage_ell=(0.03,), cutoff_mult=kappa, a2=1.0)
+            g = ctx.eval(x, lx, z, lz, np.eye(4), prm)
+            ref = oracle.eval(x, lx, z, lz, np.eye(4), ell=0.03, kappa=kappa, a2=1.0)
+            check(g, ref, what=f"duplicates kappa {kappa}")
+
+
 @pytest.mark.parametrize("fd", [1, 3, 8])
 def test_feature_dims(ctx, fd):
     rng = np.random.default_rng(fd)
