@@ -110,7 +110,8 @@ typedef struct {
 typedef struct {
   double sigma;             /* kernel signal parameter; the prefactor is sigma^2 (> 0) */
   double feat_scale;        /* s_f in c_ij = s_f <l_i, m_j> (> 0) */
-  double a2;                /* rotational metric weight a^2; <= 0 selects mean |x_i|^2 of the source */
+  double a2;                /* rotational metric weight a^2; <= 0 selects mean |x_i|^2 of the source
+                               (a source whose points all lie at the origin then gives a^2 = 0: EINVAL) */
   double b2;                /* translational metric weight b^2 (> 0) */
   double eta;               /* step rule tau = eta ell^2 / F (> 0) */
   double cutoff_mult;       /* kappa >= 0; 0 = every pair (brute force) */

@@ -240,6 +240,43 @@ def test_errors(ctx, rgbd_small):
     assert out["rc"] == CVO_ENOOVERLAP and out["iters"] == 0
 
 
+def test_size_and_schedule_limits(ctx):
+    # the largest accepted sizes are checked before any input is read: a
+    # point count above 16,000,000, feature dimensions outside 1..8 and more
+    # than 8 length-scale stages are rejected (small buffers stand behind the
+    # counts; nothing is dereferenced for a rejected request)
+    import ctypes
+    from paper_1904_02266_amd import CVO_EINVAL, _binding
+    L = _binding.load()
+    xyz = np.random.default_rng(5).uniform(-0.1, 0.1, size=(4, 3)).astype(np.float32)
+    feat = np.full((4, 8), 0.5, np.float32)
+
+    def cloud(n, fd):
+        return _binding.cvo_cloud(n, fd, xyz.ctypes.data, feat.ctypes.data, 0)
+
+    T = (ctypes.c_double * 16)(*np.eye(4).ravel())
+    F = ctypes.c_double()
+    w = (ctypes.c_double * 3)()
+    v = (ctypes.c_double * 3)()
+
+    def rc(src, tgt, prm):
+        p, keep = prm.to_c()
+        return L.cvo_eval(ctx.h, ctypes.byref(src), ctypes.byref(tgt), ctypes.byref(p), T, ctypes.byref(F), w, v)
+
+    ok = Params(stage_ell=(0.1,), a2=1.0)
+    assert rc(cloud(4, 5), cloud(4, 5), ok) == 0
+    assert rc(cloud(16_000_001, 5), cloud(4, 5), ok) == CVO_EINVAL
+    assert rc(cloud(4, 5), cloud(16_000_001, 5), ok) == CVO_EINVAL
+    assert rc(cloud(0, 5), cloud(4, 5), ok) == CVO_EINVAL
+    assert rc(cloud(4, 9), cloud(4, 9), ok) == CVO_EINVAL
+    assert rc(cloud(4, 0), cloud(4, 0), ok) == CVO_EINVAL
+    assert rc(cloud(4, 8), cloud(4, 8), ok) == 0
+    nine = Params(stage_ell=tuple(0.1 for _ in range(9)), stage_iters=tuple(1 for _ in range(8)), a2=1.0)
+    assert rc(cloud(4, 5), cloud(4, 5), nine) == CVO_EINVAL
+    eight = Params(stage_ell=tuple(0.1 for _ in range(8)), stage_iters=tuple(1 for _ in range(7)), a2=1.0)
+    assert rc(cloud(4, 5), cloud(4, 5), eight) == 0
+
+
 def test_device_inputs_same_as_host(ctx, rgbd_small):
     import torch
     p = rgbd_small
