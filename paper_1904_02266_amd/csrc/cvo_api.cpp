@@ -1012,6 +1012,7 @@ void release(cvo_ctx* c, Request* q, uint64_t& in_use, hipStream_t s) {
 // Pinned host memory per request of an admission batch: the ingest's
 // staged structures, then (at kAdmitStateOff) the state read back.
 constexpr int kAdmitBatch = 32;
+constexpr size_t kPoolKeepBytes = size_t(4) << 30;  // kept in the pool while the scheduler is idle
 constexpr size_t kAdmitStateOff = 32768;
 constexpr size_t kAdmitSlot = 49152;
 static_assert(kAdmitStateOff + sizeof(ReqState) <= kAdmitSlot, "admission slot");
@@ -1234,11 +1235,16 @@ void scheduler(cvo_ctx* c) {
       }
     }
     active.swap(still);
+    bool idle = false;
     {
       std::lock_guard<std::mutex> g(c->q_mu);
       c->st_active = (int64_t)active.size();
       c->st_hbm_in_use = in_use;
+      idle = active.empty() && c->pending.empty();
     }
+    // with nothing left to run, the pool gives back what it holds beyond
+    // kPoolKeepBytes (the frees enqueued above complete first)
+    if (idle && c->pool && hipStreamSynchronize(s) == hipSuccess) (void)hipMemPoolTrimTo(c->pool, kPoolKeepBytes);
   }
   (void)hipStreamSynchronize(s);
   if (d_reqs) (void)hipFree(d_reqs);

@@ -254,6 +254,34 @@ def test_serving_counters():
     assert s1["active"] == 0 and s1["pending"] == 0 and s1["hbm_in_use"] == 0
 
 
+def test_served_memory_returns_when_idle():
+    # a burst that holds several GB at once; once the scheduler has nothing
+    # left to run, the memory pool of served requests keeps at most 4 GiB
+    import time
+    import torch
+    dev = torch.device("cuda:0")
+    p = synth.rgbd_pair(60000, 60000, seed=5101, select="random")
+    t = [torch.from_numpy(a).to(dev) for a in (p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat)]
+    torch.cuda.synchronize()
+    prm = params_rgbd(max_iters=3, stage_iters=(1, 1, 1))
+    ctx = Context(0, max_slots=256)
+    try:
+        free0 = torch.cuda.mem_get_info()[0]
+        tks = [ctx.submit(*t, prm) for _ in range(160)]
+        outs = [ctx.poll(tk) for tk, _ in tks]
+        peak = ctx.serving_stats()["hbm_peak"]
+        t0 = time.time()
+        while ctx.serving_stats()["active"] and time.time() - t0 < 20:
+            time.sleep(0.01)
+        time.sleep(0.5)  # the scheduler trims after its last chunk
+        free1 = torch.cuda.mem_get_info()[0]
+    finally:
+        ctx.close()
+    assert all(o["rc"] == 0 for o in outs)
+    assert peak > (6 << 30), peak            # the burst did hold more than the pool keeps
+    assert free0 - free1 < (4 << 30) + (512 << 20), (free0 - free1, peak)
+
+
 def test_queue_limit_busy():
     """A bounded submission queue: with no room every submission is refused
     with CVO_EBUSY and nothing is queued; with room again it is accepted."""
