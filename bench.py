@@ -218,15 +218,19 @@ def gen_serving_pool(npairs):
         return list(ex.map(_gen_pool_pair, [5100 + k for k in range(npairs)]))
 
 
-def serving(pool, rates=(200, 500, 1000, 2000), window_s=10.0, table1_rates=(200,)):
+def serving(pool, rates=(100, 150, 200, 500, 1000, 2000), window_s=10.0, table1_rates=(200,)):
     """Poisson arrivals at each rate over window_s seconds, cloud sizes
     lognormal (median 20k, shape 1.0, clamped to 1000..300000) cut from the
     pool, RGB-D schedule with the conjugate-direction quartic step, stop once
     the last stage's applied twist |tau d| < 1e-5, at most 200 iterations
     (and the Table 1 parameter set at table1_rates); each request is submitted
     at its arrival time and its latency is submission to completion (the
-    library's wall clock).  The saturation point is the highest offered rate
-    that completes at >= 95% of the offered rate."""
+    library's wall clock).  A rate is served when, over the second half of
+    the window (past the start-up, before the drain), requests complete at
+    >= 95% of the rate they arrive at: the admitted requests share the GPU,
+    so under overload every latency grows and only the completion rate
+    shows the backlog.  throughput_per_s counts the completions over the
+    span from the first arrival to the last completion, drain included."""
     import torch
     from paper_1904_02266_amd import Context, params_rgbd, params_table1, synth
     dev = torch.device("cuda:0")
@@ -258,24 +262,30 @@ def serving(pool, rates=(200, 500, 1000, 2000), window_s=10.0, table1_rates=(200
                 fails[str(r["rc"])] = fails.get(str(r["rc"]), 0) + 1
         lat = np.array([r["wall_ms"] for r in ok])
         end = max(ts + r["wall_ms"] / 1e3 for r, ts in res)
+        h0, h1 = 0.5 * window_s, window_s
+        half_arr = sum(1 for _, ts in res if h0 <= ts < h1)
+        half_done = sum(1 for r, ts in res if r["rc"] == 0 and h0 <= ts + r["wall_ms"] / 1e3 < h1)
         progress(f"serving {pname} at {rate}/s: {len(ok)} of {len(res)} in {end:.1f} s")
         out.append({"params": pname, "rate": rate, "requests": len(res), "completed": len(ok),
                     "throughput_per_s": len(ok) / end, "span_s": end,
                     "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                    "steady_throughput_per_s": half_done / (h1 - h0),
+                    "steady_completed_per_arrived": half_done / half_arr if half_arr else None,
                     "mean_iters": float(np.mean([r["iters"] for r in ok])),
                     "converged": float(np.mean([r["converged"] for r in ok])), "failed_by_code": fails,
                     "hbm_peak_gb": st["hbm_peak"] / 1e9})
     sat = None
     for r in out:
-        if r["params"] == "rgbd" and r["throughput_per_s"] >= 0.95 * r["rate"]:
+        if r["params"] == "rgbd" and (r["steady_completed_per_arrived"] or 0.0) >= 0.95:
             sat = r["rate"] if sat is None else max(sat, r["rate"])
-    top = max((r["throughput_per_s"] for r in out if r["params"] == "rgbd"), default=None)
+    top = max((r["steady_throughput_per_s"] for r in out if r["params"] == "rgbd"), default=None)
     return {"window_s": window_s, "sizes": "lognormal median 20k, shape 1.0, clamped 1000..300000",
             "params": {"rgbd": "RGB-D schedule (a stage also ends once |tau d| < 1e-4), conjugate-direction "
                                "quartic step, stop at |tau d| < 1e-5 in the last stage, cap 200 iterations",
                        "table1": "Table 1 set: quartic step, value floor 1e-3, thresholds 1e-5 / 5e-5, cap 200"},
             "saturation": {"highest_rate_served_per_s": sat, "max_throughput_per_s": top,
-                           "criterion": "completed/s >= 0.95 x offered"},
+                           "criterion": "completions >= 0.95 x arrivals over the second half of the window; "
+                                        "max_throughput_per_s is the completion rate over that half"},
             "rates": out}
 
 
