@@ -774,15 +774,25 @@ __device__ __forceinline__ void one_pair(const CT* __restrict__ r, CT zx, CT zy,
 //    its centre (the frame origin): then |x|^2 + |z|^2 stays below ~100.
 //  * difference: d = z - x, r^2 = d.d, accumulating D directly (clusters that
 //    span more, e.g. long chains of targets at a small length-scale).
+// With the cutoff the expanded form is folded: exp2(-r^2) = exp2(-|x|^2)
+// exp2(a) with a = 2 x.z - |z|^2 (= |x|^2 - r^2), the source's factor
+// exp2(-|x|^2) is multiplied into its labels when it is staged, and the
+// cutoff r^2 <= rc2 becomes a >= |x|^2 - rc2, a threshold staged beside the
+// source: three fma for the exponent instead of an add and three fma.  A pair
+// inside the cutoff has a <= |x|^2 <= ~60 (the box within kExpandHalf of the
+// origin, the source within the cutoff of a target), so both factors stay
+// normal FP32 numbers; farther pairs (where exp2(a) may overflow against a
+// vanishing label factor) are removed by the cutoff's select.
 constexpr float kExpandHalf = 3.0f;
 
 template <typename CT, int FD, bool CUT>
 struct GradOp {
   static constexpr bool kExpanded = std::is_same<CT, float>::value;
+  static constexpr bool kFold = kExpanded && CUT;
   CT zx, zy, zz;
   CT mj[FD];
   CT rc2;
-  CT m0, m1, m2, z2;  // -2 z, |z|^2 (expanded form)
+  CT m0, m1, m2, z2;  // expanded form: -2 z, |z|^2; folded: 2 z, -|z|^2
   bool ex;            // the expanded form (wave-uniform)
   Acc<CT> acc;
   // pairs inside the cutoff: a wave-uniform 32-bit count since the last fold
@@ -791,14 +801,44 @@ struct GradOp {
   unsigned int within_blk;
   __device__ __forceinline__ void expand(bool ok) {
     ex = kExpanded && ok;
-    m0 = (CT)-2 * zx;
-    m1 = (CT)-2 * zy;
-    m2 = (CT)-2 * zz;
+    const CT two = kFold ? (CT)2 : (CT)-2;
+    m0 = two * zx;
+    m1 = two * zy;
+    m2 = two * zz;
     z2 = zx * zx + zy * zy + zz * zz;
+    if (kFold) z2 = -z2;
+  }
+  // The staged form of a source record s = (x, y, z, labels, extra word) of
+  // the expanded form: the extra word is |x|^2, or, folded, the labels are
+  // scaled by exp2(-|x|^2) and the extra word is |x|^2 - rc2.
+  __device__ __forceinline__ void stage_rec(CT (&s)[3 + FD + 1]) const {
+    const CT xx = s[0] * s[0] + s[1] * s[1] + s[2] * s[2];
+    if (kFold && ex) {
+      const CT f = kexp2(-xx);
+#pragma unroll
+      for (int q = 0; q < FD; q++) s[3 + q] *= f;
+      s[3 + FD] = xx - rc2;
+    } else {
+      s[3 + FD] = xx;
+    }
   }
   template <bool E>
   __device__ __forceinline__ void pair_t(const CT* r) {
-    if constexpr (E) {
+    if constexpr (E && kFold) {
+      const CT a = fma(r[0], m0, fma(r[1], m1, fma(r[2], m2, z2)));  // |x|^2 - r^2
+      const CT e = kexp2(a);
+      CT c = r[3] * mj[0];
+#pragma unroll
+      for (int f = 1; f < FD; f++) c += r[3 + f] * mj[f];
+      CT w = c * e;
+      const bool in = a >= r[3 + FD];  // r^2 <= rc2
+      within_blk = (unsigned)uniform((int)(within_blk + (unsigned)__popcll(__ballot(in))));
+      w = in ? w : (CT)0;
+      acc.w += w;
+      acc.dx += w * r[0];
+      acc.dy += w * r[1];
+      acc.dz += w * r[2];
+    } else if constexpr (E) {
       const CT r2 = fma(r[0], m0, fma(r[1], m1, fma(r[2], m2, r[3 + FD] + z2)));
       const CT e = kexp2(-r2);
       CT c = r[3] * mj[0];
@@ -886,35 +926,49 @@ struct QuartOp {
   // source position with q = -p and the lane's constant k = c + <z, p>, and
   // r^2 = |x|^2 + |z|^2 - 2 x.z; no difference vector is formed.
   static constexpr bool kExpanded = true;
+  // FP32 with the cutoff: the folded exponent of the gradient pass
+  static constexpr bool kFold = CUT && std::is_same<CT, float>::value;
   CT zx, zy, zz;
   CT mj[FD];
   CT rc2;
   CT q[4][3];         // expanded: -p_k; difference form: p_k
   CT k1, k2, k3, k4;  // expanded: c_k + <z, p_k>; difference form: c_k (c_1 = 0)
-  CT m0, m1, m2, z2;  // -2 z, |z|^2
+  CT m0, m1, m2, z2;  // -2 z, |z|^2; folded: 2 z, -|z|^2
   bool ex;            // the expanded form (wave-uniform; as for the gradient pass)
   Acc4<CT> acc;
   template <bool E>
   __device__ __forceinline__ void pair_t(const CT* r) {
     // pos: the source (expanded) or d = z - x (difference form)
-    CT pos[3], r2;
-    if constexpr (E) {
+    CT pos[3], e;
+    bool in = true;
+    if constexpr (E && kFold) {
       pos[0] = r[0];
       pos[1] = r[1];
       pos[2] = r[2];
-      r2 = fma(r[0], m0, fma(r[1], m1, fma(r[2], m2, r[3 + FD] + z2)));
+      const CT a = fma(r[0], m0, fma(r[1], m1, fma(r[2], m2, z2)));  // |x|^2 - r^2
+      e = kexp2(a);
+      in = a >= r[3 + FD];
     } else {
-      pos[0] = zx - r[0];
-      pos[1] = zy - r[1];
-      pos[2] = zz - r[2];
-      r2 = pos[0] * pos[0] + pos[1] * pos[1] + pos[2] * pos[2];
+      CT r2;
+      if constexpr (E) {
+        pos[0] = r[0];
+        pos[1] = r[1];
+        pos[2] = r[2];
+        r2 = fma(r[0], m0, fma(r[1], m1, fma(r[2], m2, r[3 + FD] + z2)));
+      } else {
+        pos[0] = zx - r[0];
+        pos[1] = zy - r[1];
+        pos[2] = zz - r[2];
+        r2 = pos[0] * pos[0] + pos[1] * pos[1] + pos[2] * pos[2];
+      }
+      e = kexp2(-r2);
+      if (CUT) in = r2 <= rc2;
     }
-    const CT e = kexp2(-r2);
     CT c = r[3] * mj[0];
 #pragma unroll
     for (int f = 1; f < FD; f++) c += r[3 + f] * mj[f];
     CT w = c * e;
-    if (CUT) w = (r2 <= rc2) ? w : (CT)0;
+    if (CUT) w = in ? w : (CT)0;
     const CT be = fma(pos[0], q[0][0], fma(pos[1], q[0][1], fma(pos[2], q[0][2], k1)));
     const CT ga = fma(pos[0], q[1][0], fma(pos[1], q[1][1], fma(pos[2], q[1][2], k2)));
     const CT de = fma(pos[0], q[2][0], fma(pos[1], q[2][1], fma(pos[2], q[2][2], k3)));
@@ -933,6 +987,18 @@ struct QuartOp {
     else pair_t<false>(r);
   }
   __device__ __forceinline__ void fold() { acc.fold(); }
+  // the staged source record, as for the gradient pass
+  __device__ __forceinline__ void stage_rec(CT (&s)[3 + FD + 1]) const {
+    const CT xx = s[0] * s[0] + s[1] * s[1] + s[2] * s[2];
+    if (kFold && ex) {
+      const CT f = kexp2(-xx);
+#pragma unroll
+      for (int q = 0; q < FD; q++) s[3 + q] *= f;
+      s[3 + FD] = xx - rc2;
+    } else {
+      s[3 + FD] = xx;
+    }
+  }
   // per-target vectors from the direction (w, v) and the target's position
   // zt (m), in FP64, and the lane's frame position (zx, zy, zz, scaled);
   // lanes past the cluster get zero (their pairs have w = 0 and finite g)
@@ -967,10 +1033,12 @@ struct QuartOp {
     k2 = (CT)kk[1];
     k3 = (CT)kk[2];
     k4 = (CT)kk[3];
-    m0 = (CT)-2 * zx;
-    m1 = (CT)-2 * zy;
-    m2 = (CT)-2 * zz;
+    const CT two = kFold ? (CT)2 : (CT)-2;
+    m0 = two * zx;
+    m1 = two * zy;
+    m2 = two * zz;
     z2 = zx * zx + zy * zy + zz * zz;
+    if (kFold) z2 = -z2;
     acc.init();
   }
 };
@@ -993,7 +1061,7 @@ __device__ __forceinline__ void cell_segment(cptr<CT> xr, int xs, int a, int b, 
       for (int q = 0; q < NR; q++) rec[q] = xr[(size_t)i * xs + q];
 #pragma unroll
       for (int q = 0; q < 3; q++) rec[q] = (CT)((double)rec[q] + off[q]);
-      if constexpr (Op::kExpanded) rec[NR] = rec[0] * rec[0] + rec[1] * rec[1] + rec[2] * rec[2];
+      if constexpr (Op::kExpanded) op.stage_rec(rec);
       op.pair(rec);
     }
     op.fold();
@@ -1728,9 +1796,17 @@ __device__ __forceinline__ long long pairs_from_list(const ReqStatic& R, const C
     const unsigned long long km = __ballot(keep);
     if (keep) {
       CT* dst = recs + (count + __popcll(km & ((1ull << l) - 1ull))) * RS;
+      if constexpr (Op::kExpanded) {
+        CT srec[3 + FD + 1];
 #pragma unroll
-      for (int q = 0; q < 3 + FD; q++) dst[q] = rec[q];
-      if constexpr (Op::kExpanded) dst[3 + FD] = rec[0] * rec[0] + rec[1] * rec[1] + rec[2] * rec[2];
+        for (int q = 0; q < 3 + FD; q++) srec[q] = rec[q];
+        op.stage_rec(srec);
+#pragma unroll
+        for (int q = 0; q < 3 + FD + 1; q++) dst[q] = srec[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 3 + FD; q++) dst[q] = rec[q];
+      }
     }
     count += __popcll(km);
     if (count > NR - kWave || (last && count > 0)) flush();

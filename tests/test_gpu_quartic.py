@@ -237,7 +237,13 @@ def test_register_conjugate_rgbd_schedule_follows_oracle(ctx):
 
 def test_register_conjugate_converges_with_tolerance(ctx):
     """With tol the conjugate rule stops in the last stage once the applied
-    twist is below it; the oracle stops at the same iteration."""
+    twist is below it.  In that stage the applied twist of both trajectories
+    hovers between ~1e-5 and ~2e-4 for some 25 iterations before a step falls
+    under the tolerance, so the stopping iteration is a free-running quantity
+    (reading C15): the oracle's own moves over 97..101 when the source
+    coordinates are jittered by one FP32 ulp, and the GPU's by a few more.
+    Asserted: both converge in the last stage within 8 iterations of each
+    other, at the same final pose (1e-4 rad / 1e-4 m)."""
     p = synth.rgbd_pair(5000, 5000, seed=43, select="random")
     prm = params_rgbd(max_iters=200, step_rule="conjugate", tol=1e-5)
     out = ctx.register(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, prm)
@@ -245,7 +251,7 @@ def test_register_conjugate_converges_with_tolerance(ctx):
                           stage_ell=prm.stage_ell, max_iters=200, step_rule="conjugate", tol=1e-5)
     assert out["rc"] == 0 and out["converged"] and ref["converged"]
     assert 75 < out["iters"] < 200
-    assert abs(out["iters"] - ref["iters"]) <= 3, (out["iters"], ref["iters"])
+    assert abs(out["iters"] - ref["iters"]) <= 8, (out["iters"], ref["iters"])
     assert _angle_deg(out["T"], ref["T"]) < 1e-4 * 180 / np.pi
     assert np.linalg.norm(out["T"][:3, 3] - ref["T"][:3, 3]) < 1e-4
 
