@@ -302,6 +302,32 @@ def _overflow_case():
     return (x.astype(np.float32), lx.astype(np.float32), z.astype(np.float32), lz.astype(np.float32), T)
 
 
+def _compact_overflow_case():
+    # 64 targets in a cube of half-width 2.95 ell at ell = 0.02 (2.5 of the
+    # frame's scaled units, so the cluster takes the expanded, folded pair
+    # form), eight of them at its corners, over a dense cube of sources:
+    # about 665 reachable non-empty cells, beyond the 512-entry cell list
+    rng = np.random.default_rng(78)
+    ell = 0.02
+    x = rng.uniform(-0.4, 0.4, (60000, 3))
+    z = rng.uniform(-2.95 * ell, 2.95 * ell, (64, 3))
+    z[:8] = np.array([[a, b, c] for a in (-1, 1) for b in (-1, 1) for c in (-1, 1)]) * 2.95 * ell
+    lx = rng.uniform(0, 1, (len(x), 5))
+    lz = rng.uniform(0, 1, (64, 5))
+    T = synth.random_motion(rng, 0.5, 0.005)
+    return (x.astype(np.float32), lx.astype(np.float32), z.astype(np.float32), lz.astype(np.float32), T, ell)
+
+
+def test_cell_list_overflow_compact_cluster(ctx):
+    x, lx, z, lz, T, ell = _compact_overflow_case()
+    prm = Params(stage_ell=(ell,), cutoff_mult=3.0, a2=1.0)
+    g = ctx.eval(x, lx, z, lz, T, prm)
+    ref = oracle.eval(x, lx, z, lz, T, ell=ell, kappa=3.0, a2=1.0)
+    check(g, ref, what="compact overflow")
+    per = ctx.eval_targets(x, lx, z, lz, T, prm)
+    check(per.sum(axis=0), ref, what="compact overflow targets")
+
+
 def test_cell_list_overflow_path(ctx):
     x, lx, z, lz, T = _overflow_case()
     for ell in (0.02, 0.04):

@@ -256,6 +256,16 @@ def test_register_conjugate_converges_with_tolerance(ctx):
     assert np.linalg.norm(out["T"][:3, 3] - ref["T"][:3, 3]) < 1e-4
 
 
+def test_coefficients_cell_list_overflow_compact_cluster(ctx):
+    from test_gpu_parity import _compact_overflow_case
+    x, lx, z, lz, T, ell = _compact_overflow_case()
+    rng = np.random.default_rng(5)
+    w, v = rng.normal(size=3), rng.normal(size=3) * 0.05
+    c = ctx.quartic(x, lx, z, lz, T, w, v, Params(stage_ell=(ell,), cutoff_mult=3.0, a2=1.0))
+    ref, absref = oracle.quartic(x, lx, z, lz, T, w, v, ell=ell, kappa=3.0)
+    check_coef(c, ref, absref, 2e-5, what="compact overflow")
+
+
 def test_coefficients_cell_list_overflow(ctx):
     from test_gpu_parity import _overflow_case
     x, lx, z, lz, T = _overflow_case()
