@@ -218,6 +218,17 @@ def gen_serving_pool(npairs):
         return list(ex.map(_gen_pool_pair, [5100 + k for k in range(npairs)]))
 
 
+def window_rates(arrivals, latencies_ms, ok, window_s):
+    """Completions against arrivals over the second half of an arrival
+    window: (completions per s there, completions / arrivals there, or None
+    without arrivals).  arrivals in s from the window's start, latencies from
+    submission to completion, ok the requests that succeeded."""
+    h0, h1 = 0.5 * window_s, window_s
+    half_arr = sum(1 for ts in arrivals if h0 <= ts < h1)
+    half_done = sum(1 for ts, lat, good in zip(arrivals, latencies_ms, ok) if good and h0 <= ts + lat / 1e3 < h1)
+    return half_done / (h1 - h0), (half_done / half_arr if half_arr else None)
+
+
 def serving(pool, rates=(100, 150, 200, 500, 1000, 2000), window_s=10.0, table1_rates=(200,)):
     """Poisson arrivals at each rate over window_s seconds, cloud sizes
     lognormal (median 20k, shape 1.0, clamped to 1000..300000) cut from the
@@ -262,15 +273,14 @@ def serving(pool, rates=(100, 150, 200, 500, 1000, 2000), window_s=10.0, table1_
                 fails[str(r["rc"])] = fails.get(str(r["rc"]), 0) + 1
         lat = np.array([r["wall_ms"] for r in ok])
         end = max(ts + r["wall_ms"] / 1e3 for r, ts in res)
-        h0, h1 = 0.5 * window_s, window_s
-        half_arr = sum(1 for _, ts in res if h0 <= ts < h1)
-        half_done = sum(1 for r, ts in res if r["rc"] == 0 and h0 <= ts + r["wall_ms"] / 1e3 < h1)
+        steady, steady_frac = window_rates([ts for _, ts in res], [r["wall_ms"] for r, _ in res],
+                                           [r["rc"] == 0 for r, _ in res], window_s)
         progress(f"serving {pname} at {rate}/s: {len(ok)} of {len(res)} in {end:.1f} s")
         out.append({"params": pname, "rate": rate, "requests": len(res), "completed": len(ok),
                     "throughput_per_s": len(ok) / end, "span_s": end,
                     "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-                    "steady_throughput_per_s": half_done / (h1 - h0),
-                    "steady_completed_per_arrived": half_done / half_arr if half_arr else None,
+                    "steady_throughput_per_s": steady,
+                    "steady_completed_per_arrived": steady_frac,
                     "mean_iters": float(np.mean([r["iters"] for r in ok])),
                     "converged": float(np.mean([r["converged"] for r in ok])), "failed_by_code": fails,
                     "hbm_peak_gb": st["hbm_peak"] / 1e9})
