@@ -256,6 +256,30 @@ def test_register_conjugate_converges_with_tolerance(ctx):
     assert np.linalg.norm(out["T"][:3, 3] - ref["T"][:3, 3]) < 1e-4
 
 
+@pytest.mark.parametrize("fd", [1, 3, 8])
+def test_label_channels_against_oracle(ctx, fd):
+    """Every label-channel count the kernels are built for, on an RGB-D pair
+    with random labels: the gradient sums with and without the cutoff and the
+    quartic sums with it (the folded pair form, whose staged labels carry the
+    source's factor)."""
+    p = synth.rgbd_pair(5000, 4500, seed=60 + fd)
+    rng = np.random.default_rng(fd)
+    lx = rng.uniform(0, 1, (len(p.src_xyz), fd)).astype(np.float32)
+    lz = rng.uniform(0, 1, (len(p.tgt_xyz), fd)).astype(np.float32)
+    T = synth.random_motion(rng, 3.0, 0.03) @ p.T_true
+    a2 = oracle.mean_sqnorm(p.src_xyz)
+    for kappa, ell in ((3.0, 0.1), (0.0, 0.1)):
+        g = ctx.eval(p.src_xyz, lx, p.tgt_xyz, lz, T, Params(stage_ell=(ell,), cutoff_mult=kappa, a2=a2))
+        ref = oracle.eval(p.src_xyz, lx, p.tgt_xyz, lz, T, ell=ell, kappa=kappa, a2=a2)
+        assert abs(g[0] - ref["g"][0]) <= 1e-5 * ref["g"][0], (fd, kappa)
+        for k in range(1, 7):
+            assert abs(g[k] - ref["g"][k]) <= 1e-5 * ref["abs"][k], (fd, kappa, k)
+    w, v = rng.normal(size=3), rng.normal(size=3) * 0.1
+    c = ctx.quartic(p.src_xyz, lx, p.tgt_xyz, lz, T, w, v, Params(stage_ell=(0.1,), cutoff_mult=3.0, a2=a2))
+    ref, absref = oracle.quartic(p.src_xyz, lx, p.tgt_xyz, lz, T, w, v, ell=0.1, kappa=3.0)
+    check_coef(c, ref, absref, 2e-5, what=f"fd {fd}")
+
+
 def test_coefficients_cell_list_overflow_compact_cluster(ctx):
     from test_gpu_parity import _compact_overflow_case
     x, lx, z, lz, T, ell = _compact_overflow_case()
