@@ -261,7 +261,8 @@ def test_label_channels_against_oracle(ctx, fd):
     """Every label-channel count the kernels are built for, on an RGB-D pair
     with random labels: the gradient sums with and without the cutoff and the
     quartic sums with it (the folded pair form, whose staged labels carry the
-    source's factor)."""
+    source's factor), and the FP64 path's gradient and quartic sums at its
+    1e-10 bar."""
     p = synth.rgbd_pair(5000, 4500, seed=60 + fd)
     rng = np.random.default_rng(fd)
     lx = rng.uniform(0, 1, (len(p.src_xyz), fd)).astype(np.float32)
@@ -274,10 +275,19 @@ def test_label_channels_against_oracle(ctx, fd):
         assert abs(g[0] - ref["g"][0]) <= 1e-5 * ref["g"][0], (fd, kappa)
         for k in range(1, 7):
             assert abs(g[k] - ref["g"][k]) <= 1e-5 * ref["abs"][k], (fd, kappa, k)
+    # every pair term in FP64: the FP64 bar
+    g = ctx.eval(p.src_xyz, lx, p.tgt_xyz, lz, T, Params(stage_ell=(0.1,), cutoff_mult=3.0, a2=a2, precision="fp64"))
+    ref = oracle.eval(p.src_xyz, lx, p.tgt_xyz, lz, T, ell=0.1, kappa=3.0, a2=a2)
+    assert abs(g[0] - ref["g"][0]) <= 1e-10 * ref["g"][0], (fd, "fp64")
+    for k in range(1, 7):
+        assert abs(g[k] - ref["g"][k]) <= 1e-10 * ref["abs"][k], (fd, "fp64", k)
     w, v = rng.normal(size=3), rng.normal(size=3) * 0.1
     c = ctx.quartic(p.src_xyz, lx, p.tgt_xyz, lz, T, w, v, Params(stage_ell=(0.1,), cutoff_mult=3.0, a2=a2))
     ref, absref = oracle.quartic(p.src_xyz, lx, p.tgt_xyz, lz, T, w, v, ell=0.1, kappa=3.0)
     check_coef(c, ref, absref, 2e-5, what=f"fd {fd}")
+    c = ctx.quartic(p.src_xyz, lx, p.tgt_xyz, lz, T, w, v,
+                    Params(stage_ell=(0.1,), cutoff_mult=3.0, a2=a2, precision="fp64"))
+    check_coef(c, ref, absref, 1e-10, what=f"fd {fd} fp64")
 
 
 def test_coefficients_cell_list_overflow_compact_cluster(ctx):
