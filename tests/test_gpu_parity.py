@@ -48,6 +48,33 @@ def rgbd_small():
     return synth.rgbd_pair(6000, 5000, seed=31)
 
 
+def test_two_point_golden(ctx):
+    """The hand-derived two-point case (tests/golden/two_point.json, eq.
+    scalar and eq. 3_gradient with the kernel of Sec. IV) through the C ABI:
+    F = 1e-3, omega = (0, 0, 0.016 ln 2), v = (0, 0.016 ln 2, 0), with and
+    without the cutoff, in both precisions.  The zero components are exact:
+    in the target's frame the pair's offset has no x or z part."""
+    import json
+    import math
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "two_point.json")))
+    x = np.array(g["src_xyz"], np.float32)
+    lx = np.array(g["src_feat"], np.float32)
+    z = np.array(g["tgt_xyz"], np.float32)
+    lz = np.array(g["tgt_feat"], np.float32)
+    ell = math.sqrt(g["ell_sq_times_2ln2"] / (2.0 * math.log(2.0)))
+    c = 0.016 * math.log(2.0)
+    for kappa in (3.0, 0.0):
+        for precision, rtol in (("fp32", 1e-6), ("fp64", 1e-12)):
+            r = ctx.eval(x, lx, z, lz, np.eye(4), Params(stage_ell=(ell,), cutoff_mult=kappa, a2=g["a2"], b2=g["b2"],
+                                                          sigma=g["sigma"], feat_scale=g["feat_scale"],
+                                                          precision=precision))
+            what = (kappa, precision)
+            assert abs(r[0] - g["F"]) <= rtol * g["F"], (what, r[0])
+            assert abs(r[3] - c) <= rtol * c and abs(r[5] - c) <= rtol * c, (what, r[3], r[5])
+            assert r[1] == 0.0 and r[2] == 0.0 and r[4] == 0.0 and r[6] == 0.0, (what, r)
+
+
 def test_eval_planes_brute_force(ctx, planes):
     p = planes
     rng = np.random.default_rng(0)
