@@ -118,3 +118,28 @@ def test_registration_follows_oracle_trajectory(ctx, golden, pair_dev, precision
     # the pose stays a rigid motion
     R = Tg[:3, :3]
     assert np.abs(R.T @ R - np.eye(3)).max() < 1e-12
+
+
+def test_axis_permutation_covariance(ctx, golden, pair_dev):
+    """At the full size, independently of the oracle: rotating both clouds
+    by G (here the cyclic permutation of the axes, a rotation that moves
+    every FP32 coordinate exactly) and the pose to G T G^-1 leaves F
+    unchanged (Sec. V: the action is isometric) and turns omega and v by G
+    (the metric is rotation invariant).  Bar: reading C12 on the oracle's
+    sums of |terms| of that iteration, permuted with the gradient."""
+    p, _, _ = pair_dev
+    tr, A = golden["trace"], golden["abs"]
+    perm = [2, 0, 1]                         # (x, y, z) -> (z, x, y)
+    G = np.eye(4)
+    G[:3, :3] = np.eye(3)[perm]
+    for k in (0, 25, 75):
+        T = pose_before(tr, k)
+        prm = Params(stage_ell=(tr[k, 8],), cutoff_mult=3.0, a2=golden["a2"])
+        g = ctx.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, prm)
+        h = ctx.eval(np.ascontiguousarray(p.src_xyz[:, perm]), p.src_feat,
+                     np.ascontiguousarray(p.tgt_xyz[:, perm]), p.tgt_feat, G @ T @ G.T, prm)
+        assert abs(h[0] - g[0]) <= 1e-5 * g[0], (k, h[0], g[0])
+        for q0 in (1, 4):
+            turned = np.asarray(g[q0:q0 + 3])[perm]
+            scale = np.asarray(A[k, q0:q0 + 3])[perm]
+            assert (np.abs(np.asarray(h[q0:q0 + 3]) - turned) <= 1e-5 * scale).all(), (k, q0, h, g)
