@@ -919,6 +919,12 @@ struct Acc4<double> {
 //   g1 = beta, g2 = gamma + beta^2/2, g3 = delta + beta gamma + beta^3/6,
 //   g4 = eps + beta delta + beta^2 gamma/2 + gamma^2/2 + beta^4/24
 //      = eps + beta delta + g2^2/2 - beta^4/12.
+// The lane keeps gamma, delta and eps halved (their constants scaled by 1/2,
+// exactly) and sums g1, g2/2, g3/2 and g4/2:
+//   g2/2 = gamma/2 + beta^2/4,  g3/2 = delta/2 + beta (gamma/2 + beta^2/12),
+//   g4/2 = (eps/2 + beta delta/2) + (g2/2)^2 - beta^2 (beta^2/24),
+// one multiplication fewer than g4 from g2; the item doubles the last three
+// sums (exactly) before its wave sums.
 template <typename CT, int FD, bool CUT>
 struct QuartOp {
   // Expanded form, as in the gradient pass: with dk = z - x,
@@ -931,8 +937,8 @@ struct QuartOp {
   CT zx, zy, zz;
   CT mj[FD];
   CT rc2;
-  CT q[4][3];         // expanded: -p_k; difference form: p_k
-  CT k1, k2, k3, k4;  // expanded: c_k + <z, p_k>; difference form: c_k (c_1 = 0)
+  CT q[4][3];         // expanded: -p_k; difference form: p_k (k >= 2: halved)
+  CT k1, k2, k3, k4;  // expanded: c_k + <z, p_k>; difference form: c_k (c_1 = 0; k >= 2: halved)
   CT m0, m1, m2, z2;  // -2 z, |z|^2; folded: 2 z, -|z|^2
   bool ex;            // the expanded form (wave-uniform; as for the gradient pass)
   Acc4<CT> acc;
@@ -970,17 +976,17 @@ struct QuartOp {
     CT w = c * e;
     if (CUT) w = in ? w : (CT)0;
     const CT be = fma(pos[0], q[0][0], fma(pos[1], q[0][1], fma(pos[2], q[0][2], k1)));
-    const CT ga = fma(pos[0], q[1][0], fma(pos[1], q[1][1], fma(pos[2], q[1][2], k2)));
-    const CT de = fma(pos[0], q[2][0], fma(pos[1], q[2][1], fma(pos[2], q[2][2], k3)));
-    const CT ep = fma(pos[0], q[3][0], fma(pos[1], q[3][1], fma(pos[2], q[3][2], k4)));
+    const CT gah = fma(pos[0], q[1][0], fma(pos[1], q[1][1], fma(pos[2], q[1][2], k2)));  // gamma / 2
+    const CT deh = fma(pos[0], q[2][0], fma(pos[1], q[2][1], fma(pos[2], q[2][2], k3)));  // delta / 2
+    const CT eph = fma(pos[0], q[3][0], fma(pos[1], q[3][1], fma(pos[2], q[3][2], k4)));  // eps / 2
     const CT b2 = be * be;
-    const CT g2 = b2 * (CT)0.5 + ga;
-    const CT g3 = be * (b2 * (CT)(1.0 / 6.0) + ga) + de;
-    const CT g4 = (be * de + ep) + g2 * ((CT)0.5 * g2) - b2 * (b2 * (CT)(1.0 / 12.0));
+    const CT g2h = fma(b2, (CT)0.25, gah);
+    const CT g3h = fma(be, fma(b2, (CT)(1.0 / 12.0), gah), deh);
+    const CT g4h = fma(-b2, b2 * (CT)(1.0 / 24.0), fma(g2h, g2h, fma(be, deh, eph)));
     acc.a[0] += w * be;
-    acc.a[1] += w * g2;
-    acc.a[2] += w * g3;
-    acc.a[3] += w * g4;
+    acc.a[1] += w * g2h;
+    acc.a[2] += w * g3h;
+    acc.a[3] += w * g4h;
   }
   __device__ __forceinline__ void pair(const CT* r) {
     if (ex) pair_t<true>(r);
@@ -1020,9 +1026,10 @@ struct QuartOp {
     const double f[4] = {2.0 * ln2, -ln2, ln2 / 3.0, -ln2 / 12.0};
     double pk[4][3];
     for (int n = 0; n < 4; n++)
-      for (int a = 0; a < 3; a++) pk[n][a] = f[n] * u[n][a];
+      for (int a = 0; a < 3; a++) pk[n][a] = (n > 0 ? 0.5 : 1.0) * f[n] * u[n][a];  // gamma, delta, eps halved
     auto dot = [&](int i, int j) { return u[i][0] * u[j][0] + u[i][1] * u[j][1] + u[i][2] * u[j][2]; };
-    const double cc[4] = {0.0, -ln2 * dot(0, 0), ln2 * dot(0, 1), -ln2 * (0.25 * dot(1, 1) + dot(0, 2) / 3.0)};
+    const double cc[4] = {0.0, -0.5 * ln2 * dot(0, 0), 0.5 * ln2 * dot(0, 1),
+                          -0.5 * ln2 * (0.25 * dot(1, 1) + dot(0, 2) / 3.0)};
     const double z[3] = {(double)zx, (double)zy, (double)zz};
     double kk[4];
     for (int n = 0; n < 4; n++) {
@@ -1940,7 +1947,7 @@ __device__ __forceinline__ void process_item(const ReqStatic* __restrict__ reqs,
     double a4[4];
     op.acc.result(a4);
 #pragma unroll
-    for (int q = 0; q < 4; q++) a4[q] = valid ? a4[q] : 0.0;
+    for (int q = 0; q < 4; q++) a4[q] = valid ? (q > 0 ? 2.0 * a4[q] : a4[q]) : 0.0;  // the halved sums
     const double part[kSlot] = {wave_sum(a4[0]), wave_sum(a4[1]), wave_sum(a4[2]), wave_sum(a4[3]), 0.0, 0.0,
                                 0.0, 0.0, 0.0};
 #pragma unroll
