@@ -273,6 +273,7 @@ typedef struct {
   uint64_t hbm_in_use;      /* device bytes held by admitted requests */
   uint64_t hbm_budget;      /* the admission budget (bytes) */
   uint64_t hbm_peak;        /* the largest hbm_in_use since cvo_create */
+  int64_t graph_chunks;     /* scheduler chunks replayed from a captured graph (cvo_set_graphs) */
 } cvo_serving_counters;
 int cvo_serving_stats(cvo_ctx* ctx, cvo_serving_counters* out);
 
@@ -295,13 +296,17 @@ int cvo_set_queue_limit(cvo_ctx* ctx, int64_t max_pending);
  * or a ticket polled long ago). */
 int cvo_trace(cvo_ctx* ctx, uint64_t ticket, double* buf, int32_t cap);
 
-/* Launch mode of cvo_register's iteration loop: 0 (default) launches each
- * iteration's kernels on the stream; 1 captures a chunk of iterations (the
- * whole registration, or 16 iterations when a stopping tolerance is set) as a
- * HIP graph once per launch layout and replays it per chunk (the kernels read
- * the request's state on the device and return at once after it has
- * stopped).  Graphs need a stream other than the legacy null stream; with
- * profiling on, or on the null stream, iterations are launched directly. */
+/* Launch mode of the iteration loops: 0 (default) launches each iteration's
+ * kernels on the stream; 1 captures a chunk of iterations as a HIP graph once
+ * per launch layout and replays it per chunk (the kernels read the requests'
+ * state on the device and return at once after a request has stopped).
+ * cvo_register's chunk is the whole registration, or 16 iterations when a
+ * stopping tolerance is set; it needs a stream other than the legacy null
+ * stream, and with profiling on, or on the null stream, iterations are
+ * launched directly.  The batched scheduler's chunk is its 8 iterations for
+ * all active requests, captured again whenever the set of active requests
+ * (and so the launches' grids and arguments) changes.  Results are the same
+ * in either mode, bit for bit. */
 int cvo_set_graphs(cvo_ctx* ctx, int32_t enable);
 
 /* Event timing of the kernels of each iteration (the per-cluster

@@ -57,7 +57,7 @@ class cvo_params(ctypes.Structure):
 class cvo_serving_counters(ctypes.Structure):
     _fields_ = [("pending", ctypes.c_int64), ("active", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("failed", ctypes.c_int64), ("hbm_in_use", ctypes.c_uint64), ("hbm_budget", ctypes.c_uint64),
-                ("hbm_peak", ctypes.c_uint64)]
+                ("hbm_peak", ctypes.c_uint64), ("graph_chunks", ctypes.c_int64)]
 
 
 class cvo_rgbd_frame(ctypes.Structure):
@@ -313,7 +313,8 @@ class Context:
             self.L.cvo_set_stream(self.h, None)
 
     def set_graphs(self, on=True):
-        """Replay cvo_register's iteration chunks as HIP graphs (see cvo_set_graphs)."""
+        """Replay the iteration chunks of cvo_register and of the batched
+        scheduler as HIP graphs (see cvo_set_graphs)."""
         self._check(self.L.cvo_set_graphs(self.h, 1 if on else 0), "set_graphs")
 
     def set_profiling(self, on=True):
@@ -506,7 +507,7 @@ class Context:
 
     def serving_stats(self):
         """Counters of the batched path: pending, active, completed, failed,
-        hbm_in_use, hbm_budget."""
+        hbm_in_use, hbm_budget, hbm_peak, graph_chunks."""
         st = cvo_serving_counters()
         self._check(self.L.cvo_serving_stats(self.h, ctypes.byref(st)), "cvo_serving_stats")
         return {f: getattr(st, f) for f, _ in cvo_serving_counters._fields_}

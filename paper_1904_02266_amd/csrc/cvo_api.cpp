@@ -8,6 +8,7 @@
 #include <atomic>
 #include <chrono>
 #include <climits>
+#include <cstdint>
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
@@ -269,8 +270,9 @@ struct cvo_ctx {
   Request last_register;
   bool have_last = false;
 
-  // iteration chunks replayed as HIP graphs (synchronous path)
-  bool graphs = false;
+  // iteration chunks replayed as HIP graphs (synchronous path and the
+  // batched scheduler; read by the scheduler thread)
+  std::atomic<bool> graphs{false};
   struct GraphKey {
     int nclus = -1, precision = -1, fd = -1, cut = -1, rule = -1, iters = -1;
     const void* items = nullptr;
@@ -322,6 +324,7 @@ struct cvo_ctx {
   size_t max_pending = 65536;
   // serving counters (under q_mu)
   int64_t st_active = 0, st_completed = 0, st_failed = 0;
+  int64_t st_graph_chunks = 0;  // scheduler chunks replayed from a captured graph
   uint64_t st_hbm_in_use = 0, st_hbm_peak = 0;
   // traces of polled batched tickets, newest last (cvo_trace after cvo_poll)
   std::unordered_map<uint64_t, std::vector<double>> kept_traces;
@@ -1068,6 +1071,11 @@ void scheduler(cvo_ctx* c) {
   void* h_stage = nullptr;
   if (hipHostMalloc(&h_stage, kAdmitSlot * kAdmitBatch, hipHostMallocDefault) != hipSuccess) h_stage = nullptr;
   const int chunk = 8;
+  // with cvo_set_graphs(1): a chunk's launches captured once per launch
+  // layout (the groups of active requests, their cluster counts, the request
+  // tables and the work list) and replayed while the layout stays the same
+  hipGraphExec_t sg_exec = nullptr;
+  std::vector<long long> sg_key;
   for (;;) {
     std::vector<Request*> admit;
     {
@@ -1203,13 +1211,48 @@ void scheduler(cvo_ctx* c) {
                   hipMemcpyAsync(d_reqs, h_reqs, sizeof(ReqStatic) * nreq, hipMemcpyHostToDevice, s) == hipSuccess &&
                   hipMemcpyAsync(d_end, h_end, sizeof(int) * nreq, hipMemcpyHostToDevice, s) == hipSuccess;
     roctxRangePushA("cvo_batch_iterations");
-    for (int it = 0; it < chunk && dev_ok; it++) {
-      for (const G& g : gl) {
-        if (launch_iteration_rule(g.rule, g.precision, g.fd, g.cut != 0, d_reqs + g.first, d_end + g.first, g.count,
-                                  g.clusters, queue.ref(), s) != hipSuccess)
-          dev_ok = false;
+    auto launch_chunk = [&]() {
+      hipError_t e = hipSuccess;
+      for (int it = 0; it < chunk && e == hipSuccess; it++)
+        for (const G& g : gl)
+          if (e == hipSuccess)
+            e = launch_iteration_rule(g.rule, g.precision, g.fd, g.cut != 0, d_reqs + g.first, d_end + g.first,
+                                      g.count, g.clusters, queue.ref(), s);
+      return e;
+    };
+    bool graphed = false;
+    if (dev_ok && c->graphs.load()) {
+      std::vector<long long> key = {(long long)(intptr_t)d_reqs, (long long)(intptr_t)d_end,
+                                    (long long)(intptr_t)queue.q, (long long)(intptr_t)queue.items,
+                                    (long long)queue.cap, chunk};
+      for (const G& g : gl) key.insert(key.end(), {g.rule, g.precision, g.fd, g.cut, g.first, g.count, g.clusters});
+      if (!sg_exec || key != sg_key) {
+        if (sg_exec) (void)hipGraphExecDestroy(sg_exec);
+        sg_exec = nullptr;
+        // the capture records kernel launches only (the work list's reset
+        // and the request tables' copies stay in front of it on the stream)
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+          const hipError_t e = launch_chunk();
+          hipGraph_t gr = nullptr;
+          const hipError_t e2 = hipStreamEndCapture(s, &gr);
+          if (e == hipSuccess && e2 == hipSuccess && gr &&
+              hipGraphInstantiate(&sg_exec, gr, nullptr, nullptr, 0) == hipSuccess)
+            sg_key = key;
+          else
+            sg_exec = nullptr;
+          if (gr) (void)hipGraphDestroy(gr);
+        }
+      }
+      if (sg_exec) {
+        graphed = true;
+        if (hipGraphLaunch(sg_exec, s) != hipSuccess) dev_ok = false;
+        else {
+          std::lock_guard<std::mutex> g(c->q_mu);
+          c->st_graph_chunks++;
+        }
       }
     }
+    if (dev_ok && !graphed && launch_chunk() != hipSuccess) dev_ok = false;
     if (dev_ok && (launch_gather_states(d_reqs, nreq, d_states, s) != hipSuccess ||
                    hipMemcpyAsync(h_states, d_states, sizeof(ReqState) * nreq, hipMemcpyDeviceToHost, s) !=
                        hipSuccess))
@@ -1247,6 +1290,7 @@ void scheduler(cvo_ctx* c) {
     if (idle && c->pool && hipStreamSynchronize(s) == hipSuccess) (void)hipMemPoolTrimTo(c->pool, kPoolKeepBytes);
   }
   (void)hipStreamSynchronize(s);
+  if (sg_exec) (void)hipGraphExecDestroy(sg_exec);
   if (d_reqs) (void)hipFree(d_reqs);
   if (d_end) (void)hipFree(d_end);
   if (d_states) (void)hipFree(d_states);
@@ -1700,6 +1744,7 @@ int cvo_serving_stats(cvo_ctx* c, cvo_serving_counters* out) {
   out->hbm_in_use = c->st_hbm_in_use;
   out->hbm_budget = c->budget;
   out->hbm_peak = c->st_hbm_peak;
+  out->graph_chunks = c->st_graph_chunks;
   return CVO_OK;
 }
 

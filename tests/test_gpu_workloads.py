@@ -140,6 +140,49 @@ def test_batched_equals_sync_alone_and_mixed():
         assert s["F"] == a["F"] == m["F"]
 
 
+def test_batched_graph_chunks_equal_direct_launches():
+    """With cvo_set_graphs(1) the scheduler captures a chunk of iterations
+    once per launch layout and replays it while the layout holds; the results
+    equal the direct launches' and the synchronous ones bit for bit.  The
+    batch runs twice (the second replays the graph cached from the first,
+    with the scheduler's own copies and synchronisations between replays),
+    and a mixed run with late arrivals under another step rule changes the
+    layout (new captures)."""
+    prm = params_rgbd(max_iters=20, stage_iters=(5, 5, 5))
+    reqs = _small_requests(300, 6)
+    ctx = Context(0, max_slots=8)
+    try:
+        sync = [ctx.register(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm) for q in reqs]
+        direct = [ctx.poll(t) for t in [ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)[0]
+                                        for q in reqs]]
+        assert ctx.serving_stats()["graph_chunks"] == 0
+        ctx.set_graphs(True)
+        runs = []
+        for _ in range(2):
+            tks = [ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)[0] for q in reqs]
+            runs.append([ctx.poll(t) for t in tks])
+        replayed = ctx.serving_stats()["graph_chunks"]
+        extra = _small_requests(400, 3)
+        tks = []
+        for i, q in enumerate(reqs):
+            tks.append(ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)[0])
+            if i < len(extra):
+                e = extra[i]
+                ctx.submit(e.src_xyz, e.src_feat, e.tgt_xyz, e.tgt_feat,
+                           params_rgbd(max_iters=12, stage_iters=(3, 3, 3), step_rule="quartic"))
+        runs.append([ctx.poll(t) for t in tks])
+        ctx.set_graphs(False)
+    finally:
+        ctx.close()
+    assert replayed >= 6, replayed      # three chunks per run of 20 iterations, two runs
+    for k, s in enumerate(sync):
+        assert direct[k]["rc"] == 0 and np.array_equal(s["T"], direct[k]["T"]) and s["F"] == direct[k]["F"]
+        for run in runs:
+            o = run[k]
+            assert o["rc"] == 0 and o["iters"] == 20
+            assert np.array_equal(s["T"], o["T"]) and s["F"] == o["F"], k
+
+
 def test_batched_results_are_complete_when_polled():
     """A ticket is reported only after every field of its result is written
     (status is published last, under the queue lock): polling a batch in
