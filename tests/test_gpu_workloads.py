@@ -183,6 +183,48 @@ def test_batched_graph_chunks_equal_direct_launches():
             assert np.array_equal(s["T"], o["T"]) and s["F"] == o["F"], k
 
 
+def test_concurrent_submitters_and_synchronous_calls():
+    """cvo_submit and cvo_poll from four threads at once while the main
+    thread makes synchronous cvo_register calls on the same context (they
+    serialise on the context; the scheduler runs on its own stream): every
+    result equals the synchronous one bit for bit."""
+    import threading
+    prm = params_rgbd(max_iters=12, stage_iters=(3, 3, 3))
+    reqs = _small_requests(500, 16)
+    ctx = Context(0, max_slots=32)
+    results = [None] * len(reqs)
+    errors = []
+    try:
+        sync = [ctx.register(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm) for q in reqs]
+
+        def worker(ids):
+            try:
+                tks = [(i, ctx.submit(reqs[i].src_xyz, reqs[i].src_feat, reqs[i].tgt_xyz, reqs[i].tgt_feat,
+                                      prm)[0]) for i in ids]
+                for i, t in tks:
+                    results[i] = ctx.poll(t)
+            except Exception as e:  # reported below
+                errors.append(e)
+
+        threads = [threading.Thread(target=worker, args=(list(range(k, len(reqs), 4)),)) for k in range(4)]
+        for t in threads:
+            t.start()
+        again = [ctx.register(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm) for q in reqs[:4]]
+        for t in threads:
+            t.join(timeout=120)
+        assert not any(t.is_alive() for t in threads)
+        stats = ctx.serving_stats()
+    finally:
+        ctx.close()
+    assert not errors, errors
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    for s, o in zip(sync, results):
+        assert o is not None and o["rc"] == 0 and o["iters"] == 12
+        assert np.array_equal(s["T"], o["T"]) and s["F"] == o["F"]
+    for s, a in zip(sync, again):
+        assert np.array_equal(s["T"], a["T"]) and s["F"] == a["F"]
+
+
 def test_batched_results_are_complete_when_polled():
     """A ticket is reported only after every field of its result is written
     (status is published last, under the queue lock): polling a batch in
