@@ -225,6 +225,29 @@ def test_concurrent_submitters_and_synchronous_calls():
         assert np.array_equal(s["T"], a["T"]) and s["F"] == a["F"]
 
 
+def test_destroy_with_outstanding_requests():
+    """cvo_destroy waits for the requests still queued or running (their
+    work is bounded by their iteration cap) and frees everything; a context
+    created afterwards on the same device works."""
+    import time
+    prm = params_rgbd(max_iters=12, stage_iters=(3, 3, 3))
+    reqs = _small_requests(600, 10)
+    ctx = Context(0, max_slots=4)
+    for q in reqs:
+        ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)
+    t0 = time.perf_counter()
+    ctx.close()                                  # nothing polled
+    assert time.perf_counter() - t0 < 60.0
+    ctx = Context(0, max_slots=4)
+    try:
+        q = reqs[0]
+        a = ctx.register(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)
+        b = ctx.poll(ctx.submit(q.src_xyz, q.src_feat, q.tgt_xyz, q.tgt_feat, prm)[0])
+    finally:
+        ctx.close()
+    assert a["rc"] == 0 and b["rc"] == 0 and np.array_equal(a["T"], b["T"])
+
+
 def test_batched_results_are_complete_when_polled():
     """A ticket is reported only after every field of its result is written
     (status is published last, under the queue lock): polling a batch in
