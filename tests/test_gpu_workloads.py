@@ -93,10 +93,11 @@ def test_dense300k_swap_symmetry_and_determinism(ctx, dense300k):
     9e10-pair brute-force sum; the property holds at any size)."""
     p = dense300k
     T = p.T_true
-    prm = Params(stage_ell=(0.08,), cutoff_mult=3.0)
-    a = ctx.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, prm)
-    b = ctx.eval(p.tgt_xyz, p.tgt_feat, p.src_xyz, p.src_feat, synth.invert_rigid(T), prm)
-    assert abs(a[0] - b[0]) <= 2e-5 * a[0]
+    for ell in (0.2, 0.08, 0.05):
+        prm = Params(stage_ell=(ell,), cutoff_mult=3.0)
+        a = ctx.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, prm)
+        b = ctx.eval(p.tgt_xyz, p.tgt_feat, p.src_xyz, p.src_feat, synth.invert_rigid(T), prm)
+        assert abs(a[0] - b[0]) <= 2e-5 * a[0], ell
     a2 = ctx.eval(p.src_xyz, p.src_feat, p.tgt_xyz, p.tgt_feat, T, prm)
     assert np.array_equal(a, a2)
 
